@@ -1,0 +1,282 @@
+"""Seeded synthetic scenario trees and problem data.
+
+This module only draws inputs: tree shapes, dynamics, costs, boxes, initial
+states and dual vectors.  It holds none of the solver's arithmetic, so both
+the CPU oracle and the HIP library can be fed from it without sharing any
+computation.
+
+Conventions (the problem statement of Sec. II-A/II-B of the paper):
+
+* nodes are numbered stage-major: root is 0, the nodes of stage t are
+  ``[stage_ptr[t], stage_ptr[t+1])``, the children of node i are the
+  contiguous range ``[child_ptr[i], child_ptr[i+1])`` and all leaves sit at
+  stage N, numbered last;
+* ``prob[i]`` is the node probability; the children of a node split their
+  parent's probability uniformly, so every stage sums to one;
+* dynamics ``x_j = A_j x_i + B_j u_i + c_j`` live on the child j of i
+  (``A[0]``, ``B[0]``, ``c[0]`` are unused and zero);
+* costs ``Q, R`` (and optional ``S, q, r``) live on non-leaf nodes, ``P``
+  (and optional ``p``) on leaves;
+* boxes ``xmin <= x_i <= xmax`` on every node and ``umin <= u_i <= umax`` on
+  non-leaf nodes; the root state is data, so its rows carry +-inf.
+
+Draw order for a problem is fixed: G (for A), B, c, then the cost diagonals,
+then x0.  Every array is C-contiguous float64 / int32.
+"""
+from __future__ import annotations
+
+import concurrent.futures as _cf
+import dataclasses
+import os
+
+import numpy as np
+
+__all__ = [
+    "Tree", "Problem", "tree_from_counts", "uniform_tree", "capped_tree",
+    "draw_problem", "make_config", "draw_batch_instances", "random_dual",
+    "CONFIG_SHAPES",
+]
+
+
+@dataclasses.dataclass
+class Tree:
+    N: int
+    stage_ptr: np.ndarray  # int32 [N+2]
+    anc: np.ndarray        # int32 [V], -1 at the root
+    child_ptr: np.ndarray  # int32 [Vnl+1]
+    prob: np.ndarray       # float64 [V]
+
+    @property
+    def V(self) -> int:
+        return int(self.stage_ptr[-1])
+
+    @property
+    def Vnl(self) -> int:
+        return int(self.stage_ptr[self.N])
+
+    @property
+    def Vl(self) -> int:
+        return self.V - self.Vnl
+
+
+@dataclasses.dataclass
+class Problem:
+    tree: Tree
+    nx: int
+    nu: int
+    A: np.ndarray      # [V][nx][nx]
+    B: np.ndarray      # [V][nx][nu]
+    c: np.ndarray      # [V][nx]
+    Q: np.ndarray      # [Vnl][nx][nx]
+    R: np.ndarray      # [Vnl][nu][nu]
+    P: np.ndarray      # [Vl][nx][nx]
+    xmin: np.ndarray   # [V][nx]
+    xmax: np.ndarray   # [V][nx]
+    umin: np.ndarray   # [Vnl][nu]
+    umax: np.ndarray   # [Vnl][nu]
+    x0: np.ndarray     # [nx]
+    S: np.ndarray | None = None   # [Vnl][nu][nx]
+    q: np.ndarray | None = None   # [Vnl][nx]
+    r: np.ndarray | None = None   # [Vnl][nu]
+    p: np.ndarray | None = None   # [Vl][nx]
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        """Dual dimension: (nx+nu) rows per non-leaf node, nx per leaf."""
+        t = self.tree
+        return t.Vnl * (self.nx + self.nu) + t.Vl * self.nx
+
+
+def tree_from_counts(counts: list) -> Tree:
+    """Build a tree from per-stage child counts.
+
+    ``counts[t]`` lists the number of children of each node of stage t, in
+    node order; the children of a stage are numbered contiguously in parent
+    order.  Children split the parent's probability uniformly.
+    """
+    N = len(counts)
+    sizes = [1]
+    for t in range(N):
+        ct = np.asarray(counts[t], dtype=np.int64)
+        if ct.shape != (sizes[-1],):
+            raise ValueError(f"stage {t}: expected {sizes[-1]} counts, got {ct.shape}")
+        if (ct < 1).any():
+            raise ValueError("every non-leaf node needs at least one child")
+        sizes.append(int(ct.sum()))
+    stage_ptr = np.zeros(N + 2, dtype=np.int64)
+    stage_ptr[1:] = np.cumsum(sizes)
+    V = int(stage_ptr[-1])
+    Vnl = int(stage_ptr[N])
+    anc = np.full(V, -1, dtype=np.int64)
+    child_ptr = np.zeros(Vnl + 1, dtype=np.int64)
+    prob = np.zeros(V)
+    prob[0] = 1.0
+    for t in range(N):
+        ct = np.asarray(counts[t], dtype=np.int64)
+        parents = np.arange(stage_ptr[t], stage_ptr[t + 1])
+        first = stage_ptr[t + 1] + np.concatenate([[0], np.cumsum(ct)[:-1]])
+        child_ptr[parents] = first
+        kids_parent = np.repeat(parents, ct)
+        anc[stage_ptr[t + 1]:stage_ptr[t + 2]] = kids_parent
+        prob[stage_ptr[t + 1]:stage_ptr[t + 2]] = np.repeat(prob[parents] / ct, ct)
+    child_ptr[Vnl] = V
+    return Tree(N=N, stage_ptr=stage_ptr.astype(np.int32), anc=anc.astype(np.int32),
+                child_ptr=child_ptr.astype(np.int32), prob=prob)
+
+
+def uniform_tree(branching: list) -> Tree:
+    """Every node of stage t has ``branching[t]`` children (t = 0..N-1)."""
+    counts, n = [], 1
+    for b in branching:
+        counts.append([int(b)] * n)
+        n *= int(b)
+    return tree_from_counts(counts)
+
+
+def capped_tree(N: int, scenarios: int, b0: int) -> Tree:
+    """Stage sizes n_{t+1} = min(b0 * n_t, S); at the stage where the cap bites
+    the children are split as evenly as possible (the first ``S mod n_t``
+    parents get one more), and from there on every node has one child."""
+    counts, n = [], 1
+    for _ in range(N):
+        if n >= scenarios:
+            ct = [1] * n
+        elif b0 * n <= scenarios:
+            ct = [b0] * n
+        else:
+            base, extra = divmod(scenarios, n)
+            ct = [base + 1] * extra + [base] * (n - extra)
+        counts.append(ct)
+        n = sum(ct)
+    return tree_from_counts(counts)
+
+
+def _spectral_radius(G: np.ndarray) -> np.ndarray:
+    """Batched spectral radius, split over threads for large stacks."""
+    if G.shape[0] == 0:
+        return np.zeros(0)
+    nthreads = min(16, os.cpu_count() or 1)
+    if G.shape[0] < 512 or nthreads == 1:
+        return np.abs(np.linalg.eigvals(G)).max(axis=-1)
+    chunks = np.array_split(np.arange(G.shape[0]), nthreads * 4)
+    out = np.empty(G.shape[0])
+
+    def work(ix):
+        out[ix] = np.abs(np.linalg.eigvals(G[ix])).max(axis=-1)
+
+    with _cf.ThreadPoolExecutor(nthreads) as ex:
+        list(ex.map(work, chunks))
+    return out
+
+
+def draw_problem(tree: Tree, nx: int, nu: int, rng: np.random.Generator, *,
+                 rho: float = 0.95, c_std: float = 0.1,
+                 qdiag=None, rdiag=None, xbox: float = 5.0, ubox: float = 1.0,
+                 x0_range: float = 2.0, cross_terms: bool = False,
+                 name: str = "") -> Problem:
+    """Draw dynamics, costs, boxes and x0 for a tree.
+
+    A_j = rho * G / spectral_radius(G) with G ~ N(0,1), B_j ~ N(0,1),
+    c_j ~ N(0, c_std^2).  ``qdiag``/``rdiag`` are either None (Q = I,
+    R = 0.1 I) or a pair (lo, hi) for per-node diagonals ~ U[lo, hi].  With
+    ``cross_terms`` the optional S, q, r, p terms are drawn too (S small
+    enough that the joint cost block stays positive semidefinite).
+    """
+    V, Vnl, Vl = tree.V, tree.Vnl, tree.Vl
+    A = np.zeros((V, nx, nx))
+    B = np.zeros((V, nx, nu))
+    c = np.zeros((V, nx))
+    G = rng.standard_normal((V - 1, nx, nx))
+    A[1:] = rho * G / _spectral_radius(G)[:, None, None]
+    del G
+    B[1:] = rng.standard_normal((V - 1, nx, nu))
+    c[1:] = c_std * rng.standard_normal((V - 1, nx))
+    if qdiag is None:
+        Q = np.broadcast_to(np.eye(nx), (Vnl, nx, nx)).copy()
+    else:
+        Q = np.zeros((Vnl, nx, nx))
+        Q[:, np.arange(nx), np.arange(nx)] = rng.uniform(qdiag[0], qdiag[1], (Vnl, nx))
+    if rdiag is None:
+        R = np.broadcast_to(0.1 * np.eye(nu), (Vnl, nu, nu)).copy()
+    else:
+        R = np.zeros((Vnl, nu, nu))
+        R[:, np.arange(nu), np.arange(nu)] = rng.uniform(rdiag[0], rdiag[1], (Vnl, nu))
+    P = np.broadcast_to(np.eye(nx), (Vl, nx, nx)).copy()
+    S = q = r = p = None
+    if cross_terms:
+        # |S| small relative to Q = I and R: the joint block stays PSD when
+        # ||S||_2^2 <= lambda_min(Q) * lambda_min(R).
+        lamR = np.linalg.eigvalsh(R)[:, :1]
+        lamQ = np.linalg.eigvalsh(Q)[:, :1]
+        S = rng.standard_normal((Vnl, nu, nx))
+        nrm = np.linalg.norm(S, ord=2, axis=(1, 2))
+        S *= (0.9 * np.sqrt(lamR[:, 0] * lamQ[:, 0]) / nrm)[:, None, None]
+        q = rng.standard_normal((Vnl, nx))
+        r = rng.standard_normal((Vnl, nu))
+        p = rng.standard_normal((Vl, nx))
+    xmin = np.full((V, nx), -xbox)
+    xmax = np.full((V, nx), xbox)
+    xmin[0] = -np.inf
+    xmax[0] = np.inf
+    umin = np.full((Vnl, nu), -ubox)
+    umax = np.full((Vnl, nu), ubox)
+    x0 = rng.uniform(-x0_range, x0_range, nx)
+    return Problem(tree=tree, nx=nx, nu=nu, A=A, B=B, c=c, Q=Q, R=R, P=P,
+                   xmin=xmin, xmax=xmax, umin=umin, umax=umax, x0=x0,
+                   S=S, q=q, r=r, p=p, name=name)
+
+
+# Shapes of the five workloads; the tree of config 2 is drawn per instance.
+CONFIG_SHAPES = {
+    0: dict(nx=4, nu=2, branching=[2, 2, 2, 1, 1]),
+    1: dict(nx=50, nu=30, branching=[4] * 6 + [1] * 14),
+    3: dict(nx=20, nu=10, branching=[3] * 5 + [1] * 10),
+    4: dict(nx=64, nu=32, branching=[4] * 7 + [1] * 13),
+}
+
+
+def make_config(k: int, seed: int | None = None) -> Problem:
+    """The single-tree workloads 0, 1, 3 and 4 (seed default 1000 + k)."""
+    if k not in CONFIG_SHAPES:
+        raise ValueError(f"config {k} is not a single-tree workload")
+    rng = np.random.default_rng(1000 + k if seed is None else seed)
+    sh = CONFIG_SHAPES[k]
+    tree = uniform_tree(sh["branching"])
+    kw = {}
+    if k == 1:
+        kw = dict(qdiag=(0.5, 2.0), rdiag=(0.05, 0.5))
+    if k in (3, 4):
+        kw = dict(x0_range=3.0)
+    return draw_problem(tree, sh["nx"], sh["nu"], rng, name=f"cfg{k}", **kw)
+
+
+def draw_batch_instances(count: int = 256, seed: int = 1002, *,
+                         nx_range=(8, 32), N_range=(10, 30),
+                         S_range=(16, 1024), b0_range=(2, 8),
+                         scale: float = 1.0) -> list:
+    """Uneven batch of independent instances (workload 2).
+
+    Per instance: nx ~ U{nx_range}, nu = nx // 2, N ~ U{N_range},
+    scenarios S ~ U{S_range} (times ``scale``, for reduced test sizes),
+    first-stage branching b0 ~ U{b0_range}; the tree follows ``capped_tree``.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        nx = int(rng.integers(nx_range[0], nx_range[1] + 1))
+        nu = max(1, nx // 2)
+        N = int(rng.integers(N_range[0], N_range[1] + 1))
+        S = int(rng.integers(S_range[0], S_range[1] + 1))
+        S = max(1, int(round(S * scale)))
+        b0 = int(rng.integers(b0_range[0], b0_range[1] + 1))
+        tree = capped_tree(N, S, b0)
+        out.append(draw_problem(tree, nx, nu, rng, name=f"cfg2[{b}]"))
+    return out
+
+
+def random_dual(prob: Problem, rng: np.random.Generator, nrhs: int | None = None,
+                scale: float = 1.0) -> np.ndarray:
+    """Gaussian dual vector(s) of the problem's dual dimension."""
+    shape = (prob.m,) if nrhs is None else (nrhs, prob.m)
+    return scale * rng.standard_normal(shape)
