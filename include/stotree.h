@@ -1,0 +1,205 @@
+/*
+ * stotree — dual proximal solvers for scenario-tree stochastic optimal control
+ * on AMD Instinct MI355X (gfx950), FP64.
+ *
+ * Public C ABI.  Plain pointers and sizes only; no C++ or framework types.
+ *
+ * The problem (arXiv 2107.01745, Sec. II-A/II-B):
+ *   minimise over u_i (non-leaf i) and x_i (i >= 1)
+ *     sum_{i non-leaf} pi_i ([x_i;u_i]' [[Q_i,S_i'],[S_i,R_i]] [x_i;u_i] + q_i'x_i + r_i'u_i)
+ *   + sum_{j leaf}     pi_j (x_j' P_j x_j + p_j' x_j)
+ *   subject to x_0 = p,  x_j = A_j x_i + B_j u_i + c_j for every child j of i,
+ *   xmin_i <= x_i <= xmax_i (every node), umin_i <= u_i <= umax_i (non-leaf).
+ * Costs carry no factor 1/2.  Each non-leaf node owns the stage cost of its
+ * (x_i, u_i) weighted by its own probability.
+ *
+ * Tree numbering (Sec. II-A): stage-major.  Root = 0; the nodes of stage t are
+ * [stage_ptr[t], stage_ptr[t+1]); the children of node i are the contiguous
+ * range [child_ptr[i], child_ptr[i+1]) and children appear in parent order;
+ * all leaves sit at stage N and are numbered last, so the non-leaf nodes are
+ * the prefix [0, V_nl) with V_nl = stage_ptr[N].
+ *
+ * Dual vector layout (Sec. II-C, the vector z = Hx and its dual y): for each
+ * non-leaf node i, nx state rows then nu input rows at offset i*(nx+nu); for
+ * each leaf j, nx state rows at offset V_nl*nu + j*nx.  Its length is
+ * m = V_nl*(nx+nu) + (V - V_nl)*nx.
+ *
+ * Preconditioning (Sec. III-E): when enabled at tree_factor, every dual vector
+ * handed to dual_grad and the solvers is the scaled dual ybar_i = y_i/sqrt(pi_i)
+ * and residuals are reported in those units (plus unscaled, see solver_info).
+ *
+ * Matrices are row-major FP64.  Unless stated, every call is asynchronous on
+ * the caller's HIP stream (void* hip_stream, NULL = default stream), device
+ * pointers are borrowed for the duration of the call, and calls that share a
+ * tree_factors handle must not overlap in time.
+ *
+ * Return codes: 0 OK; 1 NOT_CONVERGED (outputs hold the last iterate);
+ * -1 ERR_ARG; -2 ERR_TREE (ordering/ranges/probabilities); -3 ERR_NOT_PD (a
+ * Cholesky pivot of the factor step failed); -4 ERR_BOX (lo > hi); -5
+ * ERR_NUMERIC (NaN/Inf); -6 ERR_DIVERGED; -7 ERR_DEVICE; -8 ERR_OOM.  After
+ * a negative code stotree_last_error() describes the failure.
+ */
+#ifndef STOTREE_H
+#define STOTREE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STOTREE_OK 0
+#define STOTREE_NOT_CONVERGED 1
+#define STOTREE_ERR_ARG (-1)
+#define STOTREE_ERR_TREE (-2)
+#define STOTREE_ERR_NOT_PD (-3)
+#define STOTREE_ERR_BOX (-4)
+#define STOTREE_ERR_NUMERIC (-5)
+#define STOTREE_ERR_DIVERGED (-6)
+#define STOTREE_ERR_DEVICE (-7)
+#define STOTREE_ERR_OOM (-8)
+
+/* Scenario tree (Sec. II-A).  All arrays are HOST memory. */
+typedef struct {
+    int32_t nx, nu, N, num_nodes;   /* state/input sizes, horizon, V         */
+    const int32_t *stage_ptr;       /* [N+2]                                 */
+    const int32_t *ancestor;        /* [V], -1 at the root                   */
+    const int32_t *child_ptr;       /* [V_nl+1]                              */
+    const double *prob;             /* [V]; pi_0 = 1, each stage sums to 1   */
+} tree_desc;
+
+/* Problem data (Sec. II-A dynamics, Sec. II-B costs, Sec. III-D boxes).
+ * All arrays are HOST memory, row-major. */
+typedef struct {
+    const double *A;     /* [V][nx][nx]  dynamics into node j (row 0 unused) */
+    const double *B;     /* [V][nx][nu]                                      */
+    const double *c;     /* [V][nx]      offset of the dynamics (w_j)        */
+    const double *Q;     /* [V_nl][nx][nx]                                   */
+    const double *R;     /* [V_nl][nu][nu] positive definite                 */
+    const double *S;     /* [V_nl][nu][nx] or NULL (zero)                    */
+    const double *q;     /* [V_nl][nx] or NULL                               */
+    const double *r;     /* [V_nl][nu] or NULL                               */
+    const double *P;     /* [V-V_nl][nx][nx] terminal weights (leaf order)   */
+    const double *p;     /* [V-V_nl][nx] or NULL                             */
+    const double *xmin, *xmax;  /* [V][nx], +-INFINITY allowed              */
+    const double *umin, *umax;  /* [V_nl][nu], +-INFINITY allowed           */
+} problem_data;
+
+typedef struct {
+    double lambda;       /* step of the forward-backward map; 0 = 1/(1.1 L)
+                            with L from dual_lipschitz (100 iterations)      */
+    double eps;          /* stop when ||R_lambda||_inf <= eps (default 1e-6) */
+    double eps_curv;     /* L-BFGS curvature guard eps' (default 1e-12)      */
+    int32_t mem;         /* L-BFGS memory (default 5, at most 16)            */
+    int32_t nu_max;      /* line-search trials tau = 2^-nu, nu = 0..nu_max
+                            (default 10, at most 30)                        */
+    int32_t max_iter;    /* default 1000                                     */
+    int32_t check_every; /* host reads the stop flag every k iterations (1)  */
+} solver_opts;
+
+typedef struct {
+    int32_t iters, sweeps_affine, sweeps_hom, ls_trials, lbfgs_push, lbfgs_skip, status;
+    double res_scaled_inf;    /* ||R||_inf in the solver's (scaled) units    */
+    double res_unscaled_inf;  /* ||z - Hx||_inf in the problem's units       */
+    double lambda;            /* step used                                   */
+    double seconds;           /* host wall time of the call                  */
+} solver_info;
+
+typedef struct tree_factors tree_factors;  /* opaque; owns device memory */
+
+/*
+ * Factor step (Sec. III-D, the Riccati-type recursion computed once before the
+ * solves).  Validates the tree (stage-major order, contiguous child ranges,
+ * every stage's probabilities sum to 1 within 1e-12, leaves only at stage N),
+ * the boxes (lo <= hi) and finiteness, copies the data to the device, runs the
+ * per-stage factor kernels (batched Cholesky of R-tilde and the feedback
+ * gains) and packs every factor in the layout the sweeps stream.  precondition
+ * = 1 selects the sqrt(pi) scaling of Sec. III-E.  The handle owns all device
+ * memory it needs, including the solvers' workspace, which is sized at the
+ * first solve and reused.  Synchronous with respect to hip_stream.
+ * Errors: ERR_ARG (NULL pointers, nx < 1, nu < 1, N < 1, nx+nu > 256),
+ * ERR_TREE, ERR_BOX, ERR_NUMERIC (non-finite data), ERR_NOT_PD, ERR_OOM,
+ * ERR_DEVICE.  On error *out is NULL.
+ */
+int tree_factor(const tree_desc *tree, const problem_data *data, int precondition,
+                void *hip_stream, tree_factors **out);
+
+/* Releases the handle and its device memory (NULL is a no-op). */
+void tree_factors_free(tree_factors *f);
+
+/* Sizes of a factored tree, written to HOST out[10]: nx, nu, N, V, V_nl, m
+ * (dual length), n (primal length), s_star (first stage from which every node
+ * has one child), precondition flag, device bytes held.  ERR_ARG on NULL. */
+int tree_dims(const tree_factors *f, int64_t *out);
+
+/*
+ * Dual gradient (Algorithm 3) and Hessian-vector products (Algorithm 4).
+ * homogeneous = 0: x(y), the minimiser of the inner problem of Sec. III-D for
+ * the dual y, with x_0 = x0; the dual gradient is -H x(y).  homogeneous = 1:
+ * the linear part x-hat(y) (no affine terms, x_0 = 0); the Hessian-vector
+ * product of the dual function is -H x-hat(y).  With preconditioning, y is the
+ * scaled dual (the kernels apply sqrt(pi) per node) and x, u are unscaled.
+ * DEVICE pointers: x0 [nrhs][nx] (ignored when homogeneous; may be NULL then),
+ * y [nrhs][m], x [nrhs][V][nx] (x_0 included), u [nrhs][V_nl][nu].
+ * nrhs >= 1; right-hand sides are swept two at a time, each pair sharing
+ * one streaming of the factors.  Errors: ERR_ARG, ERR_OOM (workspace growth), ERR_DEVICE.
+ */
+int dual_grad(const tree_factors *f, const double *x0, const double *y, int homogeneous,
+              int nrhs, double *x, double *u, void *hip_stream);
+
+/*
+ * Lipschitz constant L of the dual gradient (largest eigenvalue of the dual
+ * Hessian, in the scaled variables if the handle is preconditioned) by power
+ * iteration on Algorithm 4, started from the all-ones vector; the step
+ * lambda must lie in (0, 1/L) (Algorithm 1 input).  Writes HOST *L_out.
+ * Synchronous.  Errors: ERR_ARG, ERR_DEVICE.
+ */
+int dual_lipschitz(const tree_factors *f, int iters, double *L_out, void *hip_stream);
+
+/*
+ * Dual MINFBE with L-BFGS directions (Algorithm 1).  Per iteration: one affine
+ * sweep x(y), one homogeneous sweep for the FBE gradient, one homogeneous
+ * sweep x-hat(d) for the line search, whose trial steps tau = 2^-nu are all
+ * evaluated in one pass from tau-independent coefficients (Sec. III-B); the
+ * largest tau with phi(y + tau d) <= phi(y) is taken (tau = 0 if none), then
+ * y+ = T_lambda(y + tau d).  DEVICE: x0 [nx], y_inout [m] (initial dual on
+ * entry, zeros for a cold start; last iterate on exit), x [V][nx],
+ * u [V_nl][nu] (receive x(y) at the returned y).  HOST: opts (NULL =
+ * defaults), info (may be NULL).  Synchronous.  Returns OK, NOT_CONVERGED,
+ * ERR_NUMERIC (NaN/Inf in the iterates), ERR_ARG, ERR_OOM, ERR_DEVICE.
+ */
+int minfbe_solve(const tree_factors *f, const double *x0, const solver_opts *opts,
+                 double *y_inout, double *x, double *u, solver_info *info, void *hip_stream);
+
+/*
+ * NAMA on the dual (Algorithm 2) with the extra parallelism of Sec. III-C:
+ * per iteration one affine sweep x(y) and ONE two-right-hand-side homogeneous
+ * sweep giving x-hat(r) and x-hat(d) together; trial points
+ * w = y - (1 - tau) lambda r + tau d (tau = 0 is the forward-backward step),
+ * all tau evaluated in one pass; y+ = T_lambda(w).  Same arguments, outputs
+ * and errors as minfbe_solve.
+ */
+int nama_solve(const tree_factors *f, const double *x0, const solver_opts *opts,
+               double *y_inout, double *x, double *u, solver_info *info, void *hip_stream);
+
+/*
+ * Phase timing for measurement tools.  stotree_timing(1) makes every sweep
+ * record HIP events around each of its phases on the stream it runs on
+ * (0 backward chain kernel, 1 backward per-stage kernels, 2 forward per-stage
+ * kernels, 3 forward chain kernel); stotree_timing(0) stops recording.
+ * stotree_timing_read synchronises on the recorded events and writes, per
+ * phase, the summed milliseconds (HOST ms[4]) and the number of launches
+ * (HOST count[4]), then clears the record.  Process-wide state; not for use
+ * while several threads sweep.  Errors: ERR_ARG, ERR_DEVICE.
+ */
+int stotree_timing(int enable);
+int stotree_timing_read(double *ms, int64_t *count);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *stotree_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STOTREE_H */

@@ -1,0 +1,117 @@
+// C ABI of the stotree library (declared in include/stotree.h).
+#include <chrono>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace stotree {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+}  // namespace stotree
+
+using namespace stotree;
+
+extern "C" {
+
+const char *stotree_last_error(void) { return g_last_error.c_str(); }
+
+int tree_factor(const tree_desc *tree, const problem_data *data, int precondition, void *hip_stream,
+                tree_factors **out)
+{
+    set_error("");
+    return factor_tree(tree, data, precondition, (hipStream_t)hip_stream, out);
+}
+
+void tree_factors_free(tree_factors *f) { free_tree(f); }
+
+int tree_dims(const tree_factors *f, int64_t *out)
+{
+    if (!f || !out) { set_error("tree_dims: NULL argument"); return STOTREE_ERR_ARG; }
+    out[0] = f->nx; out[1] = f->nu; out[2] = f->N; out[3] = f->V; out[4] = f->Vnl;
+    out[5] = f->m; out[6] = f->n; out[7] = f->sstar; out[8] = f->precondition;
+    out[9] = (int64_t)(f->bytes + f->sws.bytes);
+    return STOTREE_OK;
+}
+
+int dual_grad(const tree_factors *fc, const double *x0, const double *y, int homogeneous, int nrhs,
+              double *x, double *u, void *hip_stream)
+{
+    if (!fc || !y || !x || !u || nrhs < 1 || (!homogeneous && !x0)) {
+        set_error("dual_grad: NULL pointer or nrhs < 1");
+        return STOTREE_ERR_ARG;
+    }
+    tree_factors *f = const_cast<tree_factors *>(fc);  // workspace only
+    const int chunk = nrhs >= 2 ? 2 : 1;
+    int rc = ensure_sweep_ws(f, chunk);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    SweepArgs a = sweep_args(f, homogeneous ? 0 : 1);
+    a.y_rs = f->m;
+    a.x0_rs = f->nx;
+    a.xo_s = f->nx; a.xl_s = f->nx; a.uo_s = f->nu;
+    a.xo_rs = (long long)f->V * f->nx;
+    a.uo_rs = (long long)f->Vnl * f->nu;
+    for (int k0 = 0; k0 < nrhs; k0 += chunk) {
+        const int nk = (nrhs - k0 >= chunk) ? chunk : 1;
+        a.x0 = x0 ? x0 + (long long)k0 * f->nx : nullptr;
+        a.y = y + (long long)k0 * f->m;
+        a.xo = x + (long long)k0 * a.xo_rs;
+        a.xl = a.xo + (long long)f->Vnl * f->nx;
+        a.uo = u + (long long)k0 * a.uo_rs;
+        hipError_t e = launch_sweep_tree(f, a, nk, st);
+        if (e != hipSuccess) {
+            set_error(std::string("dual_grad: ") + hipGetErrorString(e));
+            return STOTREE_ERR_DEVICE;
+        }
+    }
+    return STOTREE_OK;
+}
+
+int dual_lipschitz(const tree_factors *f, int iters, double *L_out, void *hip_stream)
+{
+    if (!f || !L_out || iters < 1) { set_error("dual_lipschitz: bad argument"); return STOTREE_ERR_ARG; }
+    return lipschitz(f, iters, L_out, (hipStream_t)hip_stream);
+}
+
+static int run_solver(const tree_factors *f, const double *x0, const solver_opts *opts, double *y,
+                      double *x, double *u, solver_info *info, void *hip_stream, int method)
+{
+    if (!f || !x0 || !y || !x || !u) { set_error("solve: NULL pointer"); return STOTREE_ERR_ARG; }
+    const auto t0 = std::chrono::steady_clock::now();
+    solver_info local{};
+    const int rc = solve(f, x0, opts, y, x, u, &local, (hipStream_t)hip_stream, method);
+    local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = local;
+    return rc;
+}
+
+int minfbe_solve(const tree_factors *f, const double *x0, const solver_opts *opts, double *y_inout,
+                 double *x, double *u, solver_info *info, void *hip_stream)
+{
+    return run_solver(f, x0, opts, y_inout, x, u, info, hip_stream, 0);
+}
+
+int nama_solve(const tree_factors *f, const double *x0, const solver_opts *opts, double *y_inout,
+               double *x, double *u, solver_info *info, void *hip_stream)
+{
+    return run_solver(f, x0, opts, y_inout, x, u, info, hip_stream, 1);
+}
+
+int stotree_timing(int enable) { return timing_enable(enable); }
+
+int stotree_timing_read(double *ms, int64_t *count)
+{
+    if (!ms || !count) { set_error("stotree_timing_read: NULL argument"); return STOTREE_ERR_ARG; }
+    long long c[4];
+    const int rc = timing_read(ms, c);
+    for (int p = 0; p < 4; ++p) count[p] = c[p];
+    return rc;
+}
+
+}  // extern "C"

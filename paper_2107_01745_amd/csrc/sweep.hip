@@ -1,0 +1,488 @@
+// Stage-parallel sweeps over the scenario tree: Algorithm 3 (dual gradient
+// x(y)) and Algorithm 4 (Hessian-vector products x-hat(r)) of arXiv 2107.01745,
+// Sec. III-D, written for CDNA4 wavefronts.
+//
+// Algebra.  With R~_i the input Hessian of node i's subproblem and K_i its
+// feedback gain, the paper's per-edge factors are Theta_j = -R~_i^{-1} B_j' and
+// Lambda_j = A_j + B_j K_i, and its per-node terms are Phi_i y_i =
+// -R~_i^{-1} y_i^u, D_i' y_i = y_i^x + K_i' y_i^u.  Collecting the terms per
+// node, the backward step of node i reads
+//     g_i    = s_i y_i^u + pi_i r_i + sum_j B_j' qhat_j          (nu)
+//     k_i    = -R~_i^{-1} g_i                                    (u offset)
+//     qhat_i = chat_i + s_i y_i^x + sum_j A_j' qhat_j + K_i' g_i (nx)
+// which is the paper's recursion regrouped so that the per-edge matrices
+// streamed are the dynamics [A_j B_j] themselves (read once backward, once
+// forward) and no Lambda/Theta copies are stored.  The forward step is
+// u_i = K_i x_i + k_i and x_j = A_j x_i + B_j u_i + c_j.  s_i = sqrt(pi_i)
+// under the preconditioning of Sec. III-E (1 otherwise).  Algorithm 4 drops
+// pi r, chat, c and uses x_0 = 0.
+//
+// Mapping.  One wavefront per node (per chain, below).  Each lane owns two
+// adjacent output entries; matrices are stored in the orientation of the pass
+// that reads them, so every row of a matrix is one contiguous, 16-byte-aligned
+// load across the wavefront, multiplied by a broadcast entry of the input
+// vector held in LDS.  The nodes from stage s* on have one child each (the
+// scenario fan-out has ended); the tree below s* is a set of independent
+// chains, each walked by one wavefront through all its stages with qhat / x
+// carried in LDS, so those stages need no grid-wide synchronisation.  Stages
+// above s* are launched stage by stage.
+#include "internal.h"
+
+namespace stotree {
+
+namespace {
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ long long off_nl(const SweepArgs &a, int i)
+{
+    return (long long)i * (a.nx + a.nu);
+}
+__device__ __forceinline__ long long off_l(const SweepArgs &a, int j)
+{
+    return (long long)a.Vnl * a.nu + (long long)j * a.nx;
+}
+__device__ __forceinline__ double *x_ptr(const SweepArgs &a, int k, int i)
+{
+    return (i < a.Vnl ? a.xo + (long long)i * a.xo_s : a.xl + (long long)(i - a.Vnl) * a.xl_s) +
+           (long long)k * a.xo_rs;
+}
+
+// acc[k][ch][e] += sum_r M[r][c] * v_k[r] for the lane's columns
+// c = 2*lane + 128*ch + e < W, with M row-major of leading dimension ld and v_k
+// in LDS at v + k*ldv.
+template <int NRHS, int CH>
+__device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, int rows, int W,
+                                          const double *v, int ldv, double (&acc)[NRHS][CH][2],
+                                          int lane)
+{
+#pragma unroll 4
+    for (int r = 0; r < rows; ++r) {
+        const double *row = M + (long long)r * ld;
+        double vk[NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) vk[k] = v[k * ldv + r];
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+            const int c0 = 2 * lane + 128 * ch;
+            if (c0 < W) {
+                const double2 m2 = *reinterpret_cast<const double2 *>(row + c0);
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) {
+                    acc[k][ch][0] = fma(m2.x, vk[k], acc[k][ch][0]);
+                    acc[k][ch][1] = fma(m2.y, vk[k], acc[k][ch][1]);
+                }
+            }
+        }
+    }
+}
+
+template <int NRHS, int CH>
+__device__ __forceinline__ void zero(double (&acc)[NRHS][CH][2])
+{
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) acc[k][ch][0] = acc[k][ch][1] = 0.0;
+}
+
+// LDS carve-up per wave: qx [NRHS][ldM] (qhat or [x;u]), as [NRHS][ldM],
+// gs [NRHS][ldu].
+struct WaveLds {
+    double *qx, *as, *gs;
+    int ldq;
+};
+
+__device__ __forceinline__ WaveLds wave_lds(const SweepArgs &a, int nrhs, int wave)
+{
+    extern __shared__ double lds[];
+    const int per = nrhs * (2 * a.ldM + a.ldu);
+    WaveLds w;
+    w.qx = lds + wave * per;
+    w.as = w.qx + nrhs * a.ldM;
+    w.gs = w.as + nrhs * a.ldM;
+    w.ldq = a.ldM;
+    return w;
+}
+
+// Backward step of non-leaf node i.  If child_in_lds, qhat of the (single)
+// child is already in L.qx; otherwise each child's qhat is staged from the
+// leaf data or from the global qhat buffer.  The result qhat_i is left in
+// L.qx and, if store_q, written to the global buffer; k_i always goes to kbuf.
+template <int NRHS, int CH>
+__device__ void bwd_node(const SweepArgs &a, int i, const WaveLds &L, bool child_in_lds,
+                         bool store_q, int lane)
+{
+    const int nx = a.nx, nu = a.nu, W = nx + nu;
+    double acc[NRHS][CH][2];
+    zero(acc);
+    const int j0 = a.child_ptr[i], j1 = a.child_ptr[i + 1];
+    for (int j = j0; j < j1; ++j) {
+        if (!child_in_lds) {
+            if (j >= a.Vnl) {
+                const double sj = a.sc ? a.sc[j] : 1.0;
+                for (int r = lane; r < nx; r += kWave)
+#pragma unroll
+                    for (int k = 0; k < NRHS; ++k)
+                        L.qx[k * L.ldq + r] = sj * a.y[k * a.y_rs + off_l(a, j) + r] +
+                                              (a.affine ? a.chat[(long long)j * nx + r] : 0.0);
+            } else {
+                for (int r = lane; r < nx; r += kWave)
+#pragma unroll
+                    for (int k = 0; k < NRHS; ++k)
+                        L.qx[k * L.ldq + r] = a.qhat[k * a.qhat_rs + (long long)j * nx + r];
+            }
+            wave_sync();
+        }
+        gemv_rows<NRHS, CH>(a.Mb + (long long)j * nx * a.ldM, a.ldM, nx, W, L.qx, L.ldq, acc, lane);
+        wave_sync();
+    }
+    // scatter [sum A'q ; sum B'q] to LDS
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = 2 * lane + 128 * ch;
+        if (c0 < W) {
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) {
+                L.as[k * a.ldM + c0] = acc[k][ch][0];
+                L.as[k * a.ldM + c0 + 1] = acc[k][ch][1];
+            }
+        }
+    }
+    wave_sync();
+    const double si = a.sc ? a.sc[i] : 1.0;
+    for (int c = lane; c < nu; c += kWave)
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k)
+            L.gs[k * a.ldu + c] = L.as[k * a.ldM + nx + c] +
+                                  si * a.y[k * a.y_rs + off_nl(a, i) + nx + c] +
+                                  (a.affine ? a.sig[(long long)i * nu + c] : 0.0);
+    wave_sync();
+    double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
+    zero(kacc);
+    zero(qacc);
+    gemv_rows<NRHS, CH>(a.Rn + (long long)i * nu * a.ldu, a.ldu, nu, nu, L.gs, a.ldu, kacc, lane);
+    gemv_rows<NRHS, CH>(a.Kb + (long long)i * nu * a.ldx, a.ldx, nu, nx, L.gs, a.ldu, qacc, lane);
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = 2 * lane + 128 * ch;
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            double *kb = a.kbuf + k * a.kbuf_rs + (long long)i * nu;
+            if (c0 < nu) kb[c0] = kacc[k][ch][0];
+            if (c0 + 1 < nu) kb[c0 + 1] = kacc[k][ch][1];
+        }
+    }
+    // qhat_i = [sum A'q]_c + s_i y_i^x + chat_i + (K_i' g_i)
+    double qv[NRHS][CH][2];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = 2 * lane + 128 * ch;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int c = c0 + e;
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) {
+                double v = 0.0;
+                if (c < nx)
+                    v = L.as[k * a.ldM + c] + si * a.y[k * a.y_rs + off_nl(a, i) + c] +
+                        (a.affine ? a.chat[(long long)i * nx + c] : 0.0) + qacc[k][ch][e];
+                qv[k][ch][e] = v;
+            }
+        }
+    }
+    wave_sync();  // every lane has finished reading L.qx / L.as
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = 2 * lane + 128 * ch;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int c = c0 + e;
+            if (c < nx) {
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) {
+                    L.qx[k * L.ldq + c] = qv[k][ch][e];
+                    if (store_q) a.qhat[k * a.qhat_rs + (long long)i * nx + c] = qv[k][ch][e];
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+// Forward step of non-leaf node i with x_i in L.qx[0..nx).  Writes u_i and the
+// children's x_j to the outputs; for a single-child chain the child's x is
+// left in L.qx.
+template <int NRHS, int CH>
+__device__ void fwd_node(const SweepArgs &a, int i, const WaveLds &L, bool keep_child, int lane)
+{
+    const int nx = a.nx, nu = a.nu;
+    double uacc[NRHS][CH][2];
+    zero(uacc);
+    gemv_rows<NRHS, CH>(a.Kf + (long long)i * nx * a.ldu, a.ldu, nx, nu, L.qx, L.ldq, uacc, lane);
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = 2 * lane + 128 * ch;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int c = c0 + e;
+            if (c < nu) {
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) {
+                    const double uval = uacc[k][ch][e] + a.kbuf[k * a.kbuf_rs + (long long)i * nu + c];
+                    a.uo[k * a.uo_rs + (long long)i * a.uo_s + c] = uval;
+                    L.qx[k * L.ldq + nx + c] = uval;
+                }
+            }
+        }
+    }
+    wave_sync();
+    const int j0 = a.child_ptr[i], j1 = a.child_ptr[i + 1];
+    double keep[NRHS][CH][2];
+    for (int j = j0; j < j1; ++j) {
+        double xacc[NRHS][CH][2];
+        zero(xacc);
+        gemv_rows<NRHS, CH>(a.Mf + (long long)j * (nx + nu) * a.ldx, a.ldx, nx + nu, nx, L.qx,
+                            L.ldq, xacc, lane);
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+            const int c0 = 2 * lane + 128 * ch;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int c = c0 + e;
+                if (c < nx) {
+#pragma unroll
+                    for (int k = 0; k < NRHS; ++k) {
+                        const double xv = xacc[k][ch][e] + (a.affine ? a.cvec[(long long)j * nx + c] : 0.0);
+                        x_ptr(a, k, j)[c] = xv;
+                        keep[k][ch][e] = xv;
+                    }
+                }
+            }
+        }
+    }
+    if (keep_child) {
+        wave_sync();
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+            const int c0 = 2 * lane + 128 * ch;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int c = c0 + e;
+                if (c < nx)
+#pragma unroll
+                    for (int k = 0; k < NRHS; ++k) L.qx[k * L.ldq + c] = keep[k][ch][e];
+            }
+        }
+        wave_sync();
+    }
+}
+
+// x_i of the first node a forward pass visits: x0 at the root (written to
+// the output too), else the value the previous stage stored.
+template <int NRHS>
+__device__ void load_x(const SweepArgs &a, int i, const WaveLds &L, int lane)
+{
+    for (int c = lane; c < a.nx; c += kWave)
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            double v;
+            if (i == 0) {
+                v = a.affine ? a.x0[k * a.x0_rs + c] : 0.0;
+                x_ptr(a, k, 0)[c] = v;
+            } else {
+                v = x_ptr(a, k, i)[c];
+            }
+            L.qx[k * L.ldq + c] = v;
+        }
+    wave_sync();
+}
+
+template <int NRHS, int CH>
+__global__ void __launch_bounds__(kWave *kWavesPerBlock)
+bwd_stage_kernel(SweepArgs a, int t)
+{
+    if (a.done && *a.done) return;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int i = a.stage_ptr[t] + blockIdx.x * kWavesPerBlock + wave;
+    if (i >= a.stage_ptr[t + 1]) return;
+    const WaveLds L = wave_lds(a, NRHS, wave);
+    bwd_node<NRHS, CH>(a, i, L, false, true, lane);
+}
+
+template <int NRHS, int CH>
+__global__ void __launch_bounds__(kWave *kWavesPerBlock)
+fwd_stage_kernel(SweepArgs a, int t)
+{
+    if (a.done && *a.done) return;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int i = a.stage_ptr[t] + blockIdx.x * kWavesPerBlock + wave;
+    if (i >= a.stage_ptr[t + 1]) return;
+    const WaveLds L = wave_lds(a, NRHS, wave);
+    load_x<NRHS>(a, i, L, lane);
+    fwd_node<NRHS, CH>(a, i, L, false, lane);
+}
+
+// Chain c covers the nodes stage_ptr[t] + c for t = s*..N-1 (each with one
+// child) and its leaf stage_ptr[N] + c.
+template <int NRHS, int CH>
+__global__ void __launch_bounds__(kWave *kWavesPerBlock)
+bwd_chain_kernel(SweepArgs a)
+{
+    if (a.done && *a.done) return;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int c = blockIdx.x * kWavesPerBlock + wave;
+    if (c >= a.nchains) return;
+    const WaveLds L = wave_lds(a, NRHS, wave);
+    for (int t = a.N - 1; t >= a.sstar; --t) {
+        const int i = a.stage_ptr[t] + c;
+        bwd_node<NRHS, CH>(a, i, L, t != a.N - 1, t == a.sstar && t > 0, lane);
+    }
+}
+
+template <int NRHS, int CH>
+__global__ void __launch_bounds__(kWave *kWavesPerBlock)
+fwd_chain_kernel(SweepArgs a)
+{
+    if (a.done && *a.done) return;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int c = blockIdx.x * kWavesPerBlock + wave;
+    if (c >= a.nchains) return;
+    const WaveLds L = wave_lds(a, NRHS, wave);
+    load_x<NRHS>(a, a.stage_ptr[a.sstar] + c, L, lane);
+    for (int t = a.sstar; t < a.N; ++t) {
+        const int i = a.stage_ptr[t] + c;
+        fwd_node<NRHS, CH>(a, i, L, t + 1 < a.N, lane);
+    }
+}
+
+}  // namespace
+
+SweepArgs sweep_args(const tree_factors *f, int affine)
+{
+    SweepArgs a{};
+    a.nx = f->nx; a.nu = f->nu; a.N = f->N; a.V = f->V; a.Vnl = f->Vnl;
+    a.sstar = f->sstar; a.nchains = f->nchains;
+    a.ldM = f->ldM; a.ldx = f->ldx; a.ldu = f->ldu;
+    a.stage_ptr = f->d_stage_ptr; a.child_ptr = f->d_child_ptr;
+    a.Mb = f->Mb; a.Mf = f->Mf; a.Kb = f->Kb; a.Kf = f->Kf; a.Rn = f->Rn;
+    a.chat = f->chat; a.sig = f->sig; a.cvec = f->cvec; a.sc = f->precondition ? f->sc : nullptr;
+    a.qhat = f->qhat; a.kbuf = f->kbuf;
+    a.qhat_rs = (long long)f->V * f->nx;
+    a.kbuf_rs = (long long)f->Vnl * f->nu;
+    a.affine = affine;
+    return a;
+}
+
+int ensure_sweep_ws(tree_factors *f, int nrhs)
+{
+    if (f->ws_nrhs >= nrhs) return STOTREE_OK;
+    if (f->qhat) { (void)hipFree(f->qhat); f->bytes -= (size_t)f->ws_nrhs * f->V * f->nx * 8; }
+    if (f->kbuf) { (void)hipFree(f->kbuf); f->bytes -= (size_t)f->ws_nrhs * f->Vnl * f->nu * 8; }
+    f->qhat = f->kbuf = nullptr;
+    f->ws_nrhs = 0;
+    STOTREE_HIP(hipMalloc(&f->qhat, sizeof(double) * (size_t)nrhs * f->V * f->nx));
+    STOTREE_HIP(hipMalloc(&f->kbuf, sizeof(double) * (size_t)nrhs * f->Vnl * f->nu));
+    f->ws_nrhs = nrhs;
+    f->bytes += (size_t)nrhs * ((size_t)f->V * f->nx + (size_t)f->Vnl * f->nu) * 8;
+    return STOTREE_OK;
+}
+
+// ---- optional phase timing (HIP events around each phase) ----
+namespace {
+struct TimingState {
+    bool on = false;
+    struct Rec { int phase; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+};
+TimingState g_timing;
+
+struct PhaseTimer {
+    int phase;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    PhaseTimer(int ph, hipStream_t s) : phase(ph), st(s)
+    {
+        if (!g_timing.on) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        (void)hipEventRecord(a, st);
+    }
+    ~PhaseTimer()
+    {
+        if (!a) return;
+        (void)hipEventRecord(b, st);
+        g_timing.recs.push_back({phase, a, b});
+    }
+};
+}  // namespace
+
+int timing_enable(int on)
+{
+    g_timing.on = on != 0;
+    return STOTREE_OK;
+}
+
+int timing_read(double *ms, long long *count)
+{
+    for (int p = 0; p < 4; ++p) { ms[p] = 0.0; count[p] = 0; }
+    int rc = STOTREE_OK;
+    for (auto &r : g_timing.recs) {
+        float t = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+            rc = STOTREE_ERR_DEVICE;
+        ms[r.phase] += t;
+        count[r.phase] += 1;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_timing.recs.clear();
+    if (rc) set_error("stotree_timing_read: event query failed");
+    return rc;
+}
+
+template <int NRHS, int CH>
+static hipError_t sweep_impl(const SweepArgs &a, const int *host_stage_ptr, hipStream_t st)
+{
+    const dim3 blk(kWave * kWavesPerBlock);
+    const size_t lds = sizeof(double) * kWavesPerBlock * NRHS * (2 * a.ldM + a.ldu);
+    auto blocks = [](int n) { return dim3((n + kWavesPerBlock - 1) / kWavesPerBlock); };
+    if (a.sstar < a.N) {
+        PhaseTimer tm(0, st);
+        hipLaunchKernelGGL((bwd_chain_kernel<NRHS, CH>), blocks(a.nchains), blk, lds, st, a);
+    }
+    if (a.sstar > 0) {
+        PhaseTimer tm(1, st);
+        for (int t = a.sstar - 1; t >= 0; --t) {
+            const int n = host_stage_ptr[t + 1] - host_stage_ptr[t];
+            hipLaunchKernelGGL((bwd_stage_kernel<NRHS, CH>), blocks(n), blk, lds, st, a, t);
+        }
+    }
+    if (a.sstar > 0) {
+        PhaseTimer tm(2, st);
+        for (int t = 0; t < a.sstar; ++t) {
+            const int n = host_stage_ptr[t + 1] - host_stage_ptr[t];
+            hipLaunchKernelGGL((fwd_stage_kernel<NRHS, CH>), blocks(n), blk, lds, st, a, t);
+        }
+    }
+    if (a.sstar < a.N) {
+        PhaseTimer tm(3, st);
+        hipLaunchKernelGGL((fwd_chain_kernel<NRHS, CH>), blocks(a.nchains), blk, lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_tree(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st)
+{
+    const bool wide = (a.nx + a.nu) > 128;
+    const int *sp = f->stage_ptr.data();
+    if (nrhs == 1) return wide ? sweep_impl<1, 2>(a, sp, st) : sweep_impl<1, 1>(a, sp, st);
+    if (nrhs == 2) return wide ? sweep_impl<2, 2>(a, sp, st) : sweep_impl<2, 1>(a, sp, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace stotree

@@ -1,0 +1,219 @@
+"""Thin Python binding of libstotree.so (argument marshalling only).
+
+Every function has the name of the C entry point it calls (include/stotree.h).
+Device buffers are torch tensors on a ROCm device; the library receives their
+raw pointers and the current HIP stream.  There is no fallback: if the
+compiled library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstotree.so")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+OK, NOT_CONVERGED = 0, 1
+ERRORS = {-1: "ERR_ARG", -2: "ERR_TREE", -3: "ERR_NOT_PD", -4: "ERR_BOX", -5: "ERR_NUMERIC",
+          -6: "ERR_DIVERGED", -7: "ERR_DEVICE", -8: "ERR_OOM"}
+
+
+class StotreeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class TreeDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nu", C.c_int32), ("N", C.c_int32), ("num_nodes", C.c_int32),
+                ("stage_ptr", _ip), ("ancestor", _ip), ("child_ptr", _ip), ("prob", _dp)]
+
+
+class ProblemData(C.Structure):
+    _fields_ = [(n, _dp) for n in ("A", "B", "c", "Q", "R", "S", "q", "r", "P", "p",
+                                   "xmin", "xmax", "umin", "umax")]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("lam", C.c_double), ("eps", C.c_double), ("eps_curv", C.c_double),
+                ("mem", C.c_int32), ("nu_max", C.c_int32), ("max_iter", C.c_int32),
+                ("check_every", C.c_int32)]
+
+
+class SolverInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("sweeps_affine", C.c_int32), ("sweeps_hom", C.c_int32),
+                ("ls_trials", C.c_int32), ("lbfgs_push", C.c_int32), ("lbfgs_skip", C.c_int32),
+                ("status", C.c_int32), ("res_scaled_inf", C.c_double),
+                ("res_unscaled_inf", C.c_double), ("lam", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+EXPORTS = ("tree_factor", "tree_factors_free", "tree_dims", "dual_grad", "dual_lipschitz",
+           "minfbe_solve", "nama_solve", "stotree_timing", "stotree_timing_read",
+           "stotree_last_error")
+PHASES = ("bwd_chain", "bwd_stages", "fwd_stages", "fwd_chain")
+
+_lib = None
+
+
+def lib():
+    """Load the compiled library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2107_01745_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.tree_factor.argtypes = [C.POINTER(TreeDesc), C.POINTER(ProblemData), C.c_int, vp,
+                                  C.POINTER(vp)]
+        L.tree_factor.restype = C.c_int
+        L.tree_factors_free.argtypes = [vp]
+        L.tree_factors_free.restype = None
+        L.tree_dims.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.tree_dims.restype = C.c_int
+        L.dual_grad.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp, vp, vp]
+        L.dual_grad.restype = C.c_int
+        L.dual_lipschitz.argtypes = [vp, C.c_int, _dp, vp]
+        L.dual_lipschitz.restype = C.c_int
+        for fn in (L.minfbe_solve, L.nama_solve):
+            fn.argtypes = [vp, vp, C.POINTER(SolverOpts), vp, vp, vp, C.POINTER(SolverInfo), vp]
+            fn.restype = C.c_int
+        L.stotree_timing.argtypes = [C.c_int]
+        L.stotree_timing.restype = C.c_int
+        L.stotree_timing_read.argtypes = [_dp, C.POINTER(C.c_int64)]
+        L.stotree_timing_read.restype = C.c_int
+        L.stotree_last_error.argtypes = []
+        L.stotree_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def stotree_last_error() -> str:
+    return lib().stotree_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise StotreeError(rc, stotree_last_error())
+    return rc
+
+
+def _stream(stream):
+    """The given HIP stream, else torch's current stream, else the NULL stream."""
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    if not torch.cuda.is_available():
+        return C.c_void_p(None)
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    """Raw device pointer of a contiguous float64 torch tensor (or None)."""
+    if t is None:
+        return None
+    import torch
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), (t.device, t.dtype)
+    return C.c_void_p(t.data_ptr())
+
+
+class TreeFactors:
+    """Owns the handle returned by tree_factor."""
+
+    def __init__(self, handle, dims):
+        self.handle = handle
+        (self.nx, self.nu, self.N, self.V, self.Vnl, self.m, self.n, self.sstar,
+         self.precondition, self.device_bytes) = [int(v) for v in dims]
+
+    def free(self):
+        if self.handle:
+            lib().tree_factors_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def tree_factor(prob, precondition: bool = True, stream=None) -> TreeFactors:
+    """Factor step on a treegen.Problem (host arrays)."""
+    t = prob.tree
+    keep = []
+
+    def d(a, dtype=np.float64):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dtype)
+        keep.append(a)
+        return a.ctypes.data_as(_ip if dtype == np.int32 else _dp)
+
+    td = TreeDesc(nx=prob.nx, nu=prob.nu, N=t.N, num_nodes=t.V,
+                  stage_ptr=d(t.stage_ptr, np.int32), ancestor=d(t.anc, np.int32),
+                  child_ptr=d(t.child_ptr, np.int32), prob=d(t.prob))
+    pd = ProblemData(**{n: d(getattr(prob, n)) for n, _ in ProblemData._fields_})
+    h = C.c_void_p()
+    _check(lib().tree_factor(C.byref(td), C.byref(pd), int(bool(precondition)), _stream(stream),
+                             C.byref(h)))
+    return TreeFactors(h, tree_dims(h))
+
+
+def tree_dims(handle) -> list:
+    out = (C.c_int64 * 10)()
+    _check(lib().tree_dims(handle.handle if isinstance(handle, TreeFactors) else handle, out))
+    return list(out)
+
+
+def dual_grad(tf: TreeFactors, x0, y, homogeneous: bool, x, u, nrhs: int = 1, stream=None) -> None:
+    """x(y) (Algorithm 3) or x-hat(y) (Algorithm 4) into the device tensors x, u."""
+    _check(lib().dual_grad(tf.handle, _ptr(x0), _ptr(y), int(bool(homogeneous)), int(nrhs),
+                           _ptr(x), _ptr(u), _stream(stream)))
+
+
+def dual_lipschitz(tf: TreeFactors, iters: int = 100, stream=None) -> float:
+    L = C.c_double()
+    _check(lib().dual_lipschitz(tf.handle, int(iters), C.byref(L), _stream(stream)))
+    return L.value
+
+
+def make_opts(lam=0.0, eps=1e-6, eps_curv=1e-12, mem=5, nu_max=10, max_iter=1000, check_every=1):
+    return SolverOpts(lam=lam, eps=eps, eps_curv=eps_curv, mem=mem, nu_max=nu_max,
+                      max_iter=max_iter, check_every=check_every)
+
+
+def _solve(fn, tf, x0, y, x, u, opts, stream):
+    info = SolverInfo()
+    rc = fn(tf.handle, _ptr(x0), C.byref(opts), _ptr(y), _ptr(x), _ptr(u), C.byref(info),
+            _stream(stream))
+    _check(rc)
+    return rc, info.as_dict()
+
+
+def minfbe_solve(tf, x0, y, x, u, opts=None, stream=None):
+    """Algorithm 1; y holds the initial dual and receives the last iterate."""
+    return _solve(lib().minfbe_solve, tf, x0, y, x, u, opts or make_opts(), stream)
+
+
+def nama_solve(tf, x0, y, x, u, opts=None, stream=None):
+    """Algorithm 2 (two-right-hand-side homogeneous sweep per iteration)."""
+    return _solve(lib().nama_solve, tf, x0, y, x, u, opts or make_opts(), stream)
+
+
+def stotree_timing(enable: bool) -> None:
+    _check(lib().stotree_timing(int(bool(enable))))
+
+
+def stotree_timing_read() -> dict:
+    """{phase: (total_ms, launches)} accumulated since the last read."""
+    ms = (C.c_double * 4)()
+    cnt = (C.c_int64 * 4)()
+    _check(lib().stotree_timing_read(ms, cnt))
+    return {PHASES[p]: (ms[p], int(cnt[p])) for p in range(4)}

@@ -1,0 +1,122 @@
+"""Shared cases and helpers for the GPU parity tests.
+
+Problem instances come from ``treegen`` (seeded); expected values come from the
+CPU oracle or from the problem statement itself (dynamics and stationarity of
+the inner problem), never from the HIP path.
+"""
+from __future__ import annotations
+
+import dataclasses
+import zlib
+
+import numpy as np
+
+import treegen
+
+# Tolerances.  FP64 dual gradient: 1e-9 relative; solver end point: 1e-6 on
+# the residual recomputed by the oracle and on the primal.
+TOL_GRAD = 1e-9
+TOL_RES = 1e-6
+TOL_PRIMAL = 1e-6
+
+
+def row_scale(prob, precondition=True):
+    """sqrt(pi) of the owning node for each dual row (layout of Sec. II-C)."""
+    t = prob.tree
+    if not precondition:
+        return np.ones(prob.m)
+    w = np.where(np.arange(t.V) < t.Vnl, prob.nx + prob.nu, prob.nx)
+    return np.repeat(np.sqrt(t.prob), w)
+
+
+def case(name):
+    """Named test instances of different shapes."""
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    if name == "tiny":            # config-0 shape
+        return treegen.draw_problem(treegen.uniform_tree([2, 2, 2, 1, 1]), 4, 2, rng)
+    if name == "odd_ragged":      # odd nx, nu; uneven branching; S, q, r, p present
+        counts, n = [], 1
+        for _ in range(5):
+            ct = rng.integers(1, 4, size=n)
+            counts.append(ct.tolist())
+            n = int(ct.sum())
+        return treegen.draw_problem(treegen.tree_from_counts(counts), 5, 3, rng, cross_terms=True)
+    if name == "cfg1_shape":      # config-1 blocks (nx=50, nu=30) on a small tree
+        return treegen.draw_problem(treegen.uniform_tree([4, 4, 1, 1, 1]), 50, 30, rng,
+                                    qdiag=(0.5, 2.0), rdiag=(0.05, 0.5))
+    if name == "wide":            # nx + nu > 128: two 128-column chunks per lane
+        return treegen.draw_problem(treegen.uniform_tree([3, 1, 1]), 97, 45, rng)
+    if name == "single_path":     # the whole tree is one chain (s* = 0)
+        return treegen.draw_problem(treegen.uniform_tree([1] * 12), 7, 3, rng)
+    if name == "no_chain":        # branching at every stage (s* = N)
+        return treegen.draw_problem(treegen.uniform_tree([2, 3, 2]), 6, 4, rng)
+    if name == "capped":          # config-2 style uneven fan-out
+        return treegen.draw_problem(treegen.capped_tree(9, 23, 3), 9, 4, rng)
+    if name == "cfg3_shape":
+        return treegen.draw_problem(treegen.uniform_tree([3, 3, 1, 1, 1, 1]), 20, 10, rng,
+                                    x0_range=3.0)
+    raise KeyError(name)
+
+
+SWEEP_CASES = ["tiny", "odd_ragged", "cfg1_shape", "wide", "single_path", "no_chain", "capped",
+               "cfg3_shape"]
+
+
+def with_tight_boxes(prob, xbox, ubox):
+    xmin = np.full_like(prob.xmin, -xbox)
+    xmax = np.full_like(prob.xmax, xbox)
+    xmin[0], xmax[0] = -np.inf, np.inf
+    return dataclasses.replace(prob, xmin=xmin, xmax=xmax,
+                               umin=np.full_like(prob.umin, -ubox), umax=np.full_like(prob.umax, ubox))
+
+
+def inner_kkt_residual(prob, y, x, u, x0, homogeneous=False):
+    """Residuals of the optimality conditions of the inner problem of
+    Sec. III-D (the problem x(y) minimises), written from the problem
+    statement: the dynamics, x_0, and stationarity in u with costates
+    nu_j = d(cost-to-go)/dx_j accumulated leaves-first.  y is unscaled.
+    Returns (dynamics, stationarity) residuals relative to the size of the
+    terms.  Linear in x, u, y: holds at any size."""
+    t = prob.tree
+    nx, nu, V, Vnl = prob.nx, prob.nu, t.V, t.Vnl
+    aff = 0.0 if homogeneous else 1.0
+    off = np.where(np.arange(V) < Vnl, np.arange(V) * (nx + nu), Vnl * nu + np.arange(V) * nx)
+    yx = y[off[:, None] + np.arange(nx)[None, :]]
+    yu = y[off[:Vnl, None] + nx + np.arange(nu)[None, :]]
+    anc = t.anc[1:].astype(np.int64)
+    pred = (np.einsum("jab,jb->ja", prob.A[1:], x[anc]) + np.einsum("jab,jb->ja", prob.B[1:], u[anc])
+            + aff * prob.c[1:])
+    dyn = np.abs(x[1:] - pred).max() / max(1.0, np.abs(pred).max())
+    root = np.abs(x[0] - aff * x0).max()
+    pi = t.prob
+    cost_nu = np.zeros((V, nx))
+    P = prob.P
+    cost_nu[Vnl:] = 2 * pi[Vnl:, None] * np.einsum("jab,jb->ja", P, x[Vnl:]) + yx[Vnl:]
+    if prob.p is not None:
+        cost_nu[Vnl:] += aff * pi[Vnl:, None] * prob.p
+    S = prob.S
+    gx = 2 * pi[:Vnl, None] * np.einsum("iab,ib->ia", prob.Q, x[:Vnl]) + yx[:Vnl]
+    gu = 2 * pi[:Vnl, None] * np.einsum("iab,ib->ia", prob.R, u) + yu
+    if S is not None:
+        gx += 2 * pi[:Vnl, None] * np.einsum("iba,ib->ia", S, u)
+        gu += 2 * pi[:Vnl, None] * np.einsum("iab,ib->ia", S, x[:Vnl])
+    if prob.q is not None:
+        gx += aff * pi[:Vnl, None] * prob.q
+    if prob.r is not None:
+        gu += aff * pi[:Vnl, None] * prob.r
+    sp = t.stage_ptr
+    su = gu.copy()
+    scale = max(np.abs(gu).max(), 1e-300)
+    for s in range(t.N - 1, -1, -1):
+        kids = np.arange(sp[s + 1], sp[s + 2])
+        par = t.anc[kids].astype(np.int64)
+        At_nu = np.einsum("jba,jb->ja", prob.A[kids], cost_nu[kids])
+        Bt_nu = np.einsum("jba,jb->ja", prob.B[kids], cost_nu[kids])
+        scale = max(scale, np.abs(Bt_nu).max())
+        np.add.at(su, par, Bt_nu)
+        nodes = np.arange(sp[s], sp[s + 1])
+        acc = gx[nodes].copy()
+        np.add.at(acc, par - sp[s], At_nu)
+        cost_nu[nodes] = acc
+    stat = np.abs(su).max() / scale
+    return max(dyn, root), stat

@@ -1,0 +1,129 @@
+"""GPU parity of the device-resident MINFBE / NAMA solvers and the power
+iteration, through the C ABI, against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+from gpu_cases import TOL_PRIMAL, TOL_RES, case, with_tight_boxes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def st():
+    import torch
+    from paper_2107_01745_amd import stotree
+    assert torch.cuda.is_available()
+    stotree.lib()
+    return stotree
+
+
+def _t(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def solver_cases():
+    return {
+        "tight_tiny": pins.tight_tiny,
+        "ragged_cross": pins.ragged_cross,
+        "cfg3_tight": lambda: with_tight_boxes(case("cfg3_shape"), 3.0, 0.4),
+    }
+
+
+def _gpu_solve(st, tf, prob, method, lam, y0=None, **kw):
+    import torch
+    y = _t(np.zeros(tf.m) if y0 is None else y0)
+    x = torch.zeros(tf.V, tf.nx, dtype=torch.float64, device="cuda:0")
+    u = torch.zeros(tf.Vnl, tf.nu, dtype=torch.float64, device="cuda:0")
+    fn = st.minfbe_solve if method == "minfbe" else st.nama_solve
+    rc, info = fn(tf, _t(prob.x0), y, x, u, st.make_opts(lam=lam, **kw))
+    torch.cuda.synchronize()
+    return rc, info, y.cpu().numpy(), x.cpu().numpy(), u.cpu().numpy()
+
+
+@pytest.mark.parametrize("method", ["minfbe", "nama"])
+@pytest.mark.parametrize("name", ["tight_tiny", "ragged_cross", "cfg3_tight"])
+def test_solution_matches_oracle(st, method, name):
+    prob = solver_cases()[name]()
+    print(f"{method} {name}", flush=True)
+    pb, fac = oracle.factor(prob)
+    L = oracle.power_iteration(pb, fac, True, 500)
+    lam = 1.0 / (1.1 * L)
+    ref = oracle.solve(pb, fac, method, lam, eps=1e-10, max_iter=5000)
+    assert ref["status"] == 0
+    tf = st.tree_factor(prob, precondition=True)
+    rc, info, y, x, u = _gpu_solve(st, tf, prob, method, lam, eps=1e-8, max_iter=5000)
+    print(info, flush=True)
+    assert rc == 0 and info["status"] == 0
+    assert info["res_scaled_inf"] <= 1e-8
+    # the oracle recomputes the residual at the GPU's dual
+    ev = oracle.evaluate(pb, fac, y, lam, True)
+    assert np.abs(ev["R"]).max() <= TOL_RES
+    scale = max(1.0, np.abs(ref["x"]).max(), np.abs(ref["u"]).max())
+    assert np.abs(x - ref["x"]).max() / scale < TOL_PRIMAL
+    assert np.abs(u - ref["u"]).max() / scale < TOL_PRIMAL
+    # x returned is x(y) at the returned y
+    assert np.abs(x - ev["x"]).max() / scale < 1e-9
+    tf.free()
+
+
+@pytest.mark.parametrize("method", ["minfbe", "nama"])
+def test_first_iterations_match_oracle(st, method):
+    """Same step decisions in the first iterations give the same iterates."""
+    prob = pins.tight_tiny()
+    pb, fac = oracle.factor(prob)
+    L = oracle.power_iteration(pb, fac, True, 500)
+    lam = 1.0 / (1.1 * L)
+    tf = st.tree_factor(prob, precondition=True)
+    for iters in (1, 2, 3):
+        ref = oracle.solve(pb, fac, method, lam, eps=1e-14, max_iter=iters)
+        rc, info, y, x, u = _gpu_solve(st, tf, prob, method, lam, eps=1e-14, max_iter=iters)
+        assert rc == 1 and info["iters"] == iters
+        assert info["ls_trials"] == ref["ls_trials"]
+        assert np.abs(y - ref["y"]).max() <= 1e-9 * max(1.0, np.abs(ref["y"]).max())
+    tf.free()
+
+
+def test_lipschitz_matches_oracle_power_iteration(st):
+    prob = case("odd_ragged")
+    pb, fac = oracle.factor(prob)
+    tf = st.tree_factor(prob, precondition=True)
+    Lg = st.dual_lipschitz(tf, 300)
+    Lo = oracle.power_iteration(pb, fac, True, 300, v0=np.ones(pb.m))
+    assert abs(Lg - Lo) <= 1e-9 * Lo
+    tf.free()
+
+
+def test_max_iter_reports_not_converged(st):
+    prob = pins.tight_tiny()
+    tf = st.tree_factor(prob, precondition=True)
+    rc, info, *_ = _gpu_solve(st, tf, prob, "nama", 0.0, eps=1e-15, max_iter=2)
+    assert rc == 1 and info["iters"] == 2 and info["status"] == 1
+    tf.free()
+
+
+def test_warm_start_at_solution_stops_immediately(st):
+    prob = pins.tight_tiny()
+    pb, fac = oracle.factor(prob)
+    L = oracle.power_iteration(pb, fac, True, 500)
+    lam = 1.0 / (1.1 * L)
+    ref = oracle.solve(pb, fac, "nama", lam, eps=1e-11)
+    tf = st.tree_factor(prob, precondition=True)
+    rc, info, y, x, u = _gpu_solve(st, tf, prob, "nama", lam, y0=ref["y"], eps=1e-8)
+    assert rc == 0 and info["iters"] == 0
+    tf.free()
+
+
+@pytest.mark.parametrize("method", ["minfbe", "nama"])
+def test_config0_as_specified(st, method):
+    import treegen
+    prob = treegen.make_config(0)
+    tf = st.tree_factor(prob, precondition=True)
+    rc, info, y, x, u = _gpu_solve(st, tf, prob, method, 0.0, eps=1e-6)
+    assert rc == 0 and info["res_scaled_inf"] <= 1e-6
+    pb, fac = oracle.factor(prob)
+    ev = oracle.evaluate(pb, fac, y, info["lam"], True)
+    assert np.abs(ev["R"]).max() <= TOL_RES
+    tf.free()
