@@ -174,6 +174,23 @@ def main():
     value = 1000.0 / ms
     log(f"x(y) sweep: {ms:.4f} ms/step ({value:.1f} evals/s), host wall {wall:.3f} s")
 
+    # achievable streaming bandwidth on this device: a plain 1 GiB device copy
+    n_copy = 1 << 27
+    src = torch.ones(n_copy, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 8 * n_copy / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
+    del src, dst
+    log(f"device copy (read+write) {copy_gbs:.0f} GB/s")
+
     # per-phase timing with HIP events on the sweep's stream
     stotree.stotree_timing(True)
     for _ in range(args.profile_steps):
@@ -195,6 +212,7 @@ def main():
                 "frac": phase_rep[dom]["GBs"] / HBM_PEAK_GBS, "traffic": None,
                 "kernel": f"{dom}_kernel", "bytes_per_launch": pbytes[dom],
                 "avg_launch_ms": phase_rep[dom]["avg_ms"],
+                "copy_GBs": copy_gbs, "frac_of_copy": phase_rep[dom]["GBs"] / copy_gbs,
                 "whole_sweep": {"bytes": sweep_bytes, "GBs": sweep_bytes / (ms * 1e-3) / 1e9,
                                 "frac": sweep_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                 "flops": sweep_flops(prob)}}

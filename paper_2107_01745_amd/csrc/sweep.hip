@@ -53,31 +53,98 @@ __device__ __forceinline__ double *x_ptr(const SweepArgs &a, int k, int i)
            (long long)k * a.xo_rs;
 }
 
-// acc[k][ch][e] += sum_r M[r][c] * v_k[r] for the lane's columns
+// acc[k][ch][e] += sum_{r0<=r<r1} M[r][c] * v_k[r] for the lane's columns
 // c = 2*lane + 128*ch + e < W, with M row-major of leading dimension ld and v_k
-// in LDS at v + k*ldv.
+// in LDS at v + k*ldv.  The loads carry no lane condition (lanes past W re-read
+// column 0 and their sums are never stored) and rows go in batches of
+// kRowBatch, double-buffered: the next batch is issued before the current one
+// is multiplied, so up to 2*kRowBatch row loads are in flight per wavefront.
+constexpr int kRowBatch = 8;
+
+template <int CH>
+__device__ __forceinline__ void load_rows(double2 (&m)[kRowBatch][CH], const double *__restrict__ M,
+                                          int ld, int r, const int (&col)[CH])
+{
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+            m[u][ch] = *reinterpret_cast<const double2 *>(M + (long long)(r + u) * ld + col[ch]);
+}
+
 template <int NRHS, int CH>
-__device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, int rows, int W,
+__device__ __forceinline__ void fma_rows(const double2 (&m)[kRowBatch][CH], const double *v, int ldv,
+                                         int r, double (&acc)[NRHS][CH][2])
+{
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            const double vk = v[k * ldv + r + u];
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch) {
+                acc[k][ch][0] = fma(m[u][ch].x, vk, acc[k][ch][0]);
+                acc[k][ch][1] = fma(m[u][ch].y, vk, acc[k][ch][1]);
+            }
+        }
+}
+
+template <int NRHS, int CH>
+__device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, int r0, int r1, int W,
                                           const double *v, int ldv, double (&acc)[NRHS][CH][2],
                                           int lane)
 {
-#pragma unroll 4
-    for (int r = 0; r < rows; ++r) {
-        const double *row = M + (long long)r * ld;
-        double vk[NRHS];
+    int col[CH];
 #pragma unroll
-        for (int k = 0; k < NRHS; ++k) vk[k] = v[k * ldv + r];
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = 2 * lane + 128 * ch;
+        col[ch] = c0 < W ? c0 : 0;
+    }
+    int r = r0;
+    int nb = (r1 - r0) / kRowBatch;
+    double2 m0[kRowBatch][CH], m1[kRowBatch][CH];
+    if (nb > 0) load_rows<CH>(m0, M, ld, r, col);
+    while (nb >= 2) {
+        load_rows<CH>(m1, M, ld, r + kRowBatch, col);
+        fma_rows<NRHS, CH>(m0, v, ldv, r, acc);
+        if (nb >= 3) load_rows<CH>(m0, M, ld, r + 2 * kRowBatch, col);
+        fma_rows<NRHS, CH>(m1, v, ldv, r + kRowBatch, acc);
+        r += 2 * kRowBatch;
+        nb -= 2;
+    }
+    if (nb == 1) {
+        fma_rows<NRHS, CH>(m0, v, ldv, r, acc);
+        r += kRowBatch;
+    }
+    for (; r < r1; ++r) {
+        double2 m[CH];
 #pragma unroll
-        for (int ch = 0; ch < CH; ++ch) {
-            const int c0 = 2 * lane + 128 * ch;
-            if (c0 < W) {
-                const double2 m2 = *reinterpret_cast<const double2 *>(row + c0);
+        for (int ch = 0; ch < CH; ++ch)
+            m[ch] = *reinterpret_cast<const double2 *>(M + (long long)r * ld + col[ch]);
 #pragma unroll
-                for (int k = 0; k < NRHS; ++k) {
-                    acc[k][ch][0] = fma(m2.x, vk[k], acc[k][ch][0]);
-                    acc[k][ch][1] = fma(m2.y, vk[k], acc[k][ch][1]);
-                }
+        for (int k = 0; k < NRHS; ++k) {
+            const double vk = v[k * ldv + r];
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch) {
+                acc[k][ch][0] = fma(m[ch].x, vk, acc[k][ch][0]);
+                acc[k][ch][1] = fma(m[ch].y, vk, acc[k][ch][1]);
             }
+        }
+    }
+}
+
+// dst[k*ld + off + c] = acc[k][.][.] for the lane's columns c < dim.
+template <int NRHS, int CH>
+__device__ __forceinline__ void store_acc(double *dst, int ld, int off, int dim,
+                                          const double (&acc)[NRHS][CH][2], int lane)
+{
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = 2 * lane + 128 * ch;
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            if (c0 < dim) dst[k * ld + off + c0] = acc[k][ch][0];
+            if (c0 + 1 < dim) dst[k * ld + off + c0 + 1] = acc[k][ch][1];
         }
     }
 }
@@ -139,7 +206,7 @@ __device__ void bwd_node(const SweepArgs &a, int i, const WaveLds &L, bool child
             }
             wave_sync();
         }
-        gemv_rows<NRHS, CH>(a.Mb + (long long)j * nx * a.ldM, a.ldM, nx, W, L.qx, L.ldq, acc, lane);
+        gemv_rows<NRHS, CH>(a.Mb + (long long)j * nx * a.ldM, a.ldM, 0, nx, W, L.qx, L.ldq, acc, lane);
         wave_sync();
     }
     // scatter [sum A'q ; sum B'q] to LDS
@@ -166,8 +233,8 @@ __device__ void bwd_node(const SweepArgs &a, int i, const WaveLds &L, bool child
     double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
     zero(kacc);
     zero(qacc);
-    gemv_rows<NRHS, CH>(a.Rn + (long long)i * nu * a.ldu, a.ldu, nu, nu, L.gs, a.ldu, kacc, lane);
-    gemv_rows<NRHS, CH>(a.Kb + (long long)i * nu * a.ldx, a.ldx, nu, nx, L.gs, a.ldu, qacc, lane);
+    gemv_rows<NRHS, CH>(a.Rn + (long long)i * nu * a.ldu, a.ldu, 0, nu, nu, L.gs, a.ldu, kacc, lane);
+    gemv_rows<NRHS, CH>(a.Kb + (long long)i * nu * a.ldx, a.ldx, 0, nu, nx, L.gs, a.ldu, qacc, lane);
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
         const int c0 = 2 * lane + 128 * ch;
@@ -224,7 +291,7 @@ __device__ void fwd_node(const SweepArgs &a, int i, const WaveLds &L, bool keep_
     const int nx = a.nx, nu = a.nu;
     double uacc[NRHS][CH][2];
     zero(uacc);
-    gemv_rows<NRHS, CH>(a.Kf + (long long)i * nx * a.ldu, a.ldu, nx, nu, L.qx, L.ldq, uacc, lane);
+    gemv_rows<NRHS, CH>(a.Kf + (long long)i * nx * a.ldu, a.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
         const int c0 = 2 * lane + 128 * ch;
@@ -247,7 +314,7 @@ __device__ void fwd_node(const SweepArgs &a, int i, const WaveLds &L, bool keep_
     for (int j = j0; j < j1; ++j) {
         double xacc[NRHS][CH][2];
         zero(xacc);
-        gemv_rows<NRHS, CH>(a.Mf + (long long)j * (nx + nu) * a.ldx, a.ldx, nx + nu, nx, L.qx,
+        gemv_rows<NRHS, CH>(a.Mf + (long long)j * (nx + nu) * a.ldx, a.ldx, 0, nx + nu, nx, L.qx,
                             L.ldq, xacc, lane);
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch) {
@@ -303,29 +370,190 @@ __device__ void load_x(const SweepArgs &a, int i, const WaveLds &L, int lane)
     wave_sync();
 }
 
-template <int NRHS, int CH>
-__global__ void __launch_bounds__(kWave *kWavesPerBlock)
-bwd_stage_kernel(SweepArgs a, int t)
+// ---- stages above s*: one workgroup of NW wavefronts per node ----
+//
+// Backward: the rows of all children's [A_j B_j] are split into NW contiguous
+// ranges, one per wavefront; the partial sums meet in LDS in a fixed order
+// (deterministic), then the node's -R~^{-1} and K_i rows are split the same
+// way.  Forward: the rows of K_i' are split for u_i; the children are dealt
+// round-robin to the wavefronts, or, with fewer children than wavefronts,
+// each child's rows are split into NW/b blocks reduced through LDS.
+__host__ __device__ inline int child_batch(int nrhs, int ldx)
 {
-    if (a.done && *a.done) return;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int i = a.stage_ptr[t] + blockIdx.x * kWavesPerBlock + wave;
-    if (i >= a.stage_ptr[t + 1]) return;
-    const WaveLds L = wave_lds(a, NRHS, wave);
-    bwd_node<NRHS, CH>(a, i, L, false, true, lane);
+    const int cb = 2048 / (nrhs * ldx);
+    return cb < 1 ? 1 : (cb > 8 ? 8 : cb);
 }
 
-template <int NRHS, int CH>
-__global__ void __launch_bounds__(kWave *kWavesPerBlock)
-fwd_stage_kernel(SweepArgs a, int t)
+template <int NRHS, int CH, int NW>
+__global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a, int t)
 {
     if (a.done && *a.done) return;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int i = a.stage_ptr[t] + blockIdx.x * kWavesPerBlock + wave;
-    if (i >= a.stage_ptr[t + 1]) return;
-    const WaveLds L = wave_lds(a, NRHS, wave);
-    load_x<NRHS>(a, i, L, lane);
-    fwd_node<NRHS, CH>(a, i, L, false, lane);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int i = a.stage_ptr[t] + blockIdx.x;
+    const int nx = a.nx, nu = a.nu, W = nx + nu, ldq = a.ldx, ldM = a.ldM;
+    const int CB = child_batch(NRHS, ldq);
+    extern __shared__ double lds[];
+    double *qs = lds;                          // [CB][NRHS][ldq]
+    double *red = qs + CB * NRHS * ldq;        // [NW][NRHS][ldM]
+    double *as = red + NW * NRHS * ldM;        // [NRHS][ldM]
+    double *gs = as + NRHS * ldM;              // [NRHS][ldu]
+    const int j0 = a.child_ptr[i], nch = a.child_ptr[i + 1] - j0;
+    double acc[NRHS][CH][2];
+    zero(acc);
+    for (int cb = 0; cb < nch; cb += CB) {
+        const int nb = nch - cb < CB ? nch - cb : CB;
+        for (int e = threadIdx.x; e < nb * nx; e += blockDim.x) {
+            const int c = e / nx, r = e - c * nx, j = j0 + cb + c;
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) {
+                double q;
+                if (j >= a.Vnl) {
+                    const double sj = a.sc ? a.sc[j] : 1.0;
+                    q = sj * a.y[k * a.y_rs + off_l(a, j) + r] + (a.affine ? a.chat[(long long)j * nx + r] : 0.0);
+                } else {
+                    q = a.qhat[k * a.qhat_rs + (long long)j * nx + r];
+                }
+                qs[(c * NRHS + k) * ldq + r] = q;
+            }
+        }
+        __syncthreads();
+        const int R = nb * nx;
+        const int r0 = (int)((long long)R * w / NW), r1 = (int)((long long)R * (w + 1) / NW);
+        for (int c = r0 / nx; c < nb && c * nx < r1; ++c) {
+            const int lo = (r0 > c * nx ? r0 : c * nx) - c * nx;
+            const int hi = (r1 < (c + 1) * nx ? r1 : (c + 1) * nx) - c * nx;
+            if (lo < hi)
+                gemv_rows<NRHS, CH>(a.Mb + (long long)(j0 + cb + c) * nx * ldM, ldM, lo, hi, W,
+                                    qs + c * NRHS * ldq, ldq, acc, lane);
+        }
+        __syncthreads();
+    }
+    store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, W, acc, lane);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NRHS * W; e += blockDim.x) {
+        const int k = e / W, c = e - k * W;
+        double s = 0.0;
+        for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + c];
+        as[k * ldM + c] = s;
+    }
+    __syncthreads();
+    const double si = a.sc ? a.sc[i] : 1.0;
+    for (int e = threadIdx.x; e < NRHS * nu; e += blockDim.x) {
+        const int k = e / nu, c = e - k * nu;
+        gs[k * a.ldu + c] = as[k * ldM + nx + c] + si * a.y[k * a.y_rs + off_nl(a, i) + nx + c] +
+                            (a.affine ? a.sig[(long long)i * nu + c] : 0.0);
+    }
+    __syncthreads();
+    double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
+    zero(kacc);
+    zero(qacc);
+    {
+        const int R = 2 * nu;
+        const int r0 = R * w / NW, r1 = R * (w + 1) / NW;
+        if (r0 < nu)
+            gemv_rows<NRHS, CH>(a.Rn + (long long)i * nu * a.ldu, a.ldu, r0, r1 < nu ? r1 : nu, nu, gs,
+                                a.ldu, kacc, lane);
+        if (r1 > nu)
+            gemv_rows<NRHS, CH>(a.Kb + (long long)i * nu * a.ldx, a.ldx, (r0 > nu ? r0 : nu) - nu, r1 - nu, nx,
+                                gs, a.ldu, qacc, lane);
+    }
+    store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nu, kacc, lane);
+    store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, nu, nx, qacc, lane);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NRHS * W; e += blockDim.x) {
+        const int k = e / W, c = e - k * W;
+        double s = 0.0;
+        for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + c];
+        if (c < nu) {
+            a.kbuf[k * a.kbuf_rs + (long long)i * nu + c] = s;
+        } else {
+            const int cx = c - nu;
+            a.qhat[k * a.qhat_rs + (long long)i * nx + cx] =
+                as[k * ldM + cx] + si * a.y[k * a.y_rs + off_nl(a, i) + cx] +
+                (a.affine ? a.chat[(long long)i * nx + cx] : 0.0) + s;
+        }
+    }
+}
+
+template <int NRHS, int CH, int NW>
+__global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a, int t)
+{
+    if (a.done && *a.done) return;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int i = a.stage_ptr[t] + blockIdx.x;
+    const int nx = a.nx, nu = a.nu, W = nx + nu, ldM = a.ldM;
+    extern __shared__ double lds[];
+    double *xs = lds;                 // [NRHS][ldM]: x_i then u_i
+    double *red = xs + NRHS * ldM;    // [NW][NRHS][ldM]
+    for (int e = threadIdx.x; e < NRHS * nx; e += blockDim.x) {
+        const int k = e / nx, c = e - k * nx;
+        double v;
+        if (i == 0) {
+            v = a.affine ? a.x0[k * a.x0_rs + c] : 0.0;
+            x_ptr(a, k, 0)[c] = v;
+        } else {
+            v = x_ptr(a, k, i)[c];
+        }
+        xs[k * ldM + c] = v;
+    }
+    __syncthreads();
+    double uacc[NRHS][CH][2];
+    zero(uacc);
+    {
+        const int r0 = nx * w / NW, r1 = nx * (w + 1) / NW;
+        if (r0 < r1)
+            gemv_rows<NRHS, CH>(a.Kf + (long long)i * nx * a.ldu, a.ldu, r0, r1, nu, xs, ldM, uacc, lane);
+    }
+    store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nu, uacc, lane);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NRHS * nu; e += blockDim.x) {
+        const int k = e / nu, c = e - k * nu;
+        double s = a.kbuf[k * a.kbuf_rs + (long long)i * nu + c];
+        for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + c];
+        a.uo[k * a.uo_rs + (long long)i * a.uo_s + c] = s;
+        xs[k * ldM + nx + c] = s;
+    }
+    __syncthreads();
+    const int j0 = a.child_ptr[i], nch = a.child_ptr[i + 1] - j0;
+    const int RB = nch >= NW ? 1 : NW / nch;
+    if (RB == 1) {
+        for (int c = w; c < nch; c += NW) {
+            const int j = j0 + c;
+            double xacc[NRHS][CH][2];
+            zero(xacc);
+            gemv_rows<NRHS, CH>(a.Mf + (long long)j * W * a.ldx, a.ldx, 0, W, nx, xs, ldM, xacc, lane);
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch) {
+                const int c0 = 2 * lane + 128 * ch;
+#pragma unroll
+                for (int e2 = 0; e2 < 2; ++e2) {
+                    const int col = c0 + e2;
+                    if (col < nx)
+#pragma unroll
+                        for (int k = 0; k < NRHS; ++k)
+                            x_ptr(a, k, j)[col] = xacc[k][ch][e2] + (a.affine ? a.cvec[(long long)j * nx + col] : 0.0);
+                }
+            }
+        }
+    } else {
+        double xacc[NRHS][CH][2];
+        zero(xacc);
+        if (w < nch * RB) {
+            const int c = w / RB, blk = w - c * RB;
+            const int rr0 = W * blk / RB, rr1 = W * (blk + 1) / RB;
+            gemv_rows<NRHS, CH>(a.Mf + (long long)(j0 + c) * W * a.ldx, a.ldx, rr0, rr1, nx, xs, ldM, xacc,
+                                lane);
+        }
+        store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nx, xacc, lane);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nch * NRHS * nx; e += blockDim.x) {
+            const int c = e / (NRHS * nx), rem = e - c * NRHS * nx, k = rem / nx, col = rem - k * nx;
+            const int j = j0 + c;
+            double s = a.affine ? a.cvec[(long long)j * nx + col] : 0.0;
+            for (int blk = 0; blk < RB; ++blk) s += red[((c * RB + blk) * NRHS + k) * ldM + col];
+            x_ptr(a, k, j)[col] = s;
+        }
+    }
 }
 
 // Chain c covers the nodes stage_ptr[t] + c for t = s*..N-1 (each with one
@@ -445,6 +673,41 @@ int timing_read(double *ms, long long *count)
     return rc;
 }
 
+// Wavefronts per node for a stage of n nodes: enough to keep about 4096
+// wavefronts busy, within the LDS budget of the reduction buffers.
+static int trunk_waves(int n, int nrhs, int ldM)
+{
+    int nw = 16;
+    while (nw > 1 && (long long)n * nw > 4096) nw /= 2;
+    while (nw > 1 && (size_t)(nw + 2) * nrhs * ldM * sizeof(double) > 40 * 1024) nw /= 2;
+    return nw;
+}
+
+template <int NRHS, int CH, int NW>
+static void launch_trunk_nw(bool backward, const SweepArgs &a, int t, int n, hipStream_t st)
+{
+    if (backward) {
+        const size_t lds = sizeof(double) * ((size_t)child_batch(NRHS, a.ldx) * NRHS * a.ldx +
+                                             (size_t)(NW + 1) * NRHS * a.ldM + (size_t)NRHS * a.ldu);
+        hipLaunchKernelGGL((bwd_trunk_kernel<NRHS, CH, NW>), dim3(n), dim3(kWave * NW), lds, st, a, t);
+    } else {
+        const size_t lds = sizeof(double) * (size_t)(NW + 1) * NRHS * a.ldM;
+        hipLaunchKernelGGL((fwd_trunk_kernel<NRHS, CH, NW>), dim3(n), dim3(kWave * NW), lds, st, a, t);
+    }
+}
+
+template <int NRHS, int CH>
+static void launch_trunk(bool backward, const SweepArgs &a, int t, int n, hipStream_t st)
+{
+    switch (trunk_waves(n, NRHS, a.ldM)) {
+    case 16: launch_trunk_nw<NRHS, CH, 16>(backward, a, t, n, st); break;
+    case 8: launch_trunk_nw<NRHS, CH, 8>(backward, a, t, n, st); break;
+    case 4: launch_trunk_nw<NRHS, CH, 4>(backward, a, t, n, st); break;
+    case 2: launch_trunk_nw<NRHS, CH, 2>(backward, a, t, n, st); break;
+    default: launch_trunk_nw<NRHS, CH, 1>(backward, a, t, n, st); break;
+    }
+}
+
 template <int NRHS, int CH>
 static hipError_t sweep_impl(const SweepArgs &a, const int *host_stage_ptr, hipStream_t st)
 {
@@ -459,14 +722,14 @@ static hipError_t sweep_impl(const SweepArgs &a, const int *host_stage_ptr, hipS
         PhaseTimer tm(1, st);
         for (int t = a.sstar - 1; t >= 0; --t) {
             const int n = host_stage_ptr[t + 1] - host_stage_ptr[t];
-            hipLaunchKernelGGL((bwd_stage_kernel<NRHS, CH>), blocks(n), blk, lds, st, a, t);
+            launch_trunk<NRHS, CH>(true, a, t, n, st);
         }
     }
     if (a.sstar > 0) {
         PhaseTimer tm(2, st);
         for (int t = 0; t < a.sstar; ++t) {
             const int n = host_stage_ptr[t + 1] - host_stage_ptr[t];
-            hipLaunchKernelGGL((fwd_stage_kernel<NRHS, CH>), blocks(n), blk, lds, st, a, t);
+            launch_trunk<NRHS, CH>(false, a, t, n, st);
         }
     }
     if (a.sstar < a.N) {
