@@ -127,10 +127,31 @@ int tree_factor(const tree_desc *tree, const problem_data *data, int preconditio
 /* Releases the handle and its device memory (NULL is a no-op). */
 void tree_factors_free(tree_factors *f);
 
-/* Sizes of a factored tree, written to HOST out[10]: nx, nu, N, V, V_nl, m
- * (dual length), n (primal length), s_star (first stage from which every node
- * has one child), precondition flag, device bytes held.  ERR_ARG on NULL. */
+/*
+ * Batched factor step: count independent trees ("instances", each its own
+ * tree_desc / problem_data, of any sizes and horizons) factored into one
+ * handle.  Every other entry point then works on all instances at once with
+ * the per-instance vectors concatenated in instance order: duals [sum m_b],
+ * x [sum V_b nx_b], u [sum V_nl,b nu_b], x0 [sum nx_b] (offsets from
+ * tree_instance_dims).  Each sweep is one set of launches covering every
+ * instance (work lists of (instance, node) and (instance, chain) pairs).
+ * count = 1 is exactly tree_factor.  Errors as tree_factor; the message names
+ * the failing instance.
+ */
+int tree_factor_batch(int count, const tree_desc *trees, const problem_data *data, int precondition,
+                      void *hip_stream, tree_factors **out);
+
+/* Sizes of a handle, written to HOST out[10]: instances, precondition flag,
+ * total dual length, total primal length, sum V nx (x), sum V_nl nu (u),
+ * sum nx (x0), total nodes, device bytes held, largest nx+nu.  ERR_ARG on
+ * NULL. */
 int tree_dims(const tree_factors *f, int64_t *out);
+
+/* Sizes of instance b, written to HOST out[12]: nx, nu, N, V, V_nl, m, n,
+ * s_star (first stage from which every node has one child), and the offsets
+ * of the instance in the concatenated dual, x, u and x0 vectors.  ERR_ARG on
+ * NULL or b out of range. */
+int tree_instance_dims(const tree_factors *f, int b, int64_t *out);
 
 /*
  * Dual gradient (Algorithm 3) and Hessian-vector products (Algorithm 4).
@@ -140,7 +161,8 @@ int tree_dims(const tree_factors *f, int64_t *out);
  * product of the dual function is -H x-hat(y).  With preconditioning, y is the
  * scaled dual (the kernels apply sqrt(pi) per node) and x, u are unscaled.
  * DEVICE pointers: x0 [nrhs][nx] (ignored when homogeneous; may be NULL then),
- * y [nrhs][m], x [nrhs][V][nx] (x_0 included), u [nrhs][V_nl][nu].
+ * y [nrhs][m], x [nrhs][V][nx] (x_0 included), u [nrhs][V_nl][nu] (for a
+ * batched handle, the concatenated sizes of tree_dims).
  * nrhs >= 1; right-hand sides are swept two at a time, each pair sharing
  * one streaming of the factors.  Errors: ERR_ARG, ERR_OOM (workspace growth), ERR_DEVICE.
  */
@@ -151,8 +173,9 @@ int dual_grad(const tree_factors *f, const double *x0, const double *y, int homo
  * Lipschitz constant L of the dual gradient (largest eigenvalue of the dual
  * Hessian, in the scaled variables if the handle is preconditioned) by power
  * iteration on Algorithm 4, started from the all-ones vector; the step
- * lambda must lie in (0, 1/L) (Algorithm 1 input).  Writes HOST *L_out.
- * Synchronous.  Errors: ERR_ARG, ERR_DEVICE.
+ * lambda must lie in (0, 1/L) (Algorithm 1 input).  Writes HOST L_out[b]
+ * for every instance b (one value for a single tree).  Synchronous.
+ * Errors: ERR_ARG, ERR_DEVICE.
  */
 int dual_lipschitz(const tree_factors *f, int iters, double *L_out, void *hip_stream);
 
@@ -165,8 +188,13 @@ int dual_lipschitz(const tree_factors *f, int iters, double *L_out, void *hip_st
  * y+ = T_lambda(y + tau d).  DEVICE: x0 [nx], y_inout [m] (initial dual on
  * entry, zeros for a cold start; last iterate on exit), x [V][nx],
  * u [V_nl][nu] (receive x(y) at the returned y).  HOST: opts (NULL =
- * defaults), info (may be NULL).  Synchronous.  Returns OK, NOT_CONVERGED,
- * ERR_NUMERIC (NaN/Inf in the iterates), ERR_ARG, ERR_OOM, ERR_DEVICE.
+ * defaults), info (may be NULL).  Synchronous.  On a batched handle every
+ * instance iterates with its own step, line search, L-BFGS memory and stop
+ * test in the same launches, and stops independently; lambda = 0 gives each
+ * instance 1/(1.1 L_b); info summarises (iters = largest, status = worst) and
+ * solve_info_batch gives the per-instance records.  Returns OK,
+ * NOT_CONVERGED, ERR_NUMERIC (NaN/Inf in the iterates), ERR_ARG, ERR_OOM,
+ * ERR_DEVICE.
  */
 int minfbe_solve(const tree_factors *f, const double *x0, const solver_opts *opts,
                  double *y_inout, double *x, double *u, solver_info *info, void *hip_stream);
@@ -181,6 +209,10 @@ int minfbe_solve(const tree_factors *f, const double *x0, const solver_opts *opt
  */
 int nama_solve(const tree_factors *f, const double *x0, const solver_opts *opts,
                double *y_inout, double *x, double *u, solver_info *info, void *hip_stream);
+
+/* Per-instance records of the last minfbe_solve / nama_solve on this handle,
+ * written to HOST infos[count].  ERR_ARG on NULL. */
+int solve_info_batch(const tree_factors *f, solver_info *infos);
 
 /*
  * Phase timing for measurement tools.  stotree_timing(1) makes every sweep

@@ -25,7 +25,14 @@ int tree_factor(const tree_desc *tree, const problem_data *data, int preconditio
                 tree_factors **out)
 {
     set_error("");
-    return factor_tree(tree, data, precondition, (hipStream_t)hip_stream, out);
+    return factor_forest(1, tree, data, precondition, (hipStream_t)hip_stream, out);
+}
+
+int tree_factor_batch(int count, const tree_desc *trees, const problem_data *data, int precondition,
+                      void *hip_stream, tree_factors **out)
+{
+    set_error("");
+    return factor_forest(count, trees, data, precondition, (hipStream_t)hip_stream, out);
 }
 
 void tree_factors_free(tree_factors *f) { free_tree(f); }
@@ -33,9 +40,22 @@ void tree_factors_free(tree_factors *f) { free_tree(f); }
 int tree_dims(const tree_factors *f, int64_t *out)
 {
     if (!f || !out) { set_error("tree_dims: NULL argument"); return STOTREE_ERR_ARG; }
-    out[0] = f->nx; out[1] = f->nu; out[2] = f->N; out[3] = f->V; out[4] = f->Vnl;
-    out[5] = f->m; out[6] = f->n; out[7] = f->sstar; out[8] = f->precondition;
-    out[9] = (int64_t)(f->bytes + f->sws.bytes);
+    out[0] = f->ninst; out[1] = f->precondition; out[2] = f->m_tot; out[3] = f->n_tot;
+    out[4] = f->x_tot; out[5] = f->u_tot; out[6] = f->nx_tot; out[7] = f->V_tot;
+    out[8] = (int64_t)(f->bytes + f->sws.bytes); out[9] = f->max_width;
+    return STOTREE_OK;
+}
+
+int tree_instance_dims(const tree_factors *f, int b, int64_t *out)
+{
+    if (!f || !out || b < 0 || b >= f->ninst) {
+        set_error("tree_instance_dims: NULL argument or instance out of range");
+        return STOTREE_ERR_ARG;
+    }
+    const InstDesc &I = f->inst[b];
+    out[0] = I.nx; out[1] = I.nu; out[2] = I.N; out[3] = I.V; out[4] = I.Vnl; out[5] = I.m;
+    out[6] = (int64_t)I.Vnl * I.nu + (int64_t)(I.V - 1) * I.nx; out[7] = I.sstar;
+    out[8] = I.y; out[9] = I.x; out[10] = I.u; out[11] = I.x0;
     return STOTREE_OK;
 }
 
@@ -52,18 +72,17 @@ int dual_grad(const tree_factors *fc, const double *x0, const double *y, int hom
     if (rc) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     SweepArgs a = sweep_args(f, homogeneous ? 0 : 1);
-    a.y_rs = f->m;
-    a.x0_rs = f->nx;
-    a.xo_s = f->nx; a.xl_s = f->nx; a.uo_s = f->nu;
-    a.xo_rs = (long long)f->V * f->nx;
-    a.uo_rs = (long long)f->Vnl * f->nu;
+    a.y_rs = f->m_tot;
+    a.x0_rs = f->nx_tot;
+    a.xo_rs = f->x_tot;
+    a.uo_rs = f->u_tot;
+    a.dual_out = 0;
     for (int k0 = 0; k0 < nrhs; k0 += chunk) {
         const int nk = (nrhs - k0 >= chunk) ? chunk : 1;
-        a.x0 = x0 ? x0 + (long long)k0 * f->nx : nullptr;
-        a.y = y + (long long)k0 * f->m;
-        a.xo = x + (long long)k0 * a.xo_rs;
-        a.xl = a.xo + (long long)f->Vnl * f->nx;
-        a.uo = u + (long long)k0 * a.uo_rs;
+        a.x0 = x0 ? x0 + (long long)k0 * f->nx_tot : nullptr;
+        a.y = y + (long long)k0 * f->m_tot;
+        a.xo = x + (long long)k0 * f->x_tot;
+        a.uo = u + (long long)k0 * f->u_tot;
         hipError_t e = launch_sweep_tree(f, a, nk, st);
         if (e != hipSuccess) {
             set_error(std::string("dual_grad: ") + hipGetErrorString(e));
@@ -101,6 +120,13 @@ int nama_solve(const tree_factors *f, const double *x0, const solver_opts *opts,
                double *x, double *u, solver_info *info, void *hip_stream)
 {
     return run_solver(f, x0, opts, y_inout, x, u, info, hip_stream, 1);
+}
+
+int solve_info_batch(const tree_factors *f, solver_info *infos)
+{
+    if (!f || !infos) { set_error("solve_info_batch: NULL argument"); return STOTREE_ERR_ARG; }
+    for (int b = 0; b < f->ninst; ++b) infos[b] = f->last_info[b];
+    return STOTREE_OK;
 }
 
 int stotree_timing(int enable) { return timing_enable(enable); }

@@ -1,5 +1,6 @@
 // Factor step (arXiv 2107.01745, Sec. III-D: the Riccati-type recursion that
-// precomputes the per-node factors once, before any solve).
+// precomputes the per-node factors once, before any solve), for a forest of
+// independent trees.
 //
 // The paper names the factors (Phi, Theta, D, Lambda, K, sigma, c-hat) but
 // gives no formulas; they follow from dynamic programming on the inner problem
@@ -12,16 +13,18 @@
 //                  P_i  = 2 pi_i Q_i + sum_j A_j' P_j A_j + K_i' S~_i
 //                  chat_i = P_i c_i + pi_i q_i  (c_0 = 0),  sig_i = pi_i r_i
 // (the K_i' pi_i r_i part of the paper's c-hat is applied in the sweep, where
-// pi_i r_i enters g_i).  Stages run N-1..0, one kernel per stage, one
-// workgroup per node; the products are small dense FP64 blocks computed with
-// the workgroup's threads over output entries.
+// pi_i r_i enters g_i).  Stages run from the deepest down to 0; one kernel per
+// stage covers that stage of every instance, one workgroup per node; the
+// products are small dense FP64 blocks computed over output entries.
 //
 // The sweeps then stream, per edge j, M_j = [A_j B_j] row-major (backward,
 // Mb) and its transpose (forward, Mf), and per non-leaf node K_i (Kb), K_i'
 // (Kf) and -R~_i^{-1} (Rn); rows are padded to an even length so each row is
 // one aligned 16-byte-per-lane load.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 
 #include "internal.h"
 
@@ -29,102 +32,130 @@ namespace stotree {
 
 namespace {
 
+// Offsets of one instance in the raw (input-layout) pools.
+struct RawDesc {
+    long long A, B, c, Q, R, S, q, r, P, p, prob, Pcal;
+};
+
 struct FactorArgs {
-    int nx, nu, V, Vnl, ldM, ldx, ldu;
-    const int *stage_ptr, *child_ptr;
+    const InstDesc *inst;
+    const RawDesc *raw;
+    const Item *items;
+    const int *sp, *cp;
     const double *prob, *A, *B, *c, *Q, *R, *S, *q, *r, *P, *p;
+    int hasS, hasq, hasr, hasp;
     double *Pcal, *scratch;
     long long slot;  // scratch doubles per workgroup
-    double *Mb, *Mf, *Kb, *Kf, *Rn, *chat, *sig;
+    double *Mb, *Mf, *Kb, *Kf, *Rn, *chat, *sig, *cvec, *sc;
     int *err;
 };
 
-__global__ void pack_dynamics_kernel(FactorArgs a)
+// Mb, Mf and c of every edge of instance b.
+__global__ void pack_dynamics_kernel(FactorArgs a, int b)
 {
-    const int nx = a.nx, nu = a.nu, W = nx + nu;
-    const long long per_b = (long long)nx * a.ldM, per_f = (long long)W * a.ldx;
-    const long long total = (long long)(a.V - 1) * (per_b + per_f);
+    const InstDesc I = a.inst[b];
+    const RawDesc Rw = a.raw[b];
+    const int nx = I.nx, nu = I.nu, W = nx + nu;
+    const long long per_b = (long long)nx * I.ldM, per_f = (long long)W * I.ldx;
+    const long long total = (long long)I.V * (per_b + per_f);
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
-        const long long j = 1 + e / (per_b + per_f);
+        const long long j = e / (per_b + per_f);
         const long long w = e % (per_b + per_f);
+        const double *Aj = a.A + Rw.A + j * nx * nx;
+        const double *Bj = a.B + Rw.B + j * nx * nu;
         if (w < per_b) {  // Mb[j][r][col]
-            const int r = (int)(w / a.ldM), col = (int)(w % a.ldM);
+            const int r = (int)(w / I.ldM), col = (int)(w % I.ldM);
             double v = 0.0;
-            if (col < nx) v = a.A[(j * nx + r) * nx + col];
-            else if (col < W) v = a.B[(j * nx + r) * nu + (col - nx)];
-            a.Mb[j * per_b + w] = v;
+            if (j > 0) {
+                if (col < nx) v = Aj[r * nx + col];
+                else if (col < W) v = Bj[r * nu + (col - nx)];
+            }
+            a.Mb[I.Mb + j * per_b + w] = v;
         } else {           // Mf[j][col][r] = M_j[r][col]
             const long long wf = w - per_b;
-            const int col = (int)(wf / a.ldx), r = (int)(wf % a.ldx);
+            const int col = (int)(wf / I.ldx), r = (int)(wf % I.ldx);
             double v = 0.0;
-            if (r < nx) v = (col < nx) ? a.A[(j * nx + r) * nx + col] : a.B[(j * nx + r) * nu + (col - nx)];
-            a.Mf[j * per_f + wf] = v;
+            if (j > 0 && r < nx) v = (col < nx) ? Aj[r * nx + col] : Bj[r * nu + (col - nx)];
+            a.Mf[I.Mf + j * per_f + wf] = v;
         }
     }
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)I.V * nx;
+         e += (long long)gridDim.x * blockDim.x) {
+        a.cvec[I.c + e] = (e < nx) ? 0.0 : a.c[Rw.c + e];
+    }
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < I.V;
+         e += (long long)gridDim.x * blockDim.x)
+        a.sc[I.sc + e] = sqrt(a.prob[Rw.prob + e]);
 }
 
-__global__ void factor_leaves_kernel(FactorArgs a)
+__global__ void factor_leaves_kernel(FactorArgs a, int b)
 {
-    const int nx = a.nx;
-    const int j = a.Vnl + blockIdx.x;
-    if (j >= a.V) return;
-    const long long l = j - a.Vnl;
-    const double pj = a.prob[j];
-    double *Pj = a.Pcal + (long long)j * nx * nx;
-    for (int e = threadIdx.x; e < nx * nx; e += blockDim.x) Pj[e] = 2.0 * pj * a.P[l * nx * nx + e];
+    const InstDesc I = a.inst[b];
+    const RawDesc Rw = a.raw[b];
+    const int nx = I.nx;
+    const int j = I.Vnl + blockIdx.x;
+    if (j >= I.V) return;
+    const long long l = j - I.Vnl;
+    const double pj = a.prob[Rw.prob + j];
+    double *Pj = a.Pcal + Rw.Pcal + (long long)j * nx * nx;
+    for (int e = threadIdx.x; e < nx * nx; e += blockDim.x) Pj[e] = 2.0 * pj * a.P[Rw.P + l * nx * nx + e];
     __syncthreads();
     for (int r = threadIdx.x; r < nx; r += blockDim.x) {
         double s = 0.0;
-        for (int k = 0; k < nx; ++k) s = fma(Pj[r * nx + k], a.c[(long long)j * nx + k], s);
-        if (a.p) s += pj * a.p[l * nx + r];
-        a.chat[(long long)j * nx + r] = s;
+        for (int k = 0; k < nx; ++k) s = fma(Pj[r * nx + k], a.c[Rw.c + (long long)j * nx + k], s);
+        if (a.hasp) s += pj * a.p[Rw.p + l * nx + r];
+        a.chat[I.chat + (long long)j * nx + r] = s;
     }
 }
 
-__global__ void __launch_bounds__(256) factor_stage_kernel(FactorArgs a, int t)
+__global__ void __launch_bounds__(256) factor_stage_kernel(FactorArgs a)
 {
-    const int nx = a.nx, nu = a.nu, W = nx + nu;
-    const int i = a.stage_ptr[t] + blockIdx.x;
+    const Item it = a.items[blockIdx.x];
+    const InstDesc I = a.inst[it.inst];
+    const RawDesc Rw = a.raw[it.inst];
+    const int nx = I.nx, nu = I.nu, W = nx + nu;
+    const int i = it.idx;
+    const int *cp = a.cp + I.cp;
     const int tid = threadIdx.x, nt = blockDim.x;
     double *Wsc = a.scratch + (long long)blockIdx.x * a.slot;  // [nx][W]
     double *Rt = Wsc + (long long)nx * W;                      // [nu][nu] -> Cholesky L
     double *St = Rt + nu * nu;                                  // [nu][nx]
     double *Ri = St + nu * nx;                                  // [nu][nu]
     __shared__ int fail;
-    const double pi = a.prob[i];
-    double *Pi = a.Pcal + (long long)i * nx * nx;
+    const double pi = a.prob[Rw.prob + i];
+    double *Pi = a.Pcal + Rw.Pcal + (long long)i * nx * nx;
     if (tid == 0) fail = 0;
-    for (int e = tid; e < nu * nu; e += nt) Rt[e] = 2.0 * pi * a.R[(long long)i * nu * nu + e];
-    for (int e = tid; e < nu * nx; e += nt) St[e] = a.S ? 2.0 * pi * a.S[(long long)i * nu * nx + e] : 0.0;
-    for (int e = tid; e < nx * nx; e += nt) Pi[e] = 2.0 * pi * a.Q[(long long)i * nx * nx + e];
+    for (int e = tid; e < nu * nu; e += nt) Rt[e] = 2.0 * pi * a.R[Rw.R + (long long)i * nu * nu + e];
+    for (int e = tid; e < nu * nx; e += nt) St[e] = a.hasS ? 2.0 * pi * a.S[Rw.S + (long long)i * nu * nx + e] : 0.0;
+    for (int e = tid; e < nx * nx; e += nt) Pi[e] = 2.0 * pi * a.Q[Rw.Q + (long long)i * nx * nx + e];
     __syncthreads();
-    for (int j = a.child_ptr[i]; j < a.child_ptr[i + 1]; ++j) {
-        const double *M = a.Mb + (long long)j * nx * a.ldM;
-        const double *Pj = a.Pcal + (long long)j * nx * nx;
+    for (int j = cp[i]; j < cp[i + 1]; ++j) {
+        const double *M = a.Mb + I.Mb + (long long)j * nx * I.ldM;
+        const double *Pj = a.Pcal + Rw.Pcal + (long long)j * nx * nx;
         for (int e = tid; e < nx * W; e += nt) {          // W = P_j [A_j B_j]
             const int r = e / W, col = e % W;
             double s = 0.0;
-            for (int k = 0; k < nx; ++k) s = fma(Pj[r * nx + k], M[(long long)k * a.ldM + col], s);
+            for (int k = 0; k < nx; ++k) s = fma(Pj[r * nx + k], M[(long long)k * I.ldM + col], s);
             Wsc[e] = s;
         }
         __syncthreads();
         for (int e = tid; e < nx * nx; e += nt) {          // P_i += A_j' P_j A_j
             const int r = e / nx, col = e % nx;
             double s = 0.0;
-            for (int k = 0; k < nx; ++k) s = fma(M[(long long)k * a.ldM + r], Wsc[k * W + col], s);
+            for (int k = 0; k < nx; ++k) s = fma(M[(long long)k * I.ldM + r], Wsc[k * W + col], s);
             Pi[e] += s;
         }
         for (int e = tid; e < nu * nu; e += nt) {          // R~ += B_j' P_j B_j
             const int r = e / nu, col = e % nu;
             double s = 0.0;
-            for (int k = 0; k < nx; ++k) s = fma(M[(long long)k * a.ldM + nx + r], Wsc[k * W + nx + col], s);
+            for (int k = 0; k < nx; ++k) s = fma(M[(long long)k * I.ldM + nx + r], Wsc[k * W + nx + col], s);
             Rt[e] += s;
         }
         for (int e = tid; e < nu * nx; e += nt) {          // S~ += B_j' P_j A_j
             const int r = e / nx, col = e % nx;
             double s = 0.0;
-            for (int k = 0; k < nx; ++k) s = fma(M[(long long)k * a.ldM + nx + r], Wsc[k * W + col], s);
+            for (int k = 0; k < nx; ++k) s = fma(M[(long long)k * I.ldM + nx + r], Wsc[k * W + col], s);
             St[e] += s;
         }
         __syncthreads();
@@ -164,39 +195,44 @@ __global__ void __launch_bounds__(256) factor_stage_kernel(FactorArgs a, int t)
         }
     }
     __syncthreads();
-    double *Kb = a.Kb + (long long)i * nu * a.ldx;
-    double *Kf = a.Kf + (long long)i * nx * a.ldu;
-    double *Rn = a.Rn + (long long)i * nu * a.ldu;
-    for (int e = tid; e < nu * nx; e += nt) {              // K = -R~^{-1} S~
-        const int r = e / nx, col = e % nx;
+    double *Kb = a.Kb + I.Kb + (long long)i * nu * I.ldx;
+    double *Kf = a.Kf + I.Kf + (long long)i * nx * I.ldu;
+    double *Rn = a.Rn + I.Rn + (long long)i * nu * I.ldu;
+    for (int e = tid; e < nu * I.ldx; e += nt) {           // K = -R~^{-1} S~ (pad columns zero)
+        const int r = e / I.ldx, col = e % I.ldx;
         double s = 0.0;
-        for (int k = 0; k < nu; ++k) s = fma(Ri[r * nu + k], St[k * nx + col], s);
-        Kb[r * a.ldx + col] = -s;
-        Kf[col * a.ldu + r] = -s;
+        if (col < nx)
+            for (int k = 0; k < nu; ++k) s = fma(Ri[r * nu + k], St[k * nx + col], s);
+        Kb[e] = -s;
     }
-    for (int e = tid; e < nu * nu; e += nt) Rn[(e / nu) * a.ldu + (e % nu)] = -Ri[e];
+    for (int e = tid; e < nx * I.ldu; e += nt) {           // K' (pad columns zero)
+        const int col = e / I.ldu, r = e % I.ldu;
+        double s = 0.0;
+        if (r < nu)
+            for (int k = 0; k < nu; ++k) s = fma(Ri[r * nu + k], St[k * nx + col], s);
+        Kf[e] = -s;
+    }
+    for (int e = tid; e < nu * I.ldu; e += nt) {
+        const int r = e / I.ldu, col = e % I.ldu;
+        Rn[e] = col < nu ? -Ri[r * nu + col] : 0.0;
+    }
     __syncthreads();
     for (int e = tid; e < nx * nx; e += nt) {              // P_i += K' S~
         const int r = e / nx, col = e % nx;
         double s = 0.0;
-        for (int k = 0; k < nu; ++k) s = fma(Kb[k * a.ldx + r], St[k * nx + col], s);
+        for (int k = 0; k < nu; ++k) s = fma(Kb[k * I.ldx + r], St[k * nx + col], s);
         Pi[e] += s;
     }
     __syncthreads();
     for (int rr = tid; rr < nx; rr += nt) {
         double s = 0.0;
         if (i > 0)
-            for (int k = 0; k < nx; ++k) s = fma(Pi[rr * nx + k], a.c[(long long)i * nx + k], s);
-        if (a.q) s += pi * a.q[(long long)i * nx + rr];
-        a.chat[(long long)i * nx + rr] = s;
+            for (int k = 0; k < nx; ++k) s = fma(Pi[rr * nx + k], a.c[Rw.c + (long long)i * nx + k], s);
+        if (a.hasq) s += pi * a.q[Rw.q + (long long)i * nx + rr];
+        a.chat[I.chat + (long long)i * nx + rr] = s;
     }
-    for (int rr = tid; rr < nu; rr += nt) a.sig[(long long)i * nu + rr] = a.r ? pi * a.r[(long long)i * nu + rr] : 0.0;
-}
-
-__global__ void sqrt_prob_kernel(const double *prob, double *sc, int V)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < V) sc[i] = sqrt(prob[i]);
+    for (int rr = tid; rr < nu; rr += nt)
+        a.sig[I.sig + (long long)i * nu + rr] = a.hasr ? pi * a.r[Rw.r + (long long)i * nu + rr] : 0.0;
 }
 
 bool all_finite(const double *a, size_t n)
@@ -212,89 +248,62 @@ struct DevBuf {
     ~DevBuf() { if (p) (void)hipFree(p); }
 };
 
-template <typename T>
-int upload(DevBuf &b, const T *h, size_t n)
+int validate(const tree_desc *t, const problem_data *d, const std::string &who)
 {
-    if (!h) return STOTREE_OK;
-    STOTREE_HIP(hipMalloc(&b.p, sizeof(T) * (n ? n : 1)));
-    STOTREE_HIP(hipMemcpy(b.p, h, sizeof(T) * n, hipMemcpyHostToDevice));
-    return STOTREE_OK;
-}
-
-}  // namespace
-
-void free_tree(tree_factors *f)
-{
-    if (!f) return;
-    for (void *p : {(void *)f->d_stage_ptr, (void *)f->d_child_ptr, (void *)f->Mb, (void *)f->Mf,
-                    (void *)f->Kb, (void *)f->Kf, (void *)f->Rn, (void *)f->chat, (void *)f->sig,
-                    (void *)f->cvec, (void *)f->sc, (void *)f->lo, (void *)f->hi, (void *)f->qhat,
-                    (void *)f->kbuf, (void *)f->sws.buf})
-        if (p) (void)hipFree(p);
-    delete f;
-}
-
-int factor_tree(const tree_desc *t, const problem_data *d, int precondition, hipStream_t st,
-                tree_factors **out)
-{
-    if (!out) { set_error("tree_factor: out is NULL"); return STOTREE_ERR_ARG; }
-    *out = nullptr;
-    if (!t || !d) { set_error("tree_factor: NULL tree or data"); return STOTREE_ERR_ARG; }
+    if (!t || !d) { set_error(who + ": NULL tree or data"); return STOTREE_ERR_ARG; }
     const int nx = t->nx, nu = t->nu, N = t->N, V = t->num_nodes;
     if (nx < 1 || nu < 1 || N < 1 || V < 2 || nx + nu > kMaxWidth) {
-        set_error("tree_factor: need nx>=1, nu>=1, N>=1, V>=2 and nx+nu<=256");
+        set_error(who + ": need nx>=1, nu>=1, N>=1, V>=2 and nx+nu<=256");
         return STOTREE_ERR_ARG;
     }
     if (!t->stage_ptr || !t->ancestor || !t->child_ptr || !t->prob || !d->A || !d->B || !d->c ||
         !d->Q || !d->R || !d->P || !d->xmin || !d->xmax || !d->umin || !d->umax) {
-        set_error("tree_factor: a required array is NULL");
+        set_error(who + ": a required array is NULL");
         return STOTREE_ERR_ARG;
     }
-    // ---- tree validation (Sec. II-A) ----
     const int *sp = t->stage_ptr;
     if (sp[0] != 0 || sp[1] != 1 || sp[N + 1] != V) {
-        set_error("tree_factor: stage_ptr must start 0,1 and end at num_nodes");
+        set_error(who + ": stage_ptr must start 0,1 and end at num_nodes");
         return STOTREE_ERR_TREE;
     }
     for (int s = 0; s <= N; ++s)
-        if (sp[s + 1] <= sp[s]) { set_error("tree_factor: empty stage"); return STOTREE_ERR_TREE; }
+        if (sp[s + 1] <= sp[s]) { set_error(who + ": empty stage"); return STOTREE_ERR_TREE; }
     const int Vnl = sp[N];
-    if (t->ancestor[0] != -1) { set_error("tree_factor: ancestor[0] must be -1"); return STOTREE_ERR_TREE; }
+    if (t->ancestor[0] != -1) { set_error(who + ": ancestor[0] must be -1"); return STOTREE_ERR_TREE; }
     for (int s = 1; s <= N; ++s)
         for (int i = sp[s]; i < sp[s + 1]; ++i) {
             const int a = t->ancestor[i];
             if (a < sp[s - 1] || a >= sp[s]) {
-                set_error("tree_factor: ancestor of a node is not in the previous stage");
+                set_error(who + ": ancestor of a node is not in the previous stage");
                 return STOTREE_ERR_TREE;
             }
         }
     const int *cp = t->child_ptr;
-    if (cp[0] != 1 || cp[Vnl] != V) { set_error("tree_factor: child_ptr must span [1, V)"); return STOTREE_ERR_TREE; }
+    if (cp[0] != 1 || cp[Vnl] != V) { set_error(who + ": child_ptr must span [1, V)"); return STOTREE_ERR_TREE; }
     for (int i = 0; i < Vnl; ++i) {
-        if (cp[i + 1] <= cp[i]) { set_error("tree_factor: a non-leaf node has no child"); return STOTREE_ERR_TREE; }
+        if (cp[i + 1] <= cp[i]) { set_error(who + ": a non-leaf node has no child"); return STOTREE_ERR_TREE; }
         for (int j = cp[i]; j < cp[i + 1]; ++j)
             if (t->ancestor[j] != i) {
-                set_error("tree_factor: child_ptr and ancestor disagree");
+                set_error(who + ": child_ptr and ancestor disagree");
                 return STOTREE_ERR_TREE;
             }
     }
-    if (std::fabs(t->prob[0] - 1.0) > 1e-12) { set_error("tree_factor: prob[0] must be 1"); return STOTREE_ERR_TREE; }
+    if (std::fabs(t->prob[0] - 1.0) > 1e-12) { set_error(who + ": prob[0] must be 1"); return STOTREE_ERR_TREE; }
     for (int s = 0; s <= N; ++s) {
         double tot = 0.0;
         for (int i = sp[s]; i < sp[s + 1]; ++i) {
             if (!(t->prob[i] > 0.0) || !std::isfinite(t->prob[i])) {
-                set_error("tree_factor: node probabilities must be positive");
+                set_error(who + ": node probabilities must be positive");
                 return STOTREE_ERR_TREE;
             }
             tot += t->prob[i];
         }
         if (std::fabs(tot - 1.0) > 1e-12) {
-            set_error("tree_factor: probabilities of stage " + std::to_string(s) + " do not sum to 1");
+            set_error(who + ": probabilities of stage " + std::to_string(s) + " do not sum to 1");
             return STOTREE_ERR_TREE;
         }
     }
     const size_t Vl = (size_t)V - Vnl;
-    // ---- data validation ----
     struct Chk { const double *p; size_t n; const char *name; };
     const Chk chks[] = {{d->A, (size_t)V * nx * nx, "A"}, {d->B, (size_t)V * nx * nu, "B"},
                         {d->c, (size_t)V * nx, "c"}, {d->Q, (size_t)Vnl * nx * nx, "Q"},
@@ -303,110 +312,281 @@ int factor_tree(const tree_desc *t, const problem_data *d, int precondition, hip
                         {d->P, Vl * nx * nx, "P"}, {d->p, Vl * nx, "p"}};
     for (const Chk &c : chks)
         if (c.p && !all_finite(c.p, c.n)) {
-            set_error(std::string("tree_factor: non-finite entry in ") + c.name);
+            set_error(who + ": non-finite entry in " + c.name);
             return STOTREE_ERR_NUMERIC;
         }
     for (size_t k = 0; k < (size_t)V * nx; ++k)
         if (std::isnan(d->xmin[k]) || std::isnan(d->xmax[k]) || d->xmin[k] > d->xmax[k]) {
-            set_error("tree_factor: state box with lo > hi (or NaN)");
+            set_error(who + ": state box with lo > hi (or NaN)");
             return STOTREE_ERR_BOX;
         }
     for (size_t k = 0; k < (size_t)Vnl * nu; ++k)
         if (std::isnan(d->umin[k]) || std::isnan(d->umax[k]) || d->umin[k] > d->umax[k]) {
-            set_error("tree_factor: input box with lo > hi (or NaN)");
+            set_error(who + ": input box with lo > hi (or NaN)");
             return STOTREE_ERR_BOX;
         }
+    return STOTREE_OK;
+}
 
+// Wavefronts per node for a stage of n nodes: enough to keep about 4096
+// wavefronts busy, within the LDS budget of the reduction buffers.
+int trunk_waves(int n, int nrhs_max, int ldM, int cap)
+{
+    int nw = cap;
+    while (nw > 1 && (long long)n * nw > 4096) nw /= 2;
+    while (nw > 1 && (size_t)(nw + 2) * nrhs_max * ldM * sizeof(double) > 40 * 1024) nw /= 2;
+    return nw;
+}
+
+}  // namespace
+
+void free_tree(tree_factors *f)
+{
+    if (!f) return;
+    for (void *p : {(void *)f->d_inst, (void *)f->d_sp, (void *)f->d_cp, (void *)f->Mb, (void *)f->Mf,
+                    (void *)f->Kb, (void *)f->Kf, (void *)f->Rn, (void *)f->chat, (void *)f->sig,
+                    (void *)f->cvec, (void *)f->sc, (void *)f->lo, (void *)f->hi, (void *)f->qhat,
+                    (void *)f->kbuf, (void *)f->sws.buf, (void *)f->chain_items})
+        if (p) (void)hipFree(p);
+    for (auto &lv : f->levels)
+        if (lv.items) (void)hipFree(lv.items);
+    delete f;
+}
+
+// Work lists of a sweep: all chains (longest first when chain_order is set)
+// and, per stage above s*, all (instance, node) pairs of that stage.
+int build_schedule(tree_factors *f)
+{
+    if (f->chain_items) { (void)hipFree(f->chain_items); f->chain_items = nullptr; }
+    for (auto &lv : f->levels)
+        if (lv.items) (void)hipFree(lv.items);
+    f->levels.clear();
+    std::vector<Item> chains;
+    std::vector<double> cost;
+    int max_sstar = 0, max_ldM = 0;
+    for (int b = 0; b < f->ninst; ++b) {
+        const InstDesc &I = f->inst[b];
+        max_sstar = std::max(max_sstar, I.sstar);
+        max_ldM = std::max(max_ldM, I.ldM);
+        if (I.sstar < I.N)
+            for (int c = 0; c < I.nchains; ++c) {
+                chains.push_back({b, c});
+                cost.push_back((double)(I.N - I.sstar) * I.nx * (I.nx + I.nu));
+            }
+    }
+    if (f->chain_order && !chains.empty()) {
+        std::vector<size_t> ord(chains.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t p, size_t q) { return cost[p] > cost[q]; });
+        std::vector<Item> sorted(chains.size());
+        for (size_t k = 0; k < ord.size(); ++k) sorted[k] = chains[ord[k]];
+        chains.swap(sorted);
+    }
+    f->nchain_items = (int)chains.size();
+    if (!chains.empty()) {
+        STOTREE_HIP(hipMalloc(&f->chain_items, sizeof(Item) * chains.size()));
+        STOTREE_HIP(hipMemcpy(f->chain_items, chains.data(), sizeof(Item) * chains.size(), hipMemcpyHostToDevice));
+    }
+    for (int t = 0; t < max_sstar; ++t) {
+        std::vector<Item> items;
+        for (int b = 0; b < f->ninst; ++b) {
+            const InstDesc &I = f->inst[b];
+            if (t >= I.sstar) continue;
+            const int *sp = f->sp_pool.data() + I.sp;
+            for (int i = sp[t]; i < sp[t + 1]; ++i) items.push_back({b, i});
+        }
+        LevelPlan lv{};
+        lv.t = t;
+        lv.count = (int)items.size();
+        lv.nw = trunk_waves(lv.count, 2, max_ldM, f->trunk_cap);
+        STOTREE_HIP(hipMalloc(&lv.items, sizeof(Item) * std::max<size_t>(1, items.size())));
+        STOTREE_HIP(hipMemcpy(lv.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+        f->levels.push_back(lv);
+    }
+    return STOTREE_OK;
+}
+
+int factor_forest(int count, const tree_desc *trees, const problem_data *datas, int precondition,
+                  hipStream_t st, tree_factors **out)
+{
+    if (!out) { set_error("tree_factor: out is NULL"); return STOTREE_ERR_ARG; }
+    *out = nullptr;
+    if (count < 1 || !trees || !datas) { set_error("tree_factor: no instances"); return STOTREE_ERR_ARG; }
+    for (int b = 0; b < count; ++b) {
+        const int rc = validate(&trees[b], &datas[b], count == 1 ? "tree_factor" :
+                                "tree_factor_batch[" + std::to_string(b) + "]");
+        if (rc) return rc;
+    }
     tree_factors *f = new tree_factors();
-    f->nx = nx; f->nu = nu; f->N = N; f->V = V; f->Vnl = Vnl;
-    f->m = (long long)Vnl * (nx + nu) + (long long)Vl * nx;
-    f->n = (long long)Vnl * nu + (long long)(V - 1) * nx;
-    f->precondition = precondition ? 1 : 0;
-    f->ldM = pad2(nx + nu); f->ldx = pad2(nx); f->ldu = pad2(nu);
-    f->stage_ptr.assign(sp, sp + N + 2);
-    // s*: first stage from which every stage has as many nodes as the leaves
-    int sstar = N;
-    while (sstar > 0 && sp[sstar] - sp[sstar - 1] == sp[N + 1] - sp[N]) --sstar;
-    f->sstar = sstar;
-    f->nchains = sp[N + 1] - sp[N];
     struct Guard {
         tree_factors *&f;
         bool ok = false;
         ~Guard() { if (!ok) free_tree(f); }
     } guard{f};
-
+    f->ninst = count;
+    f->precondition = precondition ? 1 : 0;
+    f->inst.resize(count);
+    std::vector<RawDesc> raw(count);
+    long long oMb = 0, oMf = 0, oKb = 0, oKf = 0, oRn = 0, ochat = 0, osig = 0, osc = 0, oy = 0, ox = 0,
+              ou = 0, ox0 = 0;
+    RawDesc ro{};
+    int osp = 0, ocp = 0;
+    bool anyS = false, anyq = false, anyr = false, anyp = false;
+    long long max_slot = 0;
+    for (int b = 0; b < count; ++b) {
+        const tree_desc &t = trees[b];
+        const problem_data &d = datas[b];
+        InstDesc &I = f->inst[b];
+        I.nx = t.nx; I.nu = t.nu; I.N = t.N; I.V = t.num_nodes; I.Vnl = t.stage_ptr[t.N];
+        I.ldM = pad2(I.nx + I.nu); I.ldx = pad2(I.nx); I.ldu = pad2(I.nu);
+        const int *sp = t.stage_ptr;
+        int sstar = I.N;
+        while (sstar > 0 && sp[sstar] - sp[sstar - 1] == sp[I.N + 1] - sp[I.N]) --sstar;
+        I.sstar = sstar;
+        I.nchains = sp[I.N + 1] - sp[I.N];
+        I.sp = osp; I.cp = ocp;
+        I.Mb = oMb; I.Mf = oMf; I.Kb = oKb; I.Kf = oKf; I.Rn = oRn;
+        I.chat = ochat; I.c = ochat; I.sig = osig; I.sc = osc;
+        I.y = oy; I.x = ox; I.u = ou; I.x0 = ox0;
+        I.m = (long long)I.Vnl * (I.nx + I.nu) + (long long)(I.V - I.Vnl) * I.nx;
+        const long long V = I.V, Vnl = I.Vnl, Vl = I.V - I.Vnl, nx = I.nx, nu = I.nu;
+        oMb += V * nx * I.ldM; oMf += V * (nx + nu) * I.ldx; oKb += Vnl * nu * I.ldx;
+        oKf += Vnl * nx * I.ldu; oRn += Vnl * nu * I.ldu; ochat += V * nx; osig += Vnl * nu; osc += V;
+        oy += I.m; ox += V * nx; ou += Vnl * nu; ox0 += nx;
+        osp += I.N + 2; ocp += I.Vnl + 1;
+        RawDesc &R = raw[b];
+        R = ro;
+        ro.A += V * nx * nx; ro.B += V * nx * nu; ro.c += V * nx; ro.Q += Vnl * nx * nx;
+        ro.R += Vnl * nu * nu; ro.S += Vnl * nu * nx; ro.q += Vnl * nx; ro.r += Vnl * nu;
+        ro.P += Vl * nx * nx; ro.p += Vl * nx; ro.prob += V; ro.Pcal += V * nx * nx;
+        anyS |= d.S != nullptr; anyq |= d.q != nullptr; anyr |= d.r != nullptr; anyp |= d.p != nullptr;
+        max_slot = std::max(max_slot, nx * (nx + nu) + 2 * nu * nu + nu * nx);
+        f->max_width = std::max(f->max_width, I.nx + I.nu);
+        f->n_tot += Vnl * nu + (V - 1) * nx;
+        f->V_tot += V;
+    }
+    f->m_tot = oy; f->x_tot = ox; f->u_tot = ou; f->nx_tot = ox0;
+    // host pools of the stage/child pointers
+    f->sp_pool.resize(osp);
+    std::vector<int> cp_pool(ocp);
+    for (int b = 0; b < count; ++b) {
+        const InstDesc &I = f->inst[b];
+        std::memcpy(f->sp_pool.data() + I.sp, trees[b].stage_ptr, sizeof(int) * (I.N + 2));
+        std::memcpy(cp_pool.data() + I.cp, trees[b].child_ptr, sizeof(int) * (I.Vnl + 1));
+    }
     auto dalloc = [&](auto **p, size_t n) -> int {
         STOTREE_HIP(hipMalloc((void **)p, sizeof(**p) * (n ? n : 1)));
         f->bytes += sizeof(**p) * n;
         return STOTREE_OK;
     };
     int rc;
-    if ((rc = dalloc(&f->d_stage_ptr, N + 2)) || (rc = dalloc(&f->d_child_ptr, Vnl + 1)) ||
-        (rc = dalloc(&f->Mb, (size_t)V * nx * f->ldM)) ||
-        (rc = dalloc(&f->Mf, (size_t)V * (nx + nu) * f->ldx)) ||
-        (rc = dalloc(&f->Kb, (size_t)Vnl * nu * f->ldx)) ||
-        (rc = dalloc(&f->Kf, (size_t)Vnl * nx * f->ldu)) ||
-        (rc = dalloc(&f->Rn, (size_t)Vnl * nu * f->ldu)) || (rc = dalloc(&f->chat, (size_t)V * nx)) ||
-        (rc = dalloc(&f->sig, (size_t)Vnl * nu)) || (rc = dalloc(&f->cvec, (size_t)V * nx)) ||
-        (rc = dalloc(&f->sc, (size_t)V)) || (rc = dalloc(&f->lo, (size_t)f->m)) ||
-        (rc = dalloc(&f->hi, (size_t)f->m)))
+    if ((rc = dalloc(&f->d_inst, count)) || (rc = dalloc(&f->d_sp, osp)) || (rc = dalloc(&f->d_cp, ocp)) ||
+        (rc = dalloc(&f->Mb, oMb)) || (rc = dalloc(&f->Mf, oMf)) || (rc = dalloc(&f->Kb, oKb)) ||
+        (rc = dalloc(&f->Kf, oKf)) || (rc = dalloc(&f->Rn, oRn)) || (rc = dalloc(&f->chat, ochat)) ||
+        (rc = dalloc(&f->sig, osig)) || (rc = dalloc(&f->cvec, ochat)) || (rc = dalloc(&f->sc, osc)) ||
+        (rc = dalloc(&f->lo, oy)) || (rc = dalloc(&f->hi, oy)))
         return rc;
-    STOTREE_HIP(hipMemcpyAsync(f->d_stage_ptr, sp, sizeof(int) * (N + 2), hipMemcpyHostToDevice, st));
-    STOTREE_HIP(hipMemcpyAsync(f->d_child_ptr, cp, sizeof(int) * (Vnl + 1), hipMemcpyHostToDevice, st));
-    STOTREE_HIP(hipMemcpyAsync(f->cvec, d->c, sizeof(double) * V * nx, hipMemcpyHostToDevice, st));
+    STOTREE_HIP(hipMemcpy(f->d_inst, f->inst.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice));
+    STOTREE_HIP(hipMemcpy(f->d_sp, f->sp_pool.data(), sizeof(int) * osp, hipMemcpyHostToDevice));
+    STOTREE_HIP(hipMemcpy(f->d_cp, cp_pool.data(), sizeof(int) * ocp, hipMemcpyHostToDevice));
     // box rows in the dual layout (a data rearrangement, no arithmetic)
     {
-        std::vector<double> lo((size_t)f->m), hi((size_t)f->m);
-        for (int i = 0; i < V; ++i) {
-            const size_t o = i < Vnl ? (size_t)i * (nx + nu) : (size_t)Vnl * nu + (size_t)i * nx;
-            std::memcpy(&lo[o], d->xmin + (size_t)i * nx, sizeof(double) * nx);
-            std::memcpy(&hi[o], d->xmax + (size_t)i * nx, sizeof(double) * nx);
-            if (i < Vnl) {
-                std::memcpy(&lo[o + nx], d->umin + (size_t)i * nu, sizeof(double) * nu);
-                std::memcpy(&hi[o + nx], d->umax + (size_t)i * nu, sizeof(double) * nu);
+        std::vector<double> lo((size_t)oy), hi((size_t)oy);
+        for (int b = 0; b < count; ++b) {
+            const InstDesc &I = f->inst[b];
+            const problem_data &d = datas[b];
+            for (int i = 0; i < I.V; ++i) {
+                const size_t o = I.y + (i < I.Vnl ? (size_t)i * (I.nx + I.nu) : (size_t)I.Vnl * I.nu + (size_t)i * I.nx);
+                std::memcpy(&lo[o], d.xmin + (size_t)i * I.nx, sizeof(double) * I.nx);
+                std::memcpy(&hi[o], d.xmax + (size_t)i * I.nx, sizeof(double) * I.nx);
+                if (i < I.Vnl) {
+                    std::memcpy(&lo[o + I.nx], d.umin + (size_t)i * I.nu, sizeof(double) * I.nu);
+                    std::memcpy(&hi[o + I.nx], d.umax + (size_t)i * I.nu, sizeof(double) * I.nu);
+                }
             }
         }
-        STOTREE_HIP(hipMemcpy(f->lo, lo.data(), sizeof(double) * f->m, hipMemcpyHostToDevice));
-        STOTREE_HIP(hipMemcpy(f->hi, hi.data(), sizeof(double) * f->m, hipMemcpyHostToDevice));
+        STOTREE_HIP(hipMemcpy(f->lo, lo.data(), sizeof(double) * oy, hipMemcpyHostToDevice));
+        STOTREE_HIP(hipMemcpy(f->hi, hi.data(), sizeof(double) * oy, hipMemcpyHostToDevice));
     }
-    DevBuf bA, bB, bc, bQ, bR, bS, bq, br, bP, bp, bprob, bPcal, bscr, berr;
-    if ((rc = upload(bA, d->A, (size_t)V * nx * nx)) || (rc = upload(bB, d->B, (size_t)V * nx * nu)) ||
-        (rc = upload(bc, d->c, (size_t)V * nx)) || (rc = upload(bQ, d->Q, (size_t)Vnl * nx * nx)) ||
-        (rc = upload(bR, d->R, (size_t)Vnl * nu * nu)) || (rc = upload(bS, d->S, (size_t)Vnl * nu * nx)) ||
-        (rc = upload(bq, d->q, (size_t)Vnl * nx)) || (rc = upload(br, d->r, (size_t)Vnl * nu)) ||
-        (rc = upload(bP, d->P, Vl * nx * nx)) || (rc = upload(bp, d->p, Vl * nx)) ||
-        (rc = upload(bprob, t->prob, (size_t)V)))
+    // raw inputs: concatenated pools (a single instance is uploaded in place)
+    DevBuf bA, bB, bc, bQ, bR, bS, bq, br, bP, bp, bprob, bPcal, bscr, berr, braw, bitems;
+    auto upload = [&](DevBuf &buf, long long total, auto get, auto len) -> int {
+        STOTREE_HIP(hipMalloc(&buf.p, sizeof(double) * (total ? total : 1)));
+        long long o = 0;
+        for (int b = 0; b < count; ++b) {
+            const double *h = get(b);
+            const long long n = len(b);
+            if (h) STOTREE_HIP(hipMemcpy((double *)buf.p + o, h, sizeof(double) * n, hipMemcpyHostToDevice));
+            else STOTREE_HIP(hipMemset((double *)buf.p + o, 0, sizeof(double) * n));
+            o += n;
+        }
+        return STOTREE_OK;
+    };
+#define NODES(expr) [&](int b) -> long long { const InstDesc &I = f->inst[b]; (void)I; return (expr); }
+    if ((rc = upload(bA, ro.A, [&](int b) { return datas[b].A; }, NODES((long long)I.V * I.nx * I.nx))) ||
+        (rc = upload(bB, ro.B, [&](int b) { return datas[b].B; }, NODES((long long)I.V * I.nx * I.nu))) ||
+        (rc = upload(bc, ro.c, [&](int b) { return datas[b].c; }, NODES((long long)I.V * I.nx))) ||
+        (rc = upload(bQ, ro.Q, [&](int b) { return datas[b].Q; }, NODES((long long)I.Vnl * I.nx * I.nx))) ||
+        (rc = upload(bR, ro.R, [&](int b) { return datas[b].R; }, NODES((long long)I.Vnl * I.nu * I.nu))) ||
+        (anyS && (rc = upload(bS, ro.S, [&](int b) { return datas[b].S; }, NODES((long long)I.Vnl * I.nu * I.nx)))) ||
+        (anyq && (rc = upload(bq, ro.q, [&](int b) { return datas[b].q; }, NODES((long long)I.Vnl * I.nx)))) ||
+        (anyr && (rc = upload(br, ro.r, [&](int b) { return datas[b].r; }, NODES((long long)I.Vnl * I.nu)))) ||
+        (rc = upload(bP, ro.P, [&](int b) { return datas[b].P; }, NODES((long long)(I.V - I.Vnl) * I.nx * I.nx))) ||
+        (anyp && (rc = upload(bp, ro.p, [&](int b) { return datas[b].p; }, NODES((long long)(I.V - I.Vnl) * I.nx))) ) ||
+        (rc = upload(bprob, ro.prob, [&](int b) { return trees[b].prob; }, NODES((long long)I.V))))
         return rc;
-    int maxw = 0;
-    for (int s = 0; s < N; ++s) maxw = std::max(maxw, sp[s + 1] - sp[s]);
-    const long long slot = (long long)nx * (nx + nu) + 2LL * nu * nu + (long long)nu * nx;
-    STOTREE_HIP(hipMalloc(&bPcal.p, sizeof(double) * (size_t)V * nx * nx));
-    STOTREE_HIP(hipMalloc(&bscr.p, sizeof(double) * (size_t)maxw * slot));
+#undef NODES
+    // scratch for the widest stage
+    int maxw = 1;
+    int max_depth = 0;
+    for (int b = 0; b < count; ++b) max_depth = std::max(max_depth, f->inst[b].N);
+    std::vector<std::vector<Item>> level_items(max_depth);
+    for (int b = 0; b < count; ++b) {
+        const InstDesc &I = f->inst[b];
+        const int *sp = f->sp_pool.data() + I.sp;
+        for (int t = 0; t < I.N; ++t)
+            for (int i = sp[t]; i < sp[t + 1]; ++i) level_items[t].push_back({b, i});
+    }
+    for (auto &li : level_items) maxw = std::max<int>(maxw, (int)li.size());
+    STOTREE_HIP(hipMalloc(&bPcal.p, sizeof(double) * (size_t)std::max(1LL, ro.Pcal)));
+    STOTREE_HIP(hipMalloc(&bscr.p, sizeof(double) * (size_t)maxw * max_slot));
     STOTREE_HIP(hipMalloc(&berr.p, sizeof(int)));
-    STOTREE_HIP(hipMemsetAsync(berr.p, 0, sizeof(int), st));
-    STOTREE_HIP(hipMemsetAsync(f->Mb, 0, sizeof(double) * f->ldM * nx, st));            // edge 0 unused
-    STOTREE_HIP(hipMemsetAsync(f->Mf, 0, sizeof(double) * f->ldx * (nx + nu), st));
-    STOTREE_HIP(hipMemsetAsync(f->Kb, 0, sizeof(double) * (size_t)Vnl * nu * f->ldx, st));
-    STOTREE_HIP(hipMemsetAsync(f->Kf, 0, sizeof(double) * (size_t)Vnl * nx * f->ldu, st));
-    STOTREE_HIP(hipMemsetAsync(f->Rn, 0, sizeof(double) * (size_t)Vnl * nu * f->ldu, st));
+    STOTREE_HIP(hipMalloc(&braw.p, sizeof(RawDesc) * count));
+    std::vector<Item> all_items;
+    std::vector<size_t> level_off(max_depth + 1, 0);
+    for (int t = 0; t < max_depth; ++t) {
+        level_off[t] = all_items.size();
+        all_items.insert(all_items.end(), level_items[t].begin(), level_items[t].end());
+    }
+    level_off[max_depth] = all_items.size();
+    STOTREE_HIP(hipMalloc(&bitems.p, sizeof(Item) * std::max<size_t>(1, all_items.size())));
+    STOTREE_HIP(hipMemcpy(bitems.p, all_items.data(), sizeof(Item) * all_items.size(), hipMemcpyHostToDevice));
+    STOTREE_HIP(hipMemcpy(braw.p, raw.data(), sizeof(RawDesc) * count, hipMemcpyHostToDevice));
+    STOTREE_HIP(hipMemset(berr.p, 0, sizeof(int)));
 
     FactorArgs a{};
-    a.nx = nx; a.nu = nu; a.V = V; a.Vnl = Vnl; a.ldM = f->ldM; a.ldx = f->ldx; a.ldu = f->ldu;
-    a.stage_ptr = f->d_stage_ptr; a.child_ptr = f->d_child_ptr;
+    a.inst = f->d_inst; a.raw = (const RawDesc *)braw.p; a.sp = f->d_sp; a.cp = f->d_cp;
     a.prob = (const double *)bprob.p; a.A = (const double *)bA.p; a.B = (const double *)bB.p;
     a.c = (const double *)bc.p; a.Q = (const double *)bQ.p; a.R = (const double *)bR.p;
     a.S = (const double *)bS.p; a.q = (const double *)bq.p; a.r = (const double *)br.p;
     a.P = (const double *)bP.p; a.p = (const double *)bp.p;
-    a.Pcal = (double *)bPcal.p; a.scratch = (double *)bscr.p; a.slot = slot;
+    a.hasS = anyS; a.hasq = anyq; a.hasr = anyr; a.hasp = anyp;
+    a.Pcal = (double *)bPcal.p; a.scratch = (double *)bscr.p; a.slot = max_slot;
     a.Mb = f->Mb; a.Mf = f->Mf; a.Kb = f->Kb; a.Kf = f->Kf; a.Rn = f->Rn;
-    a.chat = f->chat; a.sig = f->sig; a.err = (int *)berr.p;
-
-    hipLaunchKernelGGL(pack_dynamics_kernel, dim3(4096), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(factor_leaves_kernel, dim3((unsigned)Vl), dim3(64), 0, st, a);
-    for (int s = N - 1; s >= 0; --s)
-        hipLaunchKernelGGL(factor_stage_kernel, dim3(sp[s + 1] - sp[s]), dim3(256), 0, st, a, s);
-    hipLaunchKernelGGL(sqrt_prob_kernel, dim3((V + 255) / 256), dim3(256), 0, st,
-                       (const double *)bprob.p, f->sc, V);
+    a.chat = f->chat; a.sig = f->sig; a.cvec = f->cvec; a.sc = f->sc; a.err = (int *)berr.p;
+    for (int b = 0; b < count; ++b) {
+        const InstDesc &I = f->inst[b];
+        const long long work = (long long)I.V * (I.nx * I.ldM + (I.nx + I.nu) * I.ldx);
+        const unsigned g = (unsigned)std::min<long long>(4096, (work + 255) / 256);
+        hipLaunchKernelGGL(pack_dynamics_kernel, dim3(g), dim3(256), 0, st, a, b);
+        hipLaunchKernelGGL(factor_leaves_kernel, dim3((unsigned)(I.V - I.Vnl)), dim3(64), 0, st, a, b);
+    }
+    for (int t = max_depth - 1; t >= 0; --t) {
+        const size_t n = level_off[t + 1] - level_off[t];
+        if (n == 0) continue;
+        a.items = (const Item *)bitems.p + level_off[t];
+        hipLaunchKernelGGL(factor_stage_kernel, dim3((unsigned)n), dim3(256), 0, st, a);
+    }
     STOTREE_HIP(hipGetLastError());
     int err = 0;
     STOTREE_HIP(hipMemcpyAsync(&err, berr.p, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -415,6 +595,8 @@ int factor_tree(const tree_desc *t, const problem_data *d, int precondition, hip
         set_error("tree_factor: R-tilde is not positive definite at some node");
         return err;
     }
+    if ((rc = build_schedule(f))) return rc;
+    f->last_info.assign(count, solver_info{});
     guard.ok = true;
     *out = f;
     return STOTREE_OK;

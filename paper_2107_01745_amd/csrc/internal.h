@@ -1,10 +1,17 @@
 // Internal declarations of the stotree HIP library (not part of the ABI).
+//
+// A handle holds a forest: one or more independent scenario trees
+// ("instances"), possibly of different sizes, horizons and nx/nu.  Every
+// per-instance quantity lives in shared pools at an offset recorded in the
+// instance's descriptor, and every kernel works on a flat list of
+// (instance, item) pairs, so one launch covers all instances.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -13,57 +20,91 @@
 namespace stotree {
 
 constexpr int kWave = 64;            // CDNA wavefront width
-constexpr int kWavesPerBlock = 4;    // independent waves per block in sweeps
+constexpr int kWavesPerBlock = 4;    // independent wavefronts per block in chain kernels
 constexpr int kMaxWidth = 256;       // nx + nu supported by the sweep kernels
 
 inline int pad2(int n) { return (n + 1) & ~1; }
 
+// Per-instance sizes and offsets (elements) into the handle's pools.
+struct InstDesc {
+    int nx, nu, N, V, Vnl, sstar, nchains, ldM, ldx, ldu;
+    int sp, cp;                      // offsets into the stage_ptr / child_ptr pools
+    long long Mb, Mf, Kb, Kf, Rn;    // factor pools
+    long long chat, sig, c, sc;      // node-vector pools (chat, c: V*nx; sig: Vnl*nu; sc: V)
+    long long y;                     // first dual row in the concatenated dual vector
+    long long x, u;                  // offsets in the concatenated x [sum V nx], u [sum Vnl nu]
+    long long x0;                    // offset in the concatenated x0 [sum nx]
+    long long m;                     // dual rows of the instance
+};
+
+struct Item {
+    int inst, idx;                   // instance and node / chain index within it
+};
+
 // Everything a sweep launch needs; passed by value to the kernels.
 struct SweepArgs {
-    int nx, nu, N, V, Vnl, sstar, nchains;
-    int ldM, ldx, ldu;                 // padded row lengths (even)
-    const int *stage_ptr, *child_ptr;  // device copies
+    const InstDesc *inst;
+    const Item *items;
+    int nitems;
+    const int *sp, *cp;              // stage_ptr / child_ptr pools (local node ids)
     const double *Mb, *Mf, *Kb, *Kf, *Rn;
-    const double *chat, *sig, *cvec, *sc;  // sc may be null (no preconditioning)
-    const double *x0;  long long x0_rs;    // per right-hand side
-    const double *y;   long long y_rs;
-    double *qhat, *kbuf;                   // work: [nrhs][V][nx], [nrhs][Vnl][nu]
-    long long qhat_rs, kbuf_rs;
-    double *xo; long long xo_s;            // x of non-leaf i at xo + i*xo_s
-    double *xl; long long xl_s;            // x of leaf j at xl + (j-Vnl)*xl_s
-    double *uo; long long uo_s;            // u of non-leaf i at uo + i*uo_s
-    long long xo_rs, uo_rs;                // right-hand-side strides of outputs
+    const double *chat, *sig, *cvec, *sc;   // sc null: no preconditioning
+    const double *x0; long long x0_rs;      // per right-hand side strides
+    const double *y; long long y_rs;
+    double *qhat, *kbuf; long long qhat_rs, kbuf_rs;
+    double *xo, *uo; long long xo_rs, uo_rs;
+    int dual_out;                    // 1: write H x into the dual layout at xo; 0: x at xo, u at uo
     int affine;
-    const int *done;                       // if set and nonzero, the sweep is skipped
+    int t;                           // stage of a per-stage launch
+    const int *done; int done_stride;       // per-instance skip flags (may be null)
+};
+
+// One launch of the per-stage kernels: all (instance, node) pairs of one stage.
+struct LevelPlan {
+    int t;
+    int count;
+    int nw;                          // wavefronts per node
+    Item *items;                     // device
 };
 
 // Solver workspace kept in the handle (allocated at the first solve).
 struct SolverWS {
     int mem = 0;
     int nblocks = 0;
-    double *buf = nullptr;   // one allocation for all vectors
+    double *buf = nullptr;
     size_t bytes = 0;
     double *y[2], *r[2], *hx, *hr2, *d, *S, *Qv, *g[2];
-    double *partials;        // [nblocks][kPartialWidth]
-    double *ctl;             // device control block (scalars)
+    double *partials;                // [kNVMax][nblocks]
+    void *ctl;                       // device array of per-instance control blocks
+    int *blk;                        // device: per block {instance, local block, blocks of the instance}
+    int *ndone;                      // device counter of finished instances
+    std::vector<int> blk_first;      // host: first block of each instance
 };
 
 }  // namespace stotree
 
 struct tree_factors {
-    int nx, nu, N, V, Vnl;
-    long long m, n;
-    int sstar, nchains, precondition;
-    int ldM, ldx, ldu;
-    std::vector<int> stage_ptr;  // host copy
-    int *d_stage_ptr = nullptr, *d_child_ptr = nullptr;
+    int ninst = 0, precondition = 0;
+    std::vector<stotree::InstDesc> inst;    // host copy
+    stotree::InstDesc *d_inst = nullptr;
+    std::vector<int> sp_pool;               // host copy of the stage pointers
+    int *d_sp = nullptr, *d_cp = nullptr;
     double *Mb = nullptr, *Mf = nullptr, *Kb = nullptr, *Kf = nullptr, *Rn = nullptr;
     double *chat = nullptr, *sig = nullptr, *cvec = nullptr, *sc = nullptr;
-    double *lo = nullptr, *hi = nullptr;  // unscaled box rows in the dual layout
+    double *lo = nullptr, *hi = nullptr;    // unscaled box rows in the dual layout
+    long long m_tot = 0, n_tot = 0, x_tot = 0, u_tot = 0, nx_tot = 0, V_tot = 0;
+    int max_width = 0;                      // max nx+nu over instances
+    // schedule of a sweep
+    stotree::Item *chain_items = nullptr;
+    int nchain_items = 0;
+    std::vector<stotree::LevelPlan> levels;  // stages 0..max(s*)-1
+    int trunk_cap = 16;                     // tuned cap on wavefronts per node
+    int chain_order = 1;                    // 1: longest chains first, 0: instance order
     // sweep workspace (grows with nrhs)
     double *qhat = nullptr, *kbuf = nullptr;
     int ws_nrhs = 0;
     stotree::SolverWS sws;
+    std::vector<solver_info> last_info;     // per instance, from the last solve
     size_t bytes = 0;
 };
 
@@ -72,14 +113,15 @@ namespace stotree {
 void set_error(const std::string &msg);
 
 // factor.hip
-int factor_tree(const tree_desc *t, const problem_data *d, int precondition,
-                hipStream_t st, tree_factors **out);
+int factor_forest(int count, const tree_desc *t, const problem_data *d, int precondition,
+                  hipStream_t st, tree_factors **out);
 void free_tree(tree_factors *f);
+int build_schedule(tree_factors *f);
 
 // sweep.hip
 SweepArgs sweep_args(const tree_factors *f, int affine);
 int ensure_sweep_ws(tree_factors *f, int nrhs);
-// One full sweep (Algorithm 3 if a.affine, else Algorithm 4) for nrhs in {1,2}.
+// One full sweep (Algorithm 3 if a.affine, else Algorithm 4), nrhs in {1,2}.
 hipError_t launch_sweep_tree(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st);
 int timing_enable(int on);
 int timing_read(double *ms, long long *count);

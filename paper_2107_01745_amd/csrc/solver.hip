@@ -1,6 +1,9 @@
 // Device-resident dual MINFBE (Algorithm 1) and NAMA (Algorithm 2) of
 // arXiv 2107.01745, Sec. III-B/III-C, in the preconditioned dual variables of
-// Sec. III-E when the handle asks for it.
+// Sec. III-E when the handle asks for it.  A batched handle runs every
+// instance in the same launches: each block of a vector pass belongs to one
+// instance, each instance has its own control block (step, L-BFGS memory,
+// stop flag), and finished instances are skipped by every kernel.
 //
 // Every iteration is a fixed sequence of kernels on the caller's stream; all
 // scalars (residual norms, curvature test, L-BFGS coefficients, the accepted
@@ -47,6 +50,7 @@ constexpr int kNVMax = nv_pair(kMemMax) > kNuCap + 2 ? nv_pair(kMemMax) : kNuCap
 
 struct Ctl {
     int done, status, iter, have_pair;
+    int first_blk, nblk, pad0, pad1;
     int cnt, free_slot, pushes, skips;
     int ls_trials, sweeps_aff, sweeps_hom, accepted_nu;
     int max_iter, mem, nu_max, method;
@@ -61,24 +65,49 @@ struct Ctl {
 };
 
 struct VecArgs {
-    long long m;
-    unsigned nlr;  // rows owned by non-leaf nodes
-    int nxu, nx, Vnl;
+    const InstDesc *inst;
+    const int *blk;  // per block: instance, block within the instance, blocks of the instance
     const double *sc, *lo, *hi;
     Ctl *ctl;
+    int *ndone;
+    long long m_tot;
     double *part;
     int nblocks, method;
     const double *y, *yp, *hx, *rp, *gp, *hr, *hd, *d;
     double *r, *g, *S, *Q, *yn;
 };
 
-__device__ __forceinline__ double row_scale(const VecArgs &a, long long k)
+// The rows a block visits: rows lb*kVB + tid + n*nblk*kVB of its instance.
+struct BlockRows {
+    int b, lb, nb;
+    InstDesc I;
+    unsigned nlr;  // rows owned by non-leaf nodes
+};
+
+__device__ __forceinline__ BlockRows block_rows(const VecArgs &a)
+{
+    BlockRows br;
+    br.b = a.blk[3 * blockIdx.x];
+    br.lb = a.blk[3 * blockIdx.x + 1];
+    br.nb = a.blk[3 * blockIdx.x + 2];
+    br.I = a.inst[br.b];
+    br.nlr = (unsigned)((long long)br.I.Vnl * (br.I.nx + br.I.nu));
+    return br;
+}
+
+// sqrt(pi) of the node owning local row k (1 without preconditioning).
+__device__ __forceinline__ double row_scale(const VecArgs &a, const BlockRows &br, long long k)
 {
     if (!a.sc) return 1.0;
     const unsigned kk = (unsigned)k;
-    const unsigned node = kk < a.nlr ? kk / (unsigned)a.nxu : (unsigned)a.Vnl + (kk - a.nlr) / (unsigned)a.nx;
-    return a.sc[node];
+    const unsigned node = kk < br.nlr ? kk / (unsigned)(br.I.nx + br.I.nu)
+                                      : (unsigned)br.I.Vnl + (kk - br.nlr) / (unsigned)br.I.nx;
+    return a.sc[br.I.sc + node];
 }
+
+#define FOR_BLOCK_ROWS(br, kl, k)                                                             \
+    for (long long kl = (long long)(br).lb * kVB + threadIdx.x, k = (br).I.y + kl; kl < (br).I.m; \
+         kl += (long long)(br).nb * kVB, k = (br).I.y + kl)
 
 __device__ __forceinline__ double clampd(double v, double lo, double hi)
 {
@@ -116,14 +145,15 @@ __device__ void block_store(double (&acc)[NV], int nv, double *part, int nblocks
     }
 }
 
-// Finalize-side reduction of nv slots over all blocks (fixed order) into out.
-__device__ void reduce_partials(const double *part, int nblocks, int nv, double *out)
+// Finalize-side reduction of nv slots over blocks [first, first+count) (fixed
+// order) into out.
+__device__ void reduce_partials(const double *part, int nblocks, int first, int count, int nv, double *out)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int v = w; v < nv; v += nw) {
         const bool mx = v < kNMax;
-        double x = mx ? 0.0 : 0.0;
-        for (int b = lane; b < nblocks; b += 64) {
+        double x = 0.0;
+        for (int b = first + lane; b < first + count; b += 64) {
             const double p = part[(long long)v * nblocks + b];
             x = mx ? fmax(x, p) : x + p;
         }
@@ -139,8 +169,8 @@ __device__ __forceinline__ void pair_dots(const VecArgs &a, long long k, double 
                                           double (&acc)[nv_pair(MEMCAP)])
 {
     if (have_pair) {
-        a.S[(long long)fslot * a.m + k] = s;
-        a.Q[(long long)fslot * a.m + k] = q;
+        a.S[(long long)fslot * a.m_tot + k] = s;
+        a.Q[(long long)fslot * a.m_tot + k] = q;
         acc[PB + 0] += s * q;
         acc[PB + 1] += s * s;
         acc[PB + 2] += q * q;
@@ -151,8 +181,8 @@ __device__ __forceinline__ void pair_dots(const VecArgs &a, long long k, double 
 #pragma unroll
     for (int j = 0; j < MEMCAP; ++j) {
         if (j < cnt) {
-            const double sj = a.S[(long long)order[j] * a.m + k];
-            const double qj = a.Q[(long long)order[j] * a.m + k];
+            const double sj = a.S[(long long)order[j] * a.m_tot + k];
+            const double qj = a.Q[(long long)order[j] * a.m_tot + k];
             if (have_pair) {
                 acc[PB + 6 + 5 * j + 0] += s * qj;
                 acc[PB + 6 + 5 * j + 1] += sj * q;
@@ -168,7 +198,8 @@ __device__ __forceinline__ void pair_dots(const VecArgs &a, long long k, double 
 template <bool PAIR, int MEMCAP>
 __global__ void __launch_bounds__(kVB) resid_kernel(VecArgs a)
 {
-    const Ctl *c = a.ctl;
+    const BlockRows br = block_rows(a);
+    const Ctl *c = a.ctl + br.b;
     if (c->done) return;
     constexpr int NV = PAIR ? nv_pair(MEMCAP) : PB;
     double acc[nv_pair(MEMCAP)];
@@ -180,8 +211,8 @@ __global__ void __launch_bounds__(kVB) resid_kernel(VecArgs a)
     int order[MEMCAP > 0 ? MEMCAP : 1];
 #pragma unroll
     for (int j = 0; j < MEMCAP; ++j) order[j] = c->order[j];
-    for (long long k = blockIdx.x * (long long)kVB + threadIdx.x; k < a.m; k += (long long)a.nblocks * kVB) {
-        const double s = row_scale(a, k);
+    FOR_BLOCK_ROWS(br, kl, k) {
+        const double s = row_scale(a, br, kl);
         const double h = s * a.hx[k];
         const double yk = a.y[k];
         const double z = clampd(yk / lam + h, s * a.lo[k], s * a.hi[k]);
@@ -205,7 +236,8 @@ __global__ void __launch_bounds__(kVB) resid_kernel(VecArgs a)
 template <int MEMCAP>
 __global__ void __launch_bounds__(kVB) grad_kernel(VecArgs a)
 {
-    const Ctl *c = a.ctl;
+    const BlockRows br = block_rows(a);
+    const Ctl *c = a.ctl + br.b;
     if (c->done) return;
     double acc[nv_pair(MEMCAP)];
 #pragma unroll
@@ -216,8 +248,8 @@ __global__ void __launch_bounds__(kVB) grad_kernel(VecArgs a)
     int order[MEMCAP > 0 ? MEMCAP : 1];
 #pragma unroll
     for (int j = 0; j < MEMCAP; ++j) order[j] = c->order[j];
-    for (long long k = blockIdx.x * (long long)kVB + threadIdx.x; k < a.m; k += (long long)a.nblocks * kVB) {
-        const double s = row_scale(a, k);
+    FOR_BLOCK_ROWS(br, kl, k) {
+        const double s = row_scale(a, br, kl);
         const double g = a.r[k] + lam * s * a.hr[k];
         a.g[k] = g;
         const double sv = have_pair ? a.y[k] - a.yp[k] : 0.0;
@@ -230,7 +262,8 @@ __global__ void __launch_bounds__(kVB) grad_kernel(VecArgs a)
 template <int MEMCAP>
 __global__ void __launch_bounds__(kVB) combine_kernel(VecArgs a)
 {
-    const Ctl *c = a.ctl;
+    const BlockRows br = block_rows(a);
+    const Ctl *c = a.ctl + br.b;
     if (c->done) return;
     const int cnt = c->cnt;
     const double gam = c->gamma;
@@ -238,12 +271,12 @@ __global__ void __launch_bounds__(kVB) combine_kernel(VecArgs a)
     double cs[MEMCAP > 0 ? MEMCAP : 1], cq[MEMCAP > 0 ? MEMCAP : 1];
 #pragma unroll
     for (int j = 0; j < MEMCAP; ++j) { order[j] = c->order[j]; cs[j] = c->coefS[j]; cq[j] = c->coefQ[j]; }
-    for (long long k = blockIdx.x * (long long)kVB + threadIdx.x; k < a.m; k += (long long)a.nblocks * kVB) {
+    FOR_BLOCK_ROWS(br, kl, k) {
         double v = gam * a.g[k];
 #pragma unroll
         for (int j = 0; j < MEMCAP; ++j)
             if (j < cnt)
-                v += cs[j] * a.S[(long long)order[j] * a.m + k] + cq[j] * a.Q[(long long)order[j] * a.m + k];
+                v += cs[j] * a.S[(long long)order[j] * a.m_tot + k] + cq[j] * a.Q[(long long)order[j] * a.m_tot + k];
         a.r[k] = -v;  // a.r points at the direction buffer here
     }
 }
@@ -252,7 +285,8 @@ __global__ void __launch_bounds__(kVB) combine_kernel(VecArgs a)
 // the FBE at w(tau_nu) relative to y.
 __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
 {
-    const Ctl *c = a.ctl;
+    const BlockRows br = block_rows(a);
+    const Ctl *c = a.ctl + br.b;
     if (c->done) return;
     const double lam = c->lam;
     const int numax = c->nu_max;
@@ -260,12 +294,12 @@ __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
     double acc[kNuCap + 2];
 #pragma unroll
     for (int v = 0; v < kNuCap + 2; ++v) acc[v] = 0.0;
-    for (long long k = blockIdx.x * (long long)kVB + threadIdx.x; k < a.m; k += (long long)a.nblocks * kVB) {
-        const double s = row_scale(a, k);
+    FOR_BLOCK_ROWS(br, kl, k) {
+        const double s = row_scale(a, br, kl);
         const double lo = s * a.lo[k], hi = s * a.hi[k];
         const double yk = a.y[k], rk = a.rp[k], dk = a.d[k];
         const double ah = s * a.hx[k];
-        const double br = nama ? s * a.hr[k] : 0.0;
+        const double brk = nama ? s * a.hr[k] : 0.0;
         const double bd = s * a.hd[k];
         const double ey = yk * (rk + ah) - 0.5 * lam * rk * rk;
         double tau = 1.0;
@@ -274,7 +308,7 @@ __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
             if (nu <= numax) {
                 const double cr = nama ? -(1.0 - tau) * lam : 0.0;
                 const double dl = cr * rk + tau * dk;     // w - y
-                const double hd = cr * br + tau * bd;     // s H xhat(w - y)
+                const double hd = cr * brk + tau * bd;    // s H xhat(w - y)
                 const double w = yk + dl, hw = ah + hd;
                 const double zw = clampd(w / lam + hw, lo, hi);
                 const double Rw = zw - hw;
@@ -283,23 +317,24 @@ __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
             tau *= 0.5;
         }
     }
-    // slot layout for block_store: no max slots are used here, keep sums
+    // slots [0, kNMax) are the max-reduced ones; the sums follow them
     double packed[kNuCap + 2 + kNMax];
 #pragma unroll
     for (int v = 0; v < kNMax; ++v) packed[v] = 0.0;
 #pragma unroll
     for (int v = 0; v < kNuCap + 2; ++v) packed[kNMax + v] = acc[v];
-    block_store<kNuCap + 2 + kNMax>(packed, kNMax + numax + 1, a.part, a.nblocks);
+    block_store<kNuCap + 2 + kNMax>(packed, kNMax + kNuCap + 1, a.part, a.nblocks);
 }
 
 __global__ void __launch_bounds__(kVB) update_kernel(VecArgs a)
 {
-    const Ctl *c = a.ctl;
+    const BlockRows br = block_rows(a);
+    const Ctl *c = a.ctl + br.b;
     if (c->done) return;
     const double lam = c->lam, tau = c->tau, cr = c->cr;
     const bool nama = a.method == 1;
-    for (long long k = blockIdx.x * (long long)kVB + threadIdx.x; k < a.m; k += (long long)a.nblocks * kVB) {
-        const double s = row_scale(a, k);
+    FOR_BLOCK_ROWS(br, kl, k) {
+        const double s = row_scale(a, br, kl);
         const double dl = cr * a.rp[k] + tau * a.d[k];
         const double hd = (nama ? cr * s * a.hr[k] : 0.0) + tau * s * a.hd[k];
         const double w = a.y[k] + dl, hw = s * a.hx[k] + hd;
@@ -309,7 +344,8 @@ __global__ void __launch_bounds__(kVB) update_kernel(VecArgs a)
 }
 
 // ---------------------------- finalize kernels ---------------------------
-__device__ void finish_residual(Ctl *c, const double *red)
+// One block per instance; lane 0 of the block takes the scalar decisions.
+__device__ void finish_residual(Ctl *c, const double *red, int *ndone)
 {
     c->sweeps_aff++;
     c->res = red[R_MAX];
@@ -318,6 +354,7 @@ __device__ void finish_residual(Ctl *c, const double *red)
     if (red[R_BAD] > 0.0 || !isfinite(red[R_SS])) { c->done = 1; c->status = STOTREE_ERR_NUMERIC; }
     else if (red[R_MAX] <= c->eps) { c->done = 1; c->status = STOTREE_OK; }
     else if (c->iter >= c->max_iter) { c->done = 1; c->status = STOTREE_NOT_CONVERGED; }
+    if (c->done) atomicAdd(ndone, 1);
 }
 
 // Cautious push of the candidate pair (Li and Fukushima: push when
@@ -404,31 +441,35 @@ __device__ void lbfgs_update(Ctl *c, const double *red)
     c->gamma = gam;
 }
 
-__global__ void __launch_bounds__(kVB) fin_resid_kernel(Ctl *c, const double *part, int nblocks, int with_pair)
+__global__ void __launch_bounds__(kVB) fin_resid_kernel(Ctl *ctl, const double *part, int nblocks,
+                                                        int with_pair, int *ndone)
 {
+    Ctl *c = ctl + blockIdx.x;
     if (c->done) return;
     __shared__ double red[kNVMax];
-    reduce_partials(part, nblocks, with_pair ? nv_pair(c->mem) : PB, red);
+    reduce_partials(part, nblocks, c->first_blk, c->nblk, with_pair ? nv_pair(c->mem) : PB, red);
     if (threadIdx.x != 0) return;
-    finish_residual(c, red);
+    finish_residual(c, red, ndone);
     if (!c->done && with_pair) lbfgs_update(c, red);
 }
 
-__global__ void __launch_bounds__(kVB) fin_grad_kernel(Ctl *c, const double *part, int nblocks)
+__global__ void __launch_bounds__(kVB) fin_grad_kernel(Ctl *ctl, const double *part, int nblocks)
 {
+    Ctl *c = ctl + blockIdx.x;
     if (c->done) return;
     __shared__ double red[kNVMax];
-    reduce_partials(part, nblocks, nv_pair(c->mem), red);
+    reduce_partials(part, nblocks, c->first_blk, c->nblk, nv_pair(c->mem), red);
     if (threadIdx.x != 0) return;
     c->sweeps_hom++;
     lbfgs_update(c, red);
 }
 
-__global__ void __launch_bounds__(kVB) fin_ls_kernel(Ctl *c, const double *part, int nblocks)
+__global__ void __launch_bounds__(kVB) fin_ls_kernel(Ctl *ctl, const double *part, int nblocks)
 {
+    Ctl *c = ctl + blockIdx.x;
     if (c->done) return;
     __shared__ double red[kNVMax];
-    reduce_partials(part, nblocks, kNMax + c->nu_max + 1, red);
+    reduce_partials(part, nblocks, c->first_blk, c->nblk, kNMax + c->nu_max + 1, red);
     if (threadIdx.x != 0) return;
     int acc = -1;
     for (int nu = 0; nu <= c->nu_max; ++nu) {
@@ -444,13 +485,30 @@ __global__ void __launch_bounds__(kVB) fin_ls_kernel(Ctl *c, const double *part,
     c->iter++;
 }
 
+// Final dual of every instance into the caller's buffer (buffer 0): the
+// instances whose last iterate sits in buffer 1 are copied.
+__global__ void __launch_bounds__(kVB) gather_final_kernel(VecArgs a)
+{
+    const BlockRows br = block_rows(a);
+    if (!(a.ctl[br.b].iter & 1)) return;
+    FOR_BLOCK_ROWS(br, kl, k) a.yn[k] = a.y[k];
+}
+
 // ----------------------------- power iteration ---------------------------
+__global__ void __launch_bounds__(kVB) power_init_kernel(VecArgs a)
+{
+    const BlockRows br = block_rows(a);
+    const double v = 1.0 / sqrt((double)br.I.m);
+    FOR_BLOCK_ROWS(br, kl, k) a.yn[k] = v;
+}
+
 __global__ void __launch_bounds__(kVB) power_step_kernel(VecArgs a)
 {
     // w = -s H xhat(s v) (the dual Hessian applied to v), slots: <v,w>, ||w||^2
+    const BlockRows br = block_rows(a);
     double acc[kNMax + 2] = {0.0, 0.0, 0.0, 0.0};
-    for (long long k = blockIdx.x * (long long)kVB + threadIdx.x; k < a.m; k += (long long)a.nblocks * kVB) {
-        const double s = row_scale(a, k);
+    FOR_BLOCK_ROWS(br, kl, k) {
+        const double s = row_scale(a, br, kl);
         const double w = -s * a.hx[k];
         acc[kNMax + 0] += a.y[k] * w;
         acc[kNMax + 1] += w * w;
@@ -459,10 +517,11 @@ __global__ void __launch_bounds__(kVB) power_step_kernel(VecArgs a)
     block_store<kNMax + 2>(acc, kNMax + 2, a.part, a.nblocks);
 }
 
-__global__ void __launch_bounds__(kVB) power_fin_kernel(Ctl *c, const double *part, int nblocks)
+__global__ void __launch_bounds__(kVB) power_fin_kernel(Ctl *ctl, const double *part, int nblocks)
 {
+    Ctl *c = ctl + blockIdx.x;
     __shared__ double red[kNVMax];
-    reduce_partials(part, nblocks, kNMax + 2, red);
+    reduce_partials(part, nblocks, c->first_blk, c->nblk, kNMax + 2, red);
     if (threadIdx.x != 0) return;
     c->L = red[kNMax + 0];
     const double nw = sqrt(red[kNMax + 1]);
@@ -471,27 +530,32 @@ __global__ void __launch_bounds__(kVB) power_fin_kernel(Ctl *c, const double *pa
 
 __global__ void __launch_bounds__(kVB) power_scale_kernel(VecArgs a)
 {
-    const double inv = a.ctl->inv_norm;
-    for (long long k = blockIdx.x * (long long)kVB + threadIdx.x; k < a.m; k += (long long)a.nblocks * kVB)
-        a.yn[k] = a.r[k] * inv;
-}
-
-__global__ void fill_kernel(double *v, long long n, double val)
-{
-    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
-        v[k] = val;
+    const BlockRows br = block_rows(a);
+    const double inv = a.ctl[br.b].inv_norm;
+    FOR_BLOCK_ROWS(br, kl, k) a.yn[k] = a.r[k] * inv;
 }
 
 // ------------------------------- host side -------------------------------
 int ensure_solver_ws(tree_factors *f, int mem)
 {
     SolverWS &w = f->sws;
-    const long long m = f->m;
-    const int nblocks = (int)std::min<long long>(1024, (m + kVB - 1) / kVB);
     if (w.buf && w.mem >= mem) return STOTREE_OK;
     if (w.buf) { (void)hipFree(w.buf); w.buf = nullptr; w.bytes = 0; }
+    // blocks per instance: one per 1024 rows, at most 1024
+    std::vector<int> blk;
+    w.blk_first.assign(f->ninst, 0);
+    for (int b = 0; b < f->ninst; ++b) {
+        const long long m = f->inst[b].m;
+        const int nb = (int)std::max<long long>(1, std::min<long long>(1024, (m + 4 * kVB - 1) / (4 * kVB)));
+        w.blk_first[b] = (int)(blk.size() / 3);
+        for (int l = 0; l < nb; ++l) { blk.push_back(b); blk.push_back(l); blk.push_back(nb); }
+    }
+    const int nblocks = (int)(blk.size() / 3);
+    const long long m = f->m_tot;
     const long long nvec = 9 + 2LL * (mem + 1);
-    const size_t bytes = sizeof(double) * ((size_t)nvec * m + (size_t)kNVMax * nblocks) + sizeof(Ctl) + 256;
+    const size_t vec_bytes = sizeof(double) * ((size_t)nvec * m + (size_t)kNVMax * nblocks);
+    const size_t ctl_bytes = sizeof(Ctl) * (size_t)f->ninst;
+    const size_t bytes = vec_bytes + ctl_bytes + sizeof(int) * (blk.size() + 1) + 512;
     STOTREE_HIP(hipMalloc(&w.buf, bytes));
     w.bytes = bytes;
     w.mem = mem;
@@ -509,39 +573,41 @@ int ensure_solver_ws(tree_factors *f, int mem)
     w.Qv = p; p += (long long)(mem + 1) * m;
     w.partials = p; p += (size_t)kNVMax * nblocks;
     w.ctl = p;
+    char *q = reinterpret_cast<char *>(p) + ctl_bytes;
+    w.blk = reinterpret_cast<int *>(q);
+    w.ndone = w.blk + blk.size();
+    STOTREE_HIP(hipMemcpy(w.blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice));
     return STOTREE_OK;
 }
 
 VecArgs vec_args(const tree_factors *f)
 {
     VecArgs a{};
-    a.m = f->m;
-    a.nlr = (unsigned)((long long)f->Vnl * (f->nx + f->nu));
-    a.nxu = f->nx + f->nu;
-    a.nx = f->nx;
-    a.Vnl = f->Vnl;
+    a.inst = f->d_inst;
+    a.blk = f->sws.blk;
     a.sc = f->precondition ? f->sc : nullptr;
     a.lo = f->lo;
     a.hi = f->hi;
     a.ctl = reinterpret_cast<Ctl *>(f->sws.ctl);
+    a.ndone = f->sws.ndone;
+    a.m_tot = f->m_tot;
     a.part = f->sws.partials;
     a.nblocks = f->sws.nblocks;
     return a;
 }
 
-// Sweep arguments writing H x (dual layout) for nrhs right-hand sides whose
+// Sweep arguments writing H x (dual layout) for right-hand sides whose
 // inputs/outputs are at (y, y + y_rs) and (out, out + o_rs).
 SweepArgs dual_layout_sweep(const tree_factors *f, int affine, const double *x0, const double *y,
-                            long long y_rs, double *out, long long o_rs, const int *done)
+                            long long y_rs, double *out, long long o_rs, const Ctl *ctl)
 {
     SweepArgs a = sweep_args(f, affine);
     a.x0 = x0; a.x0_rs = 0;
     a.y = y; a.y_rs = y_rs;
-    a.xo = out; a.xo_s = f->nx + f->nu;
-    a.xl = out + (long long)f->Vnl * (f->nx + f->nu); a.xl_s = f->nx;
-    a.uo = out + f->nx; a.uo_s = f->nx + f->nu;
-    a.xo_rs = o_rs; a.uo_rs = o_rs;
-    a.done = done;
+    a.xo = out; a.xo_rs = o_rs;
+    a.dual_out = 1;
+    a.done = ctl ? &ctl->done : nullptr;
+    a.done_stride = (int)(sizeof(Ctl) / sizeof(int));
     return a;
 }
 
@@ -553,54 +619,46 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
     VecArgs a = vec_args(f);
     a.method = method;
     Ctl *ctl = a.ctl;
-    const int *done = &ctl->done;
-    const dim3 grid(a.nblocks), blk(kVB);
+    const dim3 grid(a.nblocks), blk(kVB), fgrid(f->ninst);
     double *y = ybuf[k & 1], *yn = ybuf[(k + 1) & 1];
     double *r = w.r[k & 1], *rp = w.r[(k + 1) & 1];
     double *g = w.g[k & 1], *gp = w.g[(k + 1) & 1];
-    double *hr = w.hr2, *hd = w.hr2 + f->m;
+    double *hr = w.hr2, *hd = w.hr2 + f->m_tot;
     hipError_t e;
     // x(y) -> H x
-    if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 1, x0, y, 0, w.hx, 0, done), 1, st))) return e;
+    if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 1, x0, y, 0, w.hx, 0, ctl), 1, st))) return e;
     a.y = y; a.yp = yn; a.hx = w.hx; a.rp = rp; a.r = r;
     a.S = w.S; a.Q = w.Qv;
     if (method == 1) {
         hipLaunchKernelGGL((resid_kernel<true, MEMCAP>), grid, blk, 0, st, a);
-        hipLaunchKernelGGL(fin_resid_kernel, dim3(1), blk, 0, st, ctl, a.part, a.nblocks, 1);
+        hipLaunchKernelGGL(fin_resid_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, 1, a.ndone);
         VecArgs cb = a;
         cb.g = r;           // g = R
         cb.r = w.d;         // output direction
-        cb.S = w.S; cb.Q = w.Qv;
         hipLaunchKernelGGL((combine_kernel<MEMCAP>), grid, blk, 0, st, cb);
         // x-hat(r) and x-hat(d) in one two-right-hand-side sweep (p-NAMA)
-        if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, r, w.d - r, hr, hd - hr, done), 2, st)))
+        if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, r, w.d - r, hr, hd - hr, ctl), 2, st)))
             return e;
-        VecArgs la = vec_args(f);
-        la.method = 1;
-        la.y = y; la.rp = r; la.d = w.d; la.hx = w.hx; la.hr = hr; la.hd = hd; la.yn = yn;
-        hipLaunchKernelGGL(ls_kernel, grid, blk, 0, st, la);
-        hipLaunchKernelGGL(fin_ls_kernel, dim3(1), blk, 0, st, ctl, a.part, a.nblocks);
-        hipLaunchKernelGGL(update_kernel, grid, blk, 0, st, la);
     } else {
         hipLaunchKernelGGL((resid_kernel<false, 0>), grid, blk, 0, st, a);
-        hipLaunchKernelGGL(fin_resid_kernel, dim3(1), blk, 0, st, ctl, a.part, a.nblocks, 0);
+        hipLaunchKernelGGL(fin_resid_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, 0, a.ndone);
         // grad phi = R + lambda s H xhat(s R)
-        if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, r, 0, hr, 0, done), 1, st))) return e;
+        if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, r, 0, hr, 0, ctl), 1, st))) return e;
         VecArgs ga = a;
-        ga.hr = hr; ga.g = g; ga.gp = gp; ga.S = w.S; ga.Q = w.Qv;
+        ga.hr = hr; ga.g = g; ga.gp = gp;
         hipLaunchKernelGGL((grad_kernel<MEMCAP>), grid, blk, 0, st, ga);
-        hipLaunchKernelGGL(fin_grad_kernel, dim3(1), blk, 0, st, ctl, a.part, a.nblocks);
+        hipLaunchKernelGGL(fin_grad_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks);
         VecArgs cb = a;
-        cb.g = g; cb.r = w.d; cb.S = w.S; cb.Q = w.Qv;
+        cb.g = g; cb.r = w.d;
         hipLaunchKernelGGL((combine_kernel<MEMCAP>), grid, blk, 0, st, cb);
-        if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, w.d, 0, hd, 0, done), 1, st))) return e;
-        VecArgs la = vec_args(f);
-        la.method = 0;
-        la.y = y; la.rp = r; la.d = w.d; la.hx = w.hx; la.hr = hr; la.hd = hd; la.yn = yn;
-        hipLaunchKernelGGL(ls_kernel, grid, blk, 0, st, la);
-        hipLaunchKernelGGL(fin_ls_kernel, dim3(1), blk, 0, st, ctl, a.part, a.nblocks);
-        hipLaunchKernelGGL(update_kernel, grid, blk, 0, st, la);
+        if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, w.d, 0, hd, 0, ctl), 1, st))) return e;
     }
+    VecArgs la = vec_args(f);
+    la.method = method;
+    la.y = y; la.rp = r; la.d = w.d; la.hx = w.hx; la.hr = hr; la.hd = hd; la.yn = yn;
+    hipLaunchKernelGGL(ls_kernel, grid, blk, 0, st, la);
+    hipLaunchKernelGGL(fin_ls_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks);
+    hipLaunchKernelGGL(update_kernel, grid, blk, 0, st, la);
     return hipGetLastError();
 }
 
@@ -613,6 +671,45 @@ IterFn pick_iter(int mem)
     return enqueue_iteration<16>;
 }
 
+// Power iteration on every instance (per-instance normalisation); leaves
+// L_b in the control blocks.
+int power_iterations(tree_factors *f, int iters, hipStream_t st)
+{
+    const SolverWS &w = f->sws;
+    VecArgs a = vec_args(f);
+    const dim3 grid(a.nblocks), blk(kVB), fgrid(f->ninst);
+    double *v = w.g[0], *wv = w.g[1], *hv = w.hx;
+    VecArgs pa = a;
+    pa.yn = v;
+    hipLaunchKernelGGL(power_init_kernel, grid, blk, 0, st, pa);
+    for (int it = 0; it < iters; ++it) {
+        hipError_t e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, v, 0, hv, 0, nullptr), 1, st);
+        if (e != hipSuccess) { set_error(std::string("dual_lipschitz: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
+        pa.y = v; pa.hx = hv; pa.r = wv; pa.yn = v;
+        hipLaunchKernelGGL(power_step_kernel, grid, blk, 0, st, pa);
+        hipLaunchKernelGGL(power_fin_kernel, fgrid, blk, 0, st, a.ctl, a.part, a.nblocks);
+        hipLaunchKernelGGL(power_scale_kernel, grid, blk, 0, st, pa);
+    }
+    STOTREE_HIP(hipGetLastError());
+    return STOTREE_OK;
+}
+
+// Host copy of the control blocks with the block ranges filled in.
+std::vector<Ctl> fresh_ctl(const tree_factors *f)
+{
+    std::vector<Ctl> h(f->ninst);
+    for (int b = 0; b < f->ninst; ++b) {
+        Ctl &c = h[b];
+        std::memset(&c, 0, sizeof(Ctl));
+        c.first_blk = f->sws.blk_first[b];
+        const int next = b + 1 < f->ninst ? f->sws.blk_first[b + 1] : f->sws.nblocks;
+        c.nblk = next - c.first_blk;
+        c.gamma = 1.0;
+        c.status = STOTREE_NOT_CONVERGED;
+    }
+    return h;
+}
+
 }  // namespace
 
 int lipschitz(const tree_factors *fc, int iters, double *L, hipStream_t st)
@@ -621,25 +718,13 @@ int lipschitz(const tree_factors *fc, int iters, double *L, hipStream_t st)
     int rc = ensure_solver_ws(f, f->sws.buf ? f->sws.mem : 1);
     if (rc) return rc;
     if ((rc = ensure_sweep_ws(f, 2))) return rc;
-    const SolverWS &w = f->sws;
-    VecArgs a = vec_args(f);
-    const dim3 grid(a.nblocks), blk(kVB);
-    double *v = w.g[0], *wv = w.g[1], *hv = w.hx;
-    hipLaunchKernelGGL(fill_kernel, dim3(1024), blk, 0, st, v, f->m, 1.0 / std::sqrt((double)f->m));
-    for (int it = 0; it < iters; ++it) {
-        hipError_t e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, v, 0, hv, 0, nullptr), 1, st);
-        if (e != hipSuccess) { set_error(std::string("dual_lipschitz: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
-        VecArgs pa = a;
-        pa.y = v; pa.hx = hv; pa.r = wv; pa.yn = v;
-        hipLaunchKernelGGL(power_step_kernel, grid, blk, 0, st, pa);
-        hipLaunchKernelGGL(power_fin_kernel, dim3(1), blk, 0, st, a.ctl, a.part, a.nblocks);
-        hipLaunchKernelGGL(power_scale_kernel, grid, blk, 0, st, pa);
-    }
-    STOTREE_HIP(hipGetLastError());
-    double Lh = 0.0;
-    STOTREE_HIP(hipMemcpyAsync(&Lh, &a.ctl->L, sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<Ctl> h = fresh_ctl(f);
+    Ctl *dctl = reinterpret_cast<Ctl *>(f->sws.ctl);
+    STOTREE_HIP(hipMemcpyAsync(dctl, h.data(), sizeof(Ctl) * h.size(), hipMemcpyHostToDevice, st));
+    if ((rc = power_iterations(f, iters, st))) return rc;
+    STOTREE_HIP(hipMemcpyAsync(h.data(), dctl, sizeof(Ctl) * h.size(), hipMemcpyDeviceToHost, st));
     STOTREE_HIP(hipStreamSynchronize(st));
-    *L = Lh;
+    for (int b = 0; b < f->ninst; ++b) L[b] = h[b].L;
     return STOTREE_OK;
 }
 
@@ -657,56 +742,81 @@ int solve(const tree_factors *fc, const double *x0, const solver_opts *opts_in, 
     int rc = ensure_solver_ws(f, o.mem);
     if (rc) return rc;
     if ((rc = ensure_sweep_ws(f, 2))) return rc;
-    double lam = o.lambda;
-    if (lam == 0.0) {
-        double L = 0.0;
-        if ((rc = lipschitz(f, 100, &L, st))) return rc;
-        if (!(L > 0.0) || !std::isfinite(L)) { set_error("solve: could not estimate L"); return STOTREE_ERR_NUMERIC; }
-        lam = 1.0 / (1.1 * L);
-    }
-    Ctl h{};
-    h.done = 0; h.status = STOTREE_NOT_CONVERGED; h.iter = 0; h.have_pair = 0;
-    h.cnt = 0; h.free_slot = 0;
-    h.max_iter = o.max_iter; h.mem = o.mem; h.nu_max = o.nu_max; h.method = method;
-    h.lam = lam; h.eps = o.eps; h.eps_curv = o.eps_curv; h.gamma = 1.0;
     const SolverWS &w = f->sws;
     Ctl *dctl = reinterpret_cast<Ctl *>(w.ctl);
-    STOTREE_HIP(hipMemcpyAsync(dctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    std::vector<Ctl> h = fresh_ctl(f);
+    std::vector<double> lam(f->ninst, o.lambda);
+    if (o.lambda == 0.0) {
+        std::vector<double> L(f->ninst);
+        if ((rc = lipschitz(f, 100, L.data(), st))) return rc;
+        for (int b = 0; b < f->ninst; ++b) {
+            if (!(L[b] > 0.0) || !std::isfinite(L[b])) {
+                set_error("solve: could not estimate L of instance " + std::to_string(b));
+                return STOTREE_ERR_NUMERIC;
+            }
+            lam[b] = 1.0 / (1.1 * L[b]);
+        }
+    }
+    for (int b = 0; b < f->ninst; ++b) {
+        Ctl &c = h[b];
+        c.max_iter = o.max_iter; c.mem = o.mem; c.nu_max = o.nu_max; c.method = method;
+        c.lam = lam[b]; c.eps = o.eps; c.eps_curv = o.eps_curv;
+    }
+    STOTREE_HIP(hipMemcpyAsync(dctl, h.data(), sizeof(Ctl) * h.size(), hipMemcpyHostToDevice, st));
+    STOTREE_HIP(hipMemsetAsync(w.ndone, 0, sizeof(int), st));
     double *ybuf[2] = {y_io, w.y[1]};
     IterFn iter = pick_iter(o.mem);
-    int k = 0, done = 0;
-    while (!done && k <= o.max_iter) {
+    int k = 0, ndone = 0;
+    while (ndone < f->ninst && k <= o.max_iter) {
         for (int c = 0; c < o.check_every && k <= o.max_iter; ++c, ++k) {
             hipError_t e = iter(f, x0, ybuf, k, method, st);
             if (e != hipSuccess) { set_error(std::string("solve: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
         }
-        STOTREE_HIP(hipMemcpyAsync(&done, &dctl->done, sizeof(int), hipMemcpyDeviceToHost, st));
+        STOTREE_HIP(hipMemcpyAsync(&ndone, w.ndone, sizeof(int), hipMemcpyDeviceToHost, st));
         STOTREE_HIP(hipStreamSynchronize(st));
     }
-    STOTREE_HIP(hipMemcpyAsync(&h, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    STOTREE_HIP(hipStreamSynchronize(st));
-    double *yf = ybuf[h.iter & 1];
-    if (yf != y_io) STOTREE_HIP(hipMemcpyAsync(y_io, yf, sizeof(double) * f->m, hipMemcpyDeviceToDevice, st));
-    // x(y) at the returned dual, in the caller's layout
+    // last iterate of every instance into y_io, then x(y) in the caller's layout
+    VecArgs ga = vec_args(f);
+    ga.y = w.y[1]; ga.yn = y_io;
+    hipLaunchKernelGGL(gather_final_kernel, dim3(ga.nblocks), dim3(kVB), 0, st, ga);
     SweepArgs a = sweep_args(f, 1);
     a.x0 = x0; a.y = y_io;
-    a.xo = x; a.xo_s = f->nx; a.xl = x + (long long)f->Vnl * f->nx; a.xl_s = f->nx;
-    a.uo = u; a.uo_s = f->nu;
+    a.xo = x; a.uo = u; a.dual_out = 0;
     hipError_t e = launch_sweep_tree(f, a, 1, st);
     if (e != hipSuccess) { set_error(std::string("solve: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
+    STOTREE_HIP(hipMemcpyAsync(h.data(), dctl, sizeof(Ctl) * h.size(), hipMemcpyDeviceToHost, st));
     STOTREE_HIP(hipStreamSynchronize(st));
-    info->iters = h.iter;
-    info->sweeps_affine = h.sweeps_aff + 1;
-    info->sweeps_hom = h.sweeps_hom;
-    info->ls_trials = h.ls_trials;
-    info->lbfgs_push = h.pushes;
-    info->lbfgs_skip = h.skips;
-    info->status = h.status;
-    info->res_scaled_inf = h.res;
-    info->res_unscaled_inf = h.resu;
-    info->lambda = lam;
-    if (h.status == STOTREE_ERR_NUMERIC) set_error("solve: non-finite values in the iterates");
-    return h.status;
+    solver_info agg{};
+    agg.status = STOTREE_OK;
+    for (int b = 0; b < f->ninst; ++b) {
+        const Ctl &c = h[b];
+        solver_info &in = f->last_info[b];
+        in = solver_info{};
+        in.iters = c.iter;
+        in.sweeps_affine = c.sweeps_aff + 1;
+        in.sweeps_hom = c.sweeps_hom;
+        in.ls_trials = c.ls_trials;
+        in.lbfgs_push = c.pushes;
+        in.lbfgs_skip = c.skips;
+        in.status = c.status;
+        in.res_scaled_inf = c.res;
+        in.res_unscaled_inf = c.resu;
+        in.lambda = c.lam;
+        agg.iters = std::max(agg.iters, in.iters);
+        agg.sweeps_affine = std::max(agg.sweeps_affine, in.sweeps_affine);
+        agg.sweeps_hom = std::max(agg.sweeps_hom, in.sweeps_hom);
+        agg.ls_trials += in.ls_trials;
+        agg.lbfgs_push += in.lbfgs_push;
+        agg.lbfgs_skip += in.lbfgs_skip;
+        agg.res_scaled_inf = std::max(agg.res_scaled_inf, in.res_scaled_inf);
+        agg.res_unscaled_inf = std::max(agg.res_unscaled_inf, in.res_unscaled_inf);
+        if (in.status < 0) agg.status = std::min(agg.status, in.status);
+        else if (agg.status >= 0 && in.status == STOTREE_NOT_CONVERGED) agg.status = STOTREE_NOT_CONVERGED;
+    }
+    agg.lambda = h[0].lam;
+    *info = agg;
+    if (agg.status == STOTREE_ERR_NUMERIC) set_error("solve: non-finite values in the iterates");
+    return agg.status;
 }
 
 }  // namespace stotree

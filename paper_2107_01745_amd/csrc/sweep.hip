@@ -17,6 +17,10 @@
 // under the preconditioning of Sec. III-E (1 otherwise).  Algorithm 4 drops
 // pi r, chat, c and uses x_0 = 0.
 //
+// Forest.  A handle may hold many independent trees of different sizes; every
+// launch walks a flat work list of (instance, node) or (instance, chain)
+// pairs and reads the instance's sizes and pool offsets from its descriptor.
+//
 // Mapping.  One wavefront per node (per chain, below).  Each lane owns two
 // adjacent output entries; matrices are stored in the orientation of the pass
 // that reads them, so every row of a matrix is one contiguous, 16-byte-aligned
@@ -26,6 +30,8 @@
 // chains, each walked by one wavefront through all its stages with qhat / x
 // carried in LDS, so those stages need no grid-wide synchronisation.  Stages
 // above s* are launched stage by stage.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace stotree {
@@ -39,18 +45,36 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ long long off_nl(const SweepArgs &a, int i)
+// Dual-layout offset of node i inside its instance.
+__device__ __forceinline__ long long dual_off(const InstDesc &I, int i)
 {
-    return (long long)i * (a.nx + a.nu);
+    return i < I.Vnl ? (long long)i * (I.nx + I.nu) : (long long)I.Vnl * I.nu + (long long)i * I.nx;
 }
-__device__ __forceinline__ long long off_l(const SweepArgs &a, int j)
+__device__ __forceinline__ const double *y_ptr(const SweepArgs &a, const InstDesc &I, int k, int i)
 {
-    return (long long)a.Vnl * a.nu + (long long)j * a.nx;
+    return a.y + k * a.y_rs + I.y + dual_off(I, i);
 }
-__device__ __forceinline__ double *x_ptr(const SweepArgs &a, int k, int i)
+__device__ __forceinline__ double *x_ptr(const SweepArgs &a, const InstDesc &I, int k, int i)
 {
-    return (i < a.Vnl ? a.xo + (long long)i * a.xo_s : a.xl + (long long)(i - a.Vnl) * a.xl_s) +
-           (long long)k * a.xo_rs;
+    return a.dual_out ? a.xo + k * a.xo_rs + I.y + dual_off(I, i)
+                      : a.xo + k * a.xo_rs + I.x + (long long)i * I.nx;
+}
+__device__ __forceinline__ double *u_ptr(const SweepArgs &a, const InstDesc &I, int k, int i)
+{
+    return a.dual_out ? a.xo + k * a.xo_rs + I.y + (long long)i * (I.nx + I.nu) + I.nx
+                      : a.uo + k * a.uo_rs + I.u + (long long)i * I.nu;
+}
+__device__ __forceinline__ double *qhat_ptr(const SweepArgs &a, const InstDesc &I, int k, int i)
+{
+    return a.qhat + k * a.qhat_rs + I.x + (long long)i * I.nx;
+}
+__device__ __forceinline__ double *kbuf_ptr(const SweepArgs &a, const InstDesc &I, int k, int i)
+{
+    return a.kbuf + k * a.kbuf_rs + I.u + (long long)i * I.nu;
+}
+__device__ __forceinline__ bool skipped(const SweepArgs &a, int b)
+{
+    return a.done && a.done[(long long)b * a.done_stride];
 }
 
 // acc[k][ch][e] += sum_{r0<=r<r1} M[r][c] * v_k[r] for the lane's columns
@@ -158,89 +182,77 @@ __device__ __forceinline__ void zero(double (&acc)[NRHS][CH][2])
         for (int ch = 0; ch < CH; ++ch) acc[k][ch][0] = acc[k][ch][1] = 0.0;
 }
 
-// LDS carve-up per wave: qx [NRHS][ldM] (qhat or [x;u]), as [NRHS][ldM],
-// gs [NRHS][ldu].
+// Per-wave LDS of the chain kernels: qx [NRHS][ldq] (qhat or [x;u]), as
+// [NRHS][ldq], gs [NRHS][ldq], with ldq the largest padded width.
 struct WaveLds {
     double *qx, *as, *gs;
     int ldq;
 };
 
-__device__ __forceinline__ WaveLds wave_lds(const SweepArgs &a, int nrhs, int wave)
+__device__ __forceinline__ WaveLds wave_lds(int ldq, int nrhs, int wave)
 {
     extern __shared__ double lds[];
-    const int per = nrhs * (2 * a.ldM + a.ldu);
     WaveLds w;
-    w.qx = lds + wave * per;
-    w.as = w.qx + nrhs * a.ldM;
-    w.gs = w.as + nrhs * a.ldM;
-    w.ldq = a.ldM;
+    w.qx = lds + wave * 3 * nrhs * ldq;
+    w.as = w.qx + nrhs * ldq;
+    w.gs = w.as + nrhs * ldq;
+    w.ldq = ldq;
     return w;
 }
 
-// Backward step of non-leaf node i.  If child_in_lds, qhat of the (single)
-// child is already in L.qx; otherwise each child's qhat is staged from the
-// leaf data or from the global qhat buffer.  The result qhat_i is left in
-// L.qx and, if store_q, written to the global buffer; k_i always goes to kbuf.
+// Backward step of non-leaf node i of instance I by one wavefront.  If
+// child_in_lds, qhat of the (single) child is already in L.qx; otherwise each
+// child's qhat is staged from the leaf data or from the global qhat buffer.
+// The result qhat_i is left in L.qx and, if store_q, written to the global
+// buffer; k_i always goes to kbuf.
 template <int NRHS, int CH>
-__device__ void bwd_node(const SweepArgs &a, int i, const WaveLds &L, bool child_in_lds,
-                         bool store_q, int lane)
+__device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const WaveLds &L,
+                         bool child_in_lds, bool store_q, int lane)
 {
-    const int nx = a.nx, nu = a.nu, W = nx + nu;
+    const int nx = I.nx, nu = I.nu, W = nx + nu;
+    const int *cp = a.cp + I.cp;
     double acc[NRHS][CH][2];
     zero(acc);
-    const int j0 = a.child_ptr[i], j1 = a.child_ptr[i + 1];
+    const int j0 = cp[i], j1 = cp[i + 1];
     for (int j = j0; j < j1; ++j) {
         if (!child_in_lds) {
-            if (j >= a.Vnl) {
-                const double sj = a.sc ? a.sc[j] : 1.0;
+            if (j >= I.Vnl) {
+                const double sj = a.sc ? a.sc[I.sc + j] : 1.0;
                 for (int r = lane; r < nx; r += kWave)
 #pragma unroll
                     for (int k = 0; k < NRHS; ++k)
-                        L.qx[k * L.ldq + r] = sj * a.y[k * a.y_rs + off_l(a, j) + r] +
-                                              (a.affine ? a.chat[(long long)j * nx + r] : 0.0);
+                        L.qx[k * L.ldq + r] = sj * y_ptr(a, I, k, j)[r] +
+                                              (a.affine ? a.chat[I.chat + (long long)j * nx + r] : 0.0);
             } else {
                 for (int r = lane; r < nx; r += kWave)
 #pragma unroll
-                    for (int k = 0; k < NRHS; ++k)
-                        L.qx[k * L.ldq + r] = a.qhat[k * a.qhat_rs + (long long)j * nx + r];
+                    for (int k = 0; k < NRHS; ++k) L.qx[k * L.ldq + r] = qhat_ptr(a, I, k, j)[r];
             }
             wave_sync();
         }
-        gemv_rows<NRHS, CH>(a.Mb + (long long)j * nx * a.ldM, a.ldM, 0, nx, W, L.qx, L.ldq, acc, lane);
+        gemv_rows<NRHS, CH>(a.Mb + I.Mb + (long long)j * nx * I.ldM, I.ldM, 0, nx, W, L.qx, L.ldq, acc, lane);
         wave_sync();
     }
-    // scatter [sum A'q ; sum B'q] to LDS
-#pragma unroll
-    for (int ch = 0; ch < CH; ++ch) {
-        const int c0 = 2 * lane + 128 * ch;
-        if (c0 < W) {
-#pragma unroll
-            for (int k = 0; k < NRHS; ++k) {
-                L.as[k * a.ldM + c0] = acc[k][ch][0];
-                L.as[k * a.ldM + c0 + 1] = acc[k][ch][1];
-            }
-        }
-    }
+    store_acc<NRHS, CH>(L.as, L.ldq, 0, W, acc, lane);  // [sum A'q ; sum B'q]
     wave_sync();
-    const double si = a.sc ? a.sc[i] : 1.0;
+    const double si = a.sc ? a.sc[I.sc + i] : 1.0;
     for (int c = lane; c < nu; c += kWave)
 #pragma unroll
         for (int k = 0; k < NRHS; ++k)
-            L.gs[k * a.ldu + c] = L.as[k * a.ldM + nx + c] +
-                                  si * a.y[k * a.y_rs + off_nl(a, i) + nx + c] +
-                                  (a.affine ? a.sig[(long long)i * nu + c] : 0.0);
+            L.gs[k * L.ldq + c] = L.as[k * L.ldq + nx + c] + si * y_ptr(a, I, k, i)[nx + c] +
+                                  (a.affine ? a.sig[I.sig + (long long)i * nu + c] : 0.0);
     wave_sync();
     double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
     zero(kacc);
     zero(qacc);
-    gemv_rows<NRHS, CH>(a.Rn + (long long)i * nu * a.ldu, a.ldu, 0, nu, nu, L.gs, a.ldu, kacc, lane);
-    gemv_rows<NRHS, CH>(a.Kb + (long long)i * nu * a.ldx, a.ldx, 0, nu, nx, L.gs, a.ldu, qacc, lane);
+    gemv_rows<NRHS, CH>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
+    gemv_rows<NRHS, CH>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
         const int c0 = 2 * lane + 128 * ch;
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
-            double *kb = a.kbuf + k * a.kbuf_rs + (long long)i * nu;
+            double *kb = kbuf_ptr(a, I, k, i);
             if (c0 < nu) kb[c0] = kacc[k][ch][0];
             if (c0 + 1 < nu) kb[c0 + 1] = kacc[k][ch][1];
         }
@@ -257,8 +269,8 @@ __device__ void bwd_node(const SweepArgs &a, int i, const WaveLds &L, bool child
             for (int k = 0; k < NRHS; ++k) {
                 double v = 0.0;
                 if (c < nx)
-                    v = L.as[k * a.ldM + c] + si * a.y[k * a.y_rs + off_nl(a, i) + c] +
-                        (a.affine ? a.chat[(long long)i * nx + c] : 0.0) + qacc[k][ch][e];
+                    v = L.as[k * L.ldq + c] + si * y_ptr(a, I, k, i)[c] +
+                        (a.affine ? a.chat[I.chat + (long long)i * nx + c] : 0.0) + qacc[k][ch][e];
                 qv[k][ch][e] = v;
             }
         }
@@ -274,7 +286,7 @@ __device__ void bwd_node(const SweepArgs &a, int i, const WaveLds &L, bool child
 #pragma unroll
                 for (int k = 0; k < NRHS; ++k) {
                     L.qx[k * L.ldq + c] = qv[k][ch][e];
-                    if (store_q) a.qhat[k * a.qhat_rs + (long long)i * nx + c] = qv[k][ch][e];
+                    if (store_q) qhat_ptr(a, I, k, i)[c] = qv[k][ch][e];
                 }
             }
         }
@@ -286,12 +298,14 @@ __device__ void bwd_node(const SweepArgs &a, int i, const WaveLds &L, bool child
 // children's x_j to the outputs; for a single-child chain the child's x is
 // left in L.qx.
 template <int NRHS, int CH>
-__device__ void fwd_node(const SweepArgs &a, int i, const WaveLds &L, bool keep_child, int lane)
+__device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const WaveLds &L, bool keep_child,
+                         int lane)
 {
-    const int nx = a.nx, nu = a.nu;
+    const int nx = I.nx, nu = I.nu;
+    const int *cp = a.cp + I.cp;
     double uacc[NRHS][CH][2];
     zero(uacc);
-    gemv_rows<NRHS, CH>(a.Kf + (long long)i * nx * a.ldu, a.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
+    gemv_rows<NRHS, CH>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
         const int c0 = 2 * lane + 128 * ch;
@@ -301,21 +315,22 @@ __device__ void fwd_node(const SweepArgs &a, int i, const WaveLds &L, bool keep_
             if (c < nu) {
 #pragma unroll
                 for (int k = 0; k < NRHS; ++k) {
-                    const double uval = uacc[k][ch][e] + a.kbuf[k * a.kbuf_rs + (long long)i * nu + c];
-                    a.uo[k * a.uo_rs + (long long)i * a.uo_s + c] = uval;
+                    const double uval = uacc[k][ch][e] + kbuf_ptr(a, I, k, i)[c];
+                    u_ptr(a, I, k, i)[c] = uval;
                     L.qx[k * L.ldq + nx + c] = uval;
                 }
             }
         }
     }
     wave_sync();
-    const int j0 = a.child_ptr[i], j1 = a.child_ptr[i + 1];
+    const int j0 = cp[i], j1 = cp[i + 1];
     double keep[NRHS][CH][2];
+    zero(keep);
     for (int j = j0; j < j1; ++j) {
         double xacc[NRHS][CH][2];
         zero(xacc);
-        gemv_rows<NRHS, CH>(a.Mf + (long long)j * (nx + nu) * a.ldx, a.ldx, 0, nx + nu, nx, L.qx,
-                            L.ldq, xacc, lane);
+        gemv_rows<NRHS, CH>(a.Mf + I.Mf + (long long)j * (nx + nu) * I.ldx, I.ldx, 0, nx + nu, nx, L.qx, L.ldq,
+                            xacc, lane);
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch) {
             const int c0 = 2 * lane + 128 * ch;
@@ -325,8 +340,8 @@ __device__ void fwd_node(const SweepArgs &a, int i, const WaveLds &L, bool keep_
                 if (c < nx) {
 #pragma unroll
                     for (int k = 0; k < NRHS; ++k) {
-                        const double xv = xacc[k][ch][e] + (a.affine ? a.cvec[(long long)j * nx + c] : 0.0);
-                        x_ptr(a, k, j)[c] = xv;
+                        const double xv = xacc[k][ch][e] + (a.affine ? a.cvec[I.c + (long long)j * nx + c] : 0.0);
+                        x_ptr(a, I, k, j)[c] = xv;
                         keep[k][ch][e] = xv;
                     }
                 }
@@ -335,17 +350,7 @@ __device__ void fwd_node(const SweepArgs &a, int i, const WaveLds &L, bool keep_
     }
     if (keep_child) {
         wave_sync();
-#pragma unroll
-        for (int ch = 0; ch < CH; ++ch) {
-            const int c0 = 2 * lane + 128 * ch;
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int c = c0 + e;
-                if (c < nx)
-#pragma unroll
-                    for (int k = 0; k < NRHS; ++k) L.qx[k * L.ldq + c] = keep[k][ch][e];
-            }
-        }
+        store_acc<NRHS, CH>(L.qx, L.ldq, 0, nx, keep, lane);
         wave_sync();
     }
 }
@@ -353,17 +358,17 @@ __device__ void fwd_node(const SweepArgs &a, int i, const WaveLds &L, bool keep_
 // x_i of the first node a forward pass visits: x0 at the root (written to
 // the output too), else the value the previous stage stored.
 template <int NRHS>
-__device__ void load_x(const SweepArgs &a, int i, const WaveLds &L, int lane)
+__device__ void load_x(const SweepArgs &a, const InstDesc &I, int i, const WaveLds &L, int lane)
 {
-    for (int c = lane; c < a.nx; c += kWave)
+    for (int c = lane; c < I.nx; c += kWave)
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             double v;
             if (i == 0) {
-                v = a.affine ? a.x0[k * a.x0_rs + c] : 0.0;
-                x_ptr(a, k, 0)[c] = v;
+                v = a.affine ? a.x0[k * a.x0_rs + I.x0 + c] : 0.0;
+                x_ptr(a, I, k, 0)[c] = v;
             } else {
-                v = x_ptr(a, k, i)[c];
+                v = x_ptr(a, I, k, i)[c];
             }
             L.qx[k * L.ldq + c] = v;
         }
@@ -385,19 +390,22 @@ __host__ __device__ inline int child_batch(int nrhs, int ldx)
 }
 
 template <int NRHS, int CH, int NW>
-__global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a, int t)
+__global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a)
 {
-    if (a.done && *a.done) return;
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int i = a.stage_ptr[t] + blockIdx.x;
-    const int nx = a.nx, nu = a.nu, W = nx + nu, ldq = a.ldx, ldM = a.ldM;
+    const Item it = a.items[blockIdx.x];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int lane = threadIdx.x & (kWave - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int i = it.idx;
+    const int nx = I.nx, nu = I.nu, W = nx + nu, ldq = I.ldx, ldM = I.ldM;
+    const int *cp = a.cp + I.cp;
     const int CB = child_batch(NRHS, ldq);
     extern __shared__ double lds[];
     double *qs = lds;                          // [CB][NRHS][ldq]
     double *red = qs + CB * NRHS * ldq;        // [NW][NRHS][ldM]
     double *as = red + NW * NRHS * ldM;        // [NRHS][ldM]
     double *gs = as + NRHS * ldM;              // [NRHS][ldu]
-    const int j0 = a.child_ptr[i], nch = a.child_ptr[i + 1] - j0;
+    const int j0 = cp[i], nch = cp[i + 1] - j0;
     double acc[NRHS][CH][2];
     zero(acc);
     for (int cb = 0; cb < nch; cb += CB) {
@@ -407,11 +415,11 @@ __global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a, int t
 #pragma unroll
             for (int k = 0; k < NRHS; ++k) {
                 double q;
-                if (j >= a.Vnl) {
-                    const double sj = a.sc ? a.sc[j] : 1.0;
-                    q = sj * a.y[k * a.y_rs + off_l(a, j) + r] + (a.affine ? a.chat[(long long)j * nx + r] : 0.0);
+                if (j >= I.Vnl) {
+                    const double sj = a.sc ? a.sc[I.sc + j] : 1.0;
+                    q = sj * y_ptr(a, I, k, j)[r] + (a.affine ? a.chat[I.chat + (long long)j * nx + r] : 0.0);
                 } else {
-                    q = a.qhat[k * a.qhat_rs + (long long)j * nx + r];
+                    q = qhat_ptr(a, I, k, j)[r];
                 }
                 qs[(c * NRHS + k) * ldq + r] = q;
             }
@@ -423,7 +431,7 @@ __global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a, int t
             const int lo = (r0 > c * nx ? r0 : c * nx) - c * nx;
             const int hi = (r1 < (c + 1) * nx ? r1 : (c + 1) * nx) - c * nx;
             if (lo < hi)
-                gemv_rows<NRHS, CH>(a.Mb + (long long)(j0 + cb + c) * nx * ldM, ldM, lo, hi, W,
+                gemv_rows<NRHS, CH>(a.Mb + I.Mb + (long long)(j0 + cb + c) * nx * ldM, ldM, lo, hi, W,
                                     qs + c * NRHS * ldq, ldq, acc, lane);
         }
         __syncthreads();
@@ -437,11 +445,11 @@ __global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a, int t
         as[k * ldM + c] = s;
     }
     __syncthreads();
-    const double si = a.sc ? a.sc[i] : 1.0;
+    const double si = a.sc ? a.sc[I.sc + i] : 1.0;
     for (int e = threadIdx.x; e < NRHS * nu; e += blockDim.x) {
         const int k = e / nu, c = e - k * nu;
-        gs[k * a.ldu + c] = as[k * ldM + nx + c] + si * a.y[k * a.y_rs + off_nl(a, i) + nx + c] +
-                            (a.affine ? a.sig[(long long)i * nu + c] : 0.0);
+        gs[k * I.ldu + c] = as[k * ldM + nx + c] + si * y_ptr(a, I, k, i)[nx + c] +
+                            (a.affine ? a.sig[I.sig + (long long)i * nu + c] : 0.0);
     }
     __syncthreads();
     double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
@@ -451,11 +459,11 @@ __global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a, int t
         const int R = 2 * nu;
         const int r0 = R * w / NW, r1 = R * (w + 1) / NW;
         if (r0 < nu)
-            gemv_rows<NRHS, CH>(a.Rn + (long long)i * nu * a.ldu, a.ldu, r0, r1 < nu ? r1 : nu, nu, gs,
-                                a.ldu, kacc, lane);
+            gemv_rows<NRHS, CH>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, r0, r1 < nu ? r1 : nu, nu, gs,
+                                I.ldu, kacc, lane);
         if (r1 > nu)
-            gemv_rows<NRHS, CH>(a.Kb + (long long)i * nu * a.ldx, a.ldx, (r0 > nu ? r0 : nu) - nu, r1 - nu, nx,
-                                gs, a.ldu, qacc, lane);
+            gemv_rows<NRHS, CH>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, (r0 > nu ? r0 : nu) - nu,
+                                r1 - nu, nx, gs, I.ldu, qacc, lane);
     }
     store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nu, kacc, lane);
     store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, nu, nx, qacc, lane);
@@ -465,23 +473,25 @@ __global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a, int t
         double s = 0.0;
         for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + c];
         if (c < nu) {
-            a.kbuf[k * a.kbuf_rs + (long long)i * nu + c] = s;
+            kbuf_ptr(a, I, k, i)[c] = s;
         } else {
             const int cx = c - nu;
-            a.qhat[k * a.qhat_rs + (long long)i * nx + cx] =
-                as[k * ldM + cx] + si * a.y[k * a.y_rs + off_nl(a, i) + cx] +
-                (a.affine ? a.chat[(long long)i * nx + cx] : 0.0) + s;
+            qhat_ptr(a, I, k, i)[cx] = as[k * ldM + cx] + si * y_ptr(a, I, k, i)[cx] +
+                                       (a.affine ? a.chat[I.chat + (long long)i * nx + cx] : 0.0) + s;
         }
     }
 }
 
 template <int NRHS, int CH, int NW>
-__global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a, int t)
+__global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a)
 {
-    if (a.done && *a.done) return;
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int i = a.stage_ptr[t] + blockIdx.x;
-    const int nx = a.nx, nu = a.nu, W = nx + nu, ldM = a.ldM;
+    const Item it = a.items[blockIdx.x];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int lane = threadIdx.x & (kWave - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int i = it.idx;
+    const int nx = I.nx, nu = I.nu, W = nx + nu, ldM = I.ldM;
+    const int *cp = a.cp + I.cp;
     extern __shared__ double lds[];
     double *xs = lds;                 // [NRHS][ldM]: x_i then u_i
     double *red = xs + NRHS * ldM;    // [NW][NRHS][ldM]
@@ -489,10 +499,10 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a, int t
         const int k = e / nx, c = e - k * nx;
         double v;
         if (i == 0) {
-            v = a.affine ? a.x0[k * a.x0_rs + c] : 0.0;
-            x_ptr(a, k, 0)[c] = v;
+            v = a.affine ? a.x0[k * a.x0_rs + I.x0 + c] : 0.0;
+            x_ptr(a, I, k, 0)[c] = v;
         } else {
-            v = x_ptr(a, k, i)[c];
+            v = x_ptr(a, I, k, i)[c];
         }
         xs[k * ldM + c] = v;
     }
@@ -502,26 +512,26 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a, int t
     {
         const int r0 = nx * w / NW, r1 = nx * (w + 1) / NW;
         if (r0 < r1)
-            gemv_rows<NRHS, CH>(a.Kf + (long long)i * nx * a.ldu, a.ldu, r0, r1, nu, xs, ldM, uacc, lane);
+            gemv_rows<NRHS, CH>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, r0, r1, nu, xs, ldM, uacc, lane);
     }
     store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nu, uacc, lane);
     __syncthreads();
     for (int e = threadIdx.x; e < NRHS * nu; e += blockDim.x) {
         const int k = e / nu, c = e - k * nu;
-        double s = a.kbuf[k * a.kbuf_rs + (long long)i * nu + c];
+        double s = kbuf_ptr(a, I, k, i)[c];
         for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + c];
-        a.uo[k * a.uo_rs + (long long)i * a.uo_s + c] = s;
+        u_ptr(a, I, k, i)[c] = s;
         xs[k * ldM + nx + c] = s;
     }
     __syncthreads();
-    const int j0 = a.child_ptr[i], nch = a.child_ptr[i + 1] - j0;
+    const int j0 = cp[i], nch = cp[i + 1] - j0;
     const int RB = nch >= NW ? 1 : NW / nch;
     if (RB == 1) {
         for (int c = w; c < nch; c += NW) {
             const int j = j0 + c;
             double xacc[NRHS][CH][2];
             zero(xacc);
-            gemv_rows<NRHS, CH>(a.Mf + (long long)j * W * a.ldx, a.ldx, 0, W, nx, xs, ldM, xacc, lane);
+            gemv_rows<NRHS, CH>(a.Mf + I.Mf + (long long)j * W * I.ldx, I.ldx, 0, W, nx, xs, ldM, xacc, lane);
 #pragma unroll
             for (int ch = 0; ch < CH; ++ch) {
                 const int c0 = 2 * lane + 128 * ch;
@@ -531,7 +541,8 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a, int t
                     if (col < nx)
 #pragma unroll
                         for (int k = 0; k < NRHS; ++k)
-                            x_ptr(a, k, j)[col] = xacc[k][ch][e2] + (a.affine ? a.cvec[(long long)j * nx + col] : 0.0);
+                            x_ptr(a, I, k, j)[col] =
+                                xacc[k][ch][e2] + (a.affine ? a.cvec[I.c + (long long)j * nx + col] : 0.0);
                 }
             }
         }
@@ -541,52 +552,51 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a, int t
         if (w < nch * RB) {
             const int c = w / RB, blk = w - c * RB;
             const int rr0 = W * blk / RB, rr1 = W * (blk + 1) / RB;
-            gemv_rows<NRHS, CH>(a.Mf + (long long)(j0 + c) * W * a.ldx, a.ldx, rr0, rr1, nx, xs, ldM, xacc,
-                                lane);
+            gemv_rows<NRHS, CH>(a.Mf + I.Mf + (long long)(j0 + c) * W * I.ldx, I.ldx, rr0, rr1, nx, xs, ldM,
+                                xacc, lane);
         }
         store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nx, xacc, lane);
         __syncthreads();
         for (int e = threadIdx.x; e < nch * NRHS * nx; e += blockDim.x) {
             const int c = e / (NRHS * nx), rem = e - c * NRHS * nx, k = rem / nx, col = rem - k * nx;
             const int j = j0 + c;
-            double s = a.affine ? a.cvec[(long long)j * nx + col] : 0.0;
+            double s = a.affine ? a.cvec[I.c + (long long)j * nx + col] : 0.0;
             for (int blk = 0; blk < RB; ++blk) s += red[((c * RB + blk) * NRHS + k) * ldM + col];
-            x_ptr(a, k, j)[col] = s;
+            x_ptr(a, I, k, j)[col] = s;
         }
     }
 }
 
-// Chain c covers the nodes stage_ptr[t] + c for t = s*..N-1 (each with one
-// child) and its leaf stage_ptr[N] + c.
+// ---- stages s*..N-1: chain c of an instance covers the nodes
+// stage_ptr[t] + c for t = s*..N-1 (one child each) and its leaf ----
 template <int NRHS, int CH>
-__global__ void __launch_bounds__(kWave *kWavesPerBlock)
-bwd_chain_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave *kWavesPerBlock, 2) bwd_chain_kernel(SweepArgs a, int ldq)
 {
-    if (a.done && *a.done) return;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int c = blockIdx.x * kWavesPerBlock + wave;
-    if (c >= a.nchains) return;
-    const WaveLds L = wave_lds(a, NRHS, wave);
-    for (int t = a.N - 1; t >= a.sstar; --t) {
-        const int i = a.stage_ptr[t] + c;
-        bwd_node<NRHS, CH>(a, i, L, t != a.N - 1, t == a.sstar && t > 0, lane);
-    }
+    const int lane = threadIdx.x & (kWave - 1), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int item = blockIdx.x * kWavesPerBlock + wave;
+    if (item >= a.nitems) return;
+    const Item it = a.items[item];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int *sp = a.sp + I.sp;
+    const WaveLds L = wave_lds(ldq, NRHS, wave);
+    for (int t = I.N - 1; t >= I.sstar; --t)
+        bwd_node<NRHS, CH>(a, I, sp[t] + it.idx, L, t != I.N - 1, t == I.sstar && t > 0, lane);
 }
 
 template <int NRHS, int CH>
-__global__ void __launch_bounds__(kWave *kWavesPerBlock)
-fwd_chain_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave *kWavesPerBlock, 2) fwd_chain_kernel(SweepArgs a, int ldq)
 {
-    if (a.done && *a.done) return;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int c = blockIdx.x * kWavesPerBlock + wave;
-    if (c >= a.nchains) return;
-    const WaveLds L = wave_lds(a, NRHS, wave);
-    load_x<NRHS>(a, a.stage_ptr[a.sstar] + c, L, lane);
-    for (int t = a.sstar; t < a.N; ++t) {
-        const int i = a.stage_ptr[t] + c;
-        fwd_node<NRHS, CH>(a, i, L, t + 1 < a.N, lane);
-    }
+    const int lane = threadIdx.x & (kWave - 1), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int item = blockIdx.x * kWavesPerBlock + wave;
+    if (item >= a.nitems) return;
+    const Item it = a.items[item];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int *sp = a.sp + I.sp;
+    const WaveLds L = wave_lds(ldq, NRHS, wave);
+    load_x<NRHS>(a, I, sp[I.sstar] + it.idx, L, lane);
+    for (int t = I.sstar; t < I.N; ++t) fwd_node<NRHS, CH>(a, I, sp[t] + it.idx, L, t + 1 < I.N, lane);
 }
 
 }  // namespace
@@ -594,15 +604,13 @@ fwd_chain_kernel(SweepArgs a)
 SweepArgs sweep_args(const tree_factors *f, int affine)
 {
     SweepArgs a{};
-    a.nx = f->nx; a.nu = f->nu; a.N = f->N; a.V = f->V; a.Vnl = f->Vnl;
-    a.sstar = f->sstar; a.nchains = f->nchains;
-    a.ldM = f->ldM; a.ldx = f->ldx; a.ldu = f->ldu;
-    a.stage_ptr = f->d_stage_ptr; a.child_ptr = f->d_child_ptr;
+    a.inst = f->d_inst;
+    a.sp = f->d_sp; a.cp = f->d_cp;
     a.Mb = f->Mb; a.Mf = f->Mf; a.Kb = f->Kb; a.Kf = f->Kf; a.Rn = f->Rn;
     a.chat = f->chat; a.sig = f->sig; a.cvec = f->cvec; a.sc = f->precondition ? f->sc : nullptr;
     a.qhat = f->qhat; a.kbuf = f->kbuf;
-    a.qhat_rs = (long long)f->V * f->nx;
-    a.kbuf_rs = (long long)f->Vnl * f->nu;
+    a.qhat_rs = f->x_tot;
+    a.kbuf_rs = f->u_tot;
     a.affine = affine;
     return a;
 }
@@ -610,17 +618,16 @@ SweepArgs sweep_args(const tree_factors *f, int affine)
 int ensure_sweep_ws(tree_factors *f, int nrhs)
 {
     if (f->ws_nrhs >= nrhs) return STOTREE_OK;
-    if (f->qhat) { (void)hipFree(f->qhat); f->bytes -= (size_t)f->ws_nrhs * f->V * f->nx * 8; }
-    if (f->kbuf) { (void)hipFree(f->kbuf); f->bytes -= (size_t)f->ws_nrhs * f->Vnl * f->nu * 8; }
+    if (f->qhat) { (void)hipFree(f->qhat); f->bytes -= (size_t)f->ws_nrhs * f->x_tot * 8; }
+    if (f->kbuf) { (void)hipFree(f->kbuf); f->bytes -= (size_t)f->ws_nrhs * f->u_tot * 8; }
     f->qhat = f->kbuf = nullptr;
     f->ws_nrhs = 0;
-    STOTREE_HIP(hipMalloc(&f->qhat, sizeof(double) * (size_t)nrhs * f->V * f->nx));
-    STOTREE_HIP(hipMalloc(&f->kbuf, sizeof(double) * (size_t)nrhs * f->Vnl * f->nu));
+    STOTREE_HIP(hipMalloc(&f->qhat, sizeof(double) * (size_t)nrhs * f->x_tot));
+    STOTREE_HIP(hipMalloc(&f->kbuf, sizeof(double) * (size_t)nrhs * f->u_tot));
     f->ws_nrhs = nrhs;
-    f->bytes += (size_t)nrhs * ((size_t)f->V * f->nx + (size_t)f->Vnl * f->nu) * 8;
+    f->bytes += (size_t)nrhs * ((size_t)f->x_tot + (size_t)f->u_tot) * 8;
     return STOTREE_OK;
 }
-
 // ---- optional phase timing (HIP events around each phase) ----
 namespace {
 struct TimingState {
@@ -673,78 +680,78 @@ int timing_read(double *ms, long long *count)
     return rc;
 }
 
-// Wavefronts per node for a stage of n nodes: enough to keep about 4096
-// wavefronts busy, within the LDS budget of the reduction buffers.
-static int trunk_waves(int n, int nrhs, int ldM)
-{
-    int nw = 16;
-    while (nw > 1 && (long long)n * nw > 4096) nw /= 2;
-    while (nw > 1 && (size_t)(nw + 2) * nrhs * ldM * sizeof(double) > 40 * 1024) nw /= 2;
-    return nw;
-}
-
 template <int NRHS, int CH, int NW>
-static void launch_trunk_nw(bool backward, const SweepArgs &a, int t, int n, hipStream_t st)
+static void launch_trunk_nw(bool backward, SweepArgs a, const LevelPlan &lv, int max_ldM, int max_qs,
+                            int max_ldu, hipStream_t st)
 {
+    a.items = lv.items;
+    a.nitems = lv.count;
+    a.t = lv.t;
     if (backward) {
-        const size_t lds = sizeof(double) * ((size_t)child_batch(NRHS, a.ldx) * NRHS * a.ldx +
-                                             (size_t)(NW + 1) * NRHS * a.ldM + (size_t)NRHS * a.ldu);
-        hipLaunchKernelGGL((bwd_trunk_kernel<NRHS, CH, NW>), dim3(n), dim3(kWave * NW), lds, st, a, t);
+        // max_qs: largest child_batch(NRHS, ldx) * ldx over the instances
+        const size_t lds = sizeof(double) * ((size_t)max_qs * NRHS + (size_t)(NW + 1) * NRHS * max_ldM +
+                                             (size_t)NRHS * max_ldu);
+        hipLaunchKernelGGL((bwd_trunk_kernel<NRHS, CH, NW>), dim3(lv.count), dim3(kWave * NW), lds, st, a);
     } else {
-        const size_t lds = sizeof(double) * (size_t)(NW + 1) * NRHS * a.ldM;
-        hipLaunchKernelGGL((fwd_trunk_kernel<NRHS, CH, NW>), dim3(n), dim3(kWave * NW), lds, st, a, t);
+        const size_t lds = sizeof(double) * (size_t)(NW + 1) * NRHS * max_ldM;
+        hipLaunchKernelGGL((fwd_trunk_kernel<NRHS, CH, NW>), dim3(lv.count), dim3(kWave * NW), lds, st, a);
     }
 }
 
 template <int NRHS, int CH>
-static void launch_trunk(bool backward, const SweepArgs &a, int t, int n, hipStream_t st)
+static void launch_trunk(bool backward, const SweepArgs &a, const LevelPlan &lv, int max_ldM, int max_qs,
+                         int max_ldu, hipStream_t st)
 {
-    switch (trunk_waves(n, NRHS, a.ldM)) {
-    case 16: launch_trunk_nw<NRHS, CH, 16>(backward, a, t, n, st); break;
-    case 8: launch_trunk_nw<NRHS, CH, 8>(backward, a, t, n, st); break;
-    case 4: launch_trunk_nw<NRHS, CH, 4>(backward, a, t, n, st); break;
-    case 2: launch_trunk_nw<NRHS, CH, 2>(backward, a, t, n, st); break;
-    default: launch_trunk_nw<NRHS, CH, 1>(backward, a, t, n, st); break;
+    switch (lv.nw) {
+    case 16: launch_trunk_nw<NRHS, CH, 16>(backward, a, lv, max_ldM, max_qs, max_ldu, st); break;
+    case 8: launch_trunk_nw<NRHS, CH, 8>(backward, a, lv, max_ldM, max_qs, max_ldu, st); break;
+    case 4: launch_trunk_nw<NRHS, CH, 4>(backward, a, lv, max_ldM, max_qs, max_ldu, st); break;
+    case 2: launch_trunk_nw<NRHS, CH, 2>(backward, a, lv, max_ldM, max_qs, max_ldu, st); break;
+    default: launch_trunk_nw<NRHS, CH, 1>(backward, a, lv, max_ldM, max_qs, max_ldu, st); break;
     }
 }
 
 template <int NRHS, int CH>
-static hipError_t sweep_impl(const SweepArgs &a, const int *host_stage_ptr, hipStream_t st)
+static hipError_t sweep_impl(const tree_factors *f, SweepArgs a, hipStream_t st)
 {
+    int ldM = 2, qs = 2, ldu = 2;
+    for (const InstDesc &I : f->inst) {
+        ldM = std::max(ldM, I.ldM);
+        qs = std::max(qs, child_batch(NRHS, I.ldx) * I.ldx);
+        ldu = std::max(ldu, I.ldu);
+    }
     const dim3 blk(kWave * kWavesPerBlock);
-    const size_t lds = sizeof(double) * kWavesPerBlock * NRHS * (2 * a.ldM + a.ldu);
-    auto blocks = [](int n) { return dim3((n + kWavesPerBlock - 1) / kWavesPerBlock); };
-    if (a.sstar < a.N) {
+    const size_t chain_lds = sizeof(double) * kWavesPerBlock * 3 * NRHS * ldM;
+    const dim3 cgrid((f->nchain_items + kWavesPerBlock - 1) / kWavesPerBlock);
+    SweepArgs ca = a;
+    ca.items = f->chain_items;
+    ca.nitems = f->nchain_items;
+    if (f->nchain_items > 0) {
         PhaseTimer tm(0, st);
-        hipLaunchKernelGGL((bwd_chain_kernel<NRHS, CH>), blocks(a.nchains), blk, lds, st, a);
+        hipLaunchKernelGGL((bwd_chain_kernel<NRHS, CH>), cgrid, blk, chain_lds, st, ca, ldM);
     }
-    if (a.sstar > 0) {
+    if (!f->levels.empty()) {
         PhaseTimer tm(1, st);
-        for (int t = a.sstar - 1; t >= 0; --t) {
-            const int n = host_stage_ptr[t + 1] - host_stage_ptr[t];
-            launch_trunk<NRHS, CH>(true, a, t, n, st);
-        }
+        for (int k = (int)f->levels.size() - 1; k >= 0; --k)
+            launch_trunk<NRHS, CH>(true, a, f->levels[k], ldM, qs, ldu, st);
     }
-    if (a.sstar > 0) {
+    if (!f->levels.empty()) {
         PhaseTimer tm(2, st);
-        for (int t = 0; t < a.sstar; ++t) {
-            const int n = host_stage_ptr[t + 1] - host_stage_ptr[t];
-            launch_trunk<NRHS, CH>(false, a, t, n, st);
-        }
+        for (size_t k = 0; k < f->levels.size(); ++k)
+            launch_trunk<NRHS, CH>(false, a, f->levels[k], ldM, qs, ldu, st);
     }
-    if (a.sstar < a.N) {
+    if (f->nchain_items > 0) {
         PhaseTimer tm(3, st);
-        hipLaunchKernelGGL((fwd_chain_kernel<NRHS, CH>), blocks(a.nchains), blk, lds, st, a);
+        hipLaunchKernelGGL((fwd_chain_kernel<NRHS, CH>), cgrid, blk, chain_lds, st, ca, ldM);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_tree(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st)
 {
-    const bool wide = (a.nx + a.nu) > 128;
-    const int *sp = f->stage_ptr.data();
-    if (nrhs == 1) return wide ? sweep_impl<1, 2>(a, sp, st) : sweep_impl<1, 1>(a, sp, st);
-    if (nrhs == 2) return wide ? sweep_impl<2, 2>(a, sp, st) : sweep_impl<2, 1>(a, sp, st);
+    const bool wide = f->max_width > 128;
+    if (nrhs == 1) return wide ? sweep_impl<1, 2>(f, a, st) : sweep_impl<1, 1>(f, a, st);
+    if (nrhs == 2) return wide ? sweep_impl<2, 2>(f, a, st) : sweep_impl<2, 1>(f, a, st);
     return hipErrorInvalidValue;
 }
 

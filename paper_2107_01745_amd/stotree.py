@@ -55,9 +55,9 @@ class SolverInfo(C.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
-EXPORTS = ("tree_factor", "tree_factors_free", "tree_dims", "dual_grad", "dual_lipschitz",
-           "minfbe_solve", "nama_solve", "stotree_timing", "stotree_timing_read",
-           "stotree_last_error")
+EXPORTS = ("tree_factor", "tree_factor_batch", "tree_factors_free", "tree_dims",
+           "tree_instance_dims", "dual_grad", "dual_lipschitz", "minfbe_solve", "nama_solve",
+           "solve_info_batch", "stotree_timing", "stotree_timing_read", "stotree_last_error")
 PHASES = ("bwd_chain", "bwd_stages", "fwd_stages", "fwd_chain")
 
 _lib = None
@@ -74,6 +74,13 @@ def lib():
         L.tree_factor.argtypes = [C.POINTER(TreeDesc), C.POINTER(ProblemData), C.c_int, vp,
                                   C.POINTER(vp)]
         L.tree_factor.restype = C.c_int
+        L.tree_factor_batch.argtypes = [C.c_int, C.POINTER(TreeDesc), C.POINTER(ProblemData), C.c_int,
+                                        vp, C.POINTER(vp)]
+        L.tree_factor_batch.restype = C.c_int
+        L.tree_instance_dims.argtypes = [vp, C.c_int, C.POINTER(C.c_int64)]
+        L.tree_instance_dims.restype = C.c_int
+        L.solve_info_batch.argtypes = [vp, C.POINTER(SolverInfo)]
+        L.solve_info_batch.restype = C.c_int
         L.tree_factors_free.argtypes = [vp]
         L.tree_factors_free.restype = None
         L.tree_dims.argtypes = [vp, C.POINTER(C.c_int64)]
@@ -125,12 +132,26 @@ def _ptr(t):
 
 
 class TreeFactors:
-    """Owns the handle returned by tree_factor."""
+    """Owns the handle returned by tree_factor / tree_factor_batch.
 
-    def __init__(self, handle, dims):
+    Totals: ninst, m (concatenated dual length), n, x_len (sum V nx), u_len
+    (sum V_nl nu), x0_len (sum nx), V (total nodes).  ``instances`` lists
+    the per-instance sizes and offsets; for a single tree its nx, nu, N, Vnl
+    and sstar are also attributes."""
+
+    def __init__(self, handle):
         self.handle = handle
-        (self.nx, self.nu, self.N, self.V, self.Vnl, self.m, self.n, self.sstar,
-         self.precondition, self.device_bytes) = [int(v) for v in dims]
+        d = tree_dims(handle)
+        (self.ninst, self.precondition, self.m, self.n, self.x_len, self.u_len, self.x0_len,
+         self.V, self.device_bytes, self.max_width) = [int(v) for v in d]
+        self.instances = []
+        for b in range(self.ninst):
+            out = (C.c_int64 * 12)()
+            _check(lib().tree_instance_dims(handle, b, out))
+            keys = ("nx", "nu", "N", "V", "Vnl", "m", "n", "sstar", "y_off", "x_off", "u_off", "x0_off")
+            self.instances.append(dict(zip(keys, [int(v) for v in out])))
+        i0 = self.instances[0]
+        self.nx, self.nu, self.N, self.Vnl, self.sstar = i0["nx"], i0["nu"], i0["N"], i0["Vnl"], i0["sstar"]
 
     def free(self):
         if self.handle:
@@ -144,10 +165,8 @@ class TreeFactors:
             pass
 
 
-def tree_factor(prob, precondition: bool = True, stream=None) -> TreeFactors:
-    """Factor step on a treegen.Problem (host arrays)."""
+def _descs(prob, keep):
     t = prob.tree
-    keep = []
 
     def d(a, dtype=np.float64):
         if a is None:
@@ -160,10 +179,29 @@ def tree_factor(prob, precondition: bool = True, stream=None) -> TreeFactors:
                   stage_ptr=d(t.stage_ptr, np.int32), ancestor=d(t.anc, np.int32),
                   child_ptr=d(t.child_ptr, np.int32), prob=d(t.prob))
     pd = ProblemData(**{n: d(getattr(prob, n)) for n, _ in ProblemData._fields_})
+    return td, pd
+
+
+def tree_factor(prob, precondition: bool = True, stream=None) -> TreeFactors:
+    """Factor step on a treegen.Problem (host arrays)."""
+    keep = []
+    td, pd = _descs(prob, keep)
     h = C.c_void_p()
     _check(lib().tree_factor(C.byref(td), C.byref(pd), int(bool(precondition)), _stream(stream),
                              C.byref(h)))
-    return TreeFactors(h, tree_dims(h))
+    return TreeFactors(h)
+
+
+def tree_factor_batch(probs, precondition: bool = True, stream=None) -> TreeFactors:
+    """Factor step on a list of treegen.Problem instances (one handle)."""
+    keep = []
+    tds, pds = zip(*[_descs(p, keep) for p in probs])
+    n = len(probs)
+    tarr = (TreeDesc * n)(*tds)
+    parr = (ProblemData * n)(*pds)
+    h = C.c_void_p()
+    _check(lib().tree_factor_batch(n, tarr, parr, int(bool(precondition)), _stream(stream), C.byref(h)))
+    return TreeFactors(h)
 
 
 def tree_dims(handle) -> list:
@@ -172,16 +210,23 @@ def tree_dims(handle) -> list:
     return list(out)
 
 
+def solve_info_batch(tf: TreeFactors) -> list:
+    infos = (SolverInfo * tf.ninst)()
+    _check(lib().solve_info_batch(tf.handle, infos))
+    return [i.as_dict() for i in infos]
+
+
 def dual_grad(tf: TreeFactors, x0, y, homogeneous: bool, x, u, nrhs: int = 1, stream=None) -> None:
     """x(y) (Algorithm 3) or x-hat(y) (Algorithm 4) into the device tensors x, u."""
     _check(lib().dual_grad(tf.handle, _ptr(x0), _ptr(y), int(bool(homogeneous)), int(nrhs),
                            _ptr(x), _ptr(u), _stream(stream)))
 
 
-def dual_lipschitz(tf: TreeFactors, iters: int = 100, stream=None) -> float:
-    L = C.c_double()
-    _check(lib().dual_lipschitz(tf.handle, int(iters), C.byref(L), _stream(stream)))
-    return L.value
+def dual_lipschitz(tf: TreeFactors, iters: int = 100, stream=None):
+    """L of every instance (a float for a single tree, else a list)."""
+    L = (C.c_double * tf.ninst)()
+    _check(lib().dual_lipschitz(tf.handle, int(iters), L, _stream(stream)))
+    return L[0] if tf.ninst == 1 else list(L)
 
 
 def make_opts(lam=0.0, eps=1e-6, eps_curv=1e-12, mem=5, nu_max=10, max_iter=1000, check_every=1):
