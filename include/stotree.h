@@ -210,6 +210,47 @@ int minfbe_solve(const tree_factors *f, const double *x0, const solver_opts *opt
 int nama_solve(const tree_factors *f, const double *x0, const solver_opts *opts,
                double *y_inout, double *x, double *u, solver_info *info, void *hip_stream);
 
+/*
+ * Learned warm start (the warm-start slot of Sec. III-F, filled by a node-wise
+ * MLP instead of accelerated-gradient iterations).  Features of node i of an
+ * instance with initial state x0: [x0, c_i/c_scale, (mean of c on the path
+ * root..i)/c_scale, one-hot(stage)], din = 3 nx + N + 1; network din -> dh ->
+ * dh -> dout = nx + nu with ReLU, FP32 parameters in one flat array
+ * [W1 (din x dh), b1, W2 (dh x dh), b2, W3 (dh x dout), b3], row-major, FP32
+ * accumulation.  Rows are nodes in instance order (the sum of V over the
+ * instances); all instances of a handle must share nx, nu and N (ERR_ARG).
+ * All pointers are DEVICE pointers except where stated; calls are
+ * asynchronous on hip_stream.  The solver's residual decides between the
+ * prediction and the cold start (dual_select); accuracy never changes.
+ */
+int64_t warm_mlp_params(int din, int dh, int dout);            /* parameter count */
+int64_t warm_mlp_work_len(int rows, int din, int dh, int dout); /* floats of work */
+/* Y [rows][dout] = MLP(X [rows][din]); H (2 rows dh floats) keeps the
+ * activations: the rows x dh block of layer 1, then the block of layer 2. */
+int warm_mlp_forward(int rows, int din, int dh, int dout, const float *params, const float *X, float *H,
+                     float *Y, void *hip_stream);
+/* Gradient of the loss w.r.t. the parameters (grad [params]) given dY [rows][dout]
+ * and the H of the forward pass; work [warm_mlp_work_len] floats.  The
+ * reductions over rows run in a fixed order (deterministic). */
+int warm_mlp_backward(int rows, int din, int dh, int dout, const float *params, const float *X,
+                      const float *H, const float *dY, float *grad, float *work, void *hip_stream);
+/* Masked squared error: dY = 2 mask (Y - T) inv_count; loss2 [2] receives
+ * (sum mask (Y - T)^2, sum mask); part is DEVICE scratch of 512 doubles. */
+int warm_mse_grad(int64_t n, const float *Y, const float *T, const float *mask, float inv_count, float *dY,
+                  double *loss2, double *part, void *hip_stream);
+/* One Adam step (Kingma and Ba) with bias correction at step >= 1. */
+int warm_adam(int64_t n, float *params, const float *grad, float *m, float *v, float lr, float beta1,
+              float beta2, float eps, int step, void *hip_stream);
+/* Features X [sum V][din] of every node; x0 [sum nx] DEVICE. */
+int warm_features(const tree_factors *f, const double *x0, float c_scale, float *X, void *hip_stream);
+/* Dual vector y [m] from the rows Y [sum V][dout] times y_scale (root state
+ * rows set to zero), and the inverse map with a mask of existing rows. */
+int warm_scatter(const tree_factors *f, const float *Y, float y_scale, double *y, void *hip_stream);
+int warm_targets(const tree_factors *f, const double *y, float y_scale, float *T, float *mask,
+                 void *hip_stream);
+/* Zero the dual rows of every instance b with keep[b] == 0 (HOST keep[count]). */
+int dual_select(const tree_factors *f, double *y, const int32_t *keep, void *hip_stream);
+
 /* Per-instance records of the last minfbe_solve / nama_solve on this handle,
  * written to HOST infos[count].  ERR_ARG on NULL. */
 int solve_info_batch(const tree_factors *f, solver_info *infos);

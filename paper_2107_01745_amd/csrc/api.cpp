@@ -129,6 +129,85 @@ int solve_info_batch(const tree_factors *f, solver_info *infos)
     return STOTREE_OK;
 }
 
+int64_t warm_mlp_params(int din, int dh, int dout)
+{
+    if (din < 1 || dh < 1 || dout < 1) return -1;
+    return mlp_param_count(din, dh, dout);
+}
+
+int64_t warm_mlp_work_len(int rows, int din, int dh, int dout)
+{
+    if (rows < 1 || din < 1 || dh < 1 || dout < 1) return -1;
+    return mlp_work_len(rows, din, dh, dout);
+}
+
+int warm_mlp_forward(int rows, int din, int dh, int dout, const float *params, const float *X, float *H, float *Y,
+                     void *hip_stream)
+{
+    if (rows < 1 || din < 1 || dh < 1 || dout < 1 || !params || !X || !H || !Y) {
+        set_error("warm_mlp_forward: bad argument");
+        return STOTREE_ERR_ARG;
+    }
+    return mlp_forward_impl(rows, din, dh, dout, params, X, H, Y, (hipStream_t)hip_stream);
+}
+
+int warm_mlp_backward(int rows, int din, int dh, int dout, const float *params, const float *X, const float *H,
+                      const float *dY, float *grad, float *work, void *hip_stream)
+{
+    if (rows < 1 || din < 1 || dh < 1 || dout < 1 || !params || !X || !H || !dY || !grad || !work) {
+        set_error("warm_mlp_backward: bad argument");
+        return STOTREE_ERR_ARG;
+    }
+    return mlp_backward_impl(rows, din, dh, dout, params, X, H, dY, grad, work, (hipStream_t)hip_stream);
+}
+
+int warm_mse_grad(int64_t n, const float *Y, const float *T, const float *mask, float inv_count, float *dY,
+                  double *loss2, double *part, void *hip_stream)
+{
+    if (n < 1 || !Y || !T || !mask || !dY || !loss2 || !part) {
+        set_error("warm_mse_grad: bad argument");
+        return STOTREE_ERR_ARG;
+    }
+    return mse_grad_impl(n, Y, T, mask, inv_count, dY, loss2, part, (hipStream_t)hip_stream);
+}
+
+int warm_adam(int64_t n, float *params, const float *grad, float *m, float *v, float lr, float beta1, float beta2,
+              float eps, int step, void *hip_stream)
+{
+    if (n < 1 || !params || !grad || !m || !v || step < 1) {
+        set_error("warm_adam: bad argument");
+        return STOTREE_ERR_ARG;
+    }
+    return adam_impl(n, params, grad, m, v, lr, beta1, beta2, eps, step, (hipStream_t)hip_stream);
+}
+
+int warm_features(const tree_factors *f, const double *x0, float c_scale, float *X, void *hip_stream)
+{
+    if (!f || !x0 || !X || !(c_scale > 0.0f)) { set_error("warm_features: bad argument"); return STOTREE_ERR_ARG; }
+    return warm_features_impl(f, x0, c_scale, X, (hipStream_t)hip_stream);
+}
+
+int warm_scatter(const tree_factors *f, const float *Y, float y_scale, double *y, void *hip_stream)
+{
+    if (!f || !Y || !y) { set_error("warm_scatter: bad argument"); return STOTREE_ERR_ARG; }
+    return warm_scatter_impl(f, Y, y_scale, y, (hipStream_t)hip_stream);
+}
+
+int warm_targets(const tree_factors *f, const double *y, float y_scale, float *T, float *mask, void *hip_stream)
+{
+    if (!f || !y || !T || !mask || !(y_scale > 0.0f)) { set_error("warm_targets: bad argument"); return STOTREE_ERR_ARG; }
+    return warm_targets_impl(f, y, y_scale, T, mask, (hipStream_t)hip_stream);
+}
+
+int dual_select(const tree_factors *f, double *y, const int32_t *keep, void *hip_stream)
+{
+    if (!f || !y || !keep) { set_error("dual_select: bad argument"); return STOTREE_ERR_ARG; }
+    for (int b = 0; b < f->ninst; ++b)
+        if (!keep[b])
+            STOTREE_HIP(hipMemsetAsync(y + f->inst[b].y, 0, sizeof(double) * f->inst[b].m, (hipStream_t)hip_stream));
+    return STOTREE_OK;
+}
+
 int stotree_timing(int enable) { return timing_enable(enable); }
 
 int stotree_timing_read(double *ms, int64_t *count)

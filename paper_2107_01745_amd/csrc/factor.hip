@@ -343,7 +343,7 @@ int trunk_waves(int n, int nrhs_max, int ldM, int cap)
 void free_tree(tree_factors *f)
 {
     if (!f) return;
-    for (void *p : {(void *)f->d_inst, (void *)f->d_sp, (void *)f->d_cp, (void *)f->Mb, (void *)f->Mf,
+    for (void *p : {(void *)f->d_inst, (void *)f->d_sp, (void *)f->d_cp, (void *)f->d_anc, (void *)f->Mb, (void *)f->Mf,
                     (void *)f->Kb, (void *)f->Kf, (void *)f->Rn, (void *)f->chat, (void *)f->sig,
                     (void *)f->cvec, (void *)f->sc, (void *)f->lo, (void *)f->hi, (void *)f->qhat,
                     (void *)f->kbuf, (void *)f->sws.buf, (void *)f->chain_items})
@@ -481,6 +481,7 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
     };
     int rc;
     if ((rc = dalloc(&f->d_inst, count)) || (rc = dalloc(&f->d_sp, osp)) || (rc = dalloc(&f->d_cp, ocp)) ||
+        (rc = dalloc(&f->d_anc, osc)) ||
         (rc = dalloc(&f->Mb, oMb)) || (rc = dalloc(&f->Mf, oMf)) || (rc = dalloc(&f->Kb, oKb)) ||
         (rc = dalloc(&f->Kf, oKf)) || (rc = dalloc(&f->Rn, oRn)) || (rc = dalloc(&f->chat, ochat)) ||
         (rc = dalloc(&f->sig, osig)) || (rc = dalloc(&f->cvec, ochat)) || (rc = dalloc(&f->sc, osc)) ||
@@ -489,6 +490,9 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
     STOTREE_HIP(hipMemcpy(f->d_inst, f->inst.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice));
     STOTREE_HIP(hipMemcpy(f->d_sp, f->sp_pool.data(), sizeof(int) * osp, hipMemcpyHostToDevice));
     STOTREE_HIP(hipMemcpy(f->d_cp, cp_pool.data(), sizeof(int) * ocp, hipMemcpyHostToDevice));
+    for (int b = 0; b < count; ++b)
+        STOTREE_HIP(hipMemcpy(f->d_anc + f->inst[b].sc, trees[b].ancestor, sizeof(int) * f->inst[b].V,
+                              hipMemcpyHostToDevice));
     // box rows in the dual layout (a data rearrangement, no arithmetic)
     {
         std::vector<double> lo((size_t)oy), hi((size_t)oy);

@@ -88,7 +88,7 @@ struct tree_factors {
     std::vector<stotree::InstDesc> inst;    // host copy
     stotree::InstDesc *d_inst = nullptr;
     std::vector<int> sp_pool;               // host copy of the stage pointers
-    int *d_sp = nullptr, *d_cp = nullptr;
+    int *d_sp = nullptr, *d_cp = nullptr, *d_anc = nullptr;  // anc: node-indexed (sc offsets)
     double *Mb = nullptr, *Mf = nullptr, *Kb = nullptr, *Kf = nullptr, *Rn = nullptr;
     double *chat = nullptr, *sig = nullptr, *cvec = nullptr, *sc = nullptr;
     double *lo = nullptr, *hi = nullptr;    // unscaled box rows in the dual layout
@@ -125,6 +125,21 @@ int ensure_sweep_ws(tree_factors *f, int nrhs);
 hipError_t launch_sweep_tree(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st);
 int timing_enable(int on);
 int timing_read(double *ms, long long *count);
+
+// warm.hip
+long long mlp_param_count(int din, int dh, int dout);
+long long mlp_work_len(int rows, int din, int dh, int dout);
+int mlp_forward_impl(int rows, int din, int dh, int dout, const float *P, const float *X, float *H, float *Y,
+                     hipStream_t st);
+int mlp_backward_impl(int rows, int din, int dh, int dout, const float *P, const float *X, const float *H,
+                      const float *dY, float *G, float *work, hipStream_t st);
+int mse_grad_impl(long long n, const float *Y, const float *T, const float *mask, float inv_count, float *dY,
+                  double *loss2, double *part, hipStream_t st);
+int adam_impl(long long n, float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
+              int step, hipStream_t st);
+int warm_features_impl(const tree_factors *f, const double *x0, float c_scale, float *X, hipStream_t st);
+int warm_scatter_impl(const tree_factors *f, const float *Y, float y_scale, double *y, hipStream_t st);
+int warm_targets_impl(const tree_factors *f, const double *y, float y_scale, float *T, float *mask, hipStream_t st);
 
 // solver.hip
 int solve(const tree_factors *f, const double *x0, const solver_opts *opts, double *y,

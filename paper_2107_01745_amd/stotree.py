@@ -57,7 +57,10 @@ class SolverInfo(C.Structure):
 
 EXPORTS = ("tree_factor", "tree_factor_batch", "tree_factors_free", "tree_dims",
            "tree_instance_dims", "dual_grad", "dual_lipschitz", "minfbe_solve", "nama_solve",
-           "solve_info_batch", "stotree_timing", "stotree_timing_read", "stotree_last_error")
+           "solve_info_batch", "stotree_timing", "stotree_timing_read", "stotree_last_error",
+           "warm_mlp_params", "warm_mlp_work_len", "warm_mlp_forward", "warm_mlp_backward",
+           "warm_mse_grad", "warm_adam", "warm_features", "warm_scatter", "warm_targets",
+           "dual_select")
 PHASES = ("bwd_chain", "bwd_stages", "fwd_stages", "fwd_chain")
 
 _lib = None
@@ -262,3 +265,82 @@ def stotree_timing_read() -> dict:
     cnt = (C.c_int64 * 4)()
     _check(lib().stotree_timing_read(ms, cnt))
     return {PHASES[p]: (ms[p], int(cnt[p])) for p in range(4)}
+
+
+# ---------------------------- learned warm start ----------------------------
+def _warm_sigs(L):
+    vp, f32 = C.c_void_p, C.c_float
+    L.warm_mlp_params.argtypes = [C.c_int, C.c_int, C.c_int]
+    L.warm_mlp_params.restype = C.c_int64
+    L.warm_mlp_work_len.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+    L.warm_mlp_work_len.restype = C.c_int64
+    L.warm_mlp_forward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp]
+    L.warm_mlp_backward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]
+    L.warm_mse_grad.argtypes = [C.c_int64, vp, vp, vp, f32, vp, vp, vp, vp]
+    L.warm_adam.argtypes = [C.c_int64, vp, vp, vp, vp, f32, f32, f32, f32, C.c_int, vp]
+    L.warm_features.argtypes = [vp, vp, f32, vp, vp]
+    L.warm_scatter.argtypes = [vp, vp, f32, vp, vp]
+    L.warm_targets.argtypes = [vp, vp, f32, vp, vp, vp]
+    L.dual_select.argtypes = [vp, vp, C.POINTER(C.c_int32), vp]
+    for fn in (L.warm_mlp_forward, L.warm_mlp_backward, L.warm_mse_grad, L.warm_adam, L.warm_features,
+               L.warm_scatter, L.warm_targets, L.dual_select):
+        fn.restype = C.c_int
+
+
+def _wl():
+    L = lib()
+    if not getattr(L, "_warm_ready", False):
+        _warm_sigs(L)
+        L._warm_ready = True
+    return L
+
+
+def _fptr(t):
+    """Raw device pointer of a contiguous tensor of any dtype."""
+    assert t.is_cuda and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+def warm_mlp_params(din, dh, dout) -> int:
+    return int(_wl().warm_mlp_params(din, dh, dout))
+
+
+def warm_mlp_work_len(rows, din, dh, dout) -> int:
+    return int(_wl().warm_mlp_work_len(rows, din, dh, dout))
+
+
+def warm_mlp_forward(rows, din, dh, dout, params, X, H, Y, stream=None):
+    _check(_wl().warm_mlp_forward(rows, din, dh, dout, _fptr(params), _fptr(X), _fptr(H), _fptr(Y),
+                                  _stream(stream)))
+
+
+def warm_mlp_backward(rows, din, dh, dout, params, X, H, dY, grad, work, stream=None):
+    _check(_wl().warm_mlp_backward(rows, din, dh, dout, _fptr(params), _fptr(X), _fptr(H), _fptr(dY),
+                                   _fptr(grad), _fptr(work), _stream(stream)))
+
+
+def warm_mse_grad(n, Y, T, mask, inv_count, dY, loss2, part, stream=None):
+    _check(_wl().warm_mse_grad(n, _fptr(Y), _fptr(T), _fptr(mask), float(inv_count), _fptr(dY),
+                               _fptr(loss2), _fptr(part), _stream(stream)))
+
+
+def warm_adam(n, params, grad, m, v, lr, beta1, beta2, eps, step, stream=None):
+    _check(_wl().warm_adam(n, _fptr(params), _fptr(grad), _fptr(m), _fptr(v), float(lr), float(beta1),
+                           float(beta2), float(eps), int(step), _stream(stream)))
+
+
+def warm_features(tf, x0, c_scale, X, stream=None):
+    _check(_wl().warm_features(tf.handle, _fptr(x0), float(c_scale), _fptr(X), _stream(stream)))
+
+
+def warm_scatter(tf, Y, y_scale, y, stream=None):
+    _check(_wl().warm_scatter(tf.handle, _fptr(Y), float(y_scale), _fptr(y), _stream(stream)))
+
+
+def warm_targets(tf, y, y_scale, T, mask, stream=None):
+    _check(_wl().warm_targets(tf.handle, _fptr(y), float(y_scale), _fptr(T), _fptr(mask), _stream(stream)))
+
+
+def dual_select(tf, y, keep, stream=None):
+    keep = (C.c_int32 * tf.ninst)(*[int(bool(k)) for k in keep])
+    _check(_wl().dual_select(tf.handle, _fptr(y), keep, _stream(stream)))

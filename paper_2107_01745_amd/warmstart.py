@@ -1,0 +1,140 @@
+"""Learned warm start driver (Python orchestration of the library's kernels).
+
+Data: the batched NAMA solver produces the optimal (preconditioned) duals of
+many draws (x0, disturbance path) on one fixed tree.  Training: the MLP's
+forward, loss-gradient, backward and Adam kernels (include/stotree.h).
+Use: predict a dual per instance, keep it only where the solver's residual at
+the prediction is below the residual at zero (the cold start), then solve.
+Every arithmetic step runs in the library; this module only moves buffers.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import stotree
+
+C_SCALE = 0.1   # standard deviation of the disturbances: feature normalisation
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def solve_batch(probs, lam, *, method="nama", eps=1e-6, max_iter=2000, y0=None, tf=None):
+    """Batched solve of a list of instances; returns (tf, y, infos, seconds)."""
+    own = tf is None
+    if own:
+        tf = stotree.tree_factor_batch(probs, precondition=True)
+    x0 = torch.tensor(np.concatenate([p.x0 for p in probs]), dtype=torch.float64, device=_dev())
+    y = torch.zeros(tf.m, dtype=torch.float64, device=_dev()) if y0 is None else y0
+    x = torch.empty(tf.x_len, dtype=torch.float64, device=_dev())
+    u = torch.empty(tf.u_len, dtype=torch.float64, device=_dev())
+    fn = stotree.nama_solve if method == "nama" else stotree.minfbe_solve
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn(tf, x0, y, x, u, stotree.make_opts(lam=lam, eps=eps, max_iter=max_iter))
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    return tf, y, stotree.solve_info_batch(tf), sec
+
+
+class WarmStartMLP:
+    """Node-wise MLP din -> dh -> dh -> nx+nu with parameters on the GPU."""
+
+    def __init__(self, nx, nu, N, dh=128, seed=0):
+        self.nx, self.nu, self.N, self.dh = nx, nu, N, dh
+        self.din, self.dout = 3 * nx + N + 1, nx + nu
+        n = stotree.warm_mlp_params(self.din, dh, self.dout)
+        rng = np.random.default_rng(seed)
+        p = np.zeros(n, dtype=np.float32)
+        k = 0
+        for fan_in, fan_out in ((self.din, dh), (dh, dh), (dh, self.dout)):
+            lim = np.sqrt(6.0 / fan_in)            # He-uniform for ReLU layers
+            p[k:k + fan_in * fan_out] = rng.uniform(-lim, lim, fan_in * fan_out)
+            k += fan_in * fan_out + fan_out        # biases start at zero
+        self.params = torch.tensor(p, device=_dev())
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.step = 0
+        self.y_scale = 1.0
+
+    def features(self, tf, x0):
+        X = torch.empty(tf.V, self.din, dtype=torch.float32, device=_dev())
+        stotree.warm_features(tf, x0, C_SCALE, X)
+        return X
+
+    def targets(self, tf, y):
+        T = torch.empty(tf.V, self.dout, dtype=torch.float32, device=_dev())
+        M = torch.empty_like(T)
+        stotree.warm_targets(tf, y, self.y_scale, T, M)
+        return T, M
+
+    def forward(self, X):
+        rows = X.shape[0]
+        H = torch.empty(rows, 2 * self.dh, dtype=torch.float32, device=_dev())
+        Y = torch.empty(rows, self.dout, dtype=torch.float32, device=_dev())
+        stotree.warm_mlp_forward(rows, self.din, self.dh, self.dout, self.params, X, H, Y)
+        return H, Y
+
+    def predict(self, tf, x0, y_out):
+        """Predicted dual of every instance of tf into y_out."""
+        X = self.features(tf, x0)
+        _, Y = self.forward(X)
+        stotree.warm_scatter(tf, Y, self.y_scale, y_out)
+
+    def fit(self, X, T, M, *, epochs=30, batch_rows=65536, lr=1e-3, seed=0, log=None):
+        rows = X.shape[0]
+        work = torch.empty(stotree.warm_mlp_work_len(batch_rows, self.din, self.dh, self.dout),
+                           dtype=torch.float32, device=_dev())
+        H = torch.empty(batch_rows, 2 * self.dh, dtype=torch.float32, device=_dev())
+        Y = torch.empty(batch_rows, self.dout, dtype=torch.float32, device=_dev())
+        dY = torch.empty_like(Y)
+        loss2 = torch.zeros(2, dtype=torch.float64, device=_dev())
+        part = torch.zeros(512, dtype=torch.float64, device=_dev())
+        rng = np.random.default_rng(seed)
+        history = []
+        for ep in range(epochs):
+            order = torch.tensor(rng.permutation(rows), device=_dev())
+            tot, cnt = 0.0, 0.0
+            for s in range(0, rows - batch_rows + 1, batch_rows):
+                idx = order[s:s + batch_rows]
+                Xb, Tb, Mb = X[idx].contiguous(), T[idx].contiguous(), M[idx].contiguous()
+                stotree.warm_mlp_forward(batch_rows, self.din, self.dh, self.dout, self.params, Xb, H, Y)
+                nmask = float(Mb.sum().item())
+                stotree.warm_mse_grad(Y.numel(), Y, Tb, Mb, 1.0 / max(nmask, 1.0), dY, loss2, part)
+                stotree.warm_mlp_backward(batch_rows, self.din, self.dh, self.dout, self.params, Xb, H, dY,
+                                          self.grad, work)
+                self.step += 1
+                stotree.warm_adam(self.params.numel(), self.params, self.grad, self.m, self.v, lr, 0.9, 0.999,
+                                  1e-8, self.step)
+                l2 = loss2.cpu().numpy()
+                tot += l2[0]
+                cnt += l2[1]
+            history.append(tot / max(cnt, 1.0))
+            if log:
+                log(f"epoch {ep}: masked MSE {history[-1]:.4e}")
+        return history
+
+
+def warm_start_duals(model, tf, probs, lam):
+    """Predicted duals with the cold start kept wherever the solver's residual
+    at the prediction is not below its residual at zero."""
+    x0 = torch.tensor(np.concatenate([p.x0 for p in probs]), dtype=torch.float64, device=_dev())
+    yw = torch.empty(tf.m, dtype=torch.float64, device=_dev())
+    model.predict(tf, x0, yw)
+    x = torch.empty(tf.x_len, dtype=torch.float64, device=_dev())
+    u = torch.empty(tf.u_len, dtype=torch.float64, device=_dev())
+    opts = stotree.make_opts(lam=lam, eps=0.0, max_iter=0)
+    probe = yw.clone()
+    stotree.nama_solve(tf, x0, probe, x, u, opts)
+    rw = [i["res_scaled_inf"] for i in stotree.solve_info_batch(tf)]
+    probe.zero_()
+    stotree.nama_solve(tf, x0, probe, x, u, opts)
+    rc = [i["res_scaled_inf"] for i in stotree.solve_info_batch(tf)]
+    keep = [a <= b for a, b in zip(rw, rc)]
+    stotree.dual_select(tf, yw, keep)
+    return yw, keep

@@ -1,0 +1,163 @@
+"""GPU parity of the learned warm start's kernels (features, MLP forward,
+loss gradient, backward, Adam, dual scatter) against the FP64 NumPy oracle
+(oracle/mlp.py), and the warm-start path end to end on a small tree."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.mlp as om
+import treegen
+
+pytestmark = pytest.mark.gpu
+
+DIN, DH, DOUT = 76, 128, 30
+
+
+@pytest.fixture(scope="module")
+def st():
+    import torch
+    from paper_2107_01745_amd import stotree
+    assert torch.cuda.is_available()
+    stotree.lib()
+    return stotree
+
+
+def _f32(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda:0")
+
+
+def _net(seed, rows):
+    rng = np.random.default_rng(seed)
+    n = om.layout(DIN, DH, DOUT)["n"]
+    p = (rng.standard_normal(n) * 0.1).astype(np.float32)
+    X = rng.standard_normal((rows, DIN)).astype(np.float32)
+    T = rng.standard_normal((rows, DOUT)).astype(np.float32)
+    M = (rng.random((rows, DOUT)) > 0.2).astype(np.float32)
+    return p, X, T, M
+
+
+def test_forward_backward_loss_match_oracle(st):
+    import torch
+    rows = 3001
+    p, X, T, M = _net(0, rows)
+    assert st.warm_mlp_params(DIN, DH, DOUT) == p.size
+    P, Xd, Td, Md = _f32(p), _f32(X), _f32(T), _f32(M)
+    H = torch.empty(rows, 2 * DH, dtype=torch.float32, device="cuda:0")
+    Y = torch.empty(rows, DOUT, dtype=torch.float32, device="cuda:0")
+    st.warm_mlp_forward(rows, DIN, DH, DOUT, P, Xd, H, Y)
+    H1, H2, Yo = om.forward(p, X, DIN, DH, DOUT)
+    torch.cuda.synchronize()
+    assert np.abs(Y.cpu().numpy() - Yo).max() <= 1e-4 * max(1.0, np.abs(Yo).max())
+    dY = torch.empty_like(Y)
+    loss2 = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+    part = torch.zeros(512, dtype=torch.float64, device="cuda:0")
+    st.warm_mse_grad(Y.numel(), Y, Td, Md, 1.0 / float(M.sum()), dY, loss2, part)
+    lo, dYo = om.mse(Y.cpu().numpy(), T, M)
+    l2 = loss2.cpu().numpy()
+    assert abs(l2[0] / l2[1] - lo) <= 1e-5 * max(1.0, lo) and l2[1] == M.sum()
+    assert np.abs(dY.cpu().numpy() - dYo).max() <= 1e-5 * max(1e-30, np.abs(dYo).max())
+    G = torch.empty_like(P)
+    work = torch.empty(st.warm_mlp_work_len(rows, DIN, DH, DOUT), dtype=torch.float32, device="cuda:0")
+    st.warm_mlp_backward(rows, DIN, DH, DOUT, P, Xd, H, dY, G, work)
+    # H holds the layer-1 activations (rows x dh) followed by layer 2's
+    Hg = H.cpu().numpy().astype(np.float64).reshape(2, rows, DH)
+    assert np.abs(Hg[0] - H1).max() <= 1e-4 * max(1.0, np.abs(H1).max())
+    assert np.abs(Hg[1] - H2).max() <= 1e-4 * max(1.0, np.abs(H2).max())
+    go = om.backward(p, X, H1, H2, dY.cpu().numpy(), DIN, DH, DOUT)
+    torch.cuda.synchronize()
+    g = G.cpu().numpy()
+    assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max()
+    # deterministic reductions
+    G2 = torch.empty_like(P)
+    st.warm_mlp_backward(rows, DIN, DH, DOUT, P, Xd, H, dY, G2, work)
+    assert torch.equal(G, G2)
+
+
+def test_adam_matches_oracle(st):
+    rng = np.random.default_rng(1)
+    n = 1000
+    p, g = rng.standard_normal(n).astype(np.float32), rng.standard_normal(n).astype(np.float32)
+    m, v = (rng.random(n) * 0.1).astype(np.float32), (rng.random(n) * 0.1).astype(np.float32)
+    P, Gd, Md, Vd = _f32(p), _f32(g), _f32(m), _f32(v)
+    st.warm_adam(n, P, Gd, Md, Vd, 1e-3, 0.9, 0.999, 1e-8, 7)
+    po, mo, vo = om.adam(p.astype(np.float64), g, m, v, 1e-3, 0.9, 0.999, 1e-8, 7)
+    assert np.abs(P.cpu().numpy() - po).max() <= 1e-6
+    assert np.abs(Md.cpu().numpy() - mo).max() <= 1e-6 and np.abs(Vd.cpu().numpy() - vo).max() <= 1e-6
+
+
+def small_base():
+    base = treegen.draw_problem(treegen.uniform_tree([3, 2, 1, 1]), 6, 3, np.random.default_rng(8))
+    return treegen.with_boxes(base, 5.0, 0.3)
+
+
+def test_features_and_dual_maps_match_oracle(st):
+    import torch
+    base = small_base()
+    probs = treegen.draw_warm_instances(base, 3, seed=4)
+    tf = st.tree_factor_batch(probs, precondition=True)
+    x0 = torch.tensor(np.concatenate([p.x0 for p in probs]), device="cuda:0")
+    din = 3 * base.nx + base.tree.N + 1
+    X = torch.empty(tf.V, din, dtype=torch.float32, device="cuda:0")
+    st.warm_features(tf, x0, 0.1, X)
+    Xh = X.cpu().numpy()
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal(tf.m)
+    T = torch.empty(tf.V, base.nx + base.nu, dtype=torch.float32, device="cuda:0")
+    Mk = torch.empty_like(T)
+    st.warm_targets(tf, torch.tensor(y, device="cuda:0"), 2.0, T, Mk)
+    Th, Mh = T.cpu().numpy(), Mk.cpu().numpy()
+    row = 0
+    for b, p in enumerate(probs):
+        d = tf.instances[b]
+        Xo = om.features(p, p.x0, 0.1)
+        assert np.abs(Xh[row:row + d["V"]] - Xo).max() <= 1e-5 * max(1.0, np.abs(Xo).max())
+        To, Mo = om.dual_to_rows(p, y[d["y_off"]:d["y_off"] + d["m"]])
+        assert np.array_equal(Mh[row:row + d["V"]], Mo)
+        assert np.abs(Th[row:row + d["V"]] * 2.0 - To * Mo).max() <= 1e-6 * np.abs(To).max()
+        row += d["V"]
+    yb = torch.empty(tf.m, dtype=torch.float64, device="cuda:0")
+    st.warm_scatter(tf, T, 2.0, yb)
+    yr = yb.cpu().numpy()
+    for b, p in enumerate(probs):
+        d = tf.instances[b]
+        seg = y[d["y_off"]:d["y_off"] + d["m"]].copy()
+        seg[:p.nx] = 0.0
+        assert np.abs(yr[d["y_off"]:d["y_off"] + d["m"]] - seg).max() <= 1e-6 * np.abs(seg).max()
+    tf.free()
+
+
+def test_training_reduces_loss_and_warm_start_helps(st):
+    """Train on solver-generated duals of a small tree; the trained network's
+    warm start keeps the tolerance and does not need more iterations than the
+    cold start on held-out draws (the residual-judged fallback guarantees the
+    start is never worse in residual)."""
+    from paper_2107_01745_amd import warmstart as ws
+    base = small_base()
+    pb, fac = oracle.factor(base)
+    lam = 1.0 / (1.1 * oracle.power_iteration(pb, fac, True, 300))
+    train = treegen.draw_warm_instances(base, 48, seed=10)
+    tf, y, infos, _ = ws.solve_batch(train, lam, eps=1e-9)
+    assert all(i["status"] == 0 for i in infos)
+    model = ws.WarmStartMLP(base.nx, base.nu, base.tree.N, dh=64, seed=0)
+    nz = y.abs()[y.abs() > 0]
+    model.y_scale = float(nz.pow(2).mean().sqrt().item()) if nz.numel() else 1.0
+    import torch
+    x0 = torch.tensor(np.concatenate([p.x0 for p in train]), device="cuda:0")
+    X = model.features(tf, x0)
+    T, M = model.targets(tf, y)
+    hist = model.fit(X, T, M, epochs=60, batch_rows=512, lr=3e-3)
+    assert hist[-1] < 0.5 * hist[0], hist[::10]
+    tf.free()
+    test = treegen.draw_warm_instances(base, 16, seed=99)
+    tf_c, _, info_c, _ = ws.solve_batch(test, lam, eps=1e-8)
+    it_cold = np.mean([i["iters"] for i in info_c])
+    tf_c.free()
+    tf_w = st.tree_factor_batch(test, precondition=True)
+    yw, keep = ws.warm_start_duals(model, tf_w, test, lam)
+    _, _, info_w, _ = ws.solve_batch(test, lam, eps=1e-8, y0=yw, tf=tf_w)
+    assert all(i["status"] == 0 and i["res_scaled_inf"] <= 1e-8 for i in info_w)
+    it_warm = np.mean([i["iters"] for i in info_w])
+    print(f"iterations cold {it_cold:.1f}, warm {it_warm:.1f}, kept {sum(keep)}/{len(keep)}", flush=True)
+    assert it_warm <= it_cold
+    tf_w.free()

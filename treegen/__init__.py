@@ -280,3 +280,31 @@ def random_dual(prob: Problem, rng: np.random.Generator, nrhs: int | None = None
     """Gaussian dual vector(s) of the problem's dual dimension."""
     shape = (prob.m,) if nrhs is None else (nrhs, prob.m)
     return scale * rng.standard_normal(shape)
+
+
+def draw_warm_instances(base: Problem, count: int, seed: int, *, x0_range: float = 3.0,
+                        c_std: float = 0.1) -> list:
+    """Instances of a fixed tree and fixed matrices that differ only in the
+    initial state x0 ~ U[-x0_range, x0_range]^nx and the disturbance path
+    c_j ~ N(0, c_std^2) (the learned warm start's training and held-out draws)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        x0 = rng.uniform(-x0_range, x0_range, base.nx)
+        c = np.zeros_like(base.c)
+        c[1:] = c_std * rng.standard_normal(c[1:].shape)
+        out.append(dataclasses.replace(base, c=c, x0=x0, name=f"{base.name}-draw{k}"))
+    return out
+
+
+def with_boxes(prob: Problem, xbox: float | None = None, ubox: float | None = None) -> Problem:
+    """The same problem with uniform boxes |x| <= xbox (root free), |u| <= ubox."""
+    xmin, xmax, umin, umax = prob.xmin, prob.xmax, prob.umin, prob.umax
+    if xbox is not None:
+        xmin = np.full_like(prob.xmin, -xbox)
+        xmax = np.full_like(prob.xmax, xbox)
+        xmin[0], xmax[0] = -np.inf, np.inf
+    if ubox is not None:
+        umin = np.full_like(prob.umin, -ubox)
+        umax = np.full_like(prob.umax, ubox)
+    return dataclasses.replace(prob, xmin=xmin, xmax=xmax, umin=umin, umax=umax)
