@@ -125,6 +125,181 @@ def cpu_baseline(prob, seconds=10.0):
                        f"sweep flop ratio {ratio:.4f}; host {cpu}, nproc {os.cpu_count()}")}
 
 
+def batched_leg(stotree, torch, steps, warmup, cache):
+    """Config 2: 256 independent trees (nx ~ U{8..32}, nu = nx/2, N ~ U{10..30},
+    16..1024 scenarios, first-stage branching 2..8) in one handle.  The
+    schedule is autotuned on the device (or read from the cache), the
+    dual-gradient sweep of all 256 trees is recorded once as a HIP graph, and
+    a step is one replay.  Reports instance-sweeps/s, HBM roofline fraction
+    against the algorithmic bytes of the 256 sweeps, the eager (un-recorded)
+    rate, and the inner-problem KKT residual of three sampled instances."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_cases import inner_kkt_residual
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    probs = treegen.draw_batch_instances(256)
+    gen_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tf = stotree.tree_factor_batch(probs, precondition=True)
+    factor_s = time.perf_counter() - t0
+    log(f"config 2: {len(probs)} trees, {tf.V} nodes, drawn in {gen_s:.1f} s, factored in {factor_s:.1f} s, "
+        f"{tf.device_bytes / 1e9:.1f} GB on device")
+    nbytes, flops = 0, 0.0
+    for p, d in zip(probs, tf.instances):
+        nbytes += sum(phase_bytes(p, d["sstar"]).values())
+        flops += sweep_flops(p)
+    t0 = time.perf_counter()
+    tune = stotree.sweep_autotune(tf, nrhs=1, reps=3, cache=cache)
+    tune_s = time.perf_counter() - t0
+    log(f"config 2 schedule {tune['knobs']} ({'cached' if tune['cached'] else 'tuned'} in {tune_s:.1f} s)")
+    rng = np.random.default_rng(12)
+    y = torch.tensor(rng.standard_normal(tf.m), dtype=torch.float64, device=dev)
+    x0 = torch.tensor(np.concatenate([p.x0 for p in probs]), dtype=torch.float64, device=dev)
+    x = torch.empty(tf.x_len, dtype=torch.float64, device=dev)
+    u = torch.empty(tf.u_len, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    for _ in range(warmup):
+        stotree.dual_grad(tf, x0, y, False, x, u)
+    eager_ms = timed(lambda: stotree.dual_grad(tf, x0, y, False, x, u), steps)
+    graph = stotree.SweepGraph(tf, x0, y, False, x, u)
+    for _ in range(warmup):
+        graph.launch()
+    graph_ms = timed(graph.launch, steps)
+    stotree.stotree_timing(True)
+    for _ in range(5):
+        stotree.dual_grad(tf, x0, y, False, x, u)
+    torch.cuda.synchronize()
+    stotree.stotree_timing(False)
+    phases = {k: v[0] / max(1, v[1]) for k, v in stotree.stotree_timing_read().items()}
+    graph.launch()
+    torch.cuda.synchronize()
+    xh, uh, yh = x.cpu().numpy(), u.cpu().numpy(), y.cpu().numpy()
+    worst = 0.0
+    for b in (0, int(np.argmax([d["V"] for d in tf.instances])), 255):
+        d, p = tf.instances[b], probs[b]
+        tr = p.tree
+        w = np.where(np.arange(tr.V) < tr.Vnl, p.nx + p.nu, p.nx)
+        yb = yh[d["y_off"]:d["y_off"] + d["m"]] * np.repeat(np.sqrt(tr.prob), w)
+        xb = xh[d["x_off"]:d["x_off"] + d["V"] * d["nx"]].reshape(d["V"], d["nx"])
+        ub = uh[d["u_off"]:d["u_off"] + d["Vnl"] * d["nu"]].reshape(d["Vnl"], d["nu"])
+        worst = max(worst, *inner_kkt_residual(p, yb, xb, ub, p.x0))
+    graph.free()
+    tf.free()
+    gbs = nbytes / (graph_ms * 1e-3) / 1e9
+    rep = {"workload": "config 2: 256 uneven trees (seed 1002), one handle, one graph replay per step",
+           "trees": 256, "nodes": int(tf.V), "m": int(tf.m), "generation_s": gen_s, "factor_s": factor_s,
+           "schedule": tune, "tune_s": tune_s, "ms_per_step_graph": graph_ms, "ms_per_step_eager": eager_ms,
+           "instance_sweeps_per_s": 256 * 1000.0 / graph_ms, "batched_sweeps_per_s": 1000.0 / graph_ms,
+           "bytes_per_step": nbytes, "flops_per_step": flops,
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS},
+           "phases_eager_ms": phases, "inner_kkt_residual_sampled": worst}
+    log(f"config 2: graph {graph_ms:.3f} ms/step, eager {eager_ms:.3f} ms ({256e3 / graph_ms:.0f} "
+        f"instance sweeps/s, {gbs:.0f} GB/s = {100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak); "
+        f"phases {phases}; KKT residual {worst:.1e}")
+    return rep
+
+
+def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
+    """Config 3 (nx=20, nu=10, N=15, branching 3 at stages 0-4; |u| <= 0.2 so
+    that the boxes bind): train the warm-start MLP on solver-generated duals
+    of n_train draws (x0, disturbance path), then compare on n_test held-out
+    draws the plain cold-start per-instance NAMA solves with the learned warm
+    start + batched solves (time to a 1e-6 residual, factor step excluded in
+    both; the warm side includes prediction and the residual check)."""
+    from paper_2107_01745_amd import warmstart as ws
+    dev = torch.device("cuda:0")
+    base = treegen.with_boxes(treegen.make_config(3), 5.0, 0.2)
+    tf0 = stotree.tree_factor(base, precondition=True)
+    lam = 1.0 / (1.1 * stotree.dual_lipschitz(tf0, 200))
+    tf0.free()
+    model = ws.WarmStartMLP(base.nx, base.nu, base.tree.N, dh=128, seed=0)
+    train = treegen.draw_warm_instances(base, n_train, seed=2003)
+    Xs, Ts, Ms = [], [], []
+    t0 = time.perf_counter()
+    gen_iters = []
+    for s in range(0, n_train, batch):
+        chunk = train[s:s + batch]
+        tf, y, infos, _ = ws.solve_batch(chunk, lam, eps=1e-6)
+        if s == 0:
+            nz = y.abs()[y.abs() > 0]
+            model.y_scale = float(nz.pow(2).mean().sqrt().item()) if nz.numel() else 1.0
+        x0 = torch.tensor(np.concatenate([p.x0 for p in chunk]), dtype=torch.float64, device=dev)
+        X = model.features(tf, x0)
+        T, M = model.targets(tf, y)
+        row = 0
+        for b, info in enumerate(infos):
+            V = tf.instances[b]["V"]
+            if info["status"] != 0:
+                M[row:row + V] = 0.0        # unsolved draws do not train
+            row += V
+            gen_iters.append(info["iters"])
+        Xs.append(X); Ts.append(T); Ms.append(M)
+        tf.free()
+    gen_s = time.perf_counter() - t0
+    X, T, M = torch.cat(Xs), torch.cat(Ts), torch.cat(Ms)
+    del Xs, Ts, Ms
+    log(f"warm leg: {n_train} training solves in {gen_s:.1f} s ({X.shape[0]} node rows)")
+    t0 = time.perf_counter()
+    hist = model.fit(X, T, M, epochs=epochs, batch_rows=65536, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"warm leg: {epochs} epochs in {train_s:.1f} s, masked MSE {hist[0]:.3e} -> {hist[-1]:.3e}")
+    del X, T, M
+    test = treegen.draw_warm_instances(base, n_test, seed=2004)
+    cold_b, warm_b, it_c, it_w, kept, ok_w = 0.0, 0.0, [], [], 0, 0
+    for s in range(0, n_test, batch):
+        chunk = test[s:s + batch]
+        tf = stotree.tree_factor_batch(chunk, precondition=True)
+        _, _, info_c, sec_c = ws.solve_batch(chunk, lam, eps=1e-6, tf=tf)
+        cold_b += sec_c
+        it_c += [i["iters"] for i in info_c]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        yw, keep = ws.warm_start_duals(model, tf, chunk, lam)
+        torch.cuda.synchronize()
+        pred_s = time.perf_counter() - t0
+        _, _, info_w, sec_w = ws.solve_batch(chunk, lam, eps=1e-6, y0=yw, tf=tf)
+        warm_b += pred_s + sec_w
+        it_w += [i["iters"] for i in info_w]
+        ok_w += sum(i["status"] == 0 for i in info_w)
+        kept += sum(keep)
+        tf.free()
+    solo_s, it_solo = 0.0, []
+    for p in test[:n_solo]:
+        tf = stotree.tree_factor(p, precondition=True)
+        _, _, info, sec = ws.solve_batch([p], lam, eps=1e-6, tf=tf)
+        solo_s += sec
+        it_solo.append(info[0]["iters"])
+        tf.free()
+    solo_total = solo_s / max(1, n_solo) * n_test
+    rep = {"tree": "config 3 (2794 nodes), |u| <= 0.2", "lambda": lam, "n_train": n_train, "n_test": n_test,
+           "batch": batch, "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]],
+           "data_generation_s": gen_s, "train_s": train_s,
+           "iters_cold_mean": float(np.mean(it_c)), "iters_warm_mean": float(np.mean(it_w)),
+           "warm_kept": int(kept), "warm_converged": int(ok_w),
+           "cold_per_instance_s_total": solo_total, "cold_per_instance_sample": n_solo,
+           "cold_per_instance_iters_mean": float(np.mean(it_solo)),
+           "cold_batched_s_total": cold_b, "warm_batched_s_total": warm_b,
+           "speedup_warm_batched_vs_cold_per_instance": solo_total / warm_b,
+           "speedup_warm_vs_cold_batched": cold_b / warm_b}
+    log(f"warm leg: iters cold {rep['iters_cold_mean']:.1f} warm {rep['iters_warm_mean']:.1f}; "
+        f"cold per-instance {solo_total:.2f} s, cold batched {cold_b:.3f} s, warm batched {warm_b:.3f} s "
+        f"-> speedup {rep['speedup_warm_batched_vs_cold_per_instance']:.1f}x")
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +310,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--tight-u", type=float, default=0.1)
+    ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--tune-cache", default=None, help="JSON cache of tuned schedules (default: tune)")
+    ap.add_argument("--warm-train", type=int, default=1024)
+    ap.add_argument("--warm-test", type=int, default=256)
+    ap.add_argument("--warm-solo", type=int, default=32)
+    ap.add_argument("--warm-epochs", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design "
@@ -251,6 +433,15 @@ def main():
             solve_rep[vname] = rep
         tf_t.free()
 
+    batched_rep = None
+    if not args.no_batched:
+        batched_rep = batched_leg(stotree, torch, min(args.steps, 50), min(args.warmup, 5), args.tune_cache)
+
+    warm_rep = None
+    if not args.no_warm:
+        warm_rep = warm_leg(stotree, torch, args.warm_train, args.warm_test, args.warm_solo, 64,
+                            args.warm_epochs)
+
     cpu = None
     if not args.no_cpu:
         t0 = time.perf_counter()
@@ -270,6 +461,8 @@ def main():
         "phases": phase_rep,
         "cpu_baseline": cpu,
         "solve": solve_rep,
+        "batched": batched_rep,
+        "warm_start": warm_rep,
     }
     tf.free()
     print(json.dumps(rec))

@@ -170,6 +170,52 @@ int dual_grad(const tree_factors *f, const double *x0, const double *y, int homo
               int nrhs, double *x, double *u, void *hip_stream);
 
 /*
+ * Sweep schedule of a handle: how the stage-parallel sweeps of Sec. III-D
+ * (Algorithms 3 and 4) are cut into GPU work.  HOST knobs[3]:
+ *   knobs[0] smallest lane group walking one chain below s*: 8, 16, 32 or 64
+ *            lanes (an instance's chains use the smallest power of two G at
+ *            least this with 2G >= nx + nu, at most 64); default 8;
+ *   knobs[1] chain order: 1 costliest wavefront items first (default), 0
+ *            instance order;
+ *   knobs[2] cap on the wavefronts sharing one node above s*: 1, 2, 4, 8 or
+ *            16 (default 16).
+ * knobs[0] and knobs[1] change no result bit; knobs[2] changes the order of
+ * the per-node sums above s* (equal to rounding).  sweep_schedule rebuilds the
+ * work lists (synchronous; ERR_ARG for values outside these sets, ERR_OOM,
+ * ERR_DEVICE); sweep_schedule_get reads them.  A schedule change invalidates
+ * the handle's sweep graphs.
+ */
+int sweep_schedule(tree_factors *f, const int32_t *knobs);
+int sweep_schedule_get(const tree_factors *f, int32_t *knobs);
+
+/*
+ * Autotuner: times homogeneous sweeps (Algorithm 4 streams the same data as
+ * Algorithm 3) of nrhs in {1, 2} right-hand sides on zero duals, one untimed
+ * and reps timed sweeps per candidate, over each knob in turn (coordinate
+ * descent from the current schedule) and keeps the fastest.  HOST
+ * knobs_out[3] and ms_out (milliseconds per sweep of the kept schedule) may
+ * be NULL.  Allocates and frees its own scratch; synchronous.  Errors:
+ * ERR_ARG, ERR_OOM, ERR_DEVICE.
+ */
+int sweep_autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms_out,
+                   void *hip_stream);
+
+/*
+ * One dual_grad call recorded as a HIP graph (kernel nodes only) and replayed
+ * with one launch.  Arguments as dual_grad with nrhs in {1, 2}; the device
+ * pointers are bound at creation, so every replay reads x0, y and writes x, u
+ * at those addresses.  sweep_graph_launch enqueues one replay on hip_stream;
+ * it returns ERR_ARG if the handle's schedule changed since creation (record
+ * a new graph then).  Free every graph of a handle before the handle.
+ * Errors: ERR_ARG, ERR_OOM, ERR_DEVICE.
+ */
+typedef struct sweep_graph sweep_graph;
+int sweep_graph_create(const tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs,
+                       double *x, double *u, sweep_graph **out);
+int sweep_graph_launch(sweep_graph *g, void *hip_stream);
+void sweep_graph_free(sweep_graph *g);
+
+/*
  * Lipschitz constant L of the dual gradient (largest eigenvalue of the dual
  * Hessian, in the scaled variables if the handle is preconditioned) by power
  * iteration on Algorithm 4, started from the all-ones vector; the step

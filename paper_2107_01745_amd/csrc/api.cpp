@@ -66,31 +66,48 @@ int dual_grad(const tree_factors *fc, const double *x0, const double *y, int hom
         set_error("dual_grad: NULL pointer or nrhs < 1");
         return STOTREE_ERR_ARG;
     }
-    tree_factors *f = const_cast<tree_factors *>(fc);  // workspace only
-    const int chunk = nrhs >= 2 ? 2 : 1;
-    int rc = ensure_sweep_ws(f, chunk);
-    if (rc) return rc;
-    hipStream_t st = (hipStream_t)hip_stream;
-    SweepArgs a = sweep_args(f, homogeneous ? 0 : 1);
-    a.y_rs = f->m_tot;
-    a.x0_rs = f->nx_tot;
-    a.xo_rs = f->x_tot;
-    a.uo_rs = f->u_tot;
-    a.dual_out = 0;
-    for (int k0 = 0; k0 < nrhs; k0 += chunk) {
-        const int nk = (nrhs - k0 >= chunk) ? chunk : 1;
-        a.x0 = x0 ? x0 + (long long)k0 * f->nx_tot : nullptr;
-        a.y = y + (long long)k0 * f->m_tot;
-        a.xo = x + (long long)k0 * f->x_tot;
-        a.uo = u + (long long)k0 * f->u_tot;
-        hipError_t e = launch_sweep_tree(f, a, nk, st);
-        if (e != hipSuccess) {
-            set_error(std::string("dual_grad: ") + hipGetErrorString(e));
-            return STOTREE_ERR_DEVICE;
-        }
-    }
+    return enqueue_dual_grad(const_cast<tree_factors *>(fc), x0, y, homogeneous, nrhs, x, u,
+                             (hipStream_t)hip_stream);
+}
+
+int sweep_schedule(tree_factors *f, const int32_t *knobs)
+{
+    if (!f || !knobs) { set_error("sweep_schedule: NULL argument"); return STOTREE_ERR_ARG; }
+    return set_schedule(f, knobs);
+}
+
+int sweep_schedule_get(const tree_factors *f, int32_t *knobs)
+{
+    if (!f || !knobs) { set_error("sweep_schedule_get: NULL argument"); return STOTREE_ERR_ARG; }
+    knobs[0] = f->group_min; knobs[1] = f->chain_order; knobs[2] = f->trunk_cap;
     return STOTREE_OK;
 }
+
+int sweep_autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms_out, void *hip_stream)
+{
+    if (!f || nrhs < 1 || nrhs > 2 || reps < 1) { set_error("sweep_autotune: bad argument"); return STOTREE_ERR_ARG; }
+    return autotune(f, nrhs, reps, knobs_out, ms_out, (hipStream_t)hip_stream);
+}
+
+int sweep_graph_create(const tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs,
+                       double *x, double *u, sweep_graph **out)
+{
+    if (!out) { set_error("sweep_graph_create: out is NULL"); return STOTREE_ERR_ARG; }
+    *out = nullptr;
+    if (!f || !y || !x || !u || nrhs < 1 || nrhs > 2 || (!homogeneous && !x0)) {
+        set_error("sweep_graph_create: NULL pointer or nrhs not in {1, 2}");
+        return STOTREE_ERR_ARG;
+    }
+    return graph_create(const_cast<tree_factors *>(f), x0, y, homogeneous, nrhs, x, u, out);
+}
+
+int sweep_graph_launch(sweep_graph *g, void *hip_stream)
+{
+    if (!g) { set_error("sweep_graph_launch: NULL graph"); return STOTREE_ERR_ARG; }
+    return graph_launch(g, (hipStream_t)hip_stream);
+}
+
+void sweep_graph_free(sweep_graph *g) { graph_free(g); }
 
 int dual_lipschitz(const tree_factors *f, int iters, double *L_out, void *hip_stream)
 {

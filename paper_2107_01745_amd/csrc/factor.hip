@@ -346,46 +346,79 @@ void free_tree(tree_factors *f)
     for (void *p : {(void *)f->d_inst, (void *)f->d_sp, (void *)f->d_cp, (void *)f->d_anc, (void *)f->Mb, (void *)f->Mf,
                     (void *)f->Kb, (void *)f->Kf, (void *)f->Rn, (void *)f->chat, (void *)f->sig,
                     (void *)f->cvec, (void *)f->sc, (void *)f->lo, (void *)f->hi, (void *)f->qhat,
-                    (void *)f->kbuf, (void *)f->sws.buf, (void *)f->chain_items})
+                    (void *)f->kbuf, (void *)f->sws.buf})
         if (p) (void)hipFree(p);
+    for (auto &cp : f->chains)
+        if (cp.items) (void)hipFree(cp.items);
     for (auto &lv : f->levels)
         if (lv.items) (void)hipFree(lv.items);
     delete f;
 }
 
-// Work lists of a sweep: all chains (longest first when chain_order is set)
-// and, per stage above s*, all (instance, node) pairs of that stage.
+int chain_group(int ldM, int group_min)
+{
+    int G = 8;
+    while (G < kWave && 2 * G < ldM) G *= 2;
+    return G < group_min ? group_min : G;
+}
+
+// Work lists of a sweep: the chains, one plan per lane-group width (each item
+// a wavefront's worth of consecutive chains of one instance; the costliest
+// first when chain_order is set) and, per stage above s*, all (instance,
+// node) pairs of that stage.
 int build_schedule(tree_factors *f)
 {
-    if (f->chain_items) { (void)hipFree(f->chain_items); f->chain_items = nullptr; }
+    for (auto &cp : f->chains)
+        if (cp.items) (void)hipFree(cp.items);
+    f->chains.clear();
     for (auto &lv : f->levels)
         if (lv.items) (void)hipFree(lv.items);
     f->levels.clear();
-    std::vector<Item> chains;
-    std::vector<double> cost;
     int max_sstar = 0, max_ldM = 0;
+    std::map<int, std::vector<std::pair<double, Item>>> by_G;
+    std::map<int, int> ldq_G;
     for (int b = 0; b < f->ninst; ++b) {
         const InstDesc &I = f->inst[b];
         max_sstar = std::max(max_sstar, I.sstar);
         max_ldM = std::max(max_ldM, I.ldM);
-        if (I.sstar < I.N)
-            for (int c = 0; c < I.nchains; ++c) {
-                chains.push_back({b, c});
-                cost.push_back((double)(I.N - I.sstar) * I.nx * (I.nx + I.nu));
-            }
+        if (I.sstar >= I.N) continue;
+        const int G = chain_group(I.ldM, f->group_min);
+        const int per = kWave / G;
+        ldq_G[G] = std::max(ldq_G[G], I.ldM);
+        for (int c = 0; c < I.nchains; c += per) {
+            const int n = std::min(per, I.nchains - c);
+            by_G[G].push_back({(double)(I.N - I.sstar) * I.nx * (I.nx + I.nu) * n, Item{b, c}});
+        }
     }
-    if (f->chain_order && !chains.empty()) {
-        std::vector<size_t> ord(chains.size());
-        std::iota(ord.begin(), ord.end(), 0);
-        std::stable_sort(ord.begin(), ord.end(), [&](size_t p, size_t q) { return cost[p] > cost[q]; });
-        std::vector<Item> sorted(chains.size());
-        for (size_t k = 0; k < ord.size(); ++k) sorted[k] = chains[ord[k]];
-        chains.swap(sorted);
+    if (f->panel_chain_items) { (void)hipFree(f->panel_chain_items); f->panel_chain_items = nullptr; }
+    {
+        std::vector<Item> all;
+        for (int b = 0; b < f->ninst; ++b) {
+            const InstDesc &I = f->inst[b];
+            if (I.sstar < I.N)
+                for (int c = 0; c < I.nchains; ++c) all.push_back({b, c});
+        }
+        f->npanel_chain_items = (int)all.size();
+        if (!all.empty()) {
+            STOTREE_HIP(hipMalloc(&f->panel_chain_items, sizeof(Item) * all.size()));
+            STOTREE_HIP(hipMemcpy(f->panel_chain_items, all.data(), sizeof(Item) * all.size(),
+                                  hipMemcpyHostToDevice));
+        }
     }
-    f->nchain_items = (int)chains.size();
-    if (!chains.empty()) {
-        STOTREE_HIP(hipMalloc(&f->chain_items, sizeof(Item) * chains.size()));
-        STOTREE_HIP(hipMemcpy(f->chain_items, chains.data(), sizeof(Item) * chains.size(), hipMemcpyHostToDevice));
+    for (auto &kv : by_G) {
+        auto &v = kv.second;
+        if (f->chain_order)
+            std::stable_sort(v.begin(), v.end(), [](const auto &p, const auto &q) { return p.first > q.first; });
+        std::vector<Item> items(v.size());
+        for (size_t k = 0; k < v.size(); ++k) items[k] = v[k].second;
+        ChainPlan cp{};
+        cp.G = kv.first;
+        cp.ldq = ldq_G[kv.first];
+        cp.CH = cp.ldq > 2 * cp.G ? 2 : 1;
+        cp.count = (int)items.size();
+        STOTREE_HIP(hipMalloc(&cp.items, sizeof(Item) * items.size()));
+        f->chains.push_back(cp);
+        STOTREE_HIP(hipMemcpy(cp.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
     }
     for (int t = 0; t < max_sstar; ++t) {
         std::vector<Item> items;

@@ -22,6 +22,7 @@ namespace stotree {
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kWavesPerBlock = 4;    // independent wavefronts per block in chain kernels
 constexpr int kMaxWidth = 256;       // nx + nu supported by the sweep kernels
+constexpr int kRhsPanel = 64;        // right-hand sides of one matrix-core (panel) sweep
 
 inline int pad2(int n) { return (n + 1) & ~1; }
 
@@ -57,6 +58,15 @@ struct SweepArgs {
     int affine;
     int t;                           // stage of a per-stage launch
     const int *done; int done_stride;       // per-instance skip flags (may be null)
+};
+
+// One launch of the chain kernels: the chains of every instance that uses
+// lane groups of G lanes (G * 2 * CH >= nx + nu), kWave / G chains per item.
+struct ChainPlan {
+    int G, CH;
+    int ldq;                         // largest padded nx + nu of its instances
+    int count;                       // items = wavefronts
+    Item *items;                     // device: (instance, first chain)
 };
 
 // One launch of the per-stage kernels: all (instance, node) pairs of one stage.
@@ -95,11 +105,15 @@ struct tree_factors {
     long long m_tot = 0, n_tot = 0, x_tot = 0, u_tot = 0, nx_tot = 0, V_tot = 0;
     int max_width = 0;                      // max nx+nu over instances
     // schedule of a sweep
-    stotree::Item *chain_items = nullptr;
-    int nchain_items = 0;
+    std::vector<stotree::ChainPlan> chains;  // stages s*..N, one plan per lane-group width
     std::vector<stotree::LevelPlan> levels;  // stages 0..max(s*)-1
-    int trunk_cap = 16;                     // tuned cap on wavefronts per node
+    stotree::Item *panel_chain_items = nullptr;  // every (instance, chain): panel sweeps
+    int npanel_chain_items = 0;
+    // tuning knobs (sweep_schedule / sweep_autotune)
+    int trunk_cap = 16;                     // cap on wavefronts per node above s*
     int chain_order = 1;                    // 1: longest chains first, 0: instance order
+    int group_min = 8;                      // smallest lane group used for chains
+    long long schedule_epoch = 0;           // bumped whenever the work lists are rebuilt
     // sweep workspace (grows with nrhs)
     double *qhat = nullptr, *kbuf = nullptr;
     int ws_nrhs = 0;
@@ -117,14 +131,31 @@ int factor_forest(int count, const tree_desc *t, const problem_data *d, int prec
                   hipStream_t st, tree_factors **out);
 void free_tree(tree_factors *f);
 int build_schedule(tree_factors *f);
+int chain_group(int ldM, int group_min);  // lanes per chain for padded width ldM
 
 // sweep.hip
 SweepArgs sweep_args(const tree_factors *f, int affine);
 int ensure_sweep_ws(tree_factors *f, int nrhs);
 // One full sweep (Algorithm 3 if a.affine, else Algorithm 4), nrhs in {1,2}.
+// sweep_mfma.hip: the same for a panel of kRhsPanel right-hand sides on the
+// matrix cores; panel_tpw == 0 if an instance is too wide for it.
+int panel_tpw(const tree_factors *f);
+hipError_t launch_panel_sweep(const tree_factors *f, const SweepArgs &a, hipStream_t st);
 hipError_t launch_sweep_tree(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st);
 int timing_enable(int on);
+bool timing_on();
 int timing_read(double *ms, long long *count);
+// dual_grad's work: right-hand sides two at a time, one sweep each pair.
+int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,
+                      double *u, hipStream_t st);
+
+// schedule.hip
+int set_schedule(tree_factors *f, const int32_t *knobs);
+int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms_out, hipStream_t st);
+int graph_create(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,
+                 double *u, sweep_graph **out);
+int graph_launch(sweep_graph *g, hipStream_t st);
+void graph_free(sweep_graph *g);
 
 // warm.hip
 long long mlp_param_count(int din, int dh, int dout);

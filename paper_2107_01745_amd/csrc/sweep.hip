@@ -21,64 +21,30 @@
 // launch walks a flat work list of (instance, node) or (instance, chain)
 // pairs and reads the instance's sizes and pool offsets from its descriptor.
 //
-// Mapping.  One wavefront per node (per chain, below).  Each lane owns two
-// adjacent output entries; matrices are stored in the orientation of the pass
-// that reads them, so every row of a matrix is one contiguous, 16-byte-aligned
-// load across the wavefront, multiplied by a broadcast entry of the input
-// vector held in LDS.  The nodes from stage s* on have one child each (the
-// scenario fan-out has ended); the tree below s* is a set of independent
-// chains, each walked by one wavefront through all its stages with qhat / x
-// carried in LDS, so those stages need no grid-wide synchronisation.  Stages
-// above s* are launched stage by stage.
+// Mapping.  One wavefront per node above s*; below it a group of G lanes
+// (G = 64, 32, 16 or 8, by default the smallest with 2G >= nx+nu) per chain.
+// Each lane owns two adjacent output entries; matrices are stored in the
+// orientation of the pass that reads them, so every row of a matrix is one
+// contiguous, 16-byte-aligned load across the lane group, multiplied by a
+// broadcast entry of the input vector held in LDS.  The nodes from stage s*
+// on have one child each (the scenario fan-out has ended); the tree below s*
+// is a set of independent chains, each walked by one lane group through all
+// its stages with qhat / x carried in LDS, so those stages need no grid-wide
+// synchronisation.  Stages above s* are launched stage by stage.
 #include <algorithm>
 
-#include "internal.h"
+#include "sweep_common.h"
 
 namespace stotree {
 
 namespace {
 
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+using namespace dev;
 
-// Dual-layout offset of node i inside its instance.
-__device__ __forceinline__ long long dual_off(const InstDesc &I, int i)
-{
-    return i < I.Vnl ? (long long)i * (I.nx + I.nu) : (long long)I.Vnl * I.nu + (long long)i * I.nx;
-}
-__device__ __forceinline__ const double *y_ptr(const SweepArgs &a, const InstDesc &I, int k, int i)
-{
-    return a.y + k * a.y_rs + I.y + dual_off(I, i);
-}
-__device__ __forceinline__ double *x_ptr(const SweepArgs &a, const InstDesc &I, int k, int i)
-{
-    return a.dual_out ? a.xo + k * a.xo_rs + I.y + dual_off(I, i)
-                      : a.xo + k * a.xo_rs + I.x + (long long)i * I.nx;
-}
-__device__ __forceinline__ double *u_ptr(const SweepArgs &a, const InstDesc &I, int k, int i)
-{
-    return a.dual_out ? a.xo + k * a.xo_rs + I.y + (long long)i * (I.nx + I.nu) + I.nx
-                      : a.uo + k * a.uo_rs + I.u + (long long)i * I.nu;
-}
-__device__ __forceinline__ double *qhat_ptr(const SweepArgs &a, const InstDesc &I, int k, int i)
-{
-    return a.qhat + k * a.qhat_rs + I.x + (long long)i * I.nx;
-}
-__device__ __forceinline__ double *kbuf_ptr(const SweepArgs &a, const InstDesc &I, int k, int i)
-{
-    return a.kbuf + k * a.kbuf_rs + I.u + (long long)i * I.nu;
-}
-__device__ __forceinline__ bool skipped(const SweepArgs &a, int b)
-{
-    return a.done && a.done[(long long)b * a.done_stride];
-}
 
 // acc[k][ch][e] += sum_{r0<=r<r1} M[r][c] * v_k[r] for the lane's columns
-// c = 2*lane + 128*ch + e < W, with M row-major of leading dimension ld and v_k
+// c = 2*lane + 2*G*ch + e < W (lane within a group of G lanes that shares
+// the matrix), with M row-major of leading dimension ld and v_k
 // in LDS at v + k*ldv.  The loads carry no lane condition (lanes past W re-read
 // column 0 and their sums are never stored) and rows go in batches of
 // kRowBatch, double-buffered: the next batch is issued before the current one
@@ -113,7 +79,7 @@ __device__ __forceinline__ void fma_rows(const double2 (&m)[kRowBatch][CH], cons
         }
 }
 
-template <int NRHS, int CH>
+template <int NRHS, int CH, int G = kWave>
 __device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, int r0, int r1, int W,
                                           const double *v, int ldv, double (&acc)[NRHS][CH][2],
                                           int lane)
@@ -121,7 +87,7 @@ __device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, 
     int col[CH];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-        const int c0 = 2 * lane + 128 * ch;
+        const int c0 = 2 * lane + 2 * G * ch;
         col[ch] = c0 < W ? c0 : 0;
     }
     int r = r0;
@@ -158,13 +124,13 @@ __device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, 
 }
 
 // dst[k*ld + off + c] = acc[k][.][.] for the lane's columns c < dim.
-template <int NRHS, int CH>
+template <int NRHS, int CH, int G = kWave>
 __device__ __forceinline__ void store_acc(double *dst, int ld, int off, int dim,
                                           const double (&acc)[NRHS][CH][2], int lane)
 {
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-        const int c0 = 2 * lane + 128 * ch;
+        const int c0 = 2 * lane + 2 * G * ch;
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             if (c0 < dim) dst[k * ld + off + c0] = acc[k][ch][0];
@@ -182,18 +148,18 @@ __device__ __forceinline__ void zero(double (&acc)[NRHS][CH][2])
         for (int ch = 0; ch < CH; ++ch) acc[k][ch][0] = acc[k][ch][1] = 0.0;
 }
 
-// Per-wave LDS of the chain kernels: qx [NRHS][ldq] (qhat or [x;u]), as
-// [NRHS][ldq], gs [NRHS][ldq], with ldq the largest padded width.
+// LDS of one lane group in the chain kernels: qx [NRHS][ldq] (qhat or
+// [x;u]), as [NRHS][ldq], gs [NRHS][ldq], with ldq the largest padded width.
 struct WaveLds {
     double *qx, *as, *gs;
     int ldq;
 };
 
-__device__ __forceinline__ WaveLds wave_lds(int ldq, int nrhs, int wave)
+__device__ __forceinline__ WaveLds wave_lds(int ldq, int nrhs, int slot)
 {
     extern __shared__ double lds[];
     WaveLds w;
-    w.qx = lds + wave * 3 * nrhs * ldq;
+    w.qx = lds + slot * 3 * nrhs * ldq;
     w.as = w.qx + nrhs * ldq;
     w.gs = w.as + nrhs * ldq;
     w.ldq = ldq;
@@ -205,7 +171,7 @@ __device__ __forceinline__ WaveLds wave_lds(int ldq, int nrhs, int wave)
 // child's qhat is staged from the leaf data or from the global qhat buffer.
 // The result qhat_i is left in L.qx and, if store_q, written to the global
 // buffer; k_i always goes to kbuf.
-template <int NRHS, int CH>
+template <int NRHS, int CH, int G>
 __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const WaveLds &L,
                          bool child_in_lds, bool store_q, int lane)
 {
@@ -218,25 +184,25 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
         if (!child_in_lds) {
             if (j >= I.Vnl) {
                 const double sj = a.sc ? a.sc[I.sc + j] : 1.0;
-                for (int r = lane; r < nx; r += kWave)
+                for (int r = lane; r < nx; r += G)
 #pragma unroll
                     for (int k = 0; k < NRHS; ++k)
                         L.qx[k * L.ldq + r] = sj * y_ptr(a, I, k, j)[r] +
                                               (a.affine ? a.chat[I.chat + (long long)j * nx + r] : 0.0);
             } else {
-                for (int r = lane; r < nx; r += kWave)
+                for (int r = lane; r < nx; r += G)
 #pragma unroll
                     for (int k = 0; k < NRHS; ++k) L.qx[k * L.ldq + r] = qhat_ptr(a, I, k, j)[r];
             }
             wave_sync();
         }
-        gemv_rows<NRHS, CH>(a.Mb + I.Mb + (long long)j * nx * I.ldM, I.ldM, 0, nx, W, L.qx, L.ldq, acc, lane);
+        gemv_rows<NRHS, CH, G>(a.Mb + I.Mb + (long long)j * nx * I.ldM, I.ldM, 0, nx, W, L.qx, L.ldq, acc, lane);
         wave_sync();
     }
-    store_acc<NRHS, CH>(L.as, L.ldq, 0, W, acc, lane);  // [sum A'q ; sum B'q]
+    store_acc<NRHS, CH, G>(L.as, L.ldq, 0, W, acc, lane);  // [sum A'q ; sum B'q]
     wave_sync();
     const double si = a.sc ? a.sc[I.sc + i] : 1.0;
-    for (int c = lane; c < nu; c += kWave)
+    for (int c = lane; c < nu; c += G)
 #pragma unroll
         for (int k = 0; k < NRHS; ++k)
             L.gs[k * L.ldq + c] = L.as[k * L.ldq + nx + c] + si * y_ptr(a, I, k, i)[nx + c] +
@@ -245,11 +211,11 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
     zero(kacc);
     zero(qacc);
-    gemv_rows<NRHS, CH>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
-    gemv_rows<NRHS, CH>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
+    gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
+    gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-        const int c0 = 2 * lane + 128 * ch;
+        const int c0 = 2 * lane + 2 * G * ch;
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             double *kb = kbuf_ptr(a, I, k, i);
@@ -261,7 +227,7 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     double qv[NRHS][CH][2];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-        const int c0 = 2 * lane + 128 * ch;
+        const int c0 = 2 * lane + 2 * G * ch;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int c = c0 + e;
@@ -278,7 +244,7 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     wave_sync();  // every lane has finished reading L.qx / L.as
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-        const int c0 = 2 * lane + 128 * ch;
+        const int c0 = 2 * lane + 2 * G * ch;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int c = c0 + e;
@@ -297,7 +263,7 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
 // Forward step of non-leaf node i with x_i in L.qx[0..nx).  Writes u_i and the
 // children's x_j to the outputs; for a single-child chain the child's x is
 // left in L.qx.
-template <int NRHS, int CH>
+template <int NRHS, int CH, int G>
 __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const WaveLds &L, bool keep_child,
                          int lane)
 {
@@ -305,10 +271,10 @@ __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     const int *cp = a.cp + I.cp;
     double uacc[NRHS][CH][2];
     zero(uacc);
-    gemv_rows<NRHS, CH>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
+    gemv_rows<NRHS, CH, G>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-        const int c0 = 2 * lane + 128 * ch;
+        const int c0 = 2 * lane + 2 * G * ch;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int c = c0 + e;
@@ -329,11 +295,11 @@ __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     for (int j = j0; j < j1; ++j) {
         double xacc[NRHS][CH][2];
         zero(xacc);
-        gemv_rows<NRHS, CH>(a.Mf + I.Mf + (long long)j * (nx + nu) * I.ldx, I.ldx, 0, nx + nu, nx, L.qx, L.ldq,
+        gemv_rows<NRHS, CH, G>(a.Mf + I.Mf + (long long)j * (nx + nu) * I.ldx, I.ldx, 0, nx + nu, nx, L.qx, L.ldq,
                             xacc, lane);
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch) {
-            const int c0 = 2 * lane + 128 * ch;
+            const int c0 = 2 * lane + 2 * G * ch;
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int c = c0 + e;
@@ -350,17 +316,17 @@ __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     }
     if (keep_child) {
         wave_sync();
-        store_acc<NRHS, CH>(L.qx, L.ldq, 0, nx, keep, lane);
+        store_acc<NRHS, CH, G>(L.qx, L.ldq, 0, nx, keep, lane);
         wave_sync();
     }
 }
 
 // x_i of the first node a forward pass visits: x0 at the root (written to
 // the output too), else the value the previous stage stored.
-template <int NRHS>
+template <int NRHS, int G>
 __device__ void load_x(const SweepArgs &a, const InstDesc &I, int i, const WaveLds &L, int lane)
 {
-    for (int c = lane; c < I.nx; c += kWave)
+    for (int c = lane; c < I.nx; c += G)
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             double v;
@@ -569,34 +535,92 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a)
 
 // ---- stages s*..N-1: chain c of an instance covers the nodes
 // stage_ptr[t] + c for t = s*..N-1 (one child each) and its leaf ----
-template <int NRHS, int CH>
-__global__ void __launch_bounds__(kWave *kWavesPerBlock, 2) bwd_chain_kernel(SweepArgs a, int ldq)
+//
+// A group of G lanes walks one chain; a wavefront holds kWave/G groups, all
+// on consecutive chains of one instance (item = instance, first chain), so
+// the instance's sizes, loop bounds and branches stay wavefront-uniform and a
+// single row load brings in one row of kWave/G different chains' matrices.
+template <int NRHS, int CH, int G>
+__device__ __forceinline__ void bwd_chain_body(const SweepArgs &a, const Item *items, int nitems, int blk, int ldq)
 {
-    const int lane = threadIdx.x & (kWave - 1), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int item = blockIdx.x * kWavesPerBlock + wave;
-    if (item >= a.nitems) return;
-    const Item it = a.items[item];
+    constexpr int kGroups = kWave / G;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int item = blk * kWavesPerBlock + wave;
+    if (item >= nitems) return;
+    const Item it = items[item];
     if (skipped(a, it.inst)) return;
     const InstDesc I = a.inst[it.inst];
+    const int lane = threadIdx.x & (G - 1), grp = (threadIdx.x & (kWave - 1)) / G;
+    const int chain = it.idx + grp;
+    if (chain >= I.nchains) return;
     const int *sp = a.sp + I.sp;
-    const WaveLds L = wave_lds(ldq, NRHS, wave);
+    const WaveLds L = wave_lds(ldq, NRHS, wave * kGroups + grp);
     for (int t = I.N - 1; t >= I.sstar; --t)
-        bwd_node<NRHS, CH>(a, I, sp[t] + it.idx, L, t != I.N - 1, t == I.sstar && t > 0, lane);
+        bwd_node<NRHS, CH, G>(a, I, sp[t] + chain, L, t != I.N - 1, t == I.sstar && t > 0, lane);
 }
 
-template <int NRHS, int CH>
-__global__ void __launch_bounds__(kWave *kWavesPerBlock, 2) fwd_chain_kernel(SweepArgs a, int ldq)
+template <int NRHS, int CH, int G>
+__device__ __forceinline__ void fwd_chain_body(const SweepArgs &a, const Item *items, int nitems, int blk, int ldq)
 {
-    const int lane = threadIdx.x & (kWave - 1), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int item = blockIdx.x * kWavesPerBlock + wave;
-    if (item >= a.nitems) return;
-    const Item it = a.items[item];
+    constexpr int kGroups = kWave / G;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int item = blk * kWavesPerBlock + wave;
+    if (item >= nitems) return;
+    const Item it = items[item];
     if (skipped(a, it.inst)) return;
     const InstDesc I = a.inst[it.inst];
+    const int lane = threadIdx.x & (G - 1), grp = (threadIdx.x & (kWave - 1)) / G;
+    const int chain = it.idx + grp;
+    if (chain >= I.nchains) return;
     const int *sp = a.sp + I.sp;
-    const WaveLds L = wave_lds(ldq, NRHS, wave);
-    load_x<NRHS>(a, I, sp[I.sstar] + it.idx, L, lane);
-    for (int t = I.sstar; t < I.N; ++t) fwd_node<NRHS, CH>(a, I, sp[t] + it.idx, L, t + 1 < I.N, lane);
+    const WaveLds L = wave_lds(ldq, NRHS, wave * kGroups + grp);
+    load_x<NRHS, G>(a, I, sp[I.sstar] + chain, L, lane);
+    for (int t = I.sstar; t < I.N; ++t) fwd_node<NRHS, CH, G>(a, I, sp[t] + chain, L, t + 1 < I.N, lane);
+}
+
+// Chains of one lane-group width (G = 64).
+template <int NRHS, int CH, int G>
+__global__ void __launch_bounds__(kWave *kWavesPerBlock, 2) bwd_chain_kernel(SweepArgs a, int ldq)
+{
+    bwd_chain_body<NRHS, CH, G>(a, a.items, a.nitems, blockIdx.x, ldq);
+}
+
+template <int NRHS, int CH, int G>
+__global__ void __launch_bounds__(kWave *kWavesPerBlock, 2) fwd_chain_kernel(SweepArgs a, int ldq)
+{
+    fwd_chain_body<NRHS, CH, G>(a, a.items, a.nitems, blockIdx.x, ldq);
+}
+
+// Chains of the narrow widths (G = 8, 16, 32) in one launch: the grid is cut
+// into consecutive block ranges, one per width, so that instances of every
+// size share the machine without a launch (and its tail) per width.
+struct NarrowChains {
+    int n;
+    int G[3], ldq[3], count[3];
+    int first_block[4];
+    const Item *items[3];
+};
+
+template <int NRHS, bool BWD>
+__global__ void __launch_bounds__(kWave *kWavesPerBlock, 2) narrow_chain_kernel(SweepArgs a, NarrowChains nc)
+{
+    int c = 0;
+    while (c + 1 < nc.n && (int)blockIdx.x >= nc.first_block[c + 1]) ++c;
+    const int blk = blockIdx.x - nc.first_block[c];
+    switch (nc.G[c]) {
+    case 8:
+        if (BWD) bwd_chain_body<NRHS, 1, 8>(a, nc.items[c], nc.count[c], blk, nc.ldq[c]);
+        else fwd_chain_body<NRHS, 1, 8>(a, nc.items[c], nc.count[c], blk, nc.ldq[c]);
+        break;
+    case 16:
+        if (BWD) bwd_chain_body<NRHS, 1, 16>(a, nc.items[c], nc.count[c], blk, nc.ldq[c]);
+        else fwd_chain_body<NRHS, 1, 16>(a, nc.items[c], nc.count[c], blk, nc.ldq[c]);
+        break;
+    default:
+        if (BWD) bwd_chain_body<NRHS, 1, 32>(a, nc.items[c], nc.count[c], blk, nc.ldq[c]);
+        else fwd_chain_body<NRHS, 1, 32>(a, nc.items[c], nc.count[c], blk, nc.ldq[c]);
+        break;
+    }
 }
 
 }  // namespace
@@ -656,6 +680,8 @@ struct PhaseTimer {
 };
 }  // namespace
 
+bool timing_on() { return g_timing.on; }
+
 int timing_enable(int on)
 {
     g_timing.on = on != 0;
@@ -711,6 +737,50 @@ static void launch_trunk(bool backward, const SweepArgs &a, const LevelPlan &lv,
     }
 }
 
+// Chain launches: one for all narrow widths together, one per wide plan.
+template <int NRHS>
+static void launch_chains(bool backward, const SweepArgs &a, const tree_factors *f, hipStream_t st)
+{
+    const dim3 blk(kWave * kWavesPerBlock);
+    NarrowChains nc{};
+    size_t narrow_lds = 0;
+    for (const ChainPlan &cp : f->chains) {
+        const int blocks = (cp.count + kWavesPerBlock - 1) / kWavesPerBlock;
+        const size_t lds = sizeof(double) * (size_t)kWavesPerBlock * (kWave / cp.G) * 3 * NRHS * cp.ldq;
+        if (cp.G < kWave) {
+            nc.G[nc.n] = cp.G;
+            nc.ldq[nc.n] = cp.ldq;
+            nc.count[nc.n] = cp.count;
+            nc.items[nc.n] = cp.items;
+            nc.first_block[nc.n + 1] = nc.first_block[nc.n] + blocks;
+            ++nc.n;
+            narrow_lds = std::max(narrow_lds, lds);
+            continue;
+        }
+        SweepArgs ca = a;
+        ca.items = cp.items;
+        ca.nitems = cp.count;
+        if (cp.CH == 1) {
+            if (backward)
+                hipLaunchKernelGGL((bwd_chain_kernel<NRHS, 1, kWave>), dim3(blocks), blk, lds, st, ca, cp.ldq);
+            else
+                hipLaunchKernelGGL((fwd_chain_kernel<NRHS, 1, kWave>), dim3(blocks), blk, lds, st, ca, cp.ldq);
+        } else {
+            if (backward)
+                hipLaunchKernelGGL((bwd_chain_kernel<NRHS, 2, kWave>), dim3(blocks), blk, lds, st, ca, cp.ldq);
+            else
+                hipLaunchKernelGGL((fwd_chain_kernel<NRHS, 2, kWave>), dim3(blocks), blk, lds, st, ca, cp.ldq);
+        }
+    }
+    if (nc.n > 0) {
+        const dim3 grid(nc.first_block[nc.n]);
+        if (backward)
+            hipLaunchKernelGGL((narrow_chain_kernel<NRHS, true>), grid, blk, narrow_lds, st, a, nc);
+        else
+            hipLaunchKernelGGL((narrow_chain_kernel<NRHS, false>), grid, blk, narrow_lds, st, a, nc);
+    }
+}
+
 template <int NRHS, int CH>
 static hipError_t sweep_impl(const tree_factors *f, SweepArgs a, hipStream_t st)
 {
@@ -720,15 +790,9 @@ static hipError_t sweep_impl(const tree_factors *f, SweepArgs a, hipStream_t st)
         qs = std::max(qs, child_batch(NRHS, I.ldx) * I.ldx);
         ldu = std::max(ldu, I.ldu);
     }
-    const dim3 blk(kWave * kWavesPerBlock);
-    const size_t chain_lds = sizeof(double) * kWavesPerBlock * 3 * NRHS * ldM;
-    const dim3 cgrid((f->nchain_items + kWavesPerBlock - 1) / kWavesPerBlock);
-    SweepArgs ca = a;
-    ca.items = f->chain_items;
-    ca.nitems = f->nchain_items;
-    if (f->nchain_items > 0) {
+    if (!f->chains.empty()) {
         PhaseTimer tm(0, st);
-        hipLaunchKernelGGL((bwd_chain_kernel<NRHS, CH>), cgrid, blk, chain_lds, st, ca, ldM);
+        launch_chains<NRHS>(true, a, f, st);
     }
     if (!f->levels.empty()) {
         PhaseTimer tm(1, st);
@@ -740,11 +804,41 @@ static hipError_t sweep_impl(const tree_factors *f, SweepArgs a, hipStream_t st)
         for (size_t k = 0; k < f->levels.size(); ++k)
             launch_trunk<NRHS, CH>(false, a, f->levels[k], ldM, qs, ldu, st);
     }
-    if (f->nchain_items > 0) {
+    if (!f->chains.empty()) {
         PhaseTimer tm(3, st);
-        hipLaunchKernelGGL((fwd_chain_kernel<NRHS, CH>), cgrid, blk, chain_lds, st, ca, ldM);
+        launch_chains<NRHS>(false, a, f, st);
     }
     return hipGetLastError();
+}
+
+int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,
+                      double *u, hipStream_t st)
+{
+    // panels of kRhsPanel right-hand sides on the matrix cores, the rest in pairs
+    const bool panel = nrhs >= kRhsPanel && panel_tpw(f) > 0;
+    const int npanel = panel ? nrhs / kRhsPanel * kRhsPanel : 0;
+    int rc = ensure_sweep_ws(f, panel ? kRhsPanel : (nrhs >= 2 ? 2 : 1));
+    if (rc) return rc;
+    SweepArgs a = sweep_args(f, homogeneous ? 0 : 1);
+    a.y_rs = f->m_tot;
+    a.x0_rs = f->nx_tot;
+    a.xo_rs = f->x_tot;
+    a.uo_rs = f->u_tot;
+    a.dual_out = 0;
+    for (int k0 = 0; k0 < nrhs;) {
+        const int nk = k0 < npanel ? kRhsPanel : (nrhs - k0 >= 2 ? 2 : 1);
+        a.x0 = x0 ? x0 + (long long)k0 * f->nx_tot : nullptr;
+        a.y = y + (long long)k0 * f->m_tot;
+        a.xo = x + (long long)k0 * f->x_tot;
+        a.uo = u + (long long)k0 * f->u_tot;
+        hipError_t e = nk == kRhsPanel ? launch_panel_sweep(f, a, st) : launch_sweep_tree(f, a, nk, st);
+        if (e != hipSuccess) {
+            set_error(std::string("dual_grad: ") + hipGetErrorString(e));
+            return STOTREE_ERR_DEVICE;
+        }
+        k0 += nk;
+    }
+    return STOTREE_OK;
 }
 
 hipError_t launch_sweep_tree(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st)

@@ -1,0 +1,410 @@
+// Sweeps of 64 right-hand sides that share one tree's factors (Algorithms 3
+// and 4 of arXiv 2107.01745, Sec. III-D, with the extra parallelism of
+// Sec. III-C taken to many dual vectors): every per-node product becomes a
+// small dense matrix product, factor (rows x cols) times a panel of 64
+// right-hand sides, which runs on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64).
+//
+// The algebra is the regrouped recursion of the single-vector sweep
+// (sweep.hip): backward g_i = s_i y_i^u + pi_i r_i + sum_j B_j' qhat_j,
+// k_i = -R~_i^{-1} g_i, qhat_i = chat_i + s_i y_i^x + sum_j A_j' qhat_j +
+// K_i' g_i; forward u_i = K_i x_i + k_i, x_j = A_j x_i + B_j u_i + c_j.
+//
+// Mapping.  One workgroup of four wavefronts per node (per chain below s*).
+// The input panel of a product (qhat, g or [x; u] of all 64 right-hand
+// sides, one LDS row per vector entry) sits in LDS; the factor operand is read
+// straight from HBM in the layout the single-vector sweep streams.  The output
+// of a product is cut into 16-row tiles of the x part and of the u part, each
+// tile in two halves of 32 right-hand sides; the (tile, half) tasks are dealt
+// round-robin to the wavefronts, and every task keeps its two 16x16 result
+// blocks in registers.  Backward: the x tiles of sum A'qhat and of K'g land on
+// the same wavefront and lanes, so qhat_i is formed in registers; g goes to LDS
+// as the input of [K; -R~^{-1}] g.  Sums over the K dimension run in a fixed
+// order (deterministic results).
+//
+// Operand layout of v_mfma_f64_16x16x4f64 (D = A B + C, A 16x4, B 4x16):
+// lane l holds A[l%16][l/16], B[l/16][l%16] and D[4(l/16)+e][l%16], e < 4.
+#include "sweep_common.h"
+
+namespace stotree {
+
+namespace {
+
+using namespace dev;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kPanel = kRhsPanel;      // right-hand sides per launch (64)
+constexpr int kLdv = kPanel + 2;       // LDS row stride of a panel (doubles)
+constexpr int kWg = 4;                 // wavefronts per workgroup
+constexpr int kTpwMax = 4;             // most tasks one wavefront can hold
+constexpr int kKu = 4;                 // K steps (of 4 rows) per batch of operand loads
+
+// Source of one output part of a product: out[c] = sum_r M[r][col0 + c] v[r]
+// for c < ncols, M row-major with leading dimension ld.
+struct Part {
+    const double *M;
+    int ld, col0, ncols;
+};
+
+// Tasks of a product: tiles of part 0 then part 1 (ceil(ncols/16) each),
+// two halves each; wavefront w owns tasks w, w + kWg, ...
+struct Tasks {
+    int t0, t1;                        // tiles of part 0 / part 1
+    __device__ int count() const { return 2 * (t0 + t1); }
+};
+
+__host__ __device__ inline int tiles(int n) { return (n + 15) >> 4; }
+
+// acc[s][h] (+)= product for task s of this wavefront; V is the LDS input
+// panel (R rows of kLdv).  Rows of A past R are zero and the matching B rows
+// are not read, so the panel needs no padding rows.  Task w + kWg*s has half
+// (w & 1): all tasks of a wavefront share the B operand.
+template <int TPW>
+__device__ __forceinline__ void product(const Part (&p)[2], const Tasks &tk, int R, const double *V,
+                                        v4d (&acc)[TPW][2], int wave, int lane)
+{
+    const int n = tk.count();
+    const int lr = lane >> 4, lc = lane & 15;
+    const int half = (wave & 1) * 32;
+    const double *ap[TPW];
+    int ld[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int task = wave + kWg * s;
+        const int tile = (task < n ? task : 0) >> 1;
+        const int part = tile < tk.t0 ? 0 : 1;
+        const int c = (part ? tile - tk.t0 : tile) * 16 + lc;
+        // columns past the part re-read its first column; their rows of D are never stored
+        ap[s] = p[part].M + p[part].col0 + (c < p[part].ncols ? c : 0);
+        ld[s] = p[part].ld;
+    }
+    for (int k0 = 0; k0 < R; k0 += 4 * kKu) {
+        double a[kKu][TPW], b[kKu][2];
+#pragma unroll
+        for (int u = 0; u < kKu; ++u) {
+            const int row = k0 + 4 * u + lr;
+            const bool in = row < R;
+            const int rr = in ? row : 0;
+#pragma unroll
+            for (int s = 0; s < TPW; ++s)
+                if (wave + kWg * s < n) a[u][s] = in ? ap[s][(long long)rr * ld[s]] : 0.0;
+            b[u][0] = in ? V[rr * kLdv + half + lc] : 0.0;
+            b[u][1] = in ? V[rr * kLdv + half + 16 + lc] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kKu; ++u)
+#pragma unroll
+            for (int s = 0; s < TPW; ++s)
+                if (wave + kWg * s < n && k0 + 4 * u < R) {
+                    acc[s][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b[u][0], acc[s][0], 0, 0, 0);
+                    acc[s][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b[u][1], acc[s][1], 0, 0, 0);
+                }
+    }
+}
+
+template <int TPW>
+__device__ __forceinline__ void zero(v4d (&acc)[TPW][2])
+{
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) acc[s][0] = acc[s][1] = v4d{0.0, 0.0, 0.0, 0.0};
+}
+
+// Position of element (s, h, e) of this lane's results: part, row within the
+// part, right-hand side.  valid is false for rows past the part's size and
+// for tasks this wavefront does not own.
+struct Slot {
+    int part, row, rhs;
+    bool valid;
+};
+
+__device__ __forceinline__ Slot slot(const Tasks &tk, const int (&ncols)[2], int s, int h, int e, int wave,
+                                     int lane)
+{
+    Slot o;
+    const int task = wave + kWg * s;
+    const int tile = task >> 1;
+    o.part = tile < tk.t0 ? 0 : 1;
+    o.row = (o.part ? tile - tk.t0 : tile) * 16 + 4 * (lane >> 4) + e;
+    o.rhs = (task & 1) * 32 + h * 16 + (lane & 15);
+    o.valid = task < tk.count() && o.row < ncols[o.part];
+    return o;
+}
+
+// Stage rows [0, n) of one node vector of every right-hand side into the
+// panel rows [r0, r0 + n): V[r0 + r][k] = src(k, r).
+template <typename Src>
+__device__ __forceinline__ void stage(double *V, int r0, int n, Src src)
+{
+    for (int e = threadIdx.x; e < kPanel * n; e += kWg * kWave) {
+        const int k = e / n, r = e - k * n;
+        V[(r0 + r) * kLdv + k] = src(k, r);
+    }
+}
+
+// Backward step of non-leaf node i (Algorithm 3 / 4 body) for the panel.  On
+// entry, if child_in_lds, rows [0, nx) of V hold qhat of the single child; on
+// exit they hold qhat_i.  k_i goes to kbuf; qhat_i to the global buffer if
+// store_q.
+template <int TPW>
+__device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double *V, bool child_in_lds,
+                           bool store_q, int wave, int lane)
+{
+    const int nx = I.nx, nu = I.nu;
+    const int *cp = a.cp + I.cp;
+    const Tasks tk{tiles(nx), tiles(nu)};
+    const int ncols[2] = {nx, nu};
+    v4d S[TPW][2];
+    zero(S);
+    for (int j = cp[i]; j < cp[i + 1]; ++j) {
+        if (!child_in_lds) {
+            if (j >= I.Vnl) {
+                const double sj = a.sc ? a.sc[I.sc + j] : 1.0;
+                const double *ch = a.affine ? a.chat + I.chat + (long long)j * nx : nullptr;
+                stage(V, 0, nx, [&](int k, int r) { return sj * y_ptr(a, I, k, j)[r] + (ch ? ch[r] : 0.0); });
+            } else {
+                stage(V, 0, nx, [&](int k, int r) { return qhat_ptr(a, I, k, j)[r]; });
+            }
+            __syncthreads();
+        }
+        const double *Mb = a.Mb + I.Mb + (long long)j * nx * I.ldM;
+        const Part p[2] = {{Mb, I.ldM, 0, nx}, {Mb, I.ldM, nx, nu}};
+        product(p, tk, nx, V, S, wave, lane);
+        __syncthreads();   // every wavefront is done with the child panel
+    }
+    // g = [sum B'qhat] + s_i y^u + pi r  ->  panel rows [nx, nx + nu)
+    const double si = a.sc ? a.sc[I.sc + i] : 1.0;
+#pragma unroll
+    for (int s = 0; s < TPW; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                if (o.valid && o.part == 1)
+                    V[(nx + o.row) * kLdv + o.rhs] =
+                        S[s][h][e] + si * y_ptr(a, I, o.rhs, i)[nx + o.row] +
+                        (a.affine ? a.sig[I.sig + (long long)i * nu + o.row] : 0.0);
+            }
+    __syncthreads();
+    // [K' g ; -R~^{-1} g]
+    v4d T[TPW][2];
+    zero(T);
+    {
+        const Part p[2] = {{a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nx},
+                           {a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu}};
+        product(p, tk, nu, V + nx * kLdv, T, wave, lane);
+    }
+    const double *ch = a.affine ? a.chat + I.chat + (long long)i * nx : nullptr;
+#pragma unroll
+    for (int s = 0; s < TPW; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                if (!o.valid) continue;
+                if (o.part == 1) {
+                    kbuf_ptr(a, I, o.rhs, i)[o.row] = T[s][h][e];
+                } else {
+                    const double q = S[s][h][e] + T[s][h][e] + si * y_ptr(a, I, o.rhs, i)[o.row] +
+                                     (ch ? ch[o.row] : 0.0);
+                    S[s][h][e] = q;
+                    if (store_q) qhat_ptr(a, I, o.rhs, i)[o.row] = q;
+                }
+            }
+    __syncthreads();   // every wavefront has read g and the old qhat rows
+#pragma unroll
+    for (int s = 0; s < TPW; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                if (o.valid && o.part == 0) V[o.row * kLdv + o.rhs] = S[s][h][e];
+            }
+    __syncthreads();
+}
+
+// Forward step of non-leaf node i with x_i in panel rows [0, nx).  Writes u_i
+// and the children's x_j; for a single-child chain (keep_child) the child's x
+// replaces x_i in the panel.
+template <int TPW>
+__device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double *V, bool keep_child, int wave,
+                           int lane)
+{
+    const int nx = I.nx, nu = I.nu, W = nx + nu;
+    const int *cp = a.cp + I.cp;
+    const int ncols[2] = {nx, nu};
+    {
+        const Tasks tk{0, tiles(nu)};
+        v4d U[TPW][2];
+        zero(U);
+        const Part p[2] = {{nullptr, 0, 0, 0}, {a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nu}};
+        product(p, tk, nx, V, U, wave, lane);
+#pragma unroll
+        for (int s = 0; s < TPW; ++s)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                    if (!o.valid) continue;
+                    const double uv = U[s][h][e] + kbuf_ptr(a, I, o.rhs, i)[o.row];
+                    u_ptr(a, I, o.rhs, i)[o.row] = uv;
+                    V[(nx + o.row) * kLdv + o.rhs] = uv;
+                }
+        __syncthreads();
+    }
+    const Tasks tk{tiles(nx), 0};
+    v4d X[TPW][2];
+    for (int j = cp[i]; j < cp[i + 1]; ++j) {
+        zero(X);
+        const Part p[2] = {{a.Mf + I.Mf + (long long)j * W * I.ldx, I.ldx, 0, nx}, {nullptr, 0, 0, 0}};
+        product(p, tk, W, V, X, wave, lane);
+        const double *cj = a.affine ? a.cvec + I.c + (long long)j * nx : nullptr;
+#pragma unroll
+        for (int s = 0; s < TPW; ++s)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                    if (!o.valid) continue;
+                    const double xv = X[s][h][e] + (cj ? cj[o.row] : 0.0);
+                    X[s][h][e] = xv;
+                    x_ptr(a, I, o.rhs, j)[o.row] = xv;
+                }
+    }
+    if (keep_child) {
+        __syncthreads();   // every wavefront is done reading [x_i; u_i]
+#pragma unroll
+        for (int s = 0; s < TPW; ++s)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                    if (o.valid) V[o.row * kLdv + o.rhs] = X[s][h][e];
+                }
+        __syncthreads();
+    }
+}
+
+// x_i into panel rows [0, nx): x0 at the root (also written to the output),
+// else the values the previous stage stored.
+__device__ void load_x64(const SweepArgs &a, const InstDesc &I, int i, double *V)
+{
+    const int nx = I.nx;
+    stage(V, 0, nx, [&](int k, int r) {
+        if (i != 0) return x_ptr(a, I, k, i)[r];
+        const double v = a.affine ? a.x0[k * a.x0_rs + I.x0 + r] : 0.0;
+        x_ptr(a, I, k, 0)[r] = v;
+        return v;
+    });
+    __syncthreads();
+}
+
+template <int TPW>
+__global__ void __launch_bounds__(kWave *kWg) bwd_trunk64_kernel(SweepArgs a)
+{
+    extern __shared__ double lds[];
+    const Item it = a.items[blockIdx.x];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+    bwd_node64<TPW>(a, I, it.idx, lds, false, true, wave, lane);
+}
+
+template <int TPW>
+__global__ void __launch_bounds__(kWave *kWg) fwd_trunk64_kernel(SweepArgs a)
+{
+    extern __shared__ double lds[];
+    const Item it = a.items[blockIdx.x];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+    load_x64(a, I, it.idx, lds);
+    fwd_node64<TPW>(a, I, it.idx, lds, false, wave, lane);
+}
+
+// Chains below s*: one workgroup per chain (items: instance, chain).
+template <int TPW>
+__global__ void __launch_bounds__(kWave *kWg) bwd_chain64_kernel(SweepArgs a)
+{
+    extern __shared__ double lds[];
+    const Item it = a.items[blockIdx.x];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+    const int *sp = a.sp + I.sp;
+    for (int t = I.N - 1; t >= I.sstar; --t)
+        bwd_node64<TPW>(a, I, sp[t] + it.idx, lds, t != I.N - 1, t == I.sstar && t > 0, wave, lane);
+}
+
+template <int TPW>
+__global__ void __launch_bounds__(kWave *kWg) fwd_chain64_kernel(SweepArgs a)
+{
+    extern __shared__ double lds[];
+    const Item it = a.items[blockIdx.x];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+    const int *sp = a.sp + I.sp;
+    load_x64(a, I, sp[I.sstar] + it.idx, lds);
+    for (int t = I.sstar; t < I.N; ++t)
+        fwd_node64<TPW>(a, I, sp[t] + it.idx, lds, t + 1 < I.N, wave, lane);
+}
+
+}  // namespace
+
+// Tasks per wavefront the largest instance needs (0: too wide for the panel sweep).
+int panel_tpw(const tree_factors *f)
+{
+    int t = 1;
+    for (const InstDesc &I : f->inst) {
+        const int need = (2 * (tiles(I.nx) + tiles(I.nu)) + kWg - 1) / kWg;
+        t = need > t ? need : t;
+    }
+    return t <= kTpwMax ? t : 0;
+}
+
+template <int TPW>
+static void launch_panel(const tree_factors *f, const SweepArgs &a, size_t lds, hipStream_t st)
+{
+    const dim3 blk(kWave * kWg);
+    SweepArgs ca = a;
+    ca.items = f->panel_chain_items;
+    ca.nitems = f->npanel_chain_items;
+    if (ca.nitems > 0) hipLaunchKernelGGL(bwd_chain64_kernel<TPW>, dim3(ca.nitems), blk, lds, st, ca);
+    for (int k = (int)f->levels.size() - 1; k >= 0; --k) {
+        SweepArgs la = a;
+        la.items = f->levels[k].items;
+        la.nitems = f->levels[k].count;
+        hipLaunchKernelGGL(bwd_trunk64_kernel<TPW>, dim3(la.nitems), blk, lds, st, la);
+    }
+    for (size_t k = 0; k < f->levels.size(); ++k) {
+        SweepArgs la = a;
+        la.items = f->levels[k].items;
+        la.nitems = f->levels[k].count;
+        hipLaunchKernelGGL(fwd_trunk64_kernel<TPW>, dim3(la.nitems), blk, lds, st, la);
+    }
+    if (ca.nitems > 0) hipLaunchKernelGGL(fwd_chain64_kernel<TPW>, dim3(ca.nitems), blk, lds, st, ca);
+}
+
+hipError_t launch_panel_sweep(const tree_factors *f, const SweepArgs &a, hipStream_t st)
+{
+    int W = 2;
+    for (const InstDesc &I : f->inst) W = W > I.nx + I.nu ? W : I.nx + I.nu;
+    const size_t lds = sizeof(double) * (size_t)W * kLdv;
+    switch (panel_tpw(f)) {
+    case 1: launch_panel<1>(f, a, lds, st); break;
+    case 2: launch_panel<2>(f, a, lds, st); break;
+    case 3: launch_panel<3>(f, a, lds, st); break;
+    case 4: launch_panel<4>(f, a, lds, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace stotree

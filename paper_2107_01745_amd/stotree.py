@@ -60,7 +60,8 @@ EXPORTS = ("tree_factor", "tree_factor_batch", "tree_factors_free", "tree_dims",
            "solve_info_batch", "stotree_timing", "stotree_timing_read", "stotree_last_error",
            "warm_mlp_params", "warm_mlp_work_len", "warm_mlp_forward", "warm_mlp_backward",
            "warm_mse_grad", "warm_adam", "warm_features", "warm_scatter", "warm_targets",
-           "dual_select")
+           "dual_select", "sweep_schedule", "sweep_schedule_get", "sweep_autotune",
+           "sweep_graph_create", "sweep_graph_launch", "sweep_graph_free")
 PHASES = ("bwd_chain", "bwd_stages", "fwd_stages", "fwd_chain")
 
 _lib = None
@@ -101,6 +102,17 @@ def lib():
         L.stotree_timing_read.restype = C.c_int
         L.stotree_last_error.argtypes = []
         L.stotree_last_error.restype = C.c_char_p
+        i32p = C.POINTER(C.c_int32)
+        L.sweep_schedule.argtypes = [vp, i32p]
+        L.sweep_schedule_get.argtypes = [vp, i32p]
+        L.sweep_autotune.argtypes = [vp, C.c_int, C.c_int, i32p, _dp, vp]
+        L.sweep_graph_create.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp, vp, C.POINTER(vp)]
+        L.sweep_graph_launch.argtypes = [vp, vp]
+        for fn in (L.sweep_schedule, L.sweep_schedule_get, L.sweep_autotune, L.sweep_graph_create,
+                   L.sweep_graph_launch):
+            fn.restype = C.c_int
+        L.sweep_graph_free.argtypes = [vp]
+        L.sweep_graph_free.restype = None
         _lib = L
     return _lib
 
@@ -157,6 +169,11 @@ class TreeFactors:
         self.nx, self.nu, self.N, self.Vnl, self.sstar = i0["nx"], i0["nu"], i0["N"], i0["Vnl"], i0["sstar"]
 
     def free(self):
+        for ref in getattr(self, "_graphs", ()):
+            g = ref()
+            if g is not None:
+                g.free()
+        self._graphs = []
         if self.handle:
             lib().tree_factors_free(self.handle)
             self.handle = None
@@ -223,6 +240,84 @@ def dual_grad(tf: TreeFactors, x0, y, homogeneous: bool, x, u, nrhs: int = 1, st
     """x(y) (Algorithm 3) or x-hat(y) (Algorithm 4) into the device tensors x, u."""
     _check(lib().dual_grad(tf.handle, _ptr(x0), _ptr(y), int(bool(homogeneous)), int(nrhs),
                            _ptr(x), _ptr(u), _stream(stream)))
+
+
+def sweep_schedule(tf: TreeFactors, knobs) -> None:
+    """Set (group_min, chain_order, trunk_cap) of the handle's sweeps."""
+    k = (C.c_int32 * 3)(*[int(v) for v in knobs])
+    _check(lib().sweep_schedule(tf.handle, k))
+
+
+def sweep_schedule_get(tf: TreeFactors) -> tuple:
+    k = (C.c_int32 * 3)()
+    _check(lib().sweep_schedule_get(tf.handle, k))
+    return tuple(int(v) for v in k)
+
+
+def forest_signature(tf: TreeFactors, nrhs: int) -> str:
+    """Key of the autotuning cache: the sizes of every instance and nrhs."""
+    import hashlib
+    h = hashlib.sha1()
+    for d in tf.instances:
+        h.update(repr((d["nx"], d["nu"], d["N"], d["V"], d["Vnl"], d["sstar"])).encode())
+    return f"{tf.ninst}x{h.hexdigest()[:16]}:nrhs{nrhs}"
+
+
+def sweep_autotune(tf: TreeFactors, nrhs: int = 1, reps: int = 5, cache: str | None = None,
+                   stream=None) -> dict:
+    """Pick the fastest schedule for this handle (timed on the device) and
+    keep it.  With ``cache`` (a JSON file), a schedule stored for the same
+    forest signature is applied without timing, and a new one is stored."""
+    import json
+    key = forest_signature(tf, nrhs)
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as fh:
+            table = json.load(fh)
+        if key in table:
+            sweep_schedule(tf, table[key]["knobs"])
+            return dict(table[key], cached=True)
+    k = (C.c_int32 * 3)()
+    ms = C.c_double()
+    _check(lib().sweep_autotune(tf.handle, int(nrhs), int(reps), k, C.byref(ms), _stream(stream)))
+    rec = {"knobs": [int(v) for v in k], "ms": ms.value}
+    if cache:
+        table[key] = rec
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return dict(rec, cached=False)
+
+
+class SweepGraph:
+    """A dual_grad call recorded as one HIP graph (pointers bound at creation)."""
+
+    def __init__(self, tf: TreeFactors, x0, y, homogeneous: bool, x, u, nrhs: int = 1):
+        h = C.c_void_p()
+        _check(lib().sweep_graph_create(tf.handle, _ptr(x0), _ptr(y), int(bool(homogeneous)), int(nrhs),
+                                        _ptr(x), _ptr(u), C.byref(h)))
+        self.handle = h
+        self._keep = (x0, y, x, u)   # the bound buffers must outlive the graph
+        import weakref
+        if not hasattr(tf, "_graphs"):
+            tf._graphs = []
+        tf._graphs.append(weakref.ref(self))   # freed with (before) the handle
+
+    def launch(self, stream=None) -> None:
+        _check(lib().sweep_graph_launch(self.handle, _stream(stream)))
+
+    def free(self) -> None:
+        if self.handle:
+            lib().sweep_graph_free(self.handle)
+            self.handle = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def dual_lipschitz(tf: TreeFactors, iters: int = 100, stream=None):

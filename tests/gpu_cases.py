@@ -52,6 +52,10 @@ def case(name):
         return treegen.draw_problem(treegen.uniform_tree([2, 3, 2]), 6, 4, rng)
     if name == "capped":          # config-2 style uneven fan-out
         return treegen.draw_problem(treegen.capped_tree(9, 23, 3), 9, 4, rng)
+    if name == "mid_width":       # nx + nu in (32, 64]: two chains per wavefront; 13 chains
+        return treegen.draw_problem(treegen.capped_tree(8, 13, 3), 24, 12, rng)
+    if name == "cfg4_shape":      # config-4 blocks (nx=64, nu=32) on a small tree
+        return treegen.draw_problem(treegen.uniform_tree([4, 4, 1, 1, 1]), 64, 32, rng)
     if name == "cfg3_shape":
         return treegen.draw_problem(treegen.uniform_tree([3, 3, 1, 1, 1, 1]), 20, 10, rng,
                                     x0_range=3.0)
@@ -59,7 +63,7 @@ def case(name):
 
 
 SWEEP_CASES = ["tiny", "odd_ragged", "cfg1_shape", "wide", "single_path", "no_chain", "capped",
-               "cfg3_shape"]
+               "mid_width", "cfg3_shape"]
 
 
 def with_tight_boxes(prob, xbox, ubox):

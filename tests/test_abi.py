@@ -95,3 +95,18 @@ def test_rejects_nonfinite_data(st):
 def test_rejects_sizes(st):
     p = treegen.draw_problem(treegen.uniform_tree([1, 1]), 200, 100, np.random.default_rng(0))
     _expect(st, p, -1)
+
+
+def test_schedule_graph_calls_reject_null_on_host(st):
+    import ctypes as C
+    L = st.lib()
+    k = (C.c_int32 * 3)(8, 1, 16)
+    assert L.sweep_schedule(None, k) == -1
+    assert L.sweep_schedule_get(None, k) == -1
+    assert L.sweep_autotune(None, 1, 3, k, None, None) == -1
+    assert L.sweep_graph_launch(None, None) == -1
+    out = C.c_void_p(1)
+    assert L.sweep_graph_create(None, None, None, 1, 1, None, None, C.byref(out)) == -1
+    assert out.value is None            # *out cleared on failure
+    L.sweep_graph_free(None)            # no-op
+    assert "NULL" in st.stotree_last_error()

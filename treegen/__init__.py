@@ -152,11 +152,11 @@ def capped_tree(N: int, scenarios: int, b0: int) -> Tree:
     return tree_from_counts(counts)
 
 
-def _spectral_radius(G: np.ndarray) -> np.ndarray:
+def _spectral_radius(G: np.ndarray, threads: int | None = None) -> np.ndarray:
     """Batched spectral radius, split over threads for large stacks."""
     if G.shape[0] == 0:
         return np.zeros(0)
-    nthreads = min(16, os.cpu_count() or 1)
+    nthreads = min(16, os.cpu_count() or 1) if threads is None else threads
     if G.shape[0] < 512 or nthreads == 1:
         return np.abs(np.linalg.eigvals(G)).max(axis=-1)
     chunks = np.array_split(np.arange(G.shape[0]), nthreads * 4)
@@ -174,7 +174,7 @@ def draw_problem(tree: Tree, nx: int, nu: int, rng: np.random.Generator, *,
                  rho: float = 0.95, c_std: float = 0.1,
                  qdiag=None, rdiag=None, xbox: float = 5.0, ubox: float = 1.0,
                  x0_range: float = 2.0, cross_terms: bool = False,
-                 name: str = "") -> Problem:
+                 name: str = "", threads: int | None = None) -> Problem:
     """Draw dynamics, costs, boxes and x0 for a tree.
 
     A_j = rho * G / spectral_radius(G) with G ~ N(0,1), B_j ~ N(0,1),
@@ -188,7 +188,7 @@ def draw_problem(tree: Tree, nx: int, nu: int, rng: np.random.Generator, *,
     B = np.zeros((V, nx, nu))
     c = np.zeros((V, nx))
     G = rng.standard_normal((V - 1, nx, nx))
-    A[1:] = rho * G / _spectral_radius(G)[:, None, None]
+    A[1:] = rho * G / _spectral_radius(G, threads)[:, None, None]
     del G
     B[1:] = rng.standard_normal((V - 1, nx, nu))
     c[1:] = c_std * rng.standard_normal((V - 1, nx))
@@ -260,9 +260,13 @@ def draw_batch_instances(count: int = 256, seed: int = 1002, *,
     Per instance: nx ~ U{nx_range}, nu = nx // 2, N ~ U{N_range},
     scenarios S ~ U{S_range} (times ``scale``, for reduced test sizes),
     first-stage branching b0 ~ U{b0_range}; the tree follows ``capped_tree``.
+    The sizes come from ``default_rng(seed)`` in instance order; instance b's
+    matrices and vectors from its own ``default_rng([seed, b])``, so the
+    instances are drawn in parallel threads with a result independent of
+    the thread count.
     """
     rng = np.random.default_rng(seed)
-    out = []
+    shapes = []
     for b in range(count):
         nx = int(rng.integers(nx_range[0], nx_range[1] + 1))
         nu = max(1, nx // 2)
@@ -270,9 +274,18 @@ def draw_batch_instances(count: int = 256, seed: int = 1002, *,
         S = int(rng.integers(S_range[0], S_range[1] + 1))
         S = max(1, int(round(S * scale)))
         b0 = int(rng.integers(b0_range[0], b0_range[1] + 1))
-        tree = capped_tree(N, S, b0)
-        out.append(draw_problem(tree, nx, nu, rng, name=f"cfg2[{b}]"))
-    return out
+        shapes.append((nx, nu, N, S, b0))
+
+    def one(b):
+        nx, nu, N, S, b0 = shapes[b]
+        return draw_problem(capped_tree(N, S, b0), nx, nu, np.random.default_rng([seed, b]),
+                            name=f"cfg2[{b}]", threads=1)
+
+    nthreads = min(16, os.cpu_count() or 1)
+    if count < 4 or nthreads == 1:
+        return [one(b) for b in range(count)]
+    with _cf.ThreadPoolExecutor(nthreads) as ex:
+        return list(ex.map(one, range(count)))
 
 
 def random_dual(prob: Problem, rng: np.random.Generator, nrhs: int | None = None,
