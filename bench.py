@@ -211,6 +211,220 @@ def batched_leg(stotree, torch, steps, warmup, cache):
     return rep
 
 
+def panel_bytes(prob, sstar, nrhs):
+    """Algorithmic HBM bytes of one affine sweep of nrhs right-hand sides that
+    share the factors: every factor entry and per-node constant once, every
+    per-right-hand-side vector entry once per right-hand side."""
+    t = prob.tree
+    nx, nu, W = prob.nx, prob.nu, prob.nx + prob.nu
+    V, Vnl, E = int(t.V), int(t.Vnl), int(t.V) - 1
+    sp = [int(v) for v in t.stage_ptr]
+    N = int(t.N)
+    factors = 8 * (2 * E * nx * W + Vnl * (nu * nu + 2 * nu * nx) + V * nx + Vnl * nu + E * nx + V)
+    heads = (sp[N + 1] - sp[N]) if 0 < sstar < N else 0
+    trunk = sp[sstar] if sstar > 0 else 0
+    per_rhs = 8 * (prob.m + 3 * Vnl * nu + V * nx + 2 * heads * nx + 2 * trunk * nx + nx)
+    return factors + nrhs * per_rhs
+
+
+def panel_leg(stotree, torch, steps, warmup):
+    """Config 4: nx=64, nu=32, N=20, branching 4 at stages 0-6 (16384
+    scenarios, 234,837 nodes); 64 instances share the tree's factors and
+    differ in x0.  A step is one x(y) sweep of all 64 instances, i.e. one
+    64-right-hand-side panel pass on the FP64 matrix cores.  Also timed: the
+    same 64 sweeps as 32 two-vector sweeps on a plain handle.  Reports HBM and
+    MFMA fractions and the inner-problem KKT residual of sampled instances."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_cases import inner_kkt_residual
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    prob = treegen.make_config(4)
+    gen_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tf = stotree.tree_factor_shared(prob, 64, precondition=True)
+    torch.cuda.synchronize()
+    factor_s = time.perf_counter() - t0
+    sstar = tf.sstar
+    log(f"config 4: V={prob.tree.V}, m={prob.m}, drawn in {gen_s:.1f} s, factor step {factor_s:.1f} s, "
+        f"{tf.device_bytes / 1e9:.1f} GB on device")
+    rng = np.random.default_rng(13)
+    X0 = rng.uniform(-3, 3, (64, prob.nx))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(13)
+    y = torch.randn(tf.m, dtype=torch.float64, device=dev, generator=gen)
+    x0 = torch.tensor(X0.ravel(), dtype=torch.float64, device=dev)
+    x = torch.empty(tf.x_len, dtype=torch.float64, device=dev)
+    u = torch.empty(tf.u_len, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    for _ in range(warmup):
+        stotree.dual_grad(tf, x0, y, False, x, u)
+    panel_ms = timed(lambda: stotree.dual_grad(tf, x0, y, False, x, u), steps)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k in (0, 37, 63):
+        d = tf.instances[k]
+        tr = prob.tree
+        w = np.where(np.arange(tr.V) < tr.Vnl, prob.nx + prob.nu, prob.nx)
+        yk = y[d["y_off"]:d["y_off"] + d["m"]].cpu().numpy() * np.repeat(np.sqrt(tr.prob), w)
+        xk = x[d["x_off"]:d["x_off"] + d["V"] * d["nx"]].cpu().numpy().reshape(d["V"], d["nx"])
+        uk = u[d["u_off"]:d["u_off"] + d["Vnl"] * d["nu"]].cpu().numpy().reshape(d["Vnl"], d["nu"])
+        worst = max(worst, *inner_kkt_residual(prob, yk, xk, uk, X0[k]))
+    del x, u
+    # the same 64 sweeps as two-vector sweeps of a plain (one-instance) handle
+    tf1 = stotree.tree_factor(prob, precondition=True)
+    x2 = torch.empty(2 * tf1.x_len, dtype=torch.float64, device=dev)
+    u2 = torch.empty(2 * tf1.u_len, dtype=torch.float64, device=dev)
+    m1 = tf1.m
+
+    def pairs():
+        for k in range(0, 64, 2):
+            stotree.dual_grad(tf1, x0[k * prob.nx:(k + 2) * prob.nx], y[k * m1:(k + 2) * m1], False, x2, u2,
+                              nrhs=2)
+
+    pairs()
+    pair_ms = timed(pairs, max(1, steps // 4))
+    tf1.free()
+    tf.free()
+    nbytes = panel_bytes(prob, sstar, 64)
+    flops = 64 * sweep_flops(prob)
+    gbs = nbytes / (panel_ms * 1e-3) / 1e9
+    tfs = flops / (panel_ms * 1e-3) / 1e12
+    rep = {"workload": ("config 4: nx=64, nu=32, N=20, branching 4 at stages 0-6 (16384 scenarios, 234837 "
+                        "nodes); 64 instances sharing the factors, different x0; step = x(y) of all 64"),
+           "generation_s": gen_s, "factor_s": factor_s, "ms_per_step_panel": panel_ms,
+           "ms_per_64_pair_sweeps": pair_ms, "speedup_panel_vs_pairs": pair_ms / panel_ms,
+           "instance_sweeps_per_s": 64 * 1000.0 / panel_ms, "bytes_per_step": nbytes, "flops_per_step": flops,
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS},
+           "mfma": {"achieved": tfs, "peak": 78.6, "unit": "TFLOP/s", "frac": tfs / 78.6},
+           "inner_kkt_residual_sampled": worst}
+    log(f"config 4: panel {panel_ms:.2f} ms per 64 sweeps, pairs {pair_ms:.2f} ms "
+        f"({pair_ms / panel_ms:.2f}x); {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% HBM), "
+        f"{tfs:.1f} TFLOP/s ({100 * tfs / 78.6:.1f}% FP64 MFMA); KKT residual {worst:.1e}")
+    return rep
+
+
+def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
+    """Config 4 solves: 64 instances sharing the tree (x0 ~ U[-3,3]^64), |u|
+    <= ubox so that the boxes bind.  The node-wise MLP is retrained on this
+    tree from n_batches x 64 batched NAMA solves (rows subsampled), then 64
+    held-out draws are solved (a) one at a time from a cold start on a plain
+    handle (n_solo timed, scaled to 64), (b) together from a cold start, every
+    sweep a 64-instance panel, and (c) together from the learned warm start.
+    Times exclude the factor step and include prediction and the residual
+    checks of the warm start."""
+    from paper_2107_01745_amd import warmstart as ws
+    dev = torch.device("cuda:0")
+    prob = treegen.with_boxes(treegen.make_config(4), 5.0, ubox)
+    nx = prob.nx
+    rng = np.random.default_rng(404)
+    draws = lambda: torch.tensor(rng.uniform(-3, 3, (64, nx)).ravel(), dtype=torch.float64, device=dev)
+    test_x0 = draws()
+    # (a) cold, one instance at a time
+    tf1 = stotree.tree_factor(prob, precondition=True)
+    lam = 1.0 / (1.1 * stotree.dual_lipschitz(tf1, 50))
+    solo_s, solo_it = 0.0, []
+    for k in range(n_solo):
+        _, _, info, sec = ws.solve_batch(test_x0[k * nx:(k + 1) * nx], lam, eps=1e-6, tf=tf1, mem=mem)
+        solo_s += sec
+        solo_it.append(info[0]["iters"])
+    tf1.free()
+    torch.cuda.empty_cache()
+    log(f"config 4 solve: lambda {lam:.4g}; cold per-instance {solo_s / n_solo:.2f} s, iters {solo_it}")
+    tfs = stotree.tree_factor_shared(prob, 64, precondition=True)
+    model = ws.WarmStartMLP(nx, prob.nu, prob.tree.N, dh=128, seed=0)
+    Xs, Ts, Ms = [], [], []
+    gen_s, gen_it = 0.0, []
+    keep_rows = 1 << 21
+    sel_gen = torch.Generator(device=dev)
+    sel_gen.manual_seed(5)
+    for b in range(n_batches):
+        x0 = draws()
+        _, y, infos, sec = ws.solve_batch(x0, lam, eps=1e-6, tf=tfs, mem=mem)
+        gen_s += sec
+        gen_it += [i["iters"] for i in infos]
+        if b == 0:
+            nz = y.abs()[y.abs() > 0]
+            model.y_scale = float(nz.pow(2).mean().sqrt().item()) if nz.numel() else 1.0
+        X = model.features(tfs, x0)
+        T, M = model.targets(tfs, y)
+        row = 0
+        for info in infos:
+            if info["status"] != 0:
+                M[row:row + prob.tree.V] = 0.0
+            row += prob.tree.V
+        idx = torch.randperm(X.shape[0], device=dev, generator=sel_gen)[:keep_rows]
+        Xs.append(X[idx]); Ts.append(T[idx]); Ms.append(M[idx])
+        del X, T, M, y
+        torch.cuda.empty_cache()
+    X, T, M = torch.cat(Xs), torch.cat(Ts), torch.cat(Ms)
+    del Xs, Ts, Ms
+    t0 = time.perf_counter()
+    hist = model.fit(X, T, M, epochs=epochs, batch_rows=65536, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del X, T, M
+    torch.cuda.empty_cache()
+    log(f"config 4 solve: {n_batches * 64} training solves in {gen_s:.1f} s (mean iters {np.mean(gen_it):.1f}); "
+        f"{epochs} epochs in {train_s:.1f} s, masked MSE {hist[0]:.3e} -> {hist[-1]:.3e}")
+    # (b) cold, batched
+    _, _, info_c, cold_s = ws.solve_batch(test_x0, lam, eps=1e-6, tf=tfs, mem=mem)
+    # (c) warm, batched
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    yw, keep = ws.warm_start_duals(model, tfs, test_x0, lam)
+    torch.cuda.synchronize()
+    pred_s = time.perf_counter() - t0
+    _, _, info_w, warm_s = ws.solve_batch(test_x0, lam, eps=1e-6, y0=yw, tf=tfs, mem=mem)
+    tfs.free()
+    del yw
+    torch.cuda.empty_cache()
+    solo_total = solo_s / n_solo * 64
+    rep = {"workload": "config 4 with |u| <= %g: 64 instances sharing the tree, x0 ~ U[-3,3]" % ubox,
+           "lambda": lam, "mem": mem, "training_solves": n_batches * 64, "training_rows": int(keep_rows * n_batches),
+           "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]], "training_generation_s": gen_s,
+           "train_s": train_s,
+           "cold_per_instance": {"sample": n_solo, "iters": solo_it, "s_per_instance": solo_s / n_solo,
+                                 "s_total_64": solo_total},
+           "cold_batched": {"s": cold_s, "iters_mean": float(np.mean([i["iters"] for i in info_c])),
+                            "converged": int(sum(i["status"] == 0 for i in info_c))},
+           "warm_batched": {"s": pred_s + warm_s, "predict_s": pred_s, "kept": int(sum(keep)),
+                            "iters_mean": float(np.mean([i["iters"] for i in info_w])),
+                            "converged": int(sum(i["status"] == 0 for i in info_w))},
+           "speedup_warm_batched_vs_cold_per_instance": solo_total / (pred_s + warm_s),
+           "speedup_cold_batched_vs_cold_per_instance": solo_total / cold_s}
+    log(f"config 4 solve: cold per-instance {solo_total:.1f} s (64, est.), cold batched {cold_s:.2f} s "
+        f"(iters {rep['cold_batched']['iters_mean']:.1f}), warm batched {pred_s + warm_s:.2f} s "
+        f"(iters {rep['warm_batched']['iters_mean']:.1f}, kept {sum(keep)}) -> "
+        f"{rep['speedup_warm_batched_vs_cold_per_instance']:.1f}x")
+    return rep
+
+
+def guarded(name, fn, *a):
+    """Run an extra leg; a failure is recorded in the JSON, not fatal."""
+    try:
+        return fn(*a)
+    except Exception as e:  # noqa: BLE001
+        log(f"{name} leg failed: {type(e).__name__}: {e}")
+        err = {"error": f"{type(e).__name__}: {e}"}
+    import gc
+    import torch
+    gc.collect()                 # release the failed leg's handles and buffers
+    torch.cuda.empty_cache()
+    return err
+
+
 def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     """Config 3 (nx=20, nu=10, N=15, branching 3 at stages 0-4; |u| <= 0.2 so
     that the boxes bind): train the warm-start MLP on solver-generated duals
@@ -312,6 +526,13 @@ def main():
     ap.add_argument("--tight-u", type=float, default=0.1)
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-panel", action="store_true")
+    ap.add_argument("--no-panel-solve", action="store_true")
+    ap.add_argument("--c4-ubox", type=float, default=0.1)
+    ap.add_argument("--c4-batches", type=int, default=2)
+    ap.add_argument("--c4-epochs", type=int, default=8)
+    ap.add_argument("--c4-solo", type=int, default=2)
+    ap.add_argument("--c4-mem", type=int, default=3)
     ap.add_argument("--tune-cache", default=None, help="JSON cache of tuned schedules (default: tune)")
     ap.add_argument("--warm-train", type=int, default=1024)
     ap.add_argument("--warm-test", type=int, default=256)
@@ -435,12 +656,21 @@ def main():
 
     batched_rep = None
     if not args.no_batched:
-        batched_rep = batched_leg(stotree, torch, min(args.steps, 50), min(args.warmup, 5), args.tune_cache)
+        batched_rep = guarded("batched", batched_leg, stotree, torch, min(args.steps, 50), min(args.warmup, 5),
+                              args.tune_cache)
+
+    panel_rep = None
+    if not args.no_panel:
+        panel_rep = guarded("panel", panel_leg, stotree, torch, min(args.steps, 20), min(args.warmup, 2))
+    panel_solve_rep = None
+    if not args.no_panel_solve:
+        panel_solve_rep = guarded("panel solve", panel_solve_leg, stotree, torch, args.c4_ubox, args.c4_batches,
+                                  args.c4_epochs, args.c4_solo, args.c4_mem)
 
     warm_rep = None
     if not args.no_warm:
-        warm_rep = warm_leg(stotree, torch, args.warm_train, args.warm_test, args.warm_solo, 64,
-                            args.warm_epochs)
+        warm_rep = guarded("warm start", warm_leg, stotree, torch, args.warm_train, args.warm_test,
+                           args.warm_solo, 64, args.warm_epochs)
 
     cpu = None
     if not args.no_cpu:
@@ -462,6 +692,8 @@ def main():
         "cpu_baseline": cpu,
         "solve": solve_rep,
         "batched": batched_rep,
+        "panel": panel_rep,
+        "panel_solve": panel_solve_rep,
         "warm_start": warm_rep,
     }
     tf.free()

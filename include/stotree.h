@@ -141,6 +141,20 @@ void tree_factors_free(tree_factors *f);
 int tree_factor_batch(int count, const tree_desc *trees, const problem_data *data, int precondition,
                       void *hip_stream, tree_factors **out);
 
+/*
+ * count instances that share one tree and all its problem data and differ
+ * only in the initial state x0 (given per call, [count][nx]): the factor step
+ * runs once and the handle keeps one copy of the factors.  Vectors are
+ * concatenated in instance order as for tree_factor_batch (instance k at k
+ * times the single-tree sizes).  When count is a multiple of 64 and
+ * nx + nu <= 128, every sweep (dual_grad, the solvers, dual_lipschitz) runs
+ * as panels of 64 instances on the FP64 matrix cores, streaming the factors
+ * once per panel (the extra parallelism of Sec. III-C across instances).
+ * Errors as tree_factor, plus ERR_ARG for count < 1.
+ */
+int tree_factor_shared(const tree_desc *tree, const problem_data *data, int precondition, int count,
+                       void *hip_stream, tree_factors **out);
+
 /* Sizes of a handle, written to HOST out[10]: instances, precondition flag,
  * total dual length, total primal length, sum V nx (x), sum V_nl nu (u),
  * sum nx (x0), total nodes, device bytes held, largest nx+nu.  ERR_ARG on
@@ -163,27 +177,31 @@ int tree_instance_dims(const tree_factors *f, int b, int64_t *out);
  * DEVICE pointers: x0 [nrhs][nx] (ignored when homogeneous; may be NULL then),
  * y [nrhs][m], x [nrhs][V][nx] (x_0 included), u [nrhs][V_nl][nu] (for a
  * batched handle, the concatenated sizes of tree_dims).
- * nrhs >= 1; right-hand sides are swept two at a time, each pair sharing
- * one streaming of the factors.  Errors: ERR_ARG, ERR_OOM (workspace growth), ERR_DEVICE.
+ * nrhs >= 1; right-hand sides are swept 64 at a time on the FP64 matrix
+ * cores while at least 64 remain (when every nx + nu <= 128), the rest two at
+ * a time, each group sharing one streaming of the factors.  Errors: ERR_ARG, ERR_OOM (workspace growth), ERR_DEVICE.
  */
 int dual_grad(const tree_factors *f, const double *x0, const double *y, int homogeneous,
               int nrhs, double *x, double *u, void *hip_stream);
 
 /*
  * Sweep schedule of a handle: how the stage-parallel sweeps of Sec. III-D
- * (Algorithms 3 and 4) are cut into GPU work.  HOST knobs[3]:
+ * (Algorithms 3 and 4) are cut into GPU work.  HOST knobs[4]:
  *   knobs[0] smallest lane group walking one chain below s*: 8, 16, 32 or 64
  *            lanes (an instance's chains use the smallest power of two G at
  *            least this with 2G >= nx + nu, at most 64); default 8;
  *   knobs[1] chain order: 1 costliest wavefront items first (default), 0
  *            instance order;
  *   knobs[2] cap on the wavefronts sharing one node above s*: 1, 2, 4, 8 or
- *            16 (default 16).
- * knobs[0] and knobs[1] change no result bit; knobs[2] changes the order of
- * the per-node sums above s* (equal to rounding).  sweep_schedule rebuilds the
- * work lists (synchronous; ERR_ARG for values outside these sets, ERR_OOM,
- * ERR_DEVICE); sweep_schedule_get reads them.  A schedule change invalidates
- * the handle's sweep graphs.
+ *            16 (default 16);
+ *   knobs[3] backward stages above s*: 1 one launch in which each node is
+ *            taken up by the workgroup that finishes its last child, 0 one
+ *            launch per stage (default).
+ * knobs[0] and knobs[1] change no result bit; knobs[2] and knobs[3] change
+ * the order of the per-node sums above s* (equal to rounding).
+ * sweep_schedule rebuilds the work lists (synchronous; ERR_ARG for values
+ * outside these sets, ERR_OOM, ERR_DEVICE); sweep_schedule_get reads them.
+ * A schedule change invalidates the handle's sweep graphs.
  */
 int sweep_schedule(tree_factors *f, const int32_t *knobs);
 int sweep_schedule_get(const tree_factors *f, int32_t *knobs);
@@ -194,8 +212,8 @@ int sweep_schedule_get(const tree_factors *f, int32_t *knobs);
  * and reps timed sweeps per candidate, over each knob in turn (coordinate
  * descent from the current schedule) and keeps the fastest.  HOST
  * knobs_out[3] and ms_out (milliseconds per sweep of the kept schedule) may
- * be NULL.  Allocates and frees its own scratch; synchronous.  Errors:
- * ERR_ARG, ERR_OOM, ERR_DEVICE.
+ * be NULL (knobs_out has 4 entries).  Allocates and frees its own scratch;
+ * synchronous.  Errors: ERR_ARG, ERR_OOM, ERR_DEVICE.
  */
 int sweep_autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms_out,
                    void *hip_stream);

@@ -35,6 +35,24 @@ int tree_factor_batch(int count, const tree_desc *trees, const problem_data *dat
     return factor_forest(count, trees, data, precondition, (hipStream_t)hip_stream, out);
 }
 
+int tree_factor_shared(const tree_desc *tree, const problem_data *data, int precondition, int count,
+                       void *hip_stream, tree_factors **out)
+{
+    set_error("");
+    if (count < 1) {
+        if (out) *out = nullptr;
+        set_error("tree_factor_shared: count < 1");
+        return STOTREE_ERR_ARG;
+    }
+    int rc = factor_forest(1, tree, data, precondition, (hipStream_t)hip_stream, out);
+    if (rc) return rc;
+    if ((rc = replicate_instances(*out, count))) {
+        free_tree(*out);
+        *out = nullptr;
+    }
+    return rc;
+}
+
 void tree_factors_free(tree_factors *f) { free_tree(f); }
 
 int tree_dims(const tree_factors *f, int64_t *out)
@@ -79,7 +97,7 @@ int sweep_schedule(tree_factors *f, const int32_t *knobs)
 int sweep_schedule_get(const tree_factors *f, int32_t *knobs)
 {
     if (!f || !knobs) { set_error("sweep_schedule_get: NULL argument"); return STOTREE_ERR_ARG; }
-    knobs[0] = f->group_min; knobs[1] = f->chain_order; knobs[2] = f->trunk_cap;
+    knobs[0] = f->group_min; knobs[1] = f->chain_order; knobs[2] = f->trunk_cap; knobs[3] = f->trunk_fused;
     return STOTREE_OK;
 }
 

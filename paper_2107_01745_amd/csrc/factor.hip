@@ -391,9 +391,13 @@ int build_schedule(tree_factors *f)
         }
     }
     if (f->panel_chain_items) { (void)hipFree(f->panel_chain_items); f->panel_chain_items = nullptr; }
+    for (auto &lv : f->panel_levels)
+        if (lv.items) (void)hipFree(lv.items);
+    f->panel_levels.clear();
+    const int panel_inst = f->shared > 1 ? 1 : f->ninst;   // a shared handle's panels cover instance 0's nodes
     {
         std::vector<Item> all;
-        for (int b = 0; b < f->ninst; ++b) {
+        for (int b = 0; b < panel_inst; ++b) {
             const InstDesc &I = f->inst[b];
             if (I.sstar < I.N)
                 for (int c = 0; c < I.nchains; ++c) all.push_back({b, c});
@@ -433,10 +437,70 @@ int build_schedule(tree_factors *f)
         lv.count = (int)items.size();
         lv.nw = trunk_waves(lv.count, 2, max_ldM, f->trunk_cap);
         STOTREE_HIP(hipMalloc(&lv.items, sizeof(Item) * std::max<size_t>(1, items.size())));
-        STOTREE_HIP(hipMemcpy(lv.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
         f->levels.push_back(lv);
+        STOTREE_HIP(hipMemcpy(lv.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+        if (panel_inst < f->ninst) {
+            const InstDesc &I = f->inst[0];
+            LevelPlan pl = lv;
+            pl.count = t < I.sstar ? f->sp_pool[I.sp + t + 1] - f->sp_pool[I.sp + t] : 0;
+            STOTREE_HIP(hipMalloc(&pl.items, sizeof(Item) * std::max(1, pl.count)));
+            f->panel_levels.push_back(pl);
+            STOTREE_HIP(hipMemcpy(pl.items, items.data(), sizeof(Item) * pl.count, hipMemcpyHostToDevice));
+        }
+    }
+    // one-launch backward trunk: its entry nodes and the per-node counters
+    if (f->trunk_entry.items) { (void)hipFree(f->trunk_entry.items); f->trunk_entry.items = nullptr; }
+    f->trunk_entry.count = 0;
+    {
+        std::vector<Item> entry;
+        for (int b = 0; b < f->ninst; ++b) {
+            const InstDesc &I = f->inst[b];
+            if (I.sstar < 1) continue;
+            const int *sp = f->sp_pool.data() + I.sp;
+            for (int i = sp[I.sstar - 1]; i < sp[I.sstar]; ++i) entry.push_back({b, i});
+        }
+        f->trunk_entry.t = -1;
+        f->trunk_entry.count = (int)entry.size();
+        f->trunk_entry.nw = trunk_waves(f->trunk_entry.count, 2, max_ldM, f->trunk_cap);
+        if (!entry.empty()) {
+            STOTREE_HIP(hipMalloc(&f->trunk_entry.items, sizeof(Item) * entry.size()));
+            STOTREE_HIP(hipMemcpy(f->trunk_entry.items, entry.data(), sizeof(Item) * entry.size(),
+                                  hipMemcpyHostToDevice));
+            if (!f->trunk_cnt) {
+                STOTREE_HIP(hipMalloc(&f->trunk_cnt, sizeof(int) * (size_t)f->V_tot));
+                STOTREE_HIP(hipMemset(f->trunk_cnt, 0, sizeof(int) * (size_t)f->V_tot));
+            }
+        }
     }
     return STOTREE_OK;
+}
+
+// Turn a one-instance handle into count instances that share its tree,
+// factors and boxes (each with its own x0 and vectors, concatenated in
+// instance order).
+int replicate_instances(tree_factors *f, int count)
+{
+    if (f->ninst != 1 || count < 1) { set_error("tree_factor_shared: bad instance count"); return STOTREE_ERR_ARG; }
+    if (count == 1) return STOTREE_OK;
+    const InstDesc I0 = f->inst[0];
+    const long long xl = (long long)I0.V * I0.nx, ul = (long long)I0.Vnl * I0.nu;
+    f->inst.assign(count, I0);
+    for (int k = 0; k < count; ++k) {
+        InstDesc &I = f->inst[k];
+        I.y = k * I0.m; I.x = k * xl; I.u = k * ul; I.x0 = (long long)k * I0.nx; I.box = 0;
+        I.node0 = (long long)k * I0.V;
+    }
+    f->ninst = count;
+    f->shared = count;
+    f->m_tot *= count; f->n_tot *= count; f->x_tot *= count; f->u_tot *= count; f->nx_tot *= count;
+    f->V_tot *= count;
+    if (f->trunk_cnt) { (void)hipFree(f->trunk_cnt); f->trunk_cnt = nullptr; }
+    if (f->d_inst) (void)hipFree(f->d_inst);
+    f->d_inst = nullptr;
+    STOTREE_HIP(hipMalloc(&f->d_inst, sizeof(InstDesc) * count));
+    STOTREE_HIP(hipMemcpy(f->d_inst, f->inst.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice));
+    f->last_info.assign(count, solver_info{});
+    return build_schedule(f);
 }
 
 int factor_forest(int count, const tree_desc *trees, const problem_data *datas, int precondition,
@@ -461,7 +525,7 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
     f->inst.resize(count);
     std::vector<RawDesc> raw(count);
     long long oMb = 0, oMf = 0, oKb = 0, oKf = 0, oRn = 0, ochat = 0, osig = 0, osc = 0, oy = 0, ox = 0,
-              ou = 0, ox0 = 0;
+              ou = 0, ox0 = 0, onode = 0;
     RawDesc ro{};
     int osp = 0, ocp = 0;
     bool anyS = false, anyq = false, anyr = false, anyp = false;
@@ -480,12 +544,12 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
         I.sp = osp; I.cp = ocp;
         I.Mb = oMb; I.Mf = oMf; I.Kb = oKb; I.Kf = oKf; I.Rn = oRn;
         I.chat = ochat; I.c = ochat; I.sig = osig; I.sc = osc;
-        I.y = oy; I.x = ox; I.u = ou; I.x0 = ox0;
+        I.y = oy; I.x = ox; I.u = ou; I.x0 = ox0; I.box = oy; I.node0 = onode;
         I.m = (long long)I.Vnl * (I.nx + I.nu) + (long long)(I.V - I.Vnl) * I.nx;
         const long long V = I.V, Vnl = I.Vnl, Vl = I.V - I.Vnl, nx = I.nx, nu = I.nu;
         oMb += V * nx * I.ldM; oMf += V * (nx + nu) * I.ldx; oKb += Vnl * nu * I.ldx;
         oKf += Vnl * nx * I.ldu; oRn += Vnl * nu * I.ldu; ochat += V * nx; osig += Vnl * nu; osc += V;
-        oy += I.m; ox += V * nx; ou += Vnl * nu; ox0 += nx;
+        oy += I.m; ox += V * nx; ou += Vnl * nu; ox0 += nx; onode += V;
         osp += I.N + 2; ocp += I.Vnl + 1;
         RawDesc &R = raw[b];
         R = ro;

@@ -36,6 +36,8 @@ struct InstDesc {
     long long x, u;                  // offsets in the concatenated x [sum V nx], u [sum Vnl nu]
     long long x0;                    // offset in the concatenated x0 [sum nx]
     long long m;                     // dual rows of the instance
+    long long box;                   // first row of the instance's boxes in lo / hi
+    long long node0;                 // first node of the instance in node-indexed work arrays
 };
 
 struct Item {
@@ -48,6 +50,7 @@ struct SweepArgs {
     const Item *items;
     int nitems;
     const int *sp, *cp;              // stage_ptr / child_ptr pools (local node ids)
+    const int *anc;                  // ancestors, node-indexed at the instance's sc offset
     const double *Mb, *Mf, *Kb, *Kf, *Rn;
     const double *chat, *sig, *cvec, *sc;   // sc null: no preconditioning
     const double *x0; long long x0_rs;      // per right-hand side strides
@@ -80,6 +83,7 @@ struct LevelPlan {
 // Solver workspace kept in the handle (allocated at the first solve).
 struct SolverWS {
     int mem = 0;
+    bool has_g = false;
     int nblocks = 0;
     double *buf = nullptr;
     size_t bytes = 0;
@@ -107,12 +111,19 @@ struct tree_factors {
     // schedule of a sweep
     std::vector<stotree::ChainPlan> chains;  // stages s*..N, one plan per lane-group width
     std::vector<stotree::LevelPlan> levels;  // stages 0..max(s*)-1
-    stotree::Item *panel_chain_items = nullptr;  // every (instance, chain): panel sweeps
+    stotree::Item *panel_chain_items = nullptr;  // (instance, chain) pairs of the panel sweeps
     int npanel_chain_items = 0;
+    // shared > 1: the instances are copies of instance 0 (same tree, factors
+    // and boxes; own x0 and vectors), and panel sweeps run across instances
+    int shared = 1;
+    std::vector<stotree::LevelPlan> panel_levels;  // shared handles: instance 0's trunk nodes
     // tuning knobs (sweep_schedule / sweep_autotune)
     int trunk_cap = 16;                     // cap on wavefronts per node above s*
     int chain_order = 1;                    // 1: longest chains first, 0: instance order
     int group_min = 8;                      // smallest lane group used for chains
+    int trunk_fused = 0;                    // 1: backward stages above s* in one launch
+    stotree::LevelPlan trunk_entry{};       // nodes of stage s*-1 of every instance
+    int *trunk_cnt = nullptr;               // per node (node0-indexed): children finished
     long long schedule_epoch = 0;           // bumped whenever the work lists are rebuilt
     // sweep workspace (grows with nrhs)
     double *qhat = nullptr, *kbuf = nullptr;
@@ -129,6 +140,7 @@ void set_error(const std::string &msg);
 // factor.hip
 int factor_forest(int count, const tree_desc *t, const problem_data *d, int precondition,
                   hipStream_t st, tree_factors **out);
+int replicate_instances(tree_factors *f, int count);
 void free_tree(tree_factors *f);
 int build_schedule(tree_factors *f);
 int chain_group(int ldM, int group_min);  // lanes per chain for padded width ldM
@@ -141,6 +153,10 @@ int ensure_sweep_ws(tree_factors *f, int nrhs);
 // matrix cores; panel_tpw == 0 if an instance is too wide for it.
 int panel_tpw(const tree_factors *f);
 hipError_t launch_panel_sweep(const tree_factors *f, const SweepArgs &a, hipStream_t st);
+// Any sweep of nrhs in {1,2} right-hand sides over every instance: on a
+// shared handle, panels of kRhsPanel instances; otherwise launch_sweep_tree.
+bool shared_panels(const tree_factors *f);
+hipError_t launch_sweep_any(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st);
 hipError_t launch_sweep_tree(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st);
 int timing_enable(int on);
 bool timing_on();
@@ -150,6 +166,7 @@ int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int ho
                       double *u, hipStream_t st);
 
 // schedule.hip
+constexpr int kKnobs = 4;            // group_min, chain_order, trunk_cap, trunk_fused
 int set_schedule(tree_factors *f, const int32_t *knobs);
 int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms_out, hipStream_t st);
 int graph_create(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,

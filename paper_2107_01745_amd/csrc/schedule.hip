@@ -30,7 +30,8 @@ bool valid_knobs(const int32_t *k)
     const bool g = k[0] == 8 || k[0] == 16 || k[0] == 32 || k[0] == 64;
     const bool o = k[1] == 0 || k[1] == 1;
     const bool t = k[2] == 1 || k[2] == 2 || k[2] == 4 || k[2] == 8 || k[2] == 16;
-    return g && o && t;
+    const bool m = k[3] == 0 || k[3] == 1;
+    return g && o && t && m;
 }
 
 // Lane-group width of every instance under group_min g (equal vectors give
@@ -47,7 +48,8 @@ std::vector<int> groups_of(const tree_factors *f, int g)
 int set_schedule(tree_factors *f, const int32_t *knobs)
 {
     if (!valid_knobs(knobs)) {
-        set_error("sweep_schedule: knobs must be group in {8,16,32,64}, order in {0,1}, cap in {1,2,4,8,16}");
+        set_error("sweep_schedule: knobs must be group in {8,16,32,64}, order in {0,1}, cap in {1,2,4,8,16}, "
+                  "trunk mode in {0,1}");
         return STOTREE_ERR_ARG;
     }
     // the old work lists may still be read by queued sweeps
@@ -55,6 +57,7 @@ int set_schedule(tree_factors *f, const int32_t *knobs)
     f->group_min = knobs[0];
     f->chain_order = knobs[1];
     f->trunk_cap = knobs[2];
+    f->trunk_fused = knobs[3];
     ++f->schedule_epoch;
     return build_schedule(f);
 }
@@ -98,18 +101,17 @@ int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms
         *ms = t / reps;
         return STOTREE_OK;
     };
-    int32_t best[3] = {f->group_min, f->chain_order, f->trunk_cap};
+    int32_t best[kKnobs] = {f->group_min, f->chain_order, f->trunk_cap, f->trunk_fused};
     double best_ms = 0.0;
     rc = measure(best, &best_ms);
-    const int groups[4] = {8, 16, 32, 64}, orders[2] = {1, 0}, caps[4] = {16, 8, 4, 2};
-    for (int knob = 0; knob < 3 && !rc; ++knob) {
-        const int n = knob == 0 ? 4 : knob == 1 ? 2 : 4;
+    const std::vector<std::vector<int>> values = {{8, 16, 32, 64}, {1, 0}, {16, 8, 4, 2}, {1, 0}};
+    for (int knob = 0; knob < kKnobs && !rc; ++knob) {
         const int32_t start = best[knob];
-        for (int c = 0; c < n && !rc; ++c) {
-            const int v = knob == 0 ? groups[c] : knob == 1 ? orders[c] : caps[c];
+        for (int v : values[knob]) {
+            if (rc) break;
             if (v == start) continue;
             if (knob == 0 && groups_of(f, v) == groups_of(f, best[0])) continue;
-            int32_t cand[3] = {best[0], best[1], best[2]};
+            int32_t cand[kKnobs] = {best[0], best[1], best[2], best[3]};
             cand[knob] = v;
             double ms = 0.0;
             rc = measure(cand, &ms);
@@ -122,7 +124,7 @@ int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms
     timing_enable(timing_was ? 1 : 0);
     if (rc) return rc;
     if ((rc = set_schedule(f, best))) return rc;
-    if (knobs_out) for (int k = 0; k < 3; ++k) knobs_out[k] = best[k];
+    if (knobs_out) for (int k = 0; k < kKnobs; ++k) knobs_out[k] = best[k];
     if (ms_out) *ms_out = best_ms;
     return STOTREE_OK;
 }

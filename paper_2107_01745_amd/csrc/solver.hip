@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(kVB) resid_kernel(VecArgs a)
         const double s = row_scale(a, br, kl);
         const double h = s * a.hx[k];
         const double yk = a.y[k];
-        const double z = clampd(yk / lam + h, s * a.lo[k], s * a.hi[k]);
+        const double z = clampd(yk / lam + h, s * a.lo[br.I.box + kl], s * a.hi[br.I.box + kl]);
         const double R = z - h;
         a.r[k] = R;
         const double aR = fabs(R);
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
     for (int v = 0; v < kNuCap + 2; ++v) acc[v] = 0.0;
     FOR_BLOCK_ROWS(br, kl, k) {
         const double s = row_scale(a, br, kl);
-        const double lo = s * a.lo[k], hi = s * a.hi[k];
+        const double lo = s * a.lo[br.I.box + kl], hi = s * a.hi[br.I.box + kl];
         const double yk = a.y[k], rk = a.rp[k], dk = a.d[k];
         const double ah = s * a.hx[k];
         const double brk = nama ? s * a.hr[k] : 0.0;
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(kVB) update_kernel(VecArgs a)
         const double dl = cr * a.rp[k] + tau * a.d[k];
         const double hd = (nama ? cr * s * a.hr[k] : 0.0) + tau * s * a.hd[k];
         const double w = a.y[k] + dl, hw = s * a.hx[k] + hd;
-        const double zw = clampd(w / lam + hw, s * a.lo[k], s * a.hi[k]);
+        const double zw = clampd(w / lam + hw, s * a.lo[br.I.box + kl], s * a.hi[br.I.box + kl]);
         a.yn[k] = w - lam * (zw - hw);
     }
 }
@@ -536,10 +536,11 @@ __global__ void __launch_bounds__(kVB) power_scale_kernel(VecArgs a)
 }
 
 // ------------------------------- host side -------------------------------
-int ensure_solver_ws(tree_factors *f, int mem)
+// need_g: the two FBE-gradient vectors (MINFBE only).
+int ensure_solver_ws(tree_factors *f, int mem, bool need_g)
 {
     SolverWS &w = f->sws;
-    if (w.buf && w.mem >= mem) return STOTREE_OK;
+    if (w.buf && w.mem >= mem && (w.has_g || !need_g)) return STOTREE_OK;
     if (w.buf) { (void)hipFree(w.buf); w.buf = nullptr; w.bytes = 0; }
     // blocks per instance: one per 1024 rows, at most 1024
     std::vector<int> blk;
@@ -552,7 +553,7 @@ int ensure_solver_ws(tree_factors *f, int mem)
     }
     const int nblocks = (int)(blk.size() / 3);
     const long long m = f->m_tot;
-    const long long nvec = 9 + 2LL * (mem + 1);
+    const long long nvec = (need_g ? 9 : 7) + 2LL * (mem + 1);
     const size_t vec_bytes = sizeof(double) * ((size_t)nvec * m + (size_t)kNVMax * nblocks);
     const size_t ctl_bytes = sizeof(Ctl) * (size_t)f->ninst;
     const size_t bytes = vec_bytes + ctl_bytes + sizeof(int) * (blk.size() + 1) + 512;
@@ -564,8 +565,12 @@ int ensure_solver_ws(tree_factors *f, int mem)
     w.y[1] = p; p += m;
     w.r[0] = p; p += m;
     w.r[1] = p; p += m;
-    w.g[0] = p; p += m;
-    w.g[1] = p; p += m;
+    w.has_g = need_g;
+    w.g[0] = w.g[1] = nullptr;
+    if (need_g) {
+        w.g[0] = p; p += m;
+        w.g[1] = p; p += m;
+    }
     w.hx = p; p += m;
     w.hr2 = p; p += 2 * m;  // hr, hd
     w.d = p; p += m;
@@ -626,7 +631,7 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
     double *hr = w.hr2, *hd = w.hr2 + f->m_tot;
     hipError_t e;
     // x(y) -> H x
-    if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 1, x0, y, 0, w.hx, 0, ctl), 1, st))) return e;
+    if ((e = launch_sweep_any(f, dual_layout_sweep(f, 1, x0, y, 0, w.hx, 0, ctl), 1, st))) return e;
     a.y = y; a.yp = yn; a.hx = w.hx; a.rp = rp; a.r = r;
     a.S = w.S; a.Q = w.Qv;
     if (method == 1) {
@@ -637,13 +642,13 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
         cb.r = w.d;         // output direction
         hipLaunchKernelGGL((combine_kernel<MEMCAP>), grid, blk, 0, st, cb);
         // x-hat(r) and x-hat(d) in one two-right-hand-side sweep (p-NAMA)
-        if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, r, w.d - r, hr, hd - hr, ctl), 2, st)))
+        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, r, w.d - r, hr, hd - hr, ctl), 2, st)))
             return e;
     } else {
         hipLaunchKernelGGL((resid_kernel<false, 0>), grid, blk, 0, st, a);
         hipLaunchKernelGGL(fin_resid_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, 0, a.ndone);
         // grad phi = R + lambda s H xhat(s R)
-        if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, r, 0, hr, 0, ctl), 1, st))) return e;
+        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, r, 0, hr, 0, ctl), 1, st))) return e;
         VecArgs ga = a;
         ga.hr = hr; ga.g = g; ga.gp = gp;
         hipLaunchKernelGGL((grad_kernel<MEMCAP>), grid, blk, 0, st, ga);
@@ -651,7 +656,7 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
         VecArgs cb = a;
         cb.g = g; cb.r = w.d;
         hipLaunchKernelGGL((combine_kernel<MEMCAP>), grid, blk, 0, st, cb);
-        if ((e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, w.d, 0, hd, 0, ctl), 1, st))) return e;
+        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, w.d, 0, hd, 0, ctl), 1, st))) return e;
     }
     VecArgs la = vec_args(f);
     la.method = method;
@@ -678,12 +683,12 @@ int power_iterations(tree_factors *f, int iters, hipStream_t st)
     const SolverWS &w = f->sws;
     VecArgs a = vec_args(f);
     const dim3 grid(a.nblocks), blk(kVB), fgrid(f->ninst);
-    double *v = w.g[0], *wv = w.g[1], *hv = w.hx;
+    double *v = w.r[0], *wv = w.r[1], *hv = w.hx;
     VecArgs pa = a;
     pa.yn = v;
     hipLaunchKernelGGL(power_init_kernel, grid, blk, 0, st, pa);
     for (int it = 0; it < iters; ++it) {
-        hipError_t e = launch_sweep_tree(f, dual_layout_sweep(f, 0, nullptr, v, 0, hv, 0, nullptr), 1, st);
+        hipError_t e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, v, 0, hv, 0, nullptr), 1, st);
         if (e != hipSuccess) { set_error(std::string("dual_lipschitz: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
         pa.y = v; pa.hx = hv; pa.r = wv; pa.yn = v;
         hipLaunchKernelGGL(power_step_kernel, grid, blk, 0, st, pa);
@@ -715,7 +720,7 @@ std::vector<Ctl> fresh_ctl(const tree_factors *f)
 int lipschitz(const tree_factors *fc, int iters, double *L, hipStream_t st)
 {
     tree_factors *f = const_cast<tree_factors *>(fc);
-    int rc = ensure_solver_ws(f, f->sws.buf ? f->sws.mem : 1);
+    int rc = ensure_solver_ws(f, f->sws.buf ? f->sws.mem : 1, false);
     if (rc) return rc;
     if ((rc = ensure_sweep_ws(f, 2))) return rc;
     std::vector<Ctl> h = fresh_ctl(f);
@@ -739,7 +744,7 @@ int solve(const tree_factors *fc, const double *x0, const solver_opts *opts_in, 
         set_error("solve: options out of range (mem 1..16, nu_max 0..30, check_every >= 1)");
         return STOTREE_ERR_ARG;
     }
-    int rc = ensure_solver_ws(f, o.mem);
+    int rc = ensure_solver_ws(f, o.mem, method == 0);
     if (rc) return rc;
     if ((rc = ensure_sweep_ws(f, 2))) return rc;
     const SolverWS &w = f->sws;
@@ -782,7 +787,7 @@ int solve(const tree_factors *fc, const double *x0, const solver_opts *opts_in, 
     SweepArgs a = sweep_args(f, 1);
     a.x0 = x0; a.y = y_io;
     a.xo = x; a.uo = u; a.dual_out = 0;
-    hipError_t e = launch_sweep_tree(f, a, 1, st);
+    hipError_t e = launch_sweep_any(f, a, 1, st);
     if (e != hipSuccess) { set_error(std::string("solve: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
     STOTREE_HIP(hipMemcpyAsync(h.data(), dctl, sizeof(Ctl) * h.size(), hipMemcpyDeviceToHost, st));
     STOTREE_HIP(hipStreamSynchronize(st));

@@ -356,13 +356,8 @@ __host__ __device__ inline int child_batch(int nrhs, int ldx)
 }
 
 template <int NRHS, int CH, int NW>
-__global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a)
+__device__ void bwd_trunk_node(const SweepArgs &a, const InstDesc &I, int i, int w, int lane)
 {
-    const Item it = a.items[blockIdx.x];
-    if (skipped(a, it.inst)) return;
-    const InstDesc I = a.inst[it.inst];
-    const int lane = threadIdx.x & (kWave - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int i = it.idx;
     const int nx = I.nx, nu = I.nu, W = nx + nu, ldq = I.ldx, ldM = I.ldM;
     const int *cp = a.cp + I.cp;
     const int CB = child_batch(NRHS, ldq);
@@ -445,6 +440,53 @@ __global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a)
             qhat_ptr(a, I, k, i)[cx] = as[k * ldM + cx] + si * y_ptr(a, I, k, i)[cx] +
                                        (a.affine ? a.chat[I.chat + (long long)i * nx + cx] : 0.0) + s;
         }
+    }
+}
+
+template <int NRHS, int CH, int NW>
+__global__ void __launch_bounds__(kWave *NW) bwd_trunk_kernel(SweepArgs a)
+{
+    const Item it = a.items[blockIdx.x];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int lane = threadIdx.x & (kWave - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    bwd_trunk_node<NRHS, CH, NW>(a, I, it.idx, w, lane);
+}
+
+// All stages above s* in one launch: a workgroup starts at a node of stage
+// s*-1 and, after finishing a node, counts it in at its parent; the workgroup
+// that brings the parent's count to its number of children goes on with the
+// parent (every child's qhat is then in memory), the others stop.  No
+// workgroup waits on another, the root is finished by exactly one, and each
+// parent's counter is reset by the workgroup that takes the parent, so the
+// counters are zero again when the launch ends.
+template <int NRHS, int CH, int NW>
+__global__ void __launch_bounds__(kWave *NW) bwd_trunk_tree_kernel(SweepArgs a, int *counters)
+{
+    const Item it = a.items[blockIdx.x];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int lane = threadIdx.x & (kWave - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    __shared__ int go;
+    int i = it.idx;
+    for (;;) {
+        bwd_trunk_node<NRHS, CH, NW>(a, I, i, w, lane);
+        if (i == 0) break;
+        const int p = a.anc[I.sc + i];
+        __syncthreads();   // every store of node i has been issued
+        if (threadIdx.x == 0) {
+            __threadfence();   // release node i's qhat and k device-wide
+            const int nch = a.cp[I.cp + p + 1] - a.cp[I.cp + p];
+            const int last = atomicAdd(&counters[I.node0 + p], 1) == nch - 1;
+            if (last) {
+                counters[I.node0 + p] = 0;
+                __threadfence();   // acquire the siblings' qhat
+            }
+            go = last;
+        }
+        __syncthreads();
+        if (!go) break;
+        i = p;
     }
 }
 
@@ -629,7 +671,7 @@ SweepArgs sweep_args(const tree_factors *f, int affine)
 {
     SweepArgs a{};
     a.inst = f->d_inst;
-    a.sp = f->d_sp; a.cp = f->d_cp;
+    a.sp = f->d_sp; a.cp = f->d_cp; a.anc = f->d_anc;
     a.Mb = f->Mb; a.Mf = f->Mf; a.Kb = f->Kb; a.Kf = f->Kf; a.Rn = f->Rn;
     a.chat = f->chat; a.sig = f->sig; a.cvec = f->cvec; a.sc = f->precondition ? f->sc : nullptr;
     a.qhat = f->qhat; a.kbuf = f->kbuf;
@@ -737,6 +779,31 @@ static void launch_trunk(bool backward, const SweepArgs &a, const LevelPlan &lv,
     }
 }
 
+template <int NRHS, int CH, int NW>
+static void launch_trunk_tree_nw(SweepArgs a, const tree_factors *f, int max_ldM, int max_qs, int max_ldu,
+                                 hipStream_t st)
+{
+    a.items = f->trunk_entry.items;
+    a.nitems = f->trunk_entry.count;
+    const size_t lds = sizeof(double) * ((size_t)max_qs * NRHS + (size_t)(NW + 1) * NRHS * max_ldM +
+                                         (size_t)NRHS * max_ldu);
+    hipLaunchKernelGGL((bwd_trunk_tree_kernel<NRHS, CH, NW>), dim3(a.nitems), dim3(kWave * NW), lds, st, a,
+                       f->trunk_cnt);
+}
+
+template <int NRHS, int CH>
+static void launch_trunk_tree(const SweepArgs &a, const tree_factors *f, int max_ldM, int max_qs, int max_ldu,
+                              hipStream_t st)
+{
+    switch (f->trunk_entry.nw) {
+    case 16: launch_trunk_tree_nw<NRHS, CH, 16>(a, f, max_ldM, max_qs, max_ldu, st); break;
+    case 8: launch_trunk_tree_nw<NRHS, CH, 8>(a, f, max_ldM, max_qs, max_ldu, st); break;
+    case 4: launch_trunk_tree_nw<NRHS, CH, 4>(a, f, max_ldM, max_qs, max_ldu, st); break;
+    case 2: launch_trunk_tree_nw<NRHS, CH, 2>(a, f, max_ldM, max_qs, max_ldu, st); break;
+    default: launch_trunk_tree_nw<NRHS, CH, 1>(a, f, max_ldM, max_qs, max_ldu, st); break;
+    }
+}
+
 // Chain launches: one for all narrow widths together, one per wide plan.
 template <int NRHS>
 static void launch_chains(bool backward, const SweepArgs &a, const tree_factors *f, hipStream_t st)
@@ -796,8 +863,11 @@ static hipError_t sweep_impl(const tree_factors *f, SweepArgs a, hipStream_t st)
     }
     if (!f->levels.empty()) {
         PhaseTimer tm(1, st);
-        for (int k = (int)f->levels.size() - 1; k >= 0; --k)
-            launch_trunk<NRHS, CH>(true, a, f->levels[k], ldM, qs, ldu, st);
+        if (f->trunk_fused && f->trunk_entry.count > 0)
+            launch_trunk_tree<NRHS, CH>(a, f, ldM, qs, ldu, st);
+        else
+            for (int k = (int)f->levels.size() - 1; k >= 0; --k)
+                launch_trunk<NRHS, CH>(true, a, f->levels[k], ldM, qs, ldu, st);
     }
     if (!f->levels.empty()) {
         PhaseTimer tm(2, st);
@@ -814,6 +884,25 @@ static hipError_t sweep_impl(const tree_factors *f, SweepArgs a, hipStream_t st)
 int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,
                       double *u, hipStream_t st)
 {
+    // shared handle: each right-hand side covers all instances in panels
+    if (shared_panels(f)) {
+        int rc = ensure_sweep_ws(f, 1);
+        if (rc) return rc;
+        SweepArgs a = sweep_args(f, homogeneous ? 0 : 1);
+        a.dual_out = 0;
+        for (int k = 0; k < nrhs; ++k) {
+            a.x0 = x0 ? x0 + (long long)k * f->nx_tot : nullptr;
+            a.y = y + (long long)k * f->m_tot;
+            a.xo = x + (long long)k * f->x_tot;
+            a.uo = u + (long long)k * f->u_tot;
+            const hipError_t e = launch_sweep_any(f, a, 1, st);
+            if (e != hipSuccess) {
+                set_error(std::string("dual_grad: ") + hipGetErrorString(e));
+                return STOTREE_ERR_DEVICE;
+            }
+        }
+        return STOTREE_OK;
+    }
     // panels of kRhsPanel right-hand sides on the matrix cores, the rest in pairs
     const bool panel = nrhs >= kRhsPanel && panel_tpw(f) > 0;
     const int npanel = panel ? nrhs / kRhsPanel * kRhsPanel : 0;

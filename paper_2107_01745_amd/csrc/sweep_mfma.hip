@@ -23,7 +23,10 @@
 // order (deterministic results).
 //
 // Operand layout of v_mfma_f64_16x16x4f64 (D = A B + C, A 16x4, B 4x16):
-// lane l holds A[l%16][l/16], B[l/16][l%16] and D[4(l/16)+e][l%16], e < 4.
+// lane l holds A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4e][l%16], e < 4
+// (checked on the device against a plain product of known operands).
+#include <vector>
+
 #include "sweep_common.h"
 
 namespace stotree {
@@ -125,7 +128,7 @@ __device__ __forceinline__ Slot slot(const Tasks &tk, const int (&ncols)[2], int
     const int task = wave + kWg * s;
     const int tile = task >> 1;
     o.part = tile < tk.t0 ? 0 : 1;
-    o.row = (o.part ? tile - tk.t0 : tile) * 16 + 4 * (lane >> 4) + e;
+    o.row = (o.part ? tile - tk.t0 : tile) * 16 + (lane >> 4) + 4 * e;
     o.rhs = (task & 1) * 32 + h * 16 + (lane & 15);
     o.valid = task < tk.count() && o.row < ncols[o.part];
     return o;
@@ -376,18 +379,19 @@ static void launch_panel(const tree_factors *f, const SweepArgs &a, size_t lds, 
     SweepArgs ca = a;
     ca.items = f->panel_chain_items;
     ca.nitems = f->npanel_chain_items;
+    const std::vector<LevelPlan> &levels = f->shared > 1 ? f->panel_levels : f->levels;
     if (ca.nitems > 0) hipLaunchKernelGGL(bwd_chain64_kernel<TPW>, dim3(ca.nitems), blk, lds, st, ca);
-    for (int k = (int)f->levels.size() - 1; k >= 0; --k) {
+    for (int k = (int)levels.size() - 1; k >= 0; --k) {
         SweepArgs la = a;
-        la.items = f->levels[k].items;
-        la.nitems = f->levels[k].count;
-        hipLaunchKernelGGL(bwd_trunk64_kernel<TPW>, dim3(la.nitems), blk, lds, st, la);
+        la.items = levels[k].items;
+        la.nitems = levels[k].count;
+        if (la.nitems > 0) hipLaunchKernelGGL(bwd_trunk64_kernel<TPW>, dim3(la.nitems), blk, lds, st, la);
     }
-    for (size_t k = 0; k < f->levels.size(); ++k) {
+    for (size_t k = 0; k < levels.size(); ++k) {
         SweepArgs la = a;
-        la.items = f->levels[k].items;
-        la.nitems = f->levels[k].count;
-        hipLaunchKernelGGL(fwd_trunk64_kernel<TPW>, dim3(la.nitems), blk, lds, st, la);
+        la.items = levels[k].items;
+        la.nitems = levels[k].count;
+        if (la.nitems > 0) hipLaunchKernelGGL(fwd_trunk64_kernel<TPW>, dim3(la.nitems), blk, lds, st, la);
     }
     if (ca.nitems > 0) hipLaunchKernelGGL(fwd_chain64_kernel<TPW>, dim3(ca.nitems), blk, lds, st, ca);
 }
@@ -405,6 +409,40 @@ hipError_t launch_panel_sweep(const tree_factors *f, const SweepArgs &a, hipStre
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+bool shared_panels(const tree_factors *f)
+{
+    return f->shared >= kRhsPanel && f->shared % kRhsPanel == 0 && f->ninst == f->shared && panel_tpw(f) > 0;
+}
+
+// On a shared handle the instances are the panel's right-hand sides: group g
+// of kRhsPanel instances is one panel starting at instance g*kRhsPanel, with
+// the instance strides as right-hand-side strides; the nrhs right-hand sides
+// of the call (directions, strides of a) are swept one after the other.
+hipError_t launch_sweep_any(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st)
+{
+    if (!shared_panels(f)) return launch_sweep_tree(f, a, nrhs, st);
+    const InstDesc &I0 = f->inst[0], &I1 = f->inst[1];
+    for (int d = 0; d < nrhs; ++d)
+        for (int g = 0; g < f->ninst / kRhsPanel; ++g) {
+            SweepArgs p = a;
+            p.inst = f->d_inst + (long long)g * kRhsPanel;
+            p.done = nullptr;        // every instance of the panel is swept (finished ones unchanged)
+            p.y = a.y + d * a.y_rs;
+            p.xo = a.xo + d * a.xo_rs;
+            p.uo = a.uo ? a.uo + d * a.uo_rs : nullptr;
+            p.x0 = a.x0 ? a.x0 + d * a.x0_rs : nullptr;
+            p.y_rs = I1.y - I0.y;
+            p.x0_rs = I1.x0 - I0.x0;
+            p.xo_rs = a.dual_out ? I1.y - I0.y : I1.x - I0.x;
+            p.uo_rs = I1.u - I0.u;
+            p.qhat_rs = I1.x - I0.x;
+            p.kbuf_rs = I1.u - I0.u;
+            const hipError_t e = launch_panel_sweep(f, p, st);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
 }
 
 }  // namespace stotree

@@ -60,7 +60,7 @@ EXPORTS = ("tree_factor", "tree_factor_batch", "tree_factors_free", "tree_dims",
            "solve_info_batch", "stotree_timing", "stotree_timing_read", "stotree_last_error",
            "warm_mlp_params", "warm_mlp_work_len", "warm_mlp_forward", "warm_mlp_backward",
            "warm_mse_grad", "warm_adam", "warm_features", "warm_scatter", "warm_targets",
-           "dual_select", "sweep_schedule", "sweep_schedule_get", "sweep_autotune",
+           "dual_select", "tree_factor_shared", "sweep_schedule", "sweep_schedule_get", "sweep_autotune",
            "sweep_graph_create", "sweep_graph_launch", "sweep_graph_free")
 PHASES = ("bwd_chain", "bwd_stages", "fwd_stages", "fwd_chain")
 
@@ -81,6 +81,9 @@ def lib():
         L.tree_factor_batch.argtypes = [C.c_int, C.POINTER(TreeDesc), C.POINTER(ProblemData), C.c_int,
                                         vp, C.POINTER(vp)]
         L.tree_factor_batch.restype = C.c_int
+        L.tree_factor_shared.argtypes = [C.POINTER(TreeDesc), C.POINTER(ProblemData), C.c_int, C.c_int, vp,
+                                         C.POINTER(vp)]
+        L.tree_factor_shared.restype = C.c_int
         L.tree_instance_dims.argtypes = [vp, C.c_int, C.POINTER(C.c_int64)]
         L.tree_instance_dims.restype = C.c_int
         L.solve_info_batch.argtypes = [vp, C.POINTER(SolverInfo)]
@@ -212,6 +215,17 @@ def tree_factor(prob, precondition: bool = True, stream=None) -> TreeFactors:
     return TreeFactors(h)
 
 
+def tree_factor_shared(prob, count: int, precondition: bool = True, stream=None) -> TreeFactors:
+    """Factor step once for ``count`` instances sharing prob's tree and data
+    (they differ only in x0, given per call)."""
+    keep = []
+    td, pd = _descs(prob, keep)
+    h = C.c_void_p()
+    _check(lib().tree_factor_shared(C.byref(td), C.byref(pd), int(bool(precondition)), int(count),
+                                    _stream(stream), C.byref(h)))
+    return TreeFactors(h)
+
+
 def tree_factor_batch(probs, precondition: bool = True, stream=None) -> TreeFactors:
     """Factor step on a list of treegen.Problem instances (one handle)."""
     keep = []
@@ -243,13 +257,13 @@ def dual_grad(tf: TreeFactors, x0, y, homogeneous: bool, x, u, nrhs: int = 1, st
 
 
 def sweep_schedule(tf: TreeFactors, knobs) -> None:
-    """Set (group_min, chain_order, trunk_cap) of the handle's sweeps."""
-    k = (C.c_int32 * 3)(*[int(v) for v in knobs])
+    """Set (group_min, chain_order, trunk_cap, trunk_fused) of the handle's sweeps."""
+    k = (C.c_int32 * 4)(*[int(v) for v in knobs])
     _check(lib().sweep_schedule(tf.handle, k))
 
 
 def sweep_schedule_get(tf: TreeFactors) -> tuple:
-    k = (C.c_int32 * 3)()
+    k = (C.c_int32 * 4)()
     _check(lib().sweep_schedule_get(tf.handle, k))
     return tuple(int(v) for v in k)
 
@@ -277,7 +291,7 @@ def sweep_autotune(tf: TreeFactors, nrhs: int = 1, reps: int = 5, cache: str | N
         if key in table:
             sweep_schedule(tf, table[key]["knobs"])
             return dict(table[key], cached=True)
-    k = (C.c_int32 * 3)()
+    k = (C.c_int32 * 4)()
     ms = C.c_double()
     _check(lib().sweep_autotune(tf.handle, int(nrhs), int(reps), k, C.byref(ms), _stream(stream)))
     rec = {"knobs": [int(v) for v in k], "ms": ms.value}

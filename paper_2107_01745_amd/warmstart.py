@@ -23,19 +23,20 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def solve_batch(probs, lam, *, method="nama", eps=1e-6, max_iter=2000, y0=None, tf=None):
-    """Batched solve of a list of instances; returns (tf, y, infos, seconds)."""
+def solve_batch(probs, lam, *, method="nama", eps=1e-6, max_iter=2000, y0=None, tf=None, mem=5):
+    """Batched solve of a list of instances (or, with tf given, of the
+    concatenated x0 tensor); returns (tf, y, infos, seconds)."""
     own = tf is None
     if own:
         tf = stotree.tree_factor_batch(probs, precondition=True)
-    x0 = torch.tensor(np.concatenate([p.x0 for p in probs]), dtype=torch.float64, device=_dev())
+    x0 = _x0_of(probs)
     y = torch.zeros(tf.m, dtype=torch.float64, device=_dev()) if y0 is None else y0
     x = torch.empty(tf.x_len, dtype=torch.float64, device=_dev())
     u = torch.empty(tf.u_len, dtype=torch.float64, device=_dev())
     fn = stotree.nama_solve if method == "nama" else stotree.minfbe_solve
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fn(tf, x0, y, x, u, stotree.make_opts(lam=lam, eps=eps, max_iter=max_iter))
+    fn(tf, x0, y, x, u, stotree.make_opts(lam=lam, eps=eps, max_iter=max_iter, mem=mem))
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     return tf, y, stotree.solve_info_batch(tf), sec
@@ -80,13 +81,21 @@ class WarmStartMLP:
         stotree.warm_mlp_forward(rows, self.din, self.dh, self.dout, self.params, X, H, Y)
         return H, Y
 
-    def predict(self, tf, x0, y_out):
-        """Predicted dual of every instance of tf into y_out."""
+    def predict(self, tf, x0, y_out, chunk_rows=1 << 20):
+        """Predicted dual of every instance of tf into y_out (the network runs
+        over chunks of rows, so its activations stay small)."""
         X = self.features(tf, x0)
-        _, Y = self.forward(X)
+        rows = X.shape[0]
+        Y = torch.empty(rows, self.dout, dtype=torch.float32, device=_dev())
+        H = torch.empty(min(rows, chunk_rows), 2 * self.dh, dtype=torch.float32, device=_dev())
+        for r0 in range(0, rows, chunk_rows):
+            n = min(chunk_rows, rows - r0)
+            stotree.warm_mlp_forward(n, self.din, self.dh, self.dout, self.params, X[r0:r0 + n], H, Y[r0:r0 + n])
+        del X, H
         stotree.warm_scatter(tf, Y, self.y_scale, y_out)
 
     def fit(self, X, T, M, *, epochs=30, batch_rows=65536, lr=1e-3, seed=0, log=None):
+        batch_rows = min(batch_rows, X.shape[0])
         rows = X.shape[0]
         work = torch.empty(stotree.warm_mlp_work_len(batch_rows, self.din, self.dh, self.dout),
                            dtype=torch.float32, device=_dev())
@@ -120,21 +129,28 @@ class WarmStartMLP:
         return history
 
 
-def warm_start_duals(model, tf, probs, lam):
+def _x0_of(probs_or_x0):
+    if isinstance(probs_or_x0, torch.Tensor):
+        return probs_or_x0
+    return torch.tensor(np.concatenate([p.x0 for p in probs_or_x0]), dtype=torch.float64, device=_dev())
+
+
+def warm_start_duals(model, tf, probs_or_x0, lam):
     """Predicted duals with the cold start kept wherever the solver's residual
-    at the prediction is not below its residual at zero."""
-    x0 = torch.tensor(np.concatenate([p.x0 for p in probs]), dtype=torch.float64, device=_dev())
-    yw = torch.empty(tf.m, dtype=torch.float64, device=_dev())
-    model.predict(tf, x0, yw)
+    at the prediction is not below its residual at zero.  probs_or_x0: the
+    instances' problems, or their concatenated x0 on the device."""
+    x0 = _x0_of(probs_or_x0)
+    yw = torch.zeros(tf.m, dtype=torch.float64, device=_dev())
     x = torch.empty(tf.x_len, dtype=torch.float64, device=_dev())
     u = torch.empty(tf.u_len, dtype=torch.float64, device=_dev())
-    opts = stotree.make_opts(lam=lam, eps=0.0, max_iter=0)
-    probe = yw.clone()
-    stotree.nama_solve(tf, x0, probe, x, u, opts)
-    rw = [i["res_scaled_inf"] for i in stotree.solve_info_batch(tf)]
-    probe.zero_()
-    stotree.nama_solve(tf, x0, probe, x, u, opts)
+    # residual of each instance at the cold start, then at the prediction (a
+    # solve with max_iter = 0 evaluates the residual and leaves y unchanged)
+    opts = stotree.make_opts(lam=lam, eps=0.0, max_iter=0, mem=1)   # mem 1: reuse any workspace
+    stotree.nama_solve(tf, x0, yw, x, u, opts)
     rc = [i["res_scaled_inf"] for i in stotree.solve_info_batch(tf)]
+    model.predict(tf, x0, yw)
+    stotree.nama_solve(tf, x0, yw, x, u, opts)
+    rw = [i["res_scaled_inf"] for i in stotree.solve_info_batch(tf)]
     keep = [a <= b for a, b in zip(rw, rc)]
     stotree.dual_select(tf, yw, keep)
     return yw, keep

@@ -75,3 +75,69 @@ def test_panel_on_batched_handle(st):
         s = max(1.0, np.abs(xs).max())
         assert np.abs(xm[k] - xs[0]).max() <= 1e-12 * s and np.abs(um[k] - us[0]).max() <= 1e-12 * s, k
     tf.free()
+
+
+def _shared_base():
+    """A small tree whose boxes bind (checked feasible for every x0 drawn)."""
+    base = treegen.draw_problem(treegen.uniform_tree([3, 2, 1, 1]), 6, 3, np.random.default_rng(8))
+    return treegen.with_boxes(base, 5.0, 0.3)
+
+
+@pytest.mark.parametrize("count", [64, 3])
+def test_shared_handle_sweeps_match_solo(st, count):
+    """count instances sharing one factor copy (panels across instances when
+    count is a multiple of 64) against each instance's own handle."""
+    import dataclasses
+    import torch
+    base = case("cfg4_shape") if count == 64 else case("odd_ragged")
+    tf = st.tree_factor_shared(base, count, precondition=True)
+    assert tf.ninst == count and tf.m == count * base.m
+    rng = np.random.default_rng(count)
+    X0 = rng.uniform(-2, 2, (count, base.nx))
+    Y = rng.standard_normal(tf.m)
+    for homogeneous in (False, True):
+        xs, us = _many(st, tf, _t(X0.ravel()), _t(Y), homogeneous, 1)
+        tf1 = st.tree_factor(base, precondition=True)
+        for k in (0, 1, count // 2, count - 1):
+            d = tf.instances[k]
+            x1, u1 = _many(st, tf1, _t(X0[k]), _t(Y[d["y_off"]:d["y_off"] + d["m"]]), homogeneous, 1)
+            s = max(1.0, np.abs(x1).max())
+            assert np.abs(xs[0][d["x_off"]:d["x_off"] + d["V"] * d["nx"]] - x1[0]).max() <= 1e-12 * s, k
+            assert np.abs(us[0][d["u_off"]:d["u_off"] + d["Vnl"] * d["nu"]] - u1[0]).max() <= 1e-12 * s, k
+        tf1.free()
+    tf.free()
+
+
+@pytest.mark.parametrize("method", ["nama", "minfbe"])
+def test_shared_handle_solves_match_oracle(st, method):
+    """64 instances that differ only in x0, solved together (every sweep a
+    64-instance panel), against the oracle's solution of each."""
+    import dataclasses
+    import torch
+    base = _shared_base()
+    rng = np.random.default_rng(21)
+    X0 = rng.uniform(-1.5, 1.5, (64, base.nx))
+    tf = st.tree_factor_shared(base, 64, precondition=True)
+    pb, fac = oracle.factor(base)
+    lam = 1.0 / (1.1 * oracle.power_iteration(pb, fac, True, 300))
+    y = _t(np.zeros(tf.m))
+    x = torch.zeros(tf.x_len, dtype=torch.float64, device="cuda:0")
+    u = torch.zeros(tf.u_len, dtype=torch.float64, device="cuda:0")
+    fn = st.nama_solve if method == "nama" else st.minfbe_solve
+    rc, agg = fn(tf, _t(X0.ravel()), y, x, u, st.make_opts(lam=lam, eps=1e-8, max_iter=3000))
+    torch.cuda.synchronize()
+    assert rc == 0, agg
+    infos = st.solve_info_batch(tf)
+    xh, uh = x.cpu().numpy(), u.cpu().numpy()
+    for k in (0, 5, 33, 63):
+        assert infos[k]["status"] == 0 and infos[k]["res_scaled_inf"] <= 1e-8, infos[k]
+        p = dataclasses.replace(base, x0=X0[k])
+        pk, fk = oracle.factor(p)
+        ref = oracle.solve(pk, fk, method, lam, eps=1e-10, max_iter=5000)
+        assert ref["status"] == 0
+        d = tf.instances[k]
+        xb = xh[d["x_off"]:d["x_off"] + d["V"] * d["nx"]].reshape(d["V"], d["nx"])
+        ub = uh[d["u_off"]:d["u_off"] + d["Vnl"] * d["nu"]].reshape(d["Vnl"], d["nu"])
+        s = max(1.0, np.abs(ref["x"]).max())
+        assert np.abs(xb - ref["x"]).max() / s < 1e-6 and np.abs(ub - ref["u"]).max() / s < 1e-6, k
+    tf.free()

@@ -46,14 +46,15 @@ def _sweep(st, tf, x0, y, homogeneous, nrhs=1):
     return x.cpu().numpy(), u.cpu().numpy()
 
 
-def _check_oracle(tf, probs, y, xh, uh, homogeneous):
+def _check_oracle(tf, probs, y, xh, uh, homogeneous, x0):
     for b, p in enumerate(probs):
         d = tf.instances[b]
         yb = y[d["y_off"]:d["y_off"] + d["m"]]
+        x0b = x0[d["x0_off"]:d["x0_off"] + d["nx"]]
         xb = xh[d["x_off"]:d["x_off"] + d["V"] * d["nx"]].reshape(d["V"], d["nx"])
         ub = uh[d["u_off"]:d["u_off"] + d["Vnl"] * d["nu"]].reshape(d["Vnl"], d["nu"])
         pb, fac = oracle.factor(p)
-        xo, uo = oracle.sweep(pb, fac, row_scale(p) * yb, homogeneous=homogeneous)
+        xo, uo = oracle.sweep(pb, fac, row_scale(p) * yb, homogeneous=homogeneous, x0=x0b)
         s = max(1.0, np.abs(xo).max())
         assert np.abs(xb - xo).max() / s < TOL_GRAD, b
         assert np.abs(ub - uo).max() / s < TOL_GRAD, b
@@ -65,22 +66,32 @@ def test_schedules_are_bit_identical(st):
     rng = np.random.default_rng(5)
     y = _t(rng.standard_normal(2 * tf.m))
     x0 = _t(rng.standard_normal(2 * tf.x0_len))
-    assert st.sweep_schedule_get(tf) == (8, 1, 16)
+    assert st.sweep_schedule_get(tf) == (8, 1, 16, 0)
     ref = {nrhs: _sweep(st, tf, x0, y, False, nrhs) for nrhs in (1, 2)}
-    _check_oracle(tf, probs, y.cpu().numpy()[:tf.m], ref[1][0], ref[1][1], False)
+    _check_oracle(tf, probs, y.cpu().numpy()[:tf.m], ref[1][0], ref[1][1], False, x0.cpu().numpy()[:tf.x0_len])
     for g in (8, 16, 32, 64):
         for order in (0, 1):
-            st.sweep_schedule(tf, (g, order, 16))
+            st.sweep_schedule(tf, (g, order, 16, 0))
             for nrhs in (1, 2):
                 xh, uh = _sweep(st, tf, x0, y, False, nrhs)
                 assert np.array_equal(xh, ref[nrhs][0]) and np.array_equal(uh, ref[nrhs][1]), (g, order, nrhs)
     for cap in (1, 2, 4, 8):
-        st.sweep_schedule(tf, (8, 1, cap))
-        xh, uh = _sweep(st, tf, x0, y, False, 1)
-        s = np.abs(ref[1][0]).max()
-        assert np.abs(xh - ref[1][0]).max() <= 1e-12 * s and np.abs(uh - ref[1][1]).max() <= 1e-12 * s, cap
+        for fused in (0, 1):
+            st.sweep_schedule(tf, (8, 1, cap, fused))
+            for nrhs in (1, 2):
+                xh, uh = _sweep(st, tf, x0, y, False, nrhs)
+                s = np.abs(ref[nrhs][0]).max()
+                assert np.abs(xh - ref[nrhs][0]).max() <= 1e-12 * s, (cap, fused, nrhs)
+                assert np.abs(uh - ref[nrhs][1]).max() <= 1e-12 * s, (cap, fused, nrhs)
+    # the one-launch trunk leaves its counters at zero: repeated sweeps agree bitwise
+    st.sweep_schedule(tf, (8, 1, 16, 1))
+    a1 = _sweep(st, tf, x0, y, False, 1)
+    a2 = _sweep(st, tf, x0, y, False, 1)
+    assert np.array_equal(a1[0], a2[0]) and np.array_equal(a1[1], a2[1])
     with pytest.raises(st.StotreeError):
-        st.sweep_schedule(tf, (12, 1, 16))
+        st.sweep_schedule(tf, (12, 1, 16, 1))
+    with pytest.raises(st.StotreeError):
+        st.sweep_schedule(tf, (8, 1, 16, 2))
     tf.free()
 
 
@@ -93,13 +104,13 @@ def test_autotune_keeps_results_and_caches(st, tmp_path):
     cache = str(tmp_path / "tune.json")
     rec = st.sweep_autotune(tf, nrhs=1, reps=3, cache=cache)
     assert not rec["cached"] and rec["ms"] > 0
-    g, order, cap = rec["knobs"]
-    assert g in (8, 16, 32, 64) and order in (0, 1) and cap in (1, 2, 4, 8, 16)
+    g, order, cap, fused = rec["knobs"]
+    assert g in (8, 16, 32, 64) and order in (0, 1) and cap in (1, 2, 4, 8, 16) and fused in (0, 1)
     assert st.sweep_schedule_get(tf) == tuple(rec["knobs"])
     for homogeneous in (False, True):
         xh, uh = _sweep(st, tf, x0, y, homogeneous)
-        _check_oracle(tf, probs, y_np, xh, uh, homogeneous)
-    st.sweep_schedule(tf, (64, 0, 1))
+        _check_oracle(tf, probs, y_np, xh, uh, homogeneous, x0.cpu().numpy())
+    st.sweep_schedule(tf, (64, 0, 1, 0))
     rec2 = st.sweep_autotune(tf, nrhs=1, cache=cache)
     assert rec2["cached"] and st.sweep_schedule_get(tf) == tuple(rec["knobs"])
     tf.free()
@@ -127,8 +138,9 @@ def test_graph_replays_match_eager(st, nrhs):
         xe, ue = _sweep(st, tf, x0, y, False, nrhs)
         assert np.array_equal(x.cpu().numpy(), xe) and np.array_equal(u.cpu().numpy(), ue), rep
         if rep == 0:
-            _check_oracle(tf, probs, y.cpu().numpy()[:tf.m], xe[:tf.x_len], ue[:tf.u_len], False)
-    st.sweep_schedule(tf, (16, 1, 16))
+            _check_oracle(tf, probs, y.cpu().numpy()[:tf.m], xe[:tf.x_len], ue[:tf.u_len], False,
+                          x0.cpu().numpy()[:tf.x0_len])
+    st.sweep_schedule(tf, (16, 1, 16, 1))
     with pytest.raises(st.StotreeError):
         g.launch()                         # schedule changed: must be recorded again
     g.free()
