@@ -309,7 +309,7 @@ __device__ void load_x64(const SweepArgs &a, const InstDesc &I, int i, double *V
 }
 
 template <int TPW>
-__global__ void __launch_bounds__(kWave *kWg) bwd_trunk64_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave *kWg, 2) bwd_trunk64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(kWave *kWg) bwd_trunk64_kernel(SweepArgs a)
 }
 
 template <int TPW>
-__global__ void __launch_bounds__(kWave *kWg) fwd_trunk64_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave *kWg, 2) fwd_trunk64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(kWave *kWg) fwd_trunk64_kernel(SweepArgs a)
 
 // Chains below s*: one workgroup per chain (items: instance, chain).
 template <int TPW>
-__global__ void __launch_bounds__(kWave *kWg) bwd_chain64_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave *kWg, 2) bwd_chain64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(kWave *kWg) bwd_chain64_kernel(SweepArgs a)
 }
 
 template <int TPW>
-__global__ void __launch_bounds__(kWave *kWg) fwd_chain64_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave *kWg, 2) fwd_chain64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
