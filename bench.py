@@ -30,6 +30,37 @@ METRIC = "dual-grad evals/s + time-to-1e-6 residual; learned warm start vs cold,
 HBM_PEAK_GBS = 8000.0
 
 
+KERNEL_SOURCES = ("paper_2107_01745_amd/csrc/sweep.hip", "paper_2107_01745_amd/csrc/sweep_common.h",
+                  "paper_2107_01745_amd/csrc/internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_cfg1.md")
+
+
+def kernel_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or
+    None if there is none or the sweep kernels changed since it was taken."""
+    try:
+        kv = {}
+        for ln in open(TRAFFIC_FILE):
+            if ln.startswith("- ") and ": " in ln:
+                k, v = ln[2:].strip().split(": ", 1)
+                kv[k.strip("`")] = v.strip().strip("`")
+        if kv.get("kernel_sources_sha1") != kernel_sources_sha1():
+            return None
+        return float(kv[f"traffic_bytes {kernel}"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -396,17 +427,18 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
            "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]], "training_generation_s": gen_s,
            "train_s": train_s,
            "cold_per_instance": {"sample": n_solo, "iters": solo_it, "s_per_instance": solo_s / n_solo,
-                                 "s_total_64": solo_total},
+                                 "s_total_64": solo_total,
+                                 "batched_iters_same_sample": [i["iters"] for i in info_c[:n_solo]]},
            "cold_batched": {"s": cold_s, "iters_mean": float(np.mean([i["iters"] for i in info_c])),
                             "converged": int(sum(i["status"] == 0 for i in info_c))},
            "warm_batched": {"s": pred_s + warm_s, "predict_s": pred_s, "kept": int(sum(keep)),
-                            "iters_mean": float(np.mean([i["iters"] for i in info_w])),
+                            "iters_mean": float(np.mean([i["iters"] + 1 for i in info_w])),
                             "converged": int(sum(i["status"] == 0 for i in info_w))},
            "speedup_warm_batched_vs_cold_per_instance": solo_total / (pred_s + warm_s),
            "speedup_cold_batched_vs_cold_per_instance": solo_total / cold_s}
     log(f"config 4 solve: cold per-instance {solo_total:.1f} s (64, est.), cold batched {cold_s:.2f} s "
         f"(iters {rep['cold_batched']['iters_mean']:.1f}), warm batched {pred_s + warm_s:.2f} s "
-        f"(iters {rep['warm_batched']['iters_mean']:.1f}, kept {sum(keep)}) -> "
+        f"(iters {rep['warm_batched']['iters_mean']:.1f} incl. the refining one, kept {sum(keep)}) -> "
         f"{rep['speedup_warm_batched_vs_cold_per_instance']:.1f}x")
     return rep
 
@@ -486,7 +518,7 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
         pred_s = time.perf_counter() - t0
         _, _, info_w, sec_w = ws.solve_batch(chunk, lam, eps=1e-6, y0=yw, tf=tf)
         warm_b += pred_s + sec_w
-        it_w += [i["iters"] for i in info_w]
+        it_w += [i["iters"] + 1 for i in info_w]      # + the refining iteration of the warm start
         ok_w += sum(i["status"] == 0 for i in info_w)
         kept += sum(keep)
         tf.free()
@@ -502,13 +534,14 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
            "batch": batch, "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]],
            "data_generation_s": gen_s, "train_s": train_s,
            "iters_cold_mean": float(np.mean(it_c)), "iters_warm_mean": float(np.mean(it_w)),
+           "iters_cold_batched_same_sample": float(np.mean(it_c[:n_solo])),
            "warm_kept": int(kept), "warm_converged": int(ok_w),
            "cold_per_instance_s_total": solo_total, "cold_per_instance_sample": n_solo,
            "cold_per_instance_iters_mean": float(np.mean(it_solo)),
            "cold_batched_s_total": cold_b, "warm_batched_s_total": warm_b,
            "speedup_warm_batched_vs_cold_per_instance": solo_total / warm_b,
            "speedup_warm_vs_cold_batched": cold_b / warm_b}
-    log(f"warm leg: iters cold {rep['iters_cold_mean']:.1f} warm {rep['iters_warm_mean']:.1f}; "
+    log(f"warm leg: iters cold {rep['iters_cold_mean']:.1f} warm {rep['iters_warm_mean']:.1f} (kept {kept}); "
         f"cold per-instance {solo_total:.2f} s, cold batched {cold_b:.3f} s, warm batched {warm_b:.3f} s "
         f"-> speedup {rep['speedup_warm_batched_vs_cold_per_instance']:.1f}x")
     return rep
@@ -613,7 +646,7 @@ def main():
     sweep_bytes = sum(pbytes.values())
     log(f"phases: {json.dumps(phase_rep)}")
     roofline = {"bound": "hbm", "achieved": phase_rep[dom]["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": phase_rep[dom]["GBs"] / HBM_PEAK_GBS, "traffic": None,
+                "frac": phase_rep[dom]["GBs"] / HBM_PEAK_GBS, "traffic": recorded_traffic(f"{dom}_kernel"),
                 "kernel": f"{dom}_kernel", "bytes_per_launch": pbytes[dom],
                 "avg_launch_ms": phase_rep[dom]["avg_ms"],
                 "copy_GBs": copy_gbs, "frac_of_copy": phase_rep[dom]["GBs"] / copy_gbs,

@@ -44,30 +44,35 @@ using namespace dev;
 
 // acc[k][ch][e] += sum_{r0<=r<r1} M[r][c] * v_k[r] for the lane's columns
 // c = 2*lane + 2*G*ch + e < W (lane within a group of G lanes that shares
-// the matrix), with M row-major of leading dimension ld and v_k
-// in LDS at v + k*ldv.  The loads carry no lane condition (lanes past W re-read
-// column 0 and their sums are never stored) and rows go in batches of
-// kRowBatch, double-buffered: the next batch is issued before the current one
-// is multiplied, so up to 2*kRowBatch row loads are in flight per wavefront.
+// the matrix), with M row-major of leading dimension ld and v_k in LDS at
+// v + k*ldv.  The loads carry no lane condition (lanes past W re-read column
+// 0 and their sums are never stored) and rows go in batches of kRowBatch,
+// double-buffered: the next batch is issued before the current one is
+// multiplied, so up to 2*kRowBatch row loads are in flight per lane group.  A
+// last, partial batch re-reads its final row in the unused slots (and skips
+// them in the sums), so no row is ever loaded on its own.
 constexpr int kRowBatch = 8;
 
 template <int CH>
 __device__ __forceinline__ void load_rows(double2 (&m)[kRowBatch][CH], const double *__restrict__ M,
-                                          int ld, int r, const int (&col)[CH])
+                                          int ld, int r, int cnt, const int (&col)[CH])
 {
 #pragma unroll
-    for (int u = 0; u < kRowBatch; ++u)
+    for (int u = 0; u < kRowBatch; ++u) {
+        const int rr = r + (u < cnt ? u : cnt - 1);
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch)
-            m[u][ch] = *reinterpret_cast<const double2 *>(M + (long long)(r + u) * ld + col[ch]);
+            m[u][ch] = *reinterpret_cast<const double2 *>(M + (long long)rr * ld + col[ch]);
+    }
 }
 
 template <int NRHS, int CH>
 __device__ __forceinline__ void fma_rows(const double2 (&m)[kRowBatch][CH], const double *v, int ldv,
-                                         int r, double (&acc)[NRHS][CH][2])
+                                         int r, int cnt, double (&acc)[NRHS][CH][2])
 {
 #pragma unroll
-    for (int u = 0; u < kRowBatch; ++u)
+    for (int u = 0; u < kRowBatch; ++u) {
+        if (u >= cnt) break;
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             const double vk = v[k * ldv + r + u];
@@ -77,6 +82,7 @@ __device__ __forceinline__ void fma_rows(const double2 (&m)[kRowBatch][CH], cons
                 acc[k][ch][1] = fma(m[u][ch].y, vk, acc[k][ch][1]);
             }
         }
+    }
 }
 
 template <int NRHS, int CH, int G = kWave>
@@ -84,43 +90,26 @@ __device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, 
                                           const double *v, int ldv, double (&acc)[NRHS][CH][2],
                                           int lane)
 {
+    const int n = r1 - r0;
+    if (n <= 0) return;
     int col[CH];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
         const int c0 = 2 * lane + 2 * G * ch;
         col[ch] = c0 < W ? c0 : 0;
     }
-    int r = r0;
-    int nb = (r1 - r0) / kRowBatch;
+    const int nbt = (n + kRowBatch - 1) / kRowBatch;   // batches, the last one possibly partial
+    auto cnt = [&](int b) { return n - b * kRowBatch < kRowBatch ? n - b * kRowBatch : kRowBatch; };
     double2 m0[kRowBatch][CH], m1[kRowBatch][CH];
-    if (nb > 0) load_rows<CH>(m0, M, ld, r, col);
-    while (nb >= 2) {
-        load_rows<CH>(m1, M, ld, r + kRowBatch, col);
-        fma_rows<NRHS, CH>(m0, v, ldv, r, acc);
-        if (nb >= 3) load_rows<CH>(m0, M, ld, r + 2 * kRowBatch, col);
-        fma_rows<NRHS, CH>(m1, v, ldv, r + kRowBatch, acc);
-        r += 2 * kRowBatch;
-        nb -= 2;
+    load_rows<CH>(m0, M, ld, r0, cnt(0), col);
+    int b = 0;
+    for (; b + 2 <= nbt; b += 2) {
+        load_rows<CH>(m1, M, ld, r0 + (b + 1) * kRowBatch, cnt(b + 1), col);
+        fma_rows<NRHS, CH>(m0, v, ldv, r0 + b * kRowBatch, kRowBatch, acc);
+        if (b + 2 < nbt) load_rows<CH>(m0, M, ld, r0 + (b + 2) * kRowBatch, cnt(b + 2), col);
+        fma_rows<NRHS, CH>(m1, v, ldv, r0 + (b + 1) * kRowBatch, cnt(b + 1), acc);
     }
-    if (nb == 1) {
-        fma_rows<NRHS, CH>(m0, v, ldv, r, acc);
-        r += kRowBatch;
-    }
-    for (; r < r1; ++r) {
-        double2 m[CH];
-#pragma unroll
-        for (int ch = 0; ch < CH; ++ch)
-            m[ch] = *reinterpret_cast<const double2 *>(M + (long long)r * ld + col[ch]);
-#pragma unroll
-        for (int k = 0; k < NRHS; ++k) {
-            const double vk = v[k * ldv + r];
-#pragma unroll
-            for (int ch = 0; ch < CH; ++ch) {
-                acc[k][ch][0] = fma(m[ch].x, vk, acc[k][ch][0]);
-                acc[k][ch][1] = fma(m[ch].y, vk, acc[k][ch][1]);
-            }
-        }
-    }
+    if (b < nbt) fma_rows<NRHS, CH>(m0, v, ldv, r0 + b * kRowBatch, cnt(b), acc);
 }
 
 // dst[k*ld + off + c] = acc[k][.][.] for the lane's columns c < dim.

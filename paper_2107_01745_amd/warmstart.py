@@ -135,21 +135,23 @@ def _x0_of(probs_or_x0):
     return torch.tensor(np.concatenate([p.x0 for p in probs_or_x0]), dtype=torch.float64, device=_dev())
 
 
-def warm_start_duals(model, tf, probs_or_x0, lam):
-    """Predicted duals with the cold start kept wherever the solver's residual
-    at the prediction is not below its residual at zero.  probs_or_x0: the
-    instances' problems, or their concatenated x0 on the device."""
+def warm_start_duals(model, tf, probs_or_x0, lam, refine_steps=1):
+    """Predicted duals, refined by refine_steps solver iterations (the first
+    forward-backward step sends the predicted duals of inactive constraints
+    to zero), with the cold start kept wherever the solver's residual at the
+    refined prediction is not below its residual at zero.  probs_or_x0: the
+    instances' problems, or their concatenated x0 on the device.  Returns
+    (y, keep); keep[b] says whether instance b starts from its prediction."""
     x0 = _x0_of(probs_or_x0)
     yw = torch.zeros(tf.m, dtype=torch.float64, device=_dev())
     x = torch.empty(tf.x_len, dtype=torch.float64, device=_dev())
     u = torch.empty(tf.u_len, dtype=torch.float64, device=_dev())
-    # residual of each instance at the cold start, then at the prediction (a
-    # solve with max_iter = 0 evaluates the residual and leaves y unchanged)
-    opts = stotree.make_opts(lam=lam, eps=0.0, max_iter=0, mem=1)   # mem 1: reuse any workspace
-    stotree.nama_solve(tf, x0, yw, x, u, opts)
+    # residual at the cold start (a solve with max_iter = 0 evaluates the
+    # residual and leaves y unchanged); mem 1 reuses any existing workspace
+    stotree.nama_solve(tf, x0, yw, x, u, stotree.make_opts(lam=lam, eps=0.0, max_iter=0, mem=1))
     rc = [i["res_scaled_inf"] for i in stotree.solve_info_batch(tf)]
     model.predict(tf, x0, yw)
-    stotree.nama_solve(tf, x0, yw, x, u, opts)
+    stotree.nama_solve(tf, x0, yw, x, u, stotree.make_opts(lam=lam, eps=0.0, max_iter=refine_steps, mem=1))
     rw = [i["res_scaled_inf"] for i in stotree.solve_info_batch(tf)]
     keep = [a <= b for a, b in zip(rw, rc)]
     stotree.dual_select(tf, yw, keep)
