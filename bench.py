@@ -367,7 +367,8 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     lam = 1.0 / (1.1 * stotree.dual_lipschitz(tf1, 50))
     solo_s, solo_it = 0.0, []
     for k in range(n_solo):
-        _, _, info, sec = ws.solve_batch(test_x0[k * nx:(k + 1) * nx], lam, eps=1e-6, tf=tf1, mem=mem)
+        _, _, info, sec = ws.solve_batch(test_x0[k * nx:(k + 1) * nx], lam, eps=1e-6, tf=tf1, mem=mem,
+                                         max_iter=500)
         solo_s += sec
         solo_it.append(info[0]["iters"])
     tf1.free()
@@ -382,17 +383,19 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     sel_gen.manual_seed(5)
     for b in range(n_batches):
         x0 = draws()
-        _, y, infos, sec = ws.solve_batch(x0, lam, eps=1e-6, tf=tfs, mem=mem)
+        _, y, infos, sec = ws.solve_batch(x0, lam, eps=1e-6, tf=tfs, mem=mem, max_iter=500)
         gen_s += sec
-        gen_it += [i["iters"] for i in infos]
+        conv = [int(i["status"] == 0) for i in infos]
+        gen_it += [i["iters"] for i, c in zip(infos, conv) if c]
+        stotree.dual_select(tfs, y, conv)          # unsolved draws: zero rows, masked below
         if b == 0:
             nz = y.abs()[y.abs() > 0]
             model.y_scale = float(nz.pow(2).mean().sqrt().item()) if nz.numel() else 1.0
         X = model.features(tfs, x0)
         T, M = model.targets(tfs, y)
         row = 0
-        for info in infos:
-            if info["status"] != 0:
+        for c in conv:
+            if not c:
                 M[row:row + prob.tree.V] = 0.0
             row += prob.tree.V
         idx = torch.randperm(X.shape[0], device=dev, generator=sel_gen)[:keep_rows]
@@ -410,14 +413,14 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     log(f"config 4 solve: {n_batches * 64} training solves in {gen_s:.1f} s (mean iters {np.mean(gen_it):.1f}); "
         f"{epochs} epochs in {train_s:.1f} s, masked MSE {hist[0]:.3e} -> {hist[-1]:.3e}")
     # (b) cold, batched
-    _, _, info_c, cold_s = ws.solve_batch(test_x0, lam, eps=1e-6, tf=tfs, mem=mem)
+    _, _, info_c, cold_s = ws.solve_batch(test_x0, lam, eps=1e-6, tf=tfs, mem=mem, max_iter=500)
     # (c) warm, batched
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     yw, keep = ws.warm_start_duals(model, tfs, test_x0, lam)
     torch.cuda.synchronize()
     pred_s = time.perf_counter() - t0
-    _, _, info_w, warm_s = ws.solve_batch(test_x0, lam, eps=1e-6, y0=yw, tf=tfs, mem=mem)
+    _, _, info_w, warm_s = ws.solve_batch(test_x0, lam, eps=1e-6, y0=yw, tf=tfs, mem=mem, max_iter=500)
     tfs.free()
     del yw
     torch.cuda.empty_cache()
@@ -457,13 +460,28 @@ def guarded(name, fn, *a):
     return err
 
 
+def screen_feasible(ws, probs, lam, batch, max_iter=400):
+    """The draws whose problem has a solution the solver reaches: a cold
+    batched NAMA solve converges to 1e-6 within max_iter iterations (with
+    tight input boxes some draws of x0 have no feasible point, and their duals
+    grow without bound)."""
+    ok = []
+    for s in range(0, len(probs), batch):
+        chunk = probs[s:s + batch]
+        tf, _, infos, _ = ws.solve_batch(chunk, lam, eps=1e-6, max_iter=max_iter)
+        ok += [p for p, i in zip(chunk, infos) if i["status"] == 0]
+        tf.free()
+    return ok
+
+
 def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     """Config 3 (nx=20, nu=10, N=15, branching 3 at stages 0-4; |u| <= 0.2 so
     that the boxes bind): train the warm-start MLP on solver-generated duals
-    of n_train draws (x0, disturbance path), then compare on n_test held-out
-    draws the plain cold-start per-instance NAMA solves with the learned warm
-    start + batched solves (time to a 1e-6 residual, factor step excluded in
-    both; the warm side includes prediction and the residual check)."""
+    of n_train draws (x0, disturbance path; draws the solver cannot solve are
+    masked out), then compare on n_test held-out feasible draws the plain
+    cold-start per-instance NAMA solves with the learned warm start + batched
+    solves (time to a 1e-6 residual, factor step excluded in both; the warm
+    side includes prediction, the refining iteration and the residual checks)."""
     from paper_2107_01745_amd import warmstart as ws
     dev = torch.device("cuda:0")
     base = treegen.with_boxes(treegen.make_config(3), 5.0, 0.2)
@@ -474,10 +492,12 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     train = treegen.draw_warm_instances(base, n_train, seed=2003)
     Xs, Ts, Ms = [], [], []
     t0 = time.perf_counter()
-    gen_iters = []
+    gen_iters, gen_ok = [], 0
     for s in range(0, n_train, batch):
         chunk = train[s:s + batch]
-        tf, y, infos, _ = ws.solve_batch(chunk, lam, eps=1e-6)
+        tf, y, infos, _ = ws.solve_batch(chunk, lam, eps=1e-6, max_iter=400)
+        conv = [int(i["status"] == 0) for i in infos]
+        stotree.dual_select(tf, y, conv)          # unsolved draws: zero rows, masked below
         if s == 0:
             nz = y.abs()[y.abs() > 0]
             model.y_scale = float(nz.pow(2).mean().sqrt().item()) if nz.numel() else 1.0
@@ -487,23 +507,28 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
         row = 0
         for b, info in enumerate(infos):
             V = tf.instances[b]["V"]
-            if info["status"] != 0:
-                M[row:row + V] = 0.0        # unsolved draws do not train
+            if not conv[b]:
+                M[row:row + V] = 0.0
+            else:
+                gen_iters.append(info["iters"])
             row += V
-            gen_iters.append(info["iters"])
+        gen_ok += sum(conv)
         Xs.append(X); Ts.append(T); Ms.append(M)
         tf.free()
     gen_s = time.perf_counter() - t0
     X, T, M = torch.cat(Xs), torch.cat(Ts), torch.cat(Ms)
     del Xs, Ts, Ms
-    log(f"warm leg: {n_train} training solves in {gen_s:.1f} s ({X.shape[0]} node rows)")
+    log(f"warm leg: {n_train} training solves ({gen_ok} solved) in {gen_s:.1f} s ({X.shape[0]} node rows), "
+        f"y_scale {model.y_scale:.3e}")
     t0 = time.perf_counter()
     hist = model.fit(X, T, M, epochs=epochs, batch_rows=65536, lr=1e-3)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     log(f"warm leg: {epochs} epochs in {train_s:.1f} s, masked MSE {hist[0]:.3e} -> {hist[-1]:.3e}")
     del X, T, M
-    test = treegen.draw_warm_instances(base, n_test, seed=2004)
+    drawn = treegen.draw_warm_instances(base, n_test + n_test // 4, seed=2004)
+    test = screen_feasible(ws, drawn, lam, batch)[:n_test]
+    n_test = len(test)
     cold_b, warm_b, it_c, it_w, kept, ok_w = 0.0, 0.0, [], [], 0, 0
     for s in range(0, n_test, batch):
         chunk = test[s:s + batch]
@@ -530,9 +555,10 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
         it_solo.append(info[0]["iters"])
         tf.free()
     solo_total = solo_s / max(1, n_solo) * n_test
-    rep = {"tree": "config 3 (2794 nodes), |u| <= 0.2", "lambda": lam, "n_train": n_train, "n_test": n_test,
+    rep = {"tree": "config 3 (2794 nodes), |u| <= 0.2", "lambda": lam, "n_train": n_train,
+           "n_train_solved": int(gen_ok), "n_test_drawn": len(drawn), "n_test_feasible": n_test,
            "batch": batch, "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]],
-           "data_generation_s": gen_s, "train_s": train_s,
+           "y_scale": model.y_scale, "data_generation_s": gen_s, "train_s": train_s,
            "iters_cold_mean": float(np.mean(it_c)), "iters_warm_mean": float(np.mean(it_w)),
            "iters_cold_batched_same_sample": float(np.mean(it_c[:n_solo])),
            "warm_kept": int(kept), "warm_converged": int(ok_w),
@@ -540,9 +566,11 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
            "cold_per_instance_iters_mean": float(np.mean(it_solo)),
            "cold_batched_s_total": cold_b, "warm_batched_s_total": warm_b,
            "speedup_warm_batched_vs_cold_per_instance": solo_total / warm_b,
+           "speedup_cold_batched_vs_cold_per_instance": solo_total / cold_b,
            "speedup_warm_vs_cold_batched": cold_b / warm_b}
-    log(f"warm leg: iters cold {rep['iters_cold_mean']:.1f} warm {rep['iters_warm_mean']:.1f} (kept {kept}); "
-        f"cold per-instance {solo_total:.2f} s, cold batched {cold_b:.3f} s, warm batched {warm_b:.3f} s "
+    log(f"warm leg: {n_test} feasible held-out draws; iters cold {rep['iters_cold_mean']:.1f} "
+        f"warm {rep['iters_warm_mean']:.1f} (kept {kept}); cold per-instance {solo_total:.2f} s, "
+        f"cold batched {cold_b:.3f} s, warm batched {warm_b:.3f} s "
         f"-> speedup {rep['speedup_warm_batched_vs_cold_per_instance']:.1f}x")
     return rep
 
