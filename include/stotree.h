@@ -194,9 +194,11 @@ int dual_grad(const tree_factors *f, const double *x0, const double *y, int homo
  *            instance order;
  *   knobs[2] cap on the wavefronts sharing one node above s*: 1, 2, 4, 8 or
  *            16 (default 16);
- *   knobs[3] backward stages above s*: 1 one launch in which each node is
- *            taken up by the workgroup that finishes its last child, 0 one
- *            launch per stage (default).
+ *   knobs[3] stages above s*: 0 one launch per stage, a workgroup per node
+ *            (default); 1 the backward stages in one launch in which each
+ *            node is taken up by the workgroup that finishes its last child;
+ *            2 one launch per stage, the nodes of instances with nx + nu <= 64
+ *            walked by lane groups as the chains are.
  * knobs[0] and knobs[1] change no result bit; knobs[2] and knobs[3] change
  * the order of the per-node sums above s* (equal to rounding).
  * sweep_schedule rebuilds the work lists (synchronous; ERR_ARG for values

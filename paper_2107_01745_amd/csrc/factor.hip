@@ -338,6 +338,16 @@ int trunk_waves(int n, int nrhs_max, int ldM, int cap)
     return nw;
 }
 
+void free_level(LevelPlan &lv)
+{
+    if (lv.items) (void)hipFree(lv.items);
+    if (lv.wide_items) (void)hipFree(lv.wide_items);
+    for (auto &g : lv.narrow)
+        if (g.items) (void)hipFree(g.items);
+    lv.items = lv.wide_items = nullptr;
+    lv.narrow.clear();
+}
+
 }  // namespace
 
 void free_tree(tree_factors *f)
@@ -350,8 +360,10 @@ void free_tree(tree_factors *f)
         if (p) (void)hipFree(p);
     for (auto &cp : f->chains)
         if (cp.items) (void)hipFree(cp.items);
-    for (auto &lv : f->levels)
-        if (lv.items) (void)hipFree(lv.items);
+    for (auto &lv : f->levels) free_level(lv);
+    for (auto &lv : f->panel_levels) free_level(lv);
+    for (void *p : {(void *)f->panel_chain_items, (void *)f->trunk_entry.items, (void *)f->trunk_cnt})
+        if (p) (void)hipFree(p);
     delete f;
 }
 
@@ -371,8 +383,7 @@ int build_schedule(tree_factors *f)
     for (auto &cp : f->chains)
         if (cp.items) (void)hipFree(cp.items);
     f->chains.clear();
-    for (auto &lv : f->levels)
-        if (lv.items) (void)hipFree(lv.items);
+    for (auto &lv : f->levels) free_level(lv);
     f->levels.clear();
     int max_sstar = 0, max_ldM = 0;
     std::map<int, std::vector<std::pair<double, Item>>> by_G;
@@ -391,8 +402,7 @@ int build_schedule(tree_factors *f)
         }
     }
     if (f->panel_chain_items) { (void)hipFree(f->panel_chain_items); f->panel_chain_items = nullptr; }
-    for (auto &lv : f->panel_levels)
-        if (lv.items) (void)hipFree(lv.items);
+    for (auto &lv : f->panel_levels) free_level(lv);
     f->panel_levels.clear();
     const int panel_inst = f->shared > 1 ? 1 : f->ninst;   // a shared handle's panels cover instance 0's nodes
     {
@@ -439,9 +449,49 @@ int build_schedule(tree_factors *f)
         STOTREE_HIP(hipMalloc(&lv.items, sizeof(Item) * std::max<size_t>(1, items.size())));
         f->levels.push_back(lv);
         STOTREE_HIP(hipMemcpy(lv.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+        if (f->trunk_fused == 2) {
+            // lane groups for the nodes of narrow instances, workgroups for the rest
+            LevelPlan &L = f->levels.back();
+            std::vector<Item> wide;
+            std::map<int, std::vector<Item>> groups;
+            std::map<int, int> gldq;
+            int wide_ldM = 2;
+            for (int b = 0; b < f->ninst; ++b) {
+                const InstDesc &I = f->inst[b];
+                if (t >= I.sstar) continue;
+                const int *sp = f->sp_pool.data() + I.sp;
+                const int G = chain_group(I.ldM, f->group_min);
+                if (G == kWave) {
+                    for (int i = sp[t]; i < sp[t + 1]; ++i) wide.push_back({b, i});
+                    wide_ldM = std::max(wide_ldM, I.ldM);
+                    continue;
+                }
+                gldq[G] = std::max(gldq[G], I.ldM);
+                for (int i = sp[t]; i < sp[t + 1]; i += kWave / G) groups[G].push_back({b, i});
+            }
+            L.wide_count = (int)wide.size();
+            L.wide_nw = trunk_waves(L.wide_count, 2, wide_ldM, f->trunk_cap);
+            if (!wide.empty()) {
+                STOTREE_HIP(hipMalloc(&L.wide_items, sizeof(Item) * wide.size()));
+                STOTREE_HIP(hipMemcpy(L.wide_items, wide.data(), sizeof(Item) * wide.size(), hipMemcpyHostToDevice));
+            }
+            for (auto &kv : groups) {
+                ChainPlan g{};
+                g.G = kv.first;
+                g.CH = 1;
+                g.ldq = gldq[kv.first];
+                g.count = (int)kv.second.size();
+                STOTREE_HIP(hipMalloc(&g.items, sizeof(Item) * kv.second.size()));
+                L.narrow.push_back(g);
+                STOTREE_HIP(hipMemcpy(g.items, kv.second.data(), sizeof(Item) * kv.second.size(),
+                                      hipMemcpyHostToDevice));
+            }
+        }
         if (panel_inst < f->ninst) {
             const InstDesc &I = f->inst[0];
-            LevelPlan pl = lv;
+            LevelPlan pl{};
+            pl.t = t;
+            pl.nw = lv.nw;
             pl.count = t < I.sstar ? f->sp_pool[I.sp + t + 1] - f->sp_pool[I.sp + t] : 0;
             STOTREE_HIP(hipMalloc(&pl.items, sizeof(Item) * std::max(1, pl.count)));
             f->panel_levels.push_back(pl);

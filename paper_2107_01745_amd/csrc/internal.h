@@ -73,11 +73,17 @@ struct ChainPlan {
 };
 
 // One launch of the per-stage kernels: all (instance, node) pairs of one stage.
+// With lane groups above s* (trunk mode 2) the stage is split into the nodes
+// of instances with nx + nu > 64 (workgroups of wide_nw wavefronts per node)
+// and lane-group items of kWave/G consecutive nodes of one instance.
 struct LevelPlan {
     int t;
     int count;
     int nw;                          // wavefronts per node
     Item *items;                     // device
+    int wide_count = 0, wide_nw = 1;
+    Item *wide_items = nullptr;
+    std::vector<ChainPlan> narrow;
 };
 
 // Solver workspace kept in the handle (allocated at the first solve).
@@ -121,7 +127,8 @@ struct tree_factors {
     int trunk_cap = 16;                     // cap on wavefronts per node above s*
     int chain_order = 1;                    // 1: longest chains first, 0: instance order
     int group_min = 8;                      // smallest lane group used for chains
-    int trunk_fused = 0;                    // 1: backward stages above s* in one launch
+    int trunk_fused = 0;                    // stages above s*: 0 per-stage launches, 1 one backward
+                                            // launch, 2 per-stage launches with lane groups
     stotree::LevelPlan trunk_entry{};       // nodes of stage s*-1 of every instance
     int *trunk_cnt = nullptr;               // per node (node0-indexed): children finished
     long long schedule_epoch = 0;           // bumped whenever the work lists are rebuilt

@@ -30,7 +30,7 @@ bool valid_knobs(const int32_t *k)
     const bool g = k[0] == 8 || k[0] == 16 || k[0] == 32 || k[0] == 64;
     const bool o = k[1] == 0 || k[1] == 1;
     const bool t = k[2] == 1 || k[2] == 2 || k[2] == 4 || k[2] == 8 || k[2] == 16;
-    const bool m = k[3] == 0 || k[3] == 1;
+    const bool m = k[3] == 0 || k[3] == 1 || k[3] == 2;
     return g && o && t && m;
 }
 
@@ -49,7 +49,7 @@ int set_schedule(tree_factors *f, const int32_t *knobs)
 {
     if (!valid_knobs(knobs)) {
         set_error("sweep_schedule: knobs must be group in {8,16,32,64}, order in {0,1}, cap in {1,2,4,8,16}, "
-                  "trunk mode in {0,1}");
+                  "trunk mode in {0,1,2}");
         return STOTREE_ERR_ARG;
     }
     // the old work lists may still be read by queued sweeps
@@ -104,7 +104,7 @@ int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms
     int32_t best[kKnobs] = {f->group_min, f->chain_order, f->trunk_cap, f->trunk_fused};
     double best_ms = 0.0;
     rc = measure(best, &best_ms);
-    const std::vector<std::vector<int>> values = {{8, 16, 32, 64}, {1, 0}, {16, 8, 4, 2}, {1, 0}};
+    const std::vector<std::vector<int>> values = {{8, 16, 32, 64}, {1, 0}, {16, 8, 4, 2}, {0, 2, 1}};
     for (int knob = 0; knob < kKnobs && !rc; ++knob) {
         const int32_t start = best[knob];
         for (int v : values[knob]) {

@@ -632,6 +632,43 @@ struct NarrowChains {
     const Item *items[3];
 };
 
+// Nodes of one stage above s* (stage a.t) of narrow instances, a lane group
+// per node (item = instance, first node of kWave/G consecutive nodes).
+template <int NRHS, int G, bool BWD>
+__device__ __forceinline__ void level_body(const SweepArgs &a, const Item *items, int nitems, int blk, int ldq)
+{
+    constexpr int kGroups = kWave / G;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int item = blk * kWavesPerBlock + wave;
+    if (item >= nitems) return;
+    const Item it = items[item];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int lane = threadIdx.x & (G - 1), grp = (threadIdx.x & (kWave - 1)) / G;
+    const int node = it.idx + grp;
+    if (node >= a.sp[I.sp + a.t + 1]) return;
+    const WaveLds L = wave_lds(ldq, NRHS, wave * kGroups + grp);
+    if (BWD) {
+        bwd_node<NRHS, 1, G>(a, I, node, L, false, true, lane);
+    } else {
+        load_x<NRHS, G>(a, I, node, L, lane);
+        fwd_node<NRHS, 1, G>(a, I, node, L, false, lane);
+    }
+}
+
+template <int NRHS, bool BWD>
+__global__ void __launch_bounds__(kWave *kWavesPerBlock, 2) narrow_level_kernel(SweepArgs a, NarrowChains nc)
+{
+    int c = 0;
+    while (c + 1 < nc.n && (int)blockIdx.x >= nc.first_block[c + 1]) ++c;
+    const int blk = blockIdx.x - nc.first_block[c];
+    switch (nc.G[c]) {
+    case 8: level_body<NRHS, 8, BWD>(a, nc.items[c], nc.count[c], blk, nc.ldq[c]); break;
+    case 16: level_body<NRHS, 16, BWD>(a, nc.items[c], nc.count[c], blk, nc.ldq[c]); break;
+    default: level_body<NRHS, 32, BWD>(a, nc.items[c], nc.count[c], blk, nc.ldq[c]); break;
+    }
+}
+
 template <int NRHS, bool BWD>
 __global__ void __launch_bounds__(kWave *kWavesPerBlock, 2) narrow_chain_kernel(SweepArgs a, NarrowChains nc)
 {
@@ -793,6 +830,46 @@ static void launch_trunk_tree(const SweepArgs &a, const tree_factors *f, int max
     }
 }
 
+// One stage above s*: per-node workgroups for every node, or (trunk mode 2)
+// lane groups for the narrow instances' nodes plus workgroups for the rest.
+template <int NRHS, int CH>
+static void launch_level(bool backward, const SweepArgs &a, const tree_factors *f, const LevelPlan &lv, int ldM,
+                         int qs, int ldu, hipStream_t st)
+{
+    if (f->trunk_fused != 2) {
+        launch_trunk<NRHS, CH>(backward, a, lv, ldM, qs, ldu, st);
+        return;
+    }
+    if (lv.wide_count > 0) {
+        LevelPlan w{};
+        w.t = lv.t;
+        w.count = lv.wide_count;
+        w.nw = lv.wide_nw;
+        w.items = lv.wide_items;
+        launch_trunk<NRHS, CH>(backward, a, w, ldM, qs, ldu, st);
+    }
+    if (lv.narrow.empty()) return;
+    NarrowChains nc{};
+    size_t lds = 0;
+    for (const ChainPlan &g : lv.narrow) {
+        const int blocks = (g.count + kWavesPerBlock - 1) / kWavesPerBlock;
+        nc.G[nc.n] = g.G;
+        nc.ldq[nc.n] = g.ldq;
+        nc.count[nc.n] = g.count;
+        nc.items[nc.n] = g.items;
+        nc.first_block[nc.n + 1] = nc.first_block[nc.n] + blocks;
+        ++nc.n;
+        lds = std::max(lds, sizeof(double) * (size_t)kWavesPerBlock * (kWave / g.G) * 3 * NRHS * g.ldq);
+    }
+    SweepArgs la = a;
+    la.t = lv.t;
+    const dim3 blk(kWave * kWavesPerBlock), grid(nc.first_block[nc.n]);
+    if (backward)
+        hipLaunchKernelGGL((narrow_level_kernel<NRHS, true>), grid, blk, lds, st, la, nc);
+    else
+        hipLaunchKernelGGL((narrow_level_kernel<NRHS, false>), grid, blk, lds, st, la, nc);
+}
+
 // Chain launches: one for all narrow widths together, one per wide plan.
 template <int NRHS>
 static void launch_chains(bool backward, const SweepArgs &a, const tree_factors *f, hipStream_t st)
@@ -852,16 +929,16 @@ static hipError_t sweep_impl(const tree_factors *f, SweepArgs a, hipStream_t st)
     }
     if (!f->levels.empty()) {
         PhaseTimer tm(1, st);
-        if (f->trunk_fused && f->trunk_entry.count > 0)
+        if (f->trunk_fused == 1 && f->trunk_entry.count > 0)
             launch_trunk_tree<NRHS, CH>(a, f, ldM, qs, ldu, st);
         else
             for (int k = (int)f->levels.size() - 1; k >= 0; --k)
-                launch_trunk<NRHS, CH>(true, a, f->levels[k], ldM, qs, ldu, st);
+                launch_level<NRHS, CH>(true, a, f, f->levels[k], ldM, qs, ldu, st);
     }
     if (!f->levels.empty()) {
         PhaseTimer tm(2, st);
         for (size_t k = 0; k < f->levels.size(); ++k)
-            launch_trunk<NRHS, CH>(false, a, f->levels[k], ldM, qs, ldu, st);
+            launch_level<NRHS, CH>(false, a, f, f->levels[k], ldM, qs, ldu, st);
     }
     if (!f->chains.empty()) {
         PhaseTimer tm(3, st);

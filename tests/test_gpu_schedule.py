@@ -76,7 +76,7 @@ def test_schedules_are_bit_identical(st):
                 xh, uh = _sweep(st, tf, x0, y, False, nrhs)
                 assert np.array_equal(xh, ref[nrhs][0]) and np.array_equal(uh, ref[nrhs][1]), (g, order, nrhs)
     for cap in (1, 2, 4, 8):
-        for fused in (0, 1):
+        for fused in (0, 1, 2):
             st.sweep_schedule(tf, (8, 1, cap, fused))
             for nrhs in (1, 2):
                 xh, uh = _sweep(st, tf, x0, y, False, nrhs)
@@ -91,7 +91,7 @@ def test_schedules_are_bit_identical(st):
     with pytest.raises(st.StotreeError):
         st.sweep_schedule(tf, (12, 1, 16, 1))
     with pytest.raises(st.StotreeError):
-        st.sweep_schedule(tf, (8, 1, 16, 2))
+        st.sweep_schedule(tf, (8, 1, 16, 3))
     tf.free()
 
 
@@ -105,7 +105,7 @@ def test_autotune_keeps_results_and_caches(st, tmp_path):
     rec = st.sweep_autotune(tf, nrhs=1, reps=3, cache=cache)
     assert not rec["cached"] and rec["ms"] > 0
     g, order, cap, fused = rec["knobs"]
-    assert g in (8, 16, 32, 64) and order in (0, 1) and cap in (1, 2, 4, 8, 16) and fused in (0, 1)
+    assert g in (8, 16, 32, 64) and order in (0, 1) and cap in (1, 2, 4, 8, 16) and fused in (0, 1, 2)
     assert st.sweep_schedule_get(tf) == tuple(rec["knobs"])
     for homogeneous in (False, True):
         xh, uh = _sweep(st, tf, x0, y, homogeneous)
