@@ -112,6 +112,69 @@ __device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, 
     if (b < nbt) fma_rows<NRHS, CH>(m0, v, ldv, r0 + b * kRowBatch, cnt(b), acc);
 }
 
+// The same product for W <= 64 columns on a full wavefront (forward chain
+// steps): each load instruction brings in two rows, the even rows of the
+// range in lanes 0..31 and the odd rows in lanes 32..63 (lane l owns columns
+// 2l, 2l+1 in both halves); the halves' partial sums are added at the end, so
+// lanes 0..31 hold the sums and lanes 32..63 (columns >= 64) a copy.
+__device__ __forceinline__ void load_pairs(double2 (&m)[kRowBatch], const double *__restrict__ M, int ld,
+                                           int rfirst, int rlast, int col)
+{
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+        const int r = rfirst + 2 * u;
+        m[u] = *reinterpret_cast<const double2 *>(M + (long long)(r < rlast ? r : rlast) * ld + col);
+    }
+}
+
+template <int NRHS>
+__device__ __forceinline__ void fma_pairs(const double2 (&m)[kRowBatch], const double *v, int ldv, int rfirst,
+                                          int r1, double (&acc)[NRHS][1][2])
+{
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+        const int r = rfirst + 2 * u;
+        const bool in = r < r1;
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            const double vk = in ? v[k * ldv + r] : 0.0;
+            acc[k][0][0] = fma(m[u].x, vk, acc[k][0][0]);
+            acc[k][0][1] = fma(m[u].y, vk, acc[k][0][1]);
+        }
+    }
+}
+
+template <int NRHS>
+__device__ __forceinline__ void gemv_pairs(const double *__restrict__ M, int ld, int r0, int r1, int W,
+                                           const double *v, int ldv, double (&acc)[NRHS][1][2], int lane)
+{
+    const int h = lane >> 5, l = lane & 31;
+    const int col = 2 * l < W ? 2 * l : 0;
+    const int np = (r1 - r0 + 1) / 2;
+    const int nbt = (np + kRowBatch - 1) / kRowBatch;
+    const int rlast = r1 - 1;
+    double part[NRHS][1][2];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) part[k][0][0] = part[k][0][1] = 0.0;
+    double2 m0[kRowBatch], m1[kRowBatch];
+    load_pairs(m0, M, ld, r0 + h, rlast, col);
+    int b = 0;
+    for (; b + 2 <= nbt; b += 2) {
+        load_pairs(m1, M, ld, r0 + 2 * (b + 1) * kRowBatch + h, rlast, col);
+        fma_pairs<NRHS>(m0, v, ldv, r0 + 2 * b * kRowBatch + h, r1, part);
+        if (b + 2 < nbt) load_pairs(m0, M, ld, r0 + 2 * (b + 2) * kRowBatch + h, rlast, col);
+        fma_pairs<NRHS>(m1, v, ldv, r0 + 2 * (b + 1) * kRowBatch + h, r1, part);
+    }
+    if (b < nbt) fma_pairs<NRHS>(m0, v, ldv, r0 + 2 * b * kRowBatch + h, r1, part);
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const double o = __shfl_xor(part[k][0][e], 32, kWave);
+            acc[k][0][e] += h ? o + part[k][0][e] : part[k][0][e] + o;
+        }
+}
+
 // dst[k*ld + off + c] = acc[k][.][.] for the lane's columns c < dim.
 template <int NRHS, int CH, int G = kWave>
 __device__ __forceinline__ void store_acc(double *dst, int ld, int off, int dim,
@@ -260,7 +323,14 @@ __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     const int *cp = a.cp + I.cp;
     double uacc[NRHS][CH][2];
     zero(uacc);
-    gemv_rows<NRHS, CH, G>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
+    if constexpr (G == kWave && CH == 1) {
+        if (nu <= kWave && nx >= 2)
+            gemv_pairs<NRHS>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
+        else
+            gemv_rows<NRHS, CH, G>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
+    } else {
+        gemv_rows<NRHS, CH, G>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
+    }
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
         const int c0 = 2 * lane + 2 * G * ch;
@@ -284,8 +354,17 @@ __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     for (int j = j0; j < j1; ++j) {
         double xacc[NRHS][CH][2];
         zero(xacc);
-        gemv_rows<NRHS, CH, G>(a.Mf + I.Mf + (long long)j * (nx + nu) * I.ldx, I.ldx, 0, nx + nu, nx, L.qx, L.ldq,
-                            xacc, lane);
+        if constexpr (G == kWave && CH == 1) {
+            if (nx <= kWave)
+                gemv_pairs<NRHS>(a.Mf + I.Mf + (long long)j * (nx + nu) * I.ldx, I.ldx, 0, nx + nu, nx, L.qx, L.ldq,
+                                 xacc, lane);
+            else
+                gemv_rows<NRHS, CH, G>(a.Mf + I.Mf + (long long)j * (nx + nu) * I.ldx, I.ldx, 0, nx + nu, nx, L.qx,
+                                       L.ldq, xacc, lane);
+        } else {
+            gemv_rows<NRHS, CH, G>(a.Mf + I.Mf + (long long)j * (nx + nu) * I.ldx, I.ldx, 0, nx + nu, nx, L.qx, L.ldq,
+                                   xacc, lane);
+        }
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch) {
             const int c0 = 2 * lane + 2 * G * ch;
