@@ -263,8 +263,18 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
     zero(kacc);
     zero(qacc);
-    gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
-    gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
+    if constexpr (G == kWave && CH == 1) {
+        if (nx <= kWave && nu >= 2) {
+            gemv_pairs<NRHS>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
+            gemv_pairs<NRHS>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
+        } else {
+            gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
+            gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
+        }
+    } else {
+        gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
+        gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
+    }
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
         const int c0 = 2 * lane + 2 * G * ch;
