@@ -199,8 +199,8 @@ int dual_grad(const tree_factors *f, const double *x0, const double *y, int homo
  *            node is taken up by the workgroup that finishes its last child;
  *            2 one launch per stage, the nodes of instances with nx + nu <= 64
  *            walked by lane groups as the chains are.
- * knobs[0] and knobs[1] change no result bit; knobs[2] and knobs[3] change
- * the order of the per-node sums above s* (equal to rounding).
+ * knobs[1] changes no result bit; knobs[0], knobs[2] and knobs[3] change the
+ * order of some per-node sums (equal to rounding).
  * sweep_schedule rebuilds the work lists (synchronous; ERR_ARG for values
  * outside these sets, ERR_OOM, ERR_DEVICE); sweep_schedule_get reads them.
  * A schedule change invalidates the handle's sweep graphs.

@@ -112,11 +112,12 @@ __device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, 
     if (b < nbt) fma_rows<NRHS, CH>(m0, v, ldv, r0 + b * kRowBatch, cnt(b), acc);
 }
 
-// The same product for W <= 64 columns on a full wavefront (forward chain
-// steps): each load instruction brings in two rows, the even rows of the
-// range in lanes 0..31 and the odd rows in lanes 32..63 (lane l owns columns
-// 2l, 2l+1 in both halves); the halves' partial sums are added at the end, so
-// lanes 0..31 hold the sums and lanes 32..63 (columns >= 64) a copy.
+// The same product for W <= G columns on a lane group of G lanes: each load
+// instruction brings in two rows per group, the even rows of the range in the
+// lower half of the group and the odd rows in the upper half (lane l of a
+// half owns columns 2l, 2l+1); the halves' partial sums are added at the end,
+// so the lower half holds the sums and the upper half (whose own columns are
+// >= G) a copy.
 __device__ __forceinline__ void load_pairs(double2 (&m)[kRowBatch], const double *__restrict__ M, int ld,
                                            int rfirst, int rlast, int col)
 {
@@ -144,11 +145,11 @@ __device__ __forceinline__ void fma_pairs(const double2 (&m)[kRowBatch], const d
     }
 }
 
-template <int NRHS>
+template <int NRHS, int G = kWave>
 __device__ __forceinline__ void gemv_pairs(const double *__restrict__ M, int ld, int r0, int r1, int W,
                                            const double *v, int ldv, double (&acc)[NRHS][1][2], int lane)
 {
-    const int h = lane >> 5, l = lane & 31;
+    const int h = lane >= G / 2 ? 1 : 0, l = lane & (G / 2 - 1);
     const int col = 2 * l < W ? 2 * l : 0;
     const int np = (r1 - r0 + 1) / 2;
     const int nbt = (np + kRowBatch - 1) / kRowBatch;
@@ -170,7 +171,7 @@ __device__ __forceinline__ void gemv_pairs(const double *__restrict__ M, int ld,
     for (int k = 0; k < NRHS; ++k)
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const double o = __shfl_xor(part[k][0][e], 32, kWave);
+            const double o = __shfl_xor(part[k][0][e], G / 2, kWave);
             acc[k][0][e] += h ? o + part[k][0][e] : part[k][0][e] + o;
         }
 }
@@ -263,10 +264,10 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
     zero(kacc);
     zero(qacc);
-    if constexpr (G == kWave && CH == 1) {
-        if (nx <= kWave && nu >= 2) {
-            gemv_pairs<NRHS>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
-            gemv_pairs<NRHS>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
+    if constexpr (CH == 1) {
+        if (nx <= G && nu >= 2) {
+            gemv_pairs<NRHS, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
+            gemv_pairs<NRHS, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
         } else {
             gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
             gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
@@ -333,9 +334,9 @@ __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     const int *cp = a.cp + I.cp;
     double uacc[NRHS][CH][2];
     zero(uacc);
-    if constexpr (G == kWave && CH == 1) {
-        if (nu <= kWave && nx >= 2)
-            gemv_pairs<NRHS>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
+    if constexpr (CH == 1) {
+        if (nu <= G && nx >= 2)
+            gemv_pairs<NRHS, G>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
         else
             gemv_rows<NRHS, CH, G>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
     } else {
@@ -364,10 +365,10 @@ __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     for (int j = j0; j < j1; ++j) {
         double xacc[NRHS][CH][2];
         zero(xacc);
-        if constexpr (G == kWave && CH == 1) {
-            if (nx <= kWave)
-                gemv_pairs<NRHS>(a.Mf + I.Mf + (long long)j * (nx + nu) * I.ldx, I.ldx, 0, nx + nu, nx, L.qx, L.ldq,
-                                 xacc, lane);
+        if constexpr (CH == 1) {
+            if (nx <= G)
+                gemv_pairs<NRHS, G>(a.Mf + I.Mf + (long long)j * (nx + nu) * I.ldx, I.ldx, 0, nx + nu, nx, L.qx,
+                                    L.ldq, xacc, lane);
             else
                 gemv_rows<NRHS, CH, G>(a.Mf + I.Mf + (long long)j * (nx + nu) * I.ldx, I.ldx, 0, nx + nu, nx, L.qx,
                                        L.ldq, xacc, lane);

@@ -1,8 +1,8 @@
 """Sweep schedules, the autotuner and the HIP-graph sweep through the C ABI.
 
-The lane-group width and the chain order only re-map work, so every schedule
-must give bit-identical sweeps; the trunk cap reorders per-node sums (equal to
-rounding).  The tuned schedule and every graph replay are checked against the
+The chain order only re-maps work, so it must give bit-identical sweeps; the
+lane-group width (a group may split the rows of a narrow product over its two
+halves), the trunk cap and the trunk mode reorder sums (equal to rounding).  The tuned schedule and every graph replay are checked against the
 CPU oracle and against eager sweeps."""
 import numpy as np
 import pytest
@@ -74,7 +74,12 @@ def test_schedules_are_bit_identical(st):
             st.sweep_schedule(tf, (g, order, 16, 0))
             for nrhs in (1, 2):
                 xh, uh = _sweep(st, tf, x0, y, False, nrhs)
-                assert np.array_equal(xh, ref[nrhs][0]) and np.array_equal(uh, ref[nrhs][1]), (g, order, nrhs)
+                if g == 8:      # the default width: the chain order alone changes no bit
+                    assert np.array_equal(xh, ref[nrhs][0]) and np.array_equal(uh, ref[nrhs][1]), (order, nrhs)
+                else:           # wider groups may split rows over two half-groups: equal to rounding
+                    s = np.abs(ref[nrhs][0]).max()
+                    assert np.abs(xh - ref[nrhs][0]).max() <= 1e-12 * s, (g, order, nrhs)
+                    assert np.abs(uh - ref[nrhs][1]).max() <= 1e-12 * s, (g, order, nrhs)
     for cap in (1, 2, 4, 8):
         for fused in (0, 1, 2):
             st.sweep_schedule(tf, (8, 1, cap, fused))
