@@ -30,8 +30,7 @@ METRIC = "dual-grad evals/s + time-to-1e-6 residual; learned warm start vs cold,
 HBM_PEAK_GBS = 8000.0
 
 
-KERNEL_SOURCES = ("paper_2107_01745_amd/csrc/sweep.hip", "paper_2107_01745_amd/csrc/sweep_common.h",
-                  "paper_2107_01745_amd/csrc/internal.h")
+KERNEL_SOURCES = ("paper_2107_01745_amd/csrc/sweep.hip", "paper_2107_01745_amd/csrc/sweep_common.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_cfg1.md")
 
 
@@ -460,7 +459,14 @@ def guarded(name, fn, *a):
     return err
 
 
-def screen_feasible(ws, probs, lam, batch, max_iter=400):
+def shared_handle(stotree, base, chunk):
+    """One handle for draws of one tree that differ in x0 and c: the matrices
+    are factored once and the draws are swept together (64 at a time on the
+    matrix cores)."""
+    return stotree.tree_factor_shared(base, len(chunk), precondition=True, c=np.stack([p.c for p in chunk]))
+
+
+def screen_feasible(stotree, ws, base, probs, lam, batch, max_iter=400):
     """The draws whose problem has a solution the solver reaches: a cold
     batched NAMA solve converges to 1e-6 within max_iter iterations (with
     tight input boxes some draws of x0 have no feasible point, and their duals
@@ -468,7 +474,8 @@ def screen_feasible(ws, probs, lam, batch, max_iter=400):
     ok = []
     for s in range(0, len(probs), batch):
         chunk = probs[s:s + batch]
-        tf, _, infos, _ = ws.solve_batch(chunk, lam, eps=1e-6, max_iter=max_iter)
+        tf = shared_handle(stotree, base, chunk)
+        _, _, infos, _ = ws.solve_batch(chunk, lam, eps=1e-6, max_iter=max_iter, tf=tf)
         ok += [p for p, i in zip(chunk, infos) if i["status"] == 0]
         tf.free()
     return ok
@@ -495,7 +502,8 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     gen_iters, gen_ok = [], 0
     for s in range(0, n_train, batch):
         chunk = train[s:s + batch]
-        tf, y, infos, _ = ws.solve_batch(chunk, lam, eps=1e-6, max_iter=400)
+        tf = shared_handle(stotree, base, chunk)
+        _, y, infos, _ = ws.solve_batch(chunk, lam, eps=1e-6, max_iter=400, tf=tf)
         conv = [int(i["status"] == 0) for i in infos]
         stotree.dual_select(tf, y, conv)          # unsolved draws: zero rows, masked below
         if s == 0:
@@ -527,12 +535,13 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     log(f"warm leg: {epochs} epochs in {train_s:.1f} s, masked MSE {hist[0]:.3e} -> {hist[-1]:.3e}")
     del X, T, M
     drawn = treegen.draw_warm_instances(base, n_test + n_test // 4, seed=2004)
-    test = screen_feasible(ws, drawn, lam, batch)[:n_test]
-    n_test = len(test)
+    test = screen_feasible(stotree, ws, base, drawn, lam, batch)
+    n_test = min(n_test, len(test) // batch * batch)    # whole 64-draw panels
+    test = test[:n_test]
     cold_b, warm_b, it_c, it_w, kept, ok_w = 0.0, 0.0, [], [], 0, 0
     for s in range(0, n_test, batch):
         chunk = test[s:s + batch]
-        tf = stotree.tree_factor_batch(chunk, precondition=True)
+        tf = shared_handle(stotree, base, chunk)
         _, _, info_c, sec_c = ws.solve_batch(chunk, lam, eps=1e-6, tf=tf)
         cold_b += sec_c
         it_c += [i["iters"] for i in info_c]

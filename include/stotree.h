@@ -142,18 +142,23 @@ int tree_factor_batch(int count, const tree_desc *trees, const problem_data *dat
                       void *hip_stream, tree_factors **out);
 
 /*
- * count instances that share one tree and all its problem data and differ
- * only in the initial state x0 (given per call, [count][nx]): the factor step
- * runs once and the handle keeps one copy of the factors.  Vectors are
- * concatenated in instance order as for tree_factor_batch (instance k at k
+ * count instances that share one tree, its matrices, costs and boxes, and
+ * differ in the initial state x0 (given per call, [count][nx]) and, if c is
+ * not NULL, in the disturbances: HOST c [count][V][nx] (node 0 ignored)
+ * replaces data->c for instance k (data->c still defines the factor step).
+ * The factor step runs once and the handle keeps one copy of the matrices;
+ * with c, the affine terms of each instance are derived from the value-
+ * function Hessians of the factor step (chat_k = chat + P (c_k - c)).  Vectors
+ * are concatenated in instance order as for tree_factor_batch (instance k at k
  * times the single-tree sizes).  When count is a multiple of 64 and
- * nx + nu <= 128, every sweep (dual_grad, the solvers, dual_lipschitz) runs
- * as panels of 64 instances on the FP64 matrix cores, streaming the factors
+ * nx + nu <= 128, every sweep (dual_grad, the solvers, dual_lipschitz) runs as
+ * panels of 64 instances on the FP64 matrix cores, streaming the matrices
  * once per panel (the extra parallelism of Sec. III-C across instances).
- * Errors as tree_factor, plus ERR_ARG for count < 1.
+ * Errors as tree_factor, plus ERR_ARG for count < 1 and ERR_NUMERIC for a
+ * non-finite c.
  */
 int tree_factor_shared(const tree_desc *tree, const problem_data *data, int precondition, int count,
-                       void *hip_stream, tree_factors **out);
+                       const double *c, void *hip_stream, tree_factors **out);
 
 /* Sizes of a handle, written to HOST out[10]: instances, precondition flag,
  * total dual length, total primal length, sum V nx (x), sum V_nl nu (u),

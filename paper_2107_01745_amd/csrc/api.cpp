@@ -36,7 +36,7 @@ int tree_factor_batch(int count, const tree_desc *trees, const problem_data *dat
 }
 
 int tree_factor_shared(const tree_desc *tree, const problem_data *data, int precondition, int count,
-                       void *hip_stream, tree_factors **out)
+                       const double *c, void *hip_stream, tree_factors **out)
 {
     set_error("");
     if (count < 1) {
@@ -44,9 +44,9 @@ int tree_factor_shared(const tree_desc *tree, const problem_data *data, int prec
         set_error("tree_factor_shared: count < 1");
         return STOTREE_ERR_ARG;
     }
-    int rc = factor_forest(1, tree, data, precondition, (hipStream_t)hip_stream, out);
+    int rc = factor_forest(1, tree, data, precondition, (hipStream_t)hip_stream, out, c != nullptr);
     if (rc) return rc;
-    if ((rc = replicate_instances(*out, count))) {
+    if ((rc = replicate_instances(*out, count, c, (hipStream_t)hip_stream))) {
         free_tree(*out);
         *out = nullptr;
     }

@@ -362,7 +362,8 @@ void free_tree(tree_factors *f)
         if (cp.items) (void)hipFree(cp.items);
     for (auto &lv : f->levels) free_level(lv);
     for (auto &lv : f->panel_levels) free_level(lv);
-    for (void *p : {(void *)f->panel_chain_items, (void *)f->trunk_entry.items, (void *)f->trunk_cnt})
+    for (void *p : {(void *)f->panel_chain_items, (void *)f->trunk_entry.items, (void *)f->trunk_cnt,
+                    (void *)f->Pcal})
         if (p) (void)hipFree(p);
     delete f;
 }
@@ -525,25 +526,88 @@ int build_schedule(tree_factors *f)
     return STOTREE_OK;
 }
 
+namespace {
+
+// Affine terms of copy k with disturbances c_k (node 0 ignored): chat_k,i =
+// chat_0,i + P_i (c_k,i - c_0,i) for i >= 1 (the q / p parts are those of
+// copy 0), chat_k,0 = chat_0,0; cvec_k = c_k with node 0 zero.
+__global__ void copy_affine_kernel(const double *Pcal, const double *chat0, const double *c0, const double *ck_all,
+                                   double *chat, double *cvec, int count, int V, int nx)
+{
+    const long long per = (long long)V * nx;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)count * per;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long k = e / per, rem = e - k * per;
+        const int i = (int)(rem / nx), r = (int)(rem - (long long)i * nx);
+        const double *ck = ck_all + k * per;
+        double s = chat0[rem];
+        if (i > 0) {
+            const double *Pi = Pcal + (long long)i * nx * nx + (long long)r * nx;
+            for (int c = 0; c < nx; ++c) s = fma(Pi[c], ck[(long long)i * nx + c] - c0[(long long)i * nx + c], s);
+        }
+        chat[e] = s;
+        cvec[e] = i > 0 ? ck[rem] : 0.0;
+    }
+}
+
+}  // namespace
+
 // Turn a one-instance handle into count instances that share its tree,
 // factors and boxes (each with its own x0 and vectors, concatenated in
-// instance order).
-int replicate_instances(tree_factors *f, int count)
+// instance order; with c_host, also its own disturbances).
+int replicate_instances(tree_factors *f, int count, const double *c_host, hipStream_t st)
 {
     if (f->ninst != 1 || count < 1) { set_error("tree_factor_shared: bad instance count"); return STOTREE_ERR_ARG; }
-    if (count == 1) return STOTREE_OK;
     const InstDesc I0 = f->inst[0];
     const long long xl = (long long)I0.V * I0.nx, ul = (long long)I0.Vnl * I0.nu;
+    if (c_host) {
+        if (!f->Pcal) { set_error("tree_factor_shared: value-function Hessians were not kept"); return STOTREE_ERR_ARG; }
+        for (long long e = 0; e < (long long)count * xl; ++e)
+            if (!std::isfinite(c_host[e]) && e % xl >= I0.nx) {
+                set_error("tree_factor_shared: non-finite disturbance");
+                return STOTREE_ERR_NUMERIC;
+            }
+        double *dc = nullptr, *chat = nullptr, *cvec = nullptr;
+        struct Tmp { double *&p; ~Tmp() { if (p) (void)hipFree(p); } } tdc{dc};
+        STOTREE_HIP(hipMalloc(&dc, sizeof(double) * (size_t)(count * xl)));
+        STOTREE_HIP(hipMemcpy(dc, c_host, sizeof(double) * (size_t)(count * xl), hipMemcpyHostToDevice));
+        STOTREE_HIP(hipMalloc(&chat, sizeof(double) * (size_t)(count * xl)));
+        if (hipMalloc(&cvec, sizeof(double) * (size_t)(count * xl)) != hipSuccess) {
+            (void)hipFree(chat);
+            set_error("tree_factor_shared: out of memory");
+            return STOTREE_ERR_OOM;
+        }
+        const long long n = count * xl;
+        const unsigned g = (unsigned)std::min<long long>(65535, (n + 255) / 256);
+        hipLaunchKernelGGL(copy_affine_kernel, dim3(g), dim3(256), 0, st, f->Pcal, f->chat + I0.chat,
+                           f->cvec + I0.c, dc, chat, cvec, count, I0.V, I0.nx);
+        const hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            (void)hipFree(chat);
+            (void)hipFree(cvec);
+            set_error(std::string("tree_factor_shared: ") + hipGetErrorString(e));
+            return STOTREE_ERR_DEVICE;
+        }
+        (void)hipFree(f->chat);
+        (void)hipFree(f->cvec);
+        f->chat = chat;
+        f->cvec = cvec;
+        f->bytes += (size_t)(count - 1) * xl * 2 * sizeof(double);
+    }
+    if (f->Pcal) { (void)hipFree(f->Pcal); f->Pcal = nullptr; }
+    if (count == 1 && !c_host) return STOTREE_OK;
     f->inst.assign(count, I0);
     for (int k = 0; k < count; ++k) {
         InstDesc &I = f->inst[k];
         I.y = k * I0.m; I.x = k * xl; I.u = k * ul; I.x0 = (long long)k * I0.nx; I.box = 0;
         I.node0 = (long long)k * I0.V;
+        if (c_host) { I.chat = k * xl; I.c = k * xl; }
     }
     f->ninst = count;
     f->shared = count;
-    f->m_tot *= count; f->n_tot *= count; f->x_tot *= count; f->u_tot *= count; f->nx_tot *= count;
-    f->V_tot *= count;
+    f->m_tot = count * I0.m; f->n_tot *= count; f->x_tot = count * xl; f->u_tot = count * ul;
+    f->nx_tot = (long long)count * I0.nx;
+    f->V_tot = (long long)count * I0.V;
     if (f->trunk_cnt) { (void)hipFree(f->trunk_cnt); f->trunk_cnt = nullptr; }
     if (f->d_inst) (void)hipFree(f->d_inst);
     f->d_inst = nullptr;
@@ -554,7 +618,7 @@ int replicate_instances(tree_factors *f, int count)
 }
 
 int factor_forest(int count, const tree_desc *trees, const problem_data *datas, int precondition,
-                  hipStream_t st, tree_factors **out)
+                  hipStream_t st, tree_factors **out, bool keep_pcal)
 {
     if (!out) { set_error("tree_factor: out is NULL"); return STOTREE_ERR_ARG; }
     *out = nullptr;
@@ -747,6 +811,10 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
         return err;
     }
     if ((rc = build_schedule(f))) return rc;
+    if (keep_pcal) {
+        f->Pcal = (double *)bPcal.p;
+        bPcal.p = nullptr;
+    }
     f->last_info.assign(count, solver_info{});
     guard.ok = true;
     *out = f;

@@ -60,6 +60,7 @@ struct SweepArgs {
     int dual_out;                    // 1: write H x into the dual layout at xo; 0: x at xo, u at uo
     int affine;
     int t;                           // stage of a per-stage launch
+    long long chat_rs, c_rs;         // panel sweeps: chat / c stride between right-hand sides
     const int *done; int done_stride;       // per-instance skip flags (may be null)
 };
 
@@ -112,6 +113,7 @@ struct tree_factors {
     double *Mb = nullptr, *Mf = nullptr, *Kb = nullptr, *Kf = nullptr, *Rn = nullptr;
     double *chat = nullptr, *sig = nullptr, *cvec = nullptr, *sc = nullptr;
     double *lo = nullptr, *hi = nullptr;    // unscaled box rows in the dual layout
+    double *Pcal = nullptr;                 // value-function Hessians [V][nx][nx] (kept only on request)
     long long m_tot = 0, n_tot = 0, x_tot = 0, u_tot = 0, nx_tot = 0, V_tot = 0;
     int max_width = 0;                      // max nx+nu over instances
     // schedule of a sweep
@@ -146,8 +148,10 @@ void set_error(const std::string &msg);
 
 // factor.hip
 int factor_forest(int count, const tree_desc *t, const problem_data *d, int precondition,
-                  hipStream_t st, tree_factors **out);
-int replicate_instances(tree_factors *f, int count);
+                  hipStream_t st, tree_factors **out, bool keep_pcal = false);
+// count copies of instance 0; c_host [count][V][nx] (or null): per-copy
+// disturbances, whose affine terms are derived from the kept P_i.
+int replicate_instances(tree_factors *f, int count, const double *c_host, hipStream_t st);
 void free_tree(tree_factors *f);
 int build_schedule(tree_factors *f);
 int chain_group(int ldM, int group_min);  // lanes per chain for padded width ldM

@@ -148,7 +148,9 @@ __device__ __forceinline__ void stage(double *V, int r0, int n, Src src)
 // Backward step of non-leaf node i (Algorithm 3 / 4 body) for the panel.  On
 // entry, if child_in_lds, rows [0, nx) of V hold qhat of the single child; on
 // exit they hold qhat_i.  k_i goes to kbuf; qhat_i to the global buffer if
-// store_q.
+// store_q.  After the first product the panel rows are reused: [0, nx) take
+// sum A'qhat + s_i y^x + chat_i (completed to qhat_i after the second
+// product, each lane on its own entries), [nx, nx + nu) take g_i.
 template <int TPW>
 __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double *V, bool child_in_lds,
                            bool store_q, int wave, int lane)
@@ -164,7 +166,8 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
             if (j >= I.Vnl) {
                 const double sj = a.sc ? a.sc[I.sc + j] : 1.0;
                 const double *ch = a.affine ? a.chat + I.chat + (long long)j * nx : nullptr;
-                stage(V, 0, nx, [&](int k, int r) { return sj * y_ptr(a, I, k, j)[r] + (ch ? ch[r] : 0.0); });
+                stage(V, 0, nx,
+                      [&](int k, int r) { return sj * y_ptr(a, I, k, j)[r] + (ch ? ch[k * a.chat_rs + r] : 0.0); });
             } else {
                 stage(V, 0, nx, [&](int k, int r) { return qhat_ptr(a, I, k, j)[r]; });
             }
@@ -175,8 +178,10 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
         product(p, tk, nx, V, S, wave, lane);
         __syncthreads();   // every wavefront is done with the child panel
     }
-    // g = [sum B'qhat] + s_i y^u + pi r  ->  panel rows [nx, nx + nu)
+    // rows [0, nx): sum A'qhat + s_i y^x + chat_i; rows [nx, nx + nu): g = sum B'qhat + s_i y^u + pi r
     const double si = a.sc ? a.sc[I.sc + i] : 1.0;
+    const double *ch = a.affine ? a.chat + I.chat + (long long)i * nx : nullptr;
+    const double *sg = a.affine ? a.sig + I.sig + (long long)i * nu : nullptr;
 #pragma unroll
     for (int s = 0; s < TPW; ++s)
 #pragma unroll
@@ -184,10 +189,13 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const Slot o = slot(tk, ncols, s, h, e, wave, lane);
-                if (o.valid && o.part == 1)
-                    V[(nx + o.row) * kLdv + o.rhs] =
-                        S[s][h][e] + si * y_ptr(a, I, o.rhs, i)[nx + o.row] +
-                        (a.affine ? a.sig[I.sig + (long long)i * nu + o.row] : 0.0);
+                if (!o.valid) continue;
+                const double *yi = y_ptr(a, I, o.rhs, i);
+                if (o.part == 1)
+                    V[(nx + o.row) * kLdv + o.rhs] = S[s][h][e] + si * yi[nx + o.row] + (sg ? sg[o.row] : 0.0);
+                else
+                    V[o.row * kLdv + o.rhs] =
+                        S[s][h][e] + si * yi[o.row] + (ch ? ch[o.rhs * a.chat_rs + o.row] : 0.0);
             }
     __syncthreads();
     // [K' g ; -R~^{-1} g]
@@ -198,7 +206,7 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
                            {a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu}};
         product(p, tk, nu, V + nx * kLdv, T, wave, lane);
     }
-    const double *ch = a.affine ? a.chat + I.chat + (long long)i * nx : nullptr;
+    // each lane completes its own entries of rows [0, nx); the g rows are not written
 #pragma unroll
     for (int s = 0; s < TPW; ++s)
 #pragma unroll
@@ -210,21 +218,10 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
                 if (o.part == 1) {
                     kbuf_ptr(a, I, o.rhs, i)[o.row] = T[s][h][e];
                 } else {
-                    const double q = S[s][h][e] + T[s][h][e] + si * y_ptr(a, I, o.rhs, i)[o.row] +
-                                     (ch ? ch[o.row] : 0.0);
-                    S[s][h][e] = q;
+                    const double q = V[o.row * kLdv + o.rhs] + T[s][h][e];
+                    V[o.row * kLdv + o.rhs] = q;
                     if (store_q) qhat_ptr(a, I, o.rhs, i)[o.row] = q;
                 }
-            }
-    __syncthreads();   // every wavefront has read g and the old qhat rows
-#pragma unroll
-    for (int s = 0; s < TPW; ++s)
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const Slot o = slot(tk, ncols, s, h, e, wave, lane);
-                if (o.valid && o.part == 0) V[o.row * kLdv + o.rhs] = S[s][h][e];
             }
     __syncthreads();
 }
@@ -274,7 +271,7 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
                 for (int e = 0; e < 4; ++e) {
                     const Slot o = slot(tk, ncols, s, h, e, wave, lane);
                     if (!o.valid) continue;
-                    const double xv = X[s][h][e] + (cj ? cj[o.row] : 0.0);
+                    const double xv = X[s][h][e] + (cj ? cj[o.rhs * a.c_rs + o.row] : 0.0);
                     X[s][h][e] = xv;
                     x_ptr(a, I, o.rhs, j)[o.row] = xv;
                 }
@@ -439,6 +436,8 @@ hipError_t launch_sweep_any(const tree_factors *f, const SweepArgs &a, int nrhs,
             p.uo_rs = I1.u - I0.u;
             p.qhat_rs = I1.x - I0.x;
             p.kbuf_rs = I1.u - I0.u;
+            p.chat_rs = I1.chat - I0.chat;   // 0 unless the copies have their own disturbances
+            p.c_rs = I1.c - I0.c;
             const hipError_t e = launch_panel_sweep(f, p, st);
             if (e != hipSuccess) return e;
         }

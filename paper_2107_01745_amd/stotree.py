@@ -81,8 +81,8 @@ def lib():
         L.tree_factor_batch.argtypes = [C.c_int, C.POINTER(TreeDesc), C.POINTER(ProblemData), C.c_int,
                                         vp, C.POINTER(vp)]
         L.tree_factor_batch.restype = C.c_int
-        L.tree_factor_shared.argtypes = [C.POINTER(TreeDesc), C.POINTER(ProblemData), C.c_int, C.c_int, vp,
-                                         C.POINTER(vp)]
+        L.tree_factor_shared.argtypes = [C.POINTER(TreeDesc), C.POINTER(ProblemData), C.c_int, C.c_int, _dp,
+                                         vp, C.POINTER(vp)]
         L.tree_factor_shared.restype = C.c_int
         L.tree_instance_dims.argtypes = [vp, C.c_int, C.POINTER(C.c_int64)]
         L.tree_instance_dims.restype = C.c_int
@@ -215,13 +215,19 @@ def tree_factor(prob, precondition: bool = True, stream=None) -> TreeFactors:
     return TreeFactors(h)
 
 
-def tree_factor_shared(prob, count: int, precondition: bool = True, stream=None) -> TreeFactors:
-    """Factor step once for ``count`` instances sharing prob's tree and data
-    (they differ only in x0, given per call)."""
+def tree_factor_shared(prob, count: int, precondition: bool = True, c=None, stream=None) -> TreeFactors:
+    """Factor step once for ``count`` instances sharing prob's tree and data;
+    they differ in x0 (given per call) and, with ``c`` ([count][V][nx] host
+    array), in the disturbances."""
     keep = []
     td, pd = _descs(prob, keep)
+    cp = None
+    if c is not None:
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        assert c.shape == (count, prob.tree.V, prob.nx), c.shape
+        cp = c.ctypes.data_as(_dp)
     h = C.c_void_p()
-    _check(lib().tree_factor_shared(C.byref(td), C.byref(pd), int(bool(precondition)), int(count),
+    _check(lib().tree_factor_shared(C.byref(td), C.byref(pd), int(bool(precondition)), int(count), cp,
                                     _stream(stream), C.byref(h)))
     return TreeFactors(h)
 

@@ -110,3 +110,9 @@ def test_schedule_graph_calls_reject_null_on_host(st):
     assert out.value is None            # *out cleared on failure
     L.sweep_graph_free(None)            # no-op
     assert "NULL" in st.stotree_last_error()
+
+
+def test_shared_handle_rejects_bad_count_on_host(st):
+    with pytest.raises(st.StotreeError) as ei:
+        st.tree_factor_shared(base(), 0)
+    assert ei.value.code == -1 and "count" in str(ei.value)

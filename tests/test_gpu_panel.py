@@ -141,3 +141,60 @@ def test_shared_handle_solves_match_oracle(st, method):
         s = max(1.0, np.abs(ref["x"]).max())
         assert np.abs(xb - ref["x"]).max() / s < 1e-6 and np.abs(ub - ref["u"]).max() / s < 1e-6, k
     tf.free()
+
+
+@pytest.mark.parametrize("count", [64, 3])
+def test_shared_handle_with_own_disturbances(st, count):
+    """Copies that differ in x0 and in the disturbances c (affine terms from
+    the kept value-function Hessians) against each copy factored on its own."""
+    import dataclasses
+    base = _shared_base() if count == 64 else case("odd_ragged")
+    draws = treegen.draw_warm_instances(base, count, seed=30 + count)
+    C = np.stack([p.c for p in draws])
+    tf = st.tree_factor_shared(base, count, precondition=True, c=C)
+    rng = np.random.default_rng(count + 1)
+    Y = rng.standard_normal(tf.m)
+    X0 = np.stack([p.x0 for p in draws])
+    for homogeneous in (False, True):
+        xs, us = _many(st, tf, _t(X0.ravel()), _t(Y), homogeneous, 1)
+        for k in (0, 1, count // 2, count - 1):
+            d = tf.instances[k]
+            tf1 = st.tree_factor(draws[k], precondition=True)
+            x1, u1 = _many(st, tf1, _t(X0[k]), _t(Y[d["y_off"]:d["y_off"] + d["m"]]), homogeneous, 1)
+            tf1.free()
+            s = max(1.0, np.abs(x1).max())
+            assert np.abs(xs[0][d["x_off"]:d["x_off"] + d["V"] * d["nx"]] - x1[0]).max() <= 1e-11 * s, k
+            assert np.abs(us[0][d["u_off"]:d["u_off"] + d["Vnl"] * d["nu"]] - u1[0]).max() <= 1e-11 * s, k
+    tf.free()
+
+
+def test_shared_handle_with_own_disturbances_solves(st):
+    """64 copies with their own x0 and c solved together (panels) against the
+    oracle solution of each copy."""
+    import torch
+    base = _shared_base()
+    draws = treegen.draw_warm_instances(base, 64, seed=77, x0_range=1.5)
+    pb, fac = oracle.factor(base)
+    lam = 1.0 / (1.1 * oracle.power_iteration(pb, fac, True, 300))
+    tf = st.tree_factor_shared(base, 64, precondition=True, c=np.stack([p.c for p in draws]))
+    y = _t(np.zeros(tf.m))
+    x = torch.zeros(tf.x_len, dtype=torch.float64, device="cuda:0")
+    u = torch.zeros(tf.u_len, dtype=torch.float64, device="cuda:0")
+    rc, agg = st.nama_solve(tf, _t(np.concatenate([p.x0 for p in draws])), y, x, u,
+                            st.make_opts(lam=lam, eps=1e-8, max_iter=3000))
+    infos = st.solve_info_batch(tf)
+    xh = x.cpu().numpy()
+    checked = 0
+    for k in (0, 9, 40, 63):
+        pk, fk = oracle.factor(draws[k])
+        ref = oracle.solve(pk, fk, "nama", lam, eps=1e-10, max_iter=5000)
+        if ref["status"] != 0:
+            continue          # a draw without a feasible point: nothing to compare
+        assert infos[k]["status"] == 0 and infos[k]["res_scaled_inf"] <= 1e-8, infos[k]
+        d = tf.instances[k]
+        xb = xh[d["x_off"]:d["x_off"] + d["V"] * d["nx"]].reshape(d["V"], d["nx"])
+        s = max(1.0, np.abs(ref["x"]).max())
+        assert np.abs(xb - ref["x"]).max() / s < 1e-6, k
+        checked += 1
+    assert checked >= 3
+    tf.free()
