@@ -374,6 +374,9 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     torch.cuda.empty_cache()
     log(f"config 4 solve: lambda {lam:.4g}; cold per-instance {solo_s / n_solo:.2f} s, iters {solo_it}")
     tfs = stotree.tree_factor_shared(prob, 64, precondition=True)
+    t0 = time.perf_counter()
+    tune = stotree.sweep_autotune(tfs, nrhs=1, reps=1)
+    log(f"config 4 solve: schedule {tune['knobs']} tuned in {time.perf_counter() - t0:.1f} s")
     model = ws.WarmStartMLP(nx, prob.nu, prob.tree.N, dh=128, seed=0)
     Xs, Ts, Ms = [], [], []
     gen_s, gen_it = 0.0, []
@@ -425,7 +428,7 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     torch.cuda.empty_cache()
     solo_total = solo_s / n_solo * 64
     rep = {"workload": "config 4 with |u| <= %g: 64 instances sharing the tree, x0 ~ U[-3,3]" % ubox,
-           "lambda": lam, "mem": mem, "training_solves": n_batches * 64, "training_rows": int(keep_rows * n_batches),
+           "lambda": lam, "mem": mem, "schedule": tune["knobs"], "training_solves": n_batches * 64, "training_rows": int(keep_rows * n_batches),
            "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]], "training_generation_s": gen_s,
            "train_s": train_s,
            "cold_per_instance": {"sample": n_solo, "iters": solo_it, "s_per_instance": solo_s / n_solo,
@@ -459,14 +462,22 @@ def guarded(name, fn, *a):
     return err
 
 
-def shared_handle(stotree, base, chunk):
+def shared_handle(stotree, base, chunk, tune):
     """One handle for draws of one tree that differ in x0 and c: the matrices
-    are factored once and the draws are swept together (64 at a time on the
-    matrix cores)."""
-    return stotree.tree_factor_shared(base, len(chunk), precondition=True, c=np.stack([p.c for p in chunk]))
+    are factored once and the draws are swept together, 64 at a time on the
+    matrix cores or on lane groups, whichever the autotuner finds faster for
+    the number of draws still unfinished (tune: the schedule record of an
+    earlier handle of the same tree, reused)."""
+    tf = stotree.tree_factor_shared(base, len(chunk), precondition=True, c=np.stack([p.c for p in chunk]))
+    if tune.get("knobs"):
+        stotree.sweep_schedule(tf, tune["knobs"])
+    else:
+        tune.update(stotree.sweep_autotune(tf, nrhs=1, reps=3))
+        log(f"shared-handle schedule {tune['knobs']} ({tune['ms']:.3f} ms per sweep)")
+    return tf
 
 
-def screen_feasible(stotree, ws, base, probs, lam, batch, max_iter=400):
+def screen_feasible(stotree, ws, base, probs, lam, batch, tune, max_iter=400):
     """The draws whose problem has a solution the solver reaches: a cold
     batched NAMA solve converges to 1e-6 within max_iter iterations (with
     tight input boxes some draws of x0 have no feasible point, and their duals
@@ -474,7 +485,7 @@ def screen_feasible(stotree, ws, base, probs, lam, batch, max_iter=400):
     ok = []
     for s in range(0, len(probs), batch):
         chunk = probs[s:s + batch]
-        tf = shared_handle(stotree, base, chunk)
+        tf = shared_handle(stotree, base, chunk, tune)
         _, _, infos, _ = ws.solve_batch(chunk, lam, eps=1e-6, max_iter=max_iter, tf=tf)
         ok += [p for p, i in zip(chunk, infos) if i["status"] == 0]
         tf.free()
@@ -498,11 +509,12 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     model = ws.WarmStartMLP(base.nx, base.nu, base.tree.N, dh=128, seed=0)
     train = treegen.draw_warm_instances(base, n_train, seed=2003)
     Xs, Ts, Ms = [], [], []
+    tune = {}
     t0 = time.perf_counter()
     gen_iters, gen_ok = [], 0
     for s in range(0, n_train, batch):
         chunk = train[s:s + batch]
-        tf = shared_handle(stotree, base, chunk)
+        tf = shared_handle(stotree, base, chunk, tune)
         _, y, infos, _ = ws.solve_batch(chunk, lam, eps=1e-6, max_iter=400, tf=tf)
         conv = [int(i["status"] == 0) for i in infos]
         stotree.dual_select(tf, y, conv)          # unsolved draws: zero rows, masked below
@@ -535,13 +547,13 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     log(f"warm leg: {epochs} epochs in {train_s:.1f} s, masked MSE {hist[0]:.3e} -> {hist[-1]:.3e}")
     del X, T, M
     drawn = treegen.draw_warm_instances(base, n_test + n_test // 4, seed=2004)
-    test = screen_feasible(stotree, ws, base, drawn, lam, batch)
+    test = screen_feasible(stotree, ws, base, drawn, lam, batch, tune)
     n_test = min(n_test, len(test) // batch * batch)    # whole 64-draw panels
     test = test[:n_test]
     cold_b, warm_b, it_c, it_w, kept, ok_w = 0.0, 0.0, [], [], 0, 0
     for s in range(0, n_test, batch):
         chunk = test[s:s + batch]
-        tf = shared_handle(stotree, base, chunk)
+        tf = shared_handle(stotree, base, chunk, tune)
         _, _, info_c, sec_c = ws.solve_batch(chunk, lam, eps=1e-6, tf=tf)
         cold_b += sec_c
         it_c += [i["iters"] for i in info_c]
@@ -566,7 +578,7 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     solo_total = solo_s / max(1, n_solo) * n_test
     rep = {"tree": "config 3 (2794 nodes), |u| <= 0.2", "lambda": lam, "n_train": n_train,
            "n_train_solved": int(gen_ok), "n_test_drawn": len(drawn), "n_test_feasible": n_test,
-           "batch": batch, "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]],
+           "batch": batch, "schedule": tune.get("knobs"), "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]],
            "y_scale": model.y_scale, "data_generation_s": gen_s, "train_s": train_s,
            "iters_cold_mean": float(np.mean(it_c)), "iters_warm_mean": float(np.mean(it_w)),
            "iters_cold_batched_same_sample": float(np.mean(it_c[:n_solo])),

@@ -191,7 +191,7 @@ int dual_grad(const tree_factors *f, const double *x0, const double *y, int homo
 
 /*
  * Sweep schedule of a handle: how the stage-parallel sweeps of Sec. III-D
- * (Algorithms 3 and 4) are cut into GPU work.  HOST knobs[4]:
+ * (Algorithms 3 and 4) are cut into GPU work.  HOST knobs[5]:
  *   knobs[0] smallest lane group walking one chain below s*: 8, 16, 32 or 64
  *            lanes (an instance's chains use the smallest power of two G at
  *            least this with 2G >= nx + nu, at most 64); default 8;
@@ -203,9 +203,16 @@ int dual_grad(const tree_factors *f, const double *x0, const double *y, int homo
  *            (default); 1 the backward stages in one launch in which each
  *            node is taken up by the workgroup that finishes its last child;
  *            2 one launch per stage, the nodes of instances with nx + nu <= 64
- *            walked by lane groups as the chains are.
- * knobs[1] changes no result bit; knobs[0], knobs[2] and knobs[3] change the
- * order of some per-node sums (equal to rounding).
+ *            walked by lane groups as the chains are;
+ *   knobs[4] shared handles whose copies form whole panels of 64: the fewest
+ *            unfinished copies for which a sweep runs as panels on the
+ *            matrix cores (a panel whose copies have all finished is
+ *            skipped); below it the solvers' sweeps take the lane-group
+ *            route, which skips each finished copy.  0 .. 2^24 (any value
+ *            above the copy count: never panels); default 16.  dual_grad
+ *            counts every copy as unfinished.
+ * knobs[1] changes no result bit; knobs[0], knobs[2], knobs[3] and knobs[4]
+ * change the order of some per-node sums (equal to rounding).
  * sweep_schedule rebuilds the work lists (synchronous; ERR_ARG for values
  * outside these sets, ERR_OOM, ERR_DEVICE); sweep_schedule_get reads them.
  * A schedule change invalidates the handle's sweep graphs.
@@ -217,10 +224,15 @@ int sweep_schedule_get(const tree_factors *f, int32_t *knobs);
  * Autotuner: times homogeneous sweeps (Algorithm 4 streams the same data as
  * Algorithm 3) of nrhs in {1, 2} right-hand sides on zero duals, one untimed
  * and reps timed sweeps per candidate, over each knob in turn (coordinate
- * descent from the current schedule) and keeps the fastest.  HOST
- * knobs_out[3] and ms_out (milliseconds per sweep of the kept schedule) may
- * be NULL (knobs_out has 4 entries).  Allocates and frees its own scratch;
- * synchronous.  Errors: ERR_ARG, ERR_OOM, ERR_DEVICE.
+ * descent from the current schedule) and keeps the fastest.  On a shared
+ * handle swept as panels it tunes knobs[0..3] on the lane-group route, then
+ * times one panel sweep of all copies and sets knobs[4] where the two costs
+ * meet, the lane-group cost taken as proportional to the unfinished copies
+ * (copy count + 1 when the lane groups are faster even for all of them);
+ * elsewhere knobs[4] is left as it is.  HOST knobs_out[5] and ms_out
+ * (milliseconds per sweep of the kept schedule, all copies) may be NULL.
+ * Allocates and frees its own scratch; synchronous.  Errors: ERR_ARG,
+ * ERR_OOM, ERR_DEVICE.
  */
 int sweep_autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms_out,
                    void *hip_stream);

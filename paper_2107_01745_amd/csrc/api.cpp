@@ -98,6 +98,7 @@ int sweep_schedule_get(const tree_factors *f, int32_t *knobs)
 {
     if (!f || !knobs) { set_error("sweep_schedule_get: NULL argument"); return STOTREE_ERR_ARG; }
     knobs[0] = f->group_min; knobs[1] = f->chain_order; knobs[2] = f->trunk_cap; knobs[3] = f->trunk_fused;
+    knobs[4] = f->panel_min;
     return STOTREE_OK;
 }
 

@@ -62,6 +62,7 @@ struct SweepArgs {
     int t;                           // stage of a per-stage launch
     long long chat_rs, c_rs;         // panel sweeps: chat / c stride between right-hand sides
     const int *done; int done_stride;       // per-instance skip flags (may be null)
+    int panel_done;                  // 1: done holds the flags of one shared panel's kRhsPanel copies
 };
 
 // One launch of the chain kernels: the chains of every instance that uses
@@ -131,6 +132,7 @@ struct tree_factors {
     int group_min = 8;                      // smallest lane group used for chains
     int trunk_fused = 0;                    // stages above s*: 0 per-stage launches, 1 one backward
                                             // launch, 2 per-stage launches with lane groups
+    int panel_min = 16;                     // shared handles: fewest unfinished copies swept as panels
     stotree::LevelPlan trunk_entry{};       // nodes of stage s*-1 of every instance
     int *trunk_cnt = nullptr;               // per node (node0-indexed): children finished
     long long schedule_epoch = 0;           // bumped whenever the work lists are rebuilt
@@ -165,9 +167,11 @@ int ensure_sweep_ws(tree_factors *f, int nrhs);
 int panel_tpw(const tree_factors *f);
 hipError_t launch_panel_sweep(const tree_factors *f, const SweepArgs &a, hipStream_t st);
 // Any sweep of nrhs in {1,2} right-hand sides over every instance: on a
-// shared handle, panels of kRhsPanel instances; otherwise launch_sweep_tree.
+// shared handle with at least panel_min of its copies unfinished (active;
+// negative: all), panels of kRhsPanel copies; otherwise launch_sweep_tree.
 bool shared_panels(const tree_factors *f);
-hipError_t launch_sweep_any(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st);
+bool panel_route(const tree_factors *f, int active);
+hipError_t launch_sweep_any(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st, int active = -1);
 hipError_t launch_sweep_tree(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st);
 int timing_enable(int on);
 bool timing_on();
@@ -177,7 +181,7 @@ int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int ho
                       double *u, hipStream_t st);
 
 // schedule.hip
-constexpr int kKnobs = 4;            // group_min, chain_order, trunk_cap, trunk_fused
+constexpr int kKnobs = 5;            // group_min, chain_order, trunk_cap, trunk_fused, panel_min
 int set_schedule(tree_factors *f, const int32_t *knobs);
 int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms_out, hipStream_t st);
 int graph_create(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,

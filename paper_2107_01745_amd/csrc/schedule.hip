@@ -5,10 +5,18 @@
 // the per-node sums above s*):
 //   group_min   smallest lane group that walks one chain below s*;
 //   chain_order costliest wavefront items first, or instance order;
-//   trunk_cap   cap on the wavefronts that share one node above s*.
+//   trunk_cap   cap on the wavefronts that share one node above s*;
+//   trunk_fused the launch form of the stages above s*;
+//   panel_min   on a shared handle, the fewest unfinished copies that are
+//               still swept as panels on the matrix cores (fewer: the
+//               lane-group sweeps, which skip finished copies one by one).
 // The autotuner times homogeneous sweeps (Algorithm 4) on zero duals, which
 // stream exactly the data of a dual-gradient sweep, for each candidate of
 // one knob at a time (coordinate descent), and keeps the fastest schedule.
+// On a shared handle it tunes the lane-group route first, then times one
+// panel sweep of all copies against it and sets panel_min where the two
+// costs meet (the lane-group cost taken as proportional to the copies swept).
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -25,13 +33,16 @@ namespace stotree {
 
 namespace {
 
+constexpr int kPanelMinMax = 1 << 24;
+
 bool valid_knobs(const int32_t *k)
 {
     const bool g = k[0] == 8 || k[0] == 16 || k[0] == 32 || k[0] == 64;
     const bool o = k[1] == 0 || k[1] == 1;
     const bool t = k[2] == 1 || k[2] == 2 || k[2] == 4 || k[2] == 8 || k[2] == 16;
     const bool m = k[3] == 0 || k[3] == 1 || k[3] == 2;
-    return g && o && t && m;
+    const bool p = k[4] >= 0 && k[4] <= kPanelMinMax;
+    return g && o && t && m && p;
 }
 
 // Lane-group width of every instance under group_min g (equal vectors give
@@ -49,7 +60,7 @@ int set_schedule(tree_factors *f, const int32_t *knobs)
 {
     if (!valid_knobs(knobs)) {
         set_error("sweep_schedule: knobs must be group in {8,16,32,64}, order in {0,1}, cap in {1,2,4,8,16}, "
-                  "trunk mode in {0,1,2}");
+                  "trunk mode in {0,1,2}, panel minimum in [0, 2^24]");
         return STOTREE_ERR_ARG;
     }
     // the old work lists may still be read by queued sweeps
@@ -58,6 +69,7 @@ int set_schedule(tree_factors *f, const int32_t *knobs)
     f->chain_order = knobs[1];
     f->trunk_cap = knobs[2];
     f->trunk_fused = knobs[3];
+    f->panel_min = knobs[4];
     ++f->schedule_epoch;
     return build_schedule(f);
 }
@@ -101,17 +113,19 @@ int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms
         *ms = t / reps;
         return STOTREE_OK;
     };
-    int32_t best[kKnobs] = {f->group_min, f->chain_order, f->trunk_cap, f->trunk_fused};
+    int32_t best[kKnobs] = {f->group_min, f->chain_order, f->trunk_cap, f->trunk_fused, f->panel_min};
+    const bool shared = shared_panels(f);
+    if (shared) best[4] = kPanelMinMax;    // lane-group route while its knobs are tuned
     double best_ms = 0.0;
     rc = measure(best, &best_ms);
     const std::vector<std::vector<int>> values = {{8, 16, 32, 64}, {1, 0}, {16, 8, 4, 2}, {0, 2, 1}};
-    for (int knob = 0; knob < kKnobs && !rc; ++knob) {
+    for (int knob = 0; knob < kKnobs - 1 && !rc; ++knob) {
         const int32_t start = best[knob];
         for (int v : values[knob]) {
             if (rc) break;
             if (v == start) continue;
             if (knob == 0 && groups_of(f, v) == groups_of(f, best[0])) continue;
-            int32_t cand[kKnobs] = {best[0], best[1], best[2], best[3]};
+            int32_t cand[kKnobs] = {best[0], best[1], best[2], best[3], best[4]};
             cand[knob] = v;
             double ms = 0.0;
             rc = measure(cand, &ms);
@@ -119,6 +133,18 @@ int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms
                 best_ms = ms;
                 best[knob] = v;
             }
+        }
+    }
+    if (shared && !rc) {
+        int32_t cand[kKnobs] = {best[0], best[1], best[2], best[3], 0};
+        double ms = 0.0;
+        rc = measure(cand, &ms);
+        if (!rc) {
+            // panels cost ms while any copy is unfinished; the lane groups
+            // best_ms * active / ninst
+            const double meet = ms < best_ms ? std::ceil(f->ninst * ms / best_ms) : f->ninst + 1.0;
+            best[4] = (int32_t)(meet < 1.0 ? 1.0 : meet);
+            if (ms < best_ms) best_ms = ms;
         }
     }
     timing_enable(timing_was ? 1 : 0);

@@ -618,7 +618,7 @@ SweepArgs dual_layout_sweep(const tree_factors *f, int affine, const double *x0,
 
 template <int MEMCAP>
 hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *ybuf[2], int k, int method,
-                             hipStream_t st)
+                             int active, hipStream_t st)
 {
     const SolverWS &w = f->sws;
     VecArgs a = vec_args(f);
@@ -631,7 +631,7 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
     double *hr = w.hr2, *hd = w.hr2 + f->m_tot;
     hipError_t e;
     // x(y) -> H x
-    if ((e = launch_sweep_any(f, dual_layout_sweep(f, 1, x0, y, 0, w.hx, 0, ctl), 1, st))) return e;
+    if ((e = launch_sweep_any(f, dual_layout_sweep(f, 1, x0, y, 0, w.hx, 0, ctl), 1, st, active))) return e;
     a.y = y; a.yp = yn; a.hx = w.hx; a.rp = rp; a.r = r;
     a.S = w.S; a.Q = w.Qv;
     if (method == 1) {
@@ -642,13 +642,15 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
         cb.r = w.d;         // output direction
         hipLaunchKernelGGL((combine_kernel<MEMCAP>), grid, blk, 0, st, cb);
         // x-hat(r) and x-hat(d) in one two-right-hand-side sweep (p-NAMA)
-        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, r, w.d - r, hr, hd - hr, ctl), 2, st)))
+        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, r, w.d - r, hr, hd - hr, ctl), 2, st,
+                                  active)))
             return e;
     } else {
         hipLaunchKernelGGL((resid_kernel<false, 0>), grid, blk, 0, st, a);
         hipLaunchKernelGGL(fin_resid_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, 0, a.ndone);
         // grad phi = R + lambda s H xhat(s R)
-        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, r, 0, hr, 0, ctl), 1, st))) return e;
+        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, r, 0, hr, 0, ctl), 1, st, active)))
+            return e;
         VecArgs ga = a;
         ga.hr = hr; ga.g = g; ga.gp = gp;
         hipLaunchKernelGGL((grad_kernel<MEMCAP>), grid, blk, 0, st, ga);
@@ -656,7 +658,8 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
         VecArgs cb = a;
         cb.g = g; cb.r = w.d;
         hipLaunchKernelGGL((combine_kernel<MEMCAP>), grid, blk, 0, st, cb);
-        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, w.d, 0, hd, 0, ctl), 1, st))) return e;
+        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, w.d, 0, hd, 0, ctl), 1, st, active)))
+            return e;
     }
     VecArgs la = vec_args(f);
     la.method = method;
@@ -667,7 +670,7 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
     return hipGetLastError();
 }
 
-using IterFn = hipError_t (*)(const tree_factors *, const double *, double *[2], int, int, hipStream_t);
+using IterFn = hipError_t (*)(const tree_factors *, const double *, double *[2], int, int, int, hipStream_t);
 
 IterFn pick_iter(int mem)
 {
@@ -773,8 +776,10 @@ int solve(const tree_factors *fc, const double *x0, const solver_opts *opts_in, 
     IterFn iter = pick_iter(o.mem);
     int k = 0, ndone = 0;
     while (ndone < f->ninst && k <= o.max_iter) {
+        // instances finished by the last check are skipped by the sweeps (the
+        // count may lag behind by check_every iterations; it only grows)
         for (int c = 0; c < o.check_every && k <= o.max_iter; ++c, ++k) {
-            hipError_t e = iter(f, x0, ybuf, k, method, st);
+            hipError_t e = iter(f, x0, ybuf, k, method, f->ninst - ndone, st);
             if (e != hipSuccess) { set_error(std::string("solve: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
         }
         STOTREE_HIP(hipMemcpyAsync(&ndone, w.ndone, sizeof(int), hipMemcpyDeviceToHost, st));

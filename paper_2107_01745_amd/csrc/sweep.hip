@@ -1041,7 +1041,7 @@ int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int ho
                       double *u, hipStream_t st)
 {
     // shared handle: each right-hand side covers all instances in panels
-    if (shared_panels(f)) {
+    if (panel_route(f, f->ninst)) {
         int rc = ensure_sweep_ws(f, 1);
         if (rc) return rc;
         SweepArgs a = sweep_args(f, homogeneous ? 0 : 1);
@@ -1051,7 +1051,7 @@ int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int ho
             a.y = y + (long long)k * f->m_tot;
             a.xo = x + (long long)k * f->x_tot;
             a.uo = u + (long long)k * f->u_tot;
-            const hipError_t e = launch_sweep_any(f, a, 1, st);
+            const hipError_t e = launch_sweep_any(f, a, 1, st, f->ninst);
             if (e != hipSuccess) {
                 set_error(std::string("dual_grad: ") + hipGetErrorString(e));
                 return STOTREE_ERR_DEVICE;
@@ -1059,8 +1059,9 @@ int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int ho
         }
         return STOTREE_OK;
     }
-    // panels of kRhsPanel right-hand sides on the matrix cores, the rest in pairs
-    const bool panel = nrhs >= kRhsPanel && panel_tpw(f) > 0;
+    // panels of kRhsPanel right-hand sides on the matrix cores, the rest in
+    // pairs (a shared handle's panel work lists hold instance 0's nodes only)
+    const bool panel = nrhs >= kRhsPanel && panel_tpw(f) > 0 && f->shared <= 1;
     const int npanel = panel ? nrhs / kRhsPanel * kRhsPanel : 0;
     int rc = ensure_sweep_ws(f, panel ? kRhsPanel : (nrhs >= 2 ? 2 : 1));
     if (rc) return rc;

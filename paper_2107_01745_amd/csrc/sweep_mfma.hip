@@ -305,12 +305,22 @@ __device__ void load_x64(const SweepArgs &a, const InstDesc &I, int i, double *V
     __syncthreads();
 }
 
+// A workgroup leaves at once when its instance has finished or, on a shared
+// panel, when every copy of the panel has (one flag per lane; the same
+// answer in every wavefront).
+__device__ __forceinline__ bool panel_skipped(const SweepArgs &a, int inst)
+{
+    if (!a.panel_done) return skipped(a, inst);
+    const int lane = threadIdx.x & (kWave - 1);
+    return __all(a.done[(long long)lane * a.done_stride] != 0);
+}
+
 template <int TPW>
 __global__ void __launch_bounds__(kWave *kWg, 2) bwd_trunk64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
-    if (skipped(a, it.inst)) return;
+    if (panel_skipped(a, it.inst)) return;
     const InstDesc I = a.inst[it.inst];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
     bwd_node64<TPW>(a, I, it.idx, lds, false, true, wave, lane);
@@ -321,7 +331,7 @@ __global__ void __launch_bounds__(kWave *kWg, 2) fwd_trunk64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
-    if (skipped(a, it.inst)) return;
+    if (panel_skipped(a, it.inst)) return;
     const InstDesc I = a.inst[it.inst];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
     load_x64(a, I, it.idx, lds);
@@ -334,7 +344,7 @@ __global__ void __launch_bounds__(kWave *kWg, 2) bwd_chain64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
-    if (skipped(a, it.inst)) return;
+    if (panel_skipped(a, it.inst)) return;
     const InstDesc I = a.inst[it.inst];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
     const int *sp = a.sp + I.sp;
@@ -347,7 +357,7 @@ __global__ void __launch_bounds__(kWave *kWg, 2) fwd_chain64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
-    if (skipped(a, it.inst)) return;
+    if (panel_skipped(a, it.inst)) return;
     const InstDesc I = a.inst[it.inst];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
     const int *sp = a.sp + I.sp;
@@ -413,19 +423,26 @@ bool shared_panels(const tree_factors *f)
     return f->shared >= kRhsPanel && f->shared % kRhsPanel == 0 && f->ninst == f->shared && panel_tpw(f) > 0;
 }
 
+bool panel_route(const tree_factors *f, int active)
+{
+    return shared_panels(f) && (active < 0 ? f->ninst : active) >= f->panel_min;
+}
+
 // On a shared handle the instances are the panel's right-hand sides: group g
 // of kRhsPanel instances is one panel starting at instance g*kRhsPanel, with
 // the instance strides as right-hand-side strides; the nrhs right-hand sides
 // of the call (directions, strides of a) are swept one after the other.
-hipError_t launch_sweep_any(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st)
+hipError_t launch_sweep_any(const tree_factors *f, const SweepArgs &a, int nrhs, hipStream_t st, int active)
 {
-    if (!shared_panels(f)) return launch_sweep_tree(f, a, nrhs, st);
+    if (!panel_route(f, active)) return launch_sweep_tree(f, a, nrhs, st);
     const InstDesc &I0 = f->inst[0], &I1 = f->inst[1];
     for (int d = 0; d < nrhs; ++d)
         for (int g = 0; g < f->ninst / kRhsPanel; ++g) {
             SweepArgs p = a;
             p.inst = f->d_inst + (long long)g * kRhsPanel;
-            p.done = nullptr;        // every instance of the panel is swept (finished ones unchanged)
+            // a panel is swept whole while any of its copies is unfinished
+            p.done = a.done ? a.done + (long long)g * kRhsPanel * a.done_stride : nullptr;
+            p.panel_done = a.done ? 1 : 0;
             p.y = a.y + d * a.y_rs;
             p.xo = a.xo + d * a.xo_rs;
             p.uo = a.uo ? a.uo + d * a.uo_rs : nullptr;

@@ -157,6 +157,8 @@ class TreeFactors:
     the per-instance sizes and offsets; for a single tree its nx, nu, N, Vnl
     and sstar are also attributes."""
 
+    shared = 1      # tree_factor_shared: the number of copies
+
     def __init__(self, handle):
         self.handle = handle
         d = tree_dims(handle)
@@ -229,7 +231,9 @@ def tree_factor_shared(prob, count: int, precondition: bool = True, c=None, stre
     h = C.c_void_p()
     _check(lib().tree_factor_shared(C.byref(td), C.byref(pd), int(bool(precondition)), int(count), cp,
                                     _stream(stream), C.byref(h)))
-    return TreeFactors(h)
+    tf = TreeFactors(h)
+    tf.shared = int(count)
+    return tf
 
 
 def tree_factor_batch(probs, precondition: bool = True, stream=None) -> TreeFactors:
@@ -263,24 +267,28 @@ def dual_grad(tf: TreeFactors, x0, y, homogeneous: bool, x, u, nrhs: int = 1, st
 
 
 def sweep_schedule(tf: TreeFactors, knobs) -> None:
-    """Set (group_min, chain_order, trunk_cap, trunk_fused) of the handle's sweeps."""
-    k = (C.c_int32 * 4)(*[int(v) for v in knobs])
+    """Set (group_min, chain_order, trunk_cap, trunk_fused, panel_min) of the
+    handle's sweeps."""
+    if len(knobs) != 5:
+        raise ValueError("sweep_schedule takes 5 knobs")
+    k = (C.c_int32 * 5)(*[int(v) for v in knobs])
     _check(lib().sweep_schedule(tf.handle, k))
 
 
 def sweep_schedule_get(tf: TreeFactors) -> tuple:
-    k = (C.c_int32 * 4)()
+    k = (C.c_int32 * 5)()
     _check(lib().sweep_schedule_get(tf.handle, k))
     return tuple(int(v) for v in k)
 
 
 def forest_signature(tf: TreeFactors, nrhs: int) -> str:
-    """Key of the autotuning cache: the sizes of every instance and nrhs."""
+    """Key of the autotuning cache: the sizes of every instance, whether the
+    instances are copies of one factored tree, and nrhs."""
     import hashlib
     h = hashlib.sha1()
     for d in tf.instances:
         h.update(repr((d["nx"], d["nu"], d["N"], d["V"], d["Vnl"], d["sstar"])).encode())
-    return f"{tf.ninst}x{h.hexdigest()[:16]}:nrhs{nrhs}"
+    return f"{tf.ninst}x{h.hexdigest()[:16]}:shared{tf.shared}:nrhs{nrhs}:k5"
 
 
 def sweep_autotune(tf: TreeFactors, nrhs: int = 1, reps: int = 5, cache: str | None = None,
@@ -297,7 +305,7 @@ def sweep_autotune(tf: TreeFactors, nrhs: int = 1, reps: int = 5, cache: str | N
         if key in table:
             sweep_schedule(tf, table[key]["knobs"])
             return dict(table[key], cached=True)
-    k = (C.c_int32 * 4)()
+    k = (C.c_int32 * 5)()
     ms = C.c_double()
     _check(lib().sweep_autotune(tf.handle, int(nrhs), int(reps), k, C.byref(ms), _stream(stream)))
     rec = {"knobs": [int(v) for v in k], "ms": ms.value}

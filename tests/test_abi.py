@@ -100,7 +100,7 @@ def test_rejects_sizes(st):
 def test_schedule_graph_calls_reject_null_on_host(st):
     import ctypes as C
     L = st.lib()
-    k = (C.c_int32 * 4)(8, 1, 16, 1)
+    k = (C.c_int32 * 5)(8, 1, 16, 1, 16)
     assert L.sweep_schedule(None, k) == -1
     assert L.sweep_schedule_get(None, k) == -1
     assert L.sweep_autotune(None, 1, 3, k, None, None) == -1

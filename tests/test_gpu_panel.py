@@ -83,8 +83,8 @@ def _shared_base():
     return treegen.with_boxes(base, 5.0, 0.3)
 
 
-@pytest.mark.parametrize("count", [64, 3])
-def test_shared_handle_sweeps_match_solo(st, count):
+@pytest.mark.parametrize("count,pmin", [(64, 16), (64, 65), (3, 16)])
+def test_shared_handle_sweeps_match_solo(st, count, pmin):
     """count instances sharing one factor copy (panels across instances when
     count is a multiple of 64) against each instance's own handle."""
     import dataclasses
@@ -92,6 +92,7 @@ def test_shared_handle_sweeps_match_solo(st, count):
     base = case("cfg4_shape") if count == 64 else case("odd_ragged")
     tf = st.tree_factor_shared(base, count, precondition=True)
     assert tf.ninst == count and tf.m == count * base.m
+    st.sweep_schedule(tf, (8, 1, 16, 0, pmin))   # 65 > count: the copies on lane groups
     rng = np.random.default_rng(count)
     X0 = rng.uniform(-2, 2, (count, base.nx))
     Y = rng.standard_normal(tf.m)
@@ -198,3 +199,57 @@ def test_shared_handle_with_own_disturbances_solves(st):
         checked += 1
     assert checked >= 3
     tf.free()
+
+
+def test_many_rhs_on_shared_handle_off_panels(st):
+    """dual_grad with 64 right-hand sides on a shared handle whose copies are
+    not swept as panels (3 copies): every copy of every right-hand side
+    against its own single sweep."""
+    base = case("odd_ragged")
+    tf = st.tree_factor_shared(base, 3, precondition=True)
+    rng = np.random.default_rng(41)
+    Y = rng.standard_normal((64, tf.m))
+    X0 = rng.uniform(-2, 2, (64, tf.x0_len))
+    xm, um = _many(st, tf, _t(X0), _t(Y), False, 64)
+    tf1 = st.tree_factor(base, precondition=True)
+    for r in (0, 30, 63):
+        for k in range(3):
+            d = tf.instances[k]
+            x1, u1 = _many(st, tf1, _t(X0[r, k * base.nx:(k + 1) * base.nx]),
+                           _t(Y[r, d["y_off"]:d["y_off"] + d["m"]]), False, 1)
+            s = max(1.0, np.abs(x1).max())
+            assert np.abs(xm[r, d["x_off"]:d["x_off"] + d["V"] * d["nx"]] - x1[0]).max() <= 1e-12 * s, (r, k)
+            assert np.abs(um[r, d["u_off"]:d["u_off"] + d["Vnl"] * d["nu"]] - u1[0]).max() <= 1e-12 * s, (r, k)
+    tf1.free()
+    tf.free()
+
+
+def test_shared_handle_route_switch_keeps_solutions(st):
+    """The same 64 copies solved with panels until every copy has finished
+    (panel minimum 1), with the default switch to lane groups for the last 15
+    unfinished copies, and on lane groups only (65): every copy converges,
+    and iterations and solutions agree (the routes differ in rounding only)."""
+    import torch
+    base = _shared_base()
+    rng = np.random.default_rng(23)
+    X0 = rng.uniform(-1.5, 1.5, (64, base.nx))
+    pb, fac = oracle.factor(base)
+    lam = 1.0 / (1.1 * oracle.power_iteration(pb, fac, True, 300))
+    out = {}
+    for pmin in (1, 16, 65):
+        tf = st.tree_factor_shared(base, 64, precondition=True)
+        st.sweep_schedule(tf, (8, 1, 16, 0, pmin))
+        y = _t(np.zeros(tf.m))
+        x = torch.zeros(tf.x_len, dtype=torch.float64, device="cuda:0")
+        u = torch.zeros(tf.u_len, dtype=torch.float64, device="cuda:0")
+        rc, _ = st.nama_solve(tf, _t(X0.ravel()), y, x, u, st.make_opts(lam=lam, eps=1e-8, max_iter=3000))
+        infos = st.solve_info_batch(tf)
+        assert rc == 0 and all(i["status"] == 0 and i["res_scaled_inf"] <= 1e-8 for i in infos), pmin
+        out[pmin] = (x.cpu().numpy(), np.array([i["iters"] for i in infos]))
+        tf.free()
+    its = out[1][1]
+    assert its.max() > its.min()          # the copies finish at different iterations
+    s = max(1.0, np.abs(out[1][0]).max())
+    for pmin in (16, 65):
+        assert abs(out[pmin][1].mean() - its.mean()) <= 1.0, (pmin, out[pmin][1], its)
+        assert np.abs(out[pmin][0] - out[1][0]).max() / s < 1e-6, pmin

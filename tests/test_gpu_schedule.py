@@ -66,12 +66,12 @@ def test_schedules_are_bit_identical(st):
     rng = np.random.default_rng(5)
     y = _t(rng.standard_normal(2 * tf.m))
     x0 = _t(rng.standard_normal(2 * tf.x0_len))
-    assert st.sweep_schedule_get(tf) == (8, 1, 16, 0)
+    assert st.sweep_schedule_get(tf) == (8, 1, 16, 0, 16)
     ref = {nrhs: _sweep(st, tf, x0, y, False, nrhs) for nrhs in (1, 2)}
     _check_oracle(tf, probs, y.cpu().numpy()[:tf.m], ref[1][0], ref[1][1], False, x0.cpu().numpy()[:tf.x0_len])
     for g in (8, 16, 32, 64):
         for order in (0, 1):
-            st.sweep_schedule(tf, (g, order, 16, 0))
+            st.sweep_schedule(tf, (g, order, 16, 0, 16))
             for nrhs in (1, 2):
                 xh, uh = _sweep(st, tf, x0, y, False, nrhs)
                 if g == 8:      # the default width: the chain order alone changes no bit
@@ -82,21 +82,25 @@ def test_schedules_are_bit_identical(st):
                     assert np.abs(uh - ref[nrhs][1]).max() <= 1e-12 * s, (g, order, nrhs)
     for cap in (1, 2, 4, 8):
         for fused in (0, 1, 2):
-            st.sweep_schedule(tf, (8, 1, cap, fused))
+            st.sweep_schedule(tf, (8, 1, cap, fused, 16))
             for nrhs in (1, 2):
                 xh, uh = _sweep(st, tf, x0, y, False, nrhs)
                 s = np.abs(ref[nrhs][0]).max()
                 assert np.abs(xh - ref[nrhs][0]).max() <= 1e-12 * s, (cap, fused, nrhs)
                 assert np.abs(uh - ref[nrhs][1]).max() <= 1e-12 * s, (cap, fused, nrhs)
     # the one-launch trunk leaves its counters at zero: repeated sweeps agree bitwise
-    st.sweep_schedule(tf, (8, 1, 16, 1))
+    st.sweep_schedule(tf, (8, 1, 16, 1, 16))
     a1 = _sweep(st, tf, x0, y, False, 1)
     a2 = _sweep(st, tf, x0, y, False, 1)
     assert np.array_equal(a1[0], a2[0]) and np.array_equal(a1[1], a2[1])
     with pytest.raises(st.StotreeError):
-        st.sweep_schedule(tf, (12, 1, 16, 1))
+        st.sweep_schedule(tf, (12, 1, 16, 1, 16))
     with pytest.raises(st.StotreeError):
-        st.sweep_schedule(tf, (8, 1, 16, 3))
+        st.sweep_schedule(tf, (8, 1, 16, 3, 16))
+    with pytest.raises(st.StotreeError):
+        st.sweep_schedule(tf, (8, 1, 16, 0, -1))
+    with pytest.raises(ValueError):
+        st.sweep_schedule(tf, (8, 1, 16, 0))
     tf.free()
 
 
@@ -109,13 +113,14 @@ def test_autotune_keeps_results_and_caches(st, tmp_path):
     cache = str(tmp_path / "tune.json")
     rec = st.sweep_autotune(tf, nrhs=1, reps=3, cache=cache)
     assert not rec["cached"] and rec["ms"] > 0
-    g, order, cap, fused = rec["knobs"]
+    g, order, cap, fused, pmin = rec["knobs"]
     assert g in (8, 16, 32, 64) and order in (0, 1) and cap in (1, 2, 4, 8, 16) and fused in (0, 1, 2)
+    assert pmin == 16        # not a shared handle: the panel knob is left as it is
     assert st.sweep_schedule_get(tf) == tuple(rec["knobs"])
     for homogeneous in (False, True):
         xh, uh = _sweep(st, tf, x0, y, homogeneous)
         _check_oracle(tf, probs, y_np, xh, uh, homogeneous, x0.cpu().numpy())
-    st.sweep_schedule(tf, (64, 0, 1, 0))
+    st.sweep_schedule(tf, (64, 0, 1, 0, 16))
     rec2 = st.sweep_autotune(tf, nrhs=1, cache=cache)
     assert rec2["cached"] and st.sweep_schedule_get(tf) == tuple(rec["knobs"])
     tf.free()
@@ -145,7 +150,7 @@ def test_graph_replays_match_eager(st, nrhs):
         if rep == 0:
             _check_oracle(tf, probs, y.cpu().numpy()[:tf.m], xe[:tf.x_len], ue[:tf.u_len], False,
                           x0.cpu().numpy()[:tf.x0_len])
-    st.sweep_schedule(tf, (16, 1, 16, 1))
+    st.sweep_schedule(tf, (16, 1, 16, 1, 16))
     with pytest.raises(st.StotreeError):
         g.launch()                         # schedule changed: must be recorded again
     g.free()
