@@ -42,6 +42,13 @@ constexpr int kLdv = kPanel + 2;       // LDS row stride of a panel (doubles)
 constexpr int kWg = 4;                 // wavefronts per workgroup
 constexpr int kTpwMax = 4;             // most tasks one wavefront can hold
 constexpr int kKu = 4;                 // K steps (of 4 rows) per batch of operand loads
+// Wavefronts per SIMD each kernel is compiled for (register budget without
+// spills): backward kernels three up to three tasks per wavefront (panels of
+// <= 96 rows fit three to the LDS), forward kernels three up to two tasks.
+template <int TPW>
+constexpr int kMinWavesBwd = TPW <= 3 ? 3 : 2;
+template <int TPW>
+constexpr int kMinWavesFwd = TPW <= 2 ? 3 : 2;
 
 // Source of one output part of a product: out[c] = sum_r M[r][col0 + c] v[r]
 // for c < ncols, M row-major with leading dimension ld.
@@ -59,50 +66,96 @@ struct Tasks {
 
 __host__ __device__ inline int tiles(int n) { return (n + 15) >> 4; }
 
-// acc[s][h] (+)= product for task s of this wavefront; V is the LDS input
-// panel (R rows of kLdv).  Rows of A past R are zero and the matching B rows
-// are not read, so the panel needs no padding rows.  Task w + kWg*s has half
-// (w & 1): all tasks of a wavefront share the B operand.
+// acc[s][h] (+)= product for task w + kWg*s of wavefront w (owned while
+// below the task count); V is the LDS input panel (R rows of kLdv).  Every
+// task of a wavefront has half (w & 1), so they share the B operand.  Whole
+// batches of 16 rows run with the factor loads of the next batch issued
+// before the matrix operations of the current one (two register buffers);
+// the last R mod 16 rows are a tail whose rows past R read a valid row and
+// are zeroed (the panel needs no padding rows).  Every load is unconditional
+// (a task past the count re-reads the first columns, a cache hit), so the
+// loads of a batch are all in flight together; only the matrix operations of
+// unowned tasks are skipped, on a wavefront-uniform test.
 template <int TPW>
 __device__ __forceinline__ void product(const Part (&p)[2], const Tasks &tk, int R, const double *V,
                                         v4d (&acc)[TPW][2], int wave, int lane)
 {
     const int n = tk.count();
     const int lr = lane >> 4, lc = lane & 15;
-    const int half = (wave & 1) * 32;
+    const double *vb = V + lr * kLdv + (wave & 1) * 32 + lc;   // this lane's B entry of row lr
     const double *ap[TPW];
-    int ld[TPW];
+    long long ld[TPW];
+    bool own[TPW];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
         const int task = wave + kWg * s;
-        const int tile = (task < n ? task : 0) >> 1;
+        own[s] = task < n;
+        const int tile = (own[s] ? task : 0) >> 1;
         const int part = tile < tk.t0 ? 0 : 1;
         const int c = (part ? tile - tk.t0 : tile) * 16 + lc;
         // columns past the part re-read its first column; their rows of D are never stored
-        ap[s] = p[part].M + p[part].col0 + (c < p[part].ncols ? c : 0);
+        ap[s] = p[part].M + p[part].col0 + (c < p[part].ncols ? c : 0) + (long long)lr * p[part].ld;
         ld[s] = p[part].ld;
     }
-    for (int k0 = 0; k0 < R; k0 += 4 * kKu) {
-        double a[kKu][TPW], b[kKu][2];
+    auto load = [&](double (&a)[kKu][TPW]) {
 #pragma unroll
-        for (int u = 0; u < kKu; ++u) {
-            const int row = k0 + 4 * u + lr;
-            const bool in = row < R;
-            const int rr = in ? row : 0;
+        for (int u = 0; u < kKu; ++u)
 #pragma unroll
-            for (int s = 0; s < TPW; ++s)
-                if (wave + kWg * s < n) a[u][s] = in ? ap[s][(long long)rr * ld[s]] : 0.0;
-            b[u][0] = in ? V[rr * kLdv + half + lc] : 0.0;
-            b[u][1] = in ? V[rr * kLdv + half + 16 + lc] : 0.0;
-        }
+            for (int s = 0; s < TPW; ++s) a[u][s] = ap[s][4 * u * ld[s]];
+#pragma unroll
+        for (int s = 0; s < TPW; ++s) ap[s] += 4 * kKu * ld[s];
+    };
+    auto mma = [&](const double (&a)[kKu][TPW], const double (&b)[kKu][2]) {
 #pragma unroll
         for (int u = 0; u < kKu; ++u)
 #pragma unroll
             for (int s = 0; s < TPW; ++s)
-                if (wave + kWg * s < n && k0 + 4 * u < R) {
+                if (own[s]) {
                     acc[s][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b[u][0], acc[s][0], 0, 0, 0);
                     acc[s][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b[u][1], acc[s][1], 0, 0, 0);
                 }
+    };
+    auto bload = [&](double (&b)[kKu][2], int k0) {
+#pragma unroll
+        for (int u = 0; u < kKu; ++u) {
+            b[u][0] = vb[(k0 + 4 * u) * kLdv];
+            b[u][1] = vb[(k0 + 4 * u) * kLdv + 16];
+        }
+    };
+    const int nfull = R / (4 * kKu);
+    double a0[kKu][TPW], a1[kKu][TPW], b[kKu][2];
+    int q = 0;
+    if (nfull > 0) load(a0);
+    for (; q + 2 <= nfull; q += 2) {
+        load(a1);
+        bload(b, q * 4 * kKu);
+        mma(a0, b);
+        if (q + 2 < nfull) load(a0);
+        bload(b, (q + 1) * 4 * kKu);
+        mma(a1, b);
+    }
+    if (q < nfull) {
+        bload(b, q * 4 * kKu);
+        mma(a0, b);
+    }
+    const int k0 = nfull * 4 * kKu;
+    if (k0 < R) {
+        // ap[s] points at row k0 + lr of its column; rows past R read row R - 1
+        const int last = R - 1 - k0;
+#pragma unroll
+        for (int u = 0; u < kKu; ++u) {
+            const bool in = 4 * u + lr <= last;
+            const int d = (in ? 4 * u + lr : last) - lr;
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) {
+                const double v = ap[s][d * ld[s]];
+                a0[u][s] = in ? v : 0.0;
+            }
+            const double v0 = vb[(k0 + d) * kLdv], v1 = vb[(k0 + d) * kLdv + 16];
+            b[u][0] = in ? v0 : 0.0;
+            b[u][1] = in ? v1 : 0.0;
+        }
+        mma(a0, b);      // the steps past R add zero products
     }
 }
 
@@ -135,22 +188,38 @@ __device__ __forceinline__ Slot slot(const Tasks &tk, const int (&ncols)[2], int
 }
 
 // Stage rows [0, n) of one node vector of every right-hand side into the
-// panel rows [r0, r0 + n): V[r0 + r][k] = src(k, r).
+// panel rows [r0, r0 + n): V[r0 + r][k] = src(k, r).  A wavefront reads one
+// right-hand side per instruction (consecutive rows on consecutive lanes),
+// all its loads issued before the first LDS write.
 template <typename Src>
 __device__ __forceinline__ void stage(double *V, int r0, int n, Src src)
 {
-    for (int e = threadIdx.x; e < kPanel * n; e += kWg * kWave) {
-        const int k = e / n, r = e - k * n;
-        V[(r0 + r) * kLdv + k] = src(k, r);
+    constexpr int Q = 8;               // right-hand sides per round (loads in flight per lane)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+    for (int rb = 0; rb < n; rb += kWave) {
+        const int r = rb + lane;
+        const bool in = r < n;
+        const int rc = in ? r : n - 1;     // lanes past n read a valid entry and store nothing
+        for (int k0 = wave; k0 < kPanel; k0 += Q * kWg) {
+            double v[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) v[q] = src(k0 + kWg * q, rc);
+            if (in) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) V[(r0 + r) * kLdv + k0 + kWg * q] = v[q];
+            }
+        }
     }
 }
 
 // Backward step of non-leaf node i (Algorithm 3 / 4 body) for the panel.  On
 // entry, if child_in_lds, rows [0, nx) of V hold qhat of the single child; on
 // exit they hold qhat_i.  k_i goes to kbuf; qhat_i to the global buffer if
-// store_q.  After the first product the panel rows are reused: [0, nx) take
+// store_q.  Rows [nx, nx + nu), idle during the children's products, take
+// s_i y^u + pi r (sig) while those run; after them rows [0, nx) take
+// s_i y^x + chat_i; each lane then adds its own product entries, giving
 // sum A'qhat + s_i y^x + chat_i (completed to qhat_i after the second
-// product, each lane on its own entries), [nx, nx + nu) take g_i.
+// product) and g_i.
 template <int TPW>
 __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double *V, bool child_in_lds,
                            bool store_q, int wave, int lane)
@@ -159,15 +228,26 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
     const int *cp = a.cp + I.cp;
     const Tasks tk{tiles(nx), tiles(nu)};
     const int ncols[2] = {nx, nu};
+    const double si = a.sc ? a.sc[I.sc + i] : 1.0;
+    const double *ch = a.chat + I.chat + (long long)i * nx;
+    const double *sg = a.sig + I.sig + (long long)i * nu;
+    const bool aff = a.affine;
+    if (aff)
+        stage(V, nx, nu, [&](int k, int r) { return si * y_ptr(a, I, k, i)[nx + r] + sg[r]; });
+    else
+        stage(V, nx, nu, [&](int k, int r) { return si * y_ptr(a, I, k, i)[nx + r]; });
     v4d S[TPW][2];
     zero(S);
     for (int j = cp[i]; j < cp[i + 1]; ++j) {
         if (!child_in_lds) {
             if (j >= I.Vnl) {
                 const double sj = a.sc ? a.sc[I.sc + j] : 1.0;
-                const double *ch = a.affine ? a.chat + I.chat + (long long)j * nx : nullptr;
-                stage(V, 0, nx,
-                      [&](int k, int r) { return sj * y_ptr(a, I, k, j)[r] + (ch ? ch[k * a.chat_rs + r] : 0.0); });
+                const double *cj = a.chat + I.chat + (long long)j * nx;
+                if (aff)
+                    stage(V, 0, nx,
+                          [&](int k, int r) { return sj * y_ptr(a, I, k, j)[r] + cj[k * a.chat_rs + r]; });
+                else
+                    stage(V, 0, nx, [&](int k, int r) { return sj * y_ptr(a, I, k, j)[r]; });
             } else {
                 stage(V, 0, nx, [&](int k, int r) { return qhat_ptr(a, I, k, j)[r]; });
             }
@@ -179,9 +259,11 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
         __syncthreads();   // every wavefront is done with the child panel
     }
     // rows [0, nx): sum A'qhat + s_i y^x + chat_i; rows [nx, nx + nu): g = sum B'qhat + s_i y^u + pi r
-    const double si = a.sc ? a.sc[I.sc + i] : 1.0;
-    const double *ch = a.affine ? a.chat + I.chat + (long long)i * nx : nullptr;
-    const double *sg = a.affine ? a.sig + I.sig + (long long)i * nu : nullptr;
+    if (aff)
+        stage(V, 0, nx, [&](int k, int r) { return si * y_ptr(a, I, k, i)[r] + ch[k * a.chat_rs + r]; });
+    else
+        stage(V, 0, nx, [&](int k, int r) { return si * y_ptr(a, I, k, i)[r]; });
+    __syncthreads();
 #pragma unroll
     for (int s = 0; s < TPW; ++s)
 #pragma unroll
@@ -189,13 +271,7 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const Slot o = slot(tk, ncols, s, h, e, wave, lane);
-                if (!o.valid) continue;
-                const double *yi = y_ptr(a, I, o.rhs, i);
-                if (o.part == 1)
-                    V[(nx + o.row) * kLdv + o.rhs] = S[s][h][e] + si * yi[nx + o.row] + (sg ? sg[o.row] : 0.0);
-                else
-                    V[o.row * kLdv + o.rhs] =
-                        S[s][h][e] + si * yi[o.row] + (ch ? ch[o.rhs * a.chat_rs + o.row] : 0.0);
+                if (o.valid) V[(o.part ? nx + o.row : o.row) * kLdv + o.rhs] += S[s][h][e];
             }
     __syncthreads();
     // [K' g ; -R~^{-1} g]
@@ -228,7 +304,8 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
 
 // Forward step of non-leaf node i with x_i in panel rows [0, nx).  Writes u_i
 // and the children's x_j; for a single-child chain (keep_child) the child's x
-// replaces x_i in the panel.
+// replaces x_i in the panel.  k_i is staged into rows [nx, nx + nu) (idle
+// during K x_i) and completed there to u_i.
 template <int TPW>
 __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double *V, bool keep_child, int wave,
                            int lane)
@@ -236,12 +313,14 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
     const int nx = I.nx, nu = I.nu, W = nx + nu;
     const int *cp = a.cp + I.cp;
     const int ncols[2] = {nx, nu};
+    stage(V, nx, nu, [&](int k, int r) { return kbuf_ptr(a, I, k, i)[r]; });
     {
         const Tasks tk{0, tiles(nu)};
         v4d U[TPW][2];
         zero(U);
         const Part p[2] = {{nullptr, 0, 0, 0}, {a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nu}};
         product(p, tk, nx, V, U, wave, lane);
+        __syncthreads();   // the staged k_i rows are visible
 #pragma unroll
         for (int s = 0; s < TPW; ++s)
 #pragma unroll
@@ -250,7 +329,7 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
                 for (int e = 0; e < 4; ++e) {
                     const Slot o = slot(tk, ncols, s, h, e, wave, lane);
                     if (!o.valid) continue;
-                    const double uv = U[s][h][e] + kbuf_ptr(a, I, o.rhs, i)[o.row];
+                    const double uv = U[s][h][e] + V[(nx + o.row) * kLdv + o.rhs];
                     u_ptr(a, I, o.rhs, i)[o.row] = uv;
                     V[(nx + o.row) * kLdv + o.rhs] = uv;
                 }
@@ -262,7 +341,25 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
         zero(X);
         const Part p[2] = {{a.Mf + I.Mf + (long long)j * W * I.ldx, I.ldx, 0, nx}, {nullptr, 0, 0, 0}};
         product(p, tk, W, V, X, wave, lane);
-        const double *cj = a.affine ? a.cvec + I.c + (long long)j * nx : nullptr;
+        if (a.affine) {
+            // c_j of a task's eight slots first (rows past nx read row nx - 1), then the sums
+            const double *cj = a.cvec + I.c + (long long)j * nx;
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) {
+                double cv[2][4];
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                        cv[h][e] = cj[o.rhs * a.c_rs + (o.row < nx ? o.row : nx - 1)];
+                    }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) X[s][h][e] += cv[h][e];
+            }
+        }
 #pragma unroll
         for (int s = 0; s < TPW; ++s)
 #pragma unroll
@@ -270,10 +367,7 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const Slot o = slot(tk, ncols, s, h, e, wave, lane);
-                    if (!o.valid) continue;
-                    const double xv = X[s][h][e] + (cj ? cj[o.rhs * a.c_rs + o.row] : 0.0);
-                    X[s][h][e] = xv;
-                    x_ptr(a, I, o.rhs, j)[o.row] = xv;
+                    if (o.valid) x_ptr(a, I, o.rhs, j)[o.row] = X[s][h][e];
                 }
     }
     if (keep_child) {
@@ -296,12 +390,19 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
 __device__ void load_x64(const SweepArgs &a, const InstDesc &I, int i, double *V)
 {
     const int nx = I.nx;
-    stage(V, 0, nx, [&](int k, int r) {
-        if (i != 0) return x_ptr(a, I, k, i)[r];
-        const double v = a.affine ? a.x0[k * a.x0_rs + I.x0 + r] : 0.0;
-        x_ptr(a, I, k, 0)[r] = v;
-        return v;
-    });
+    if (i != 0) {
+        stage(V, 0, nx, [&](int k, int r) { return x_ptr(a, I, k, i)[r]; });
+    } else if (a.affine) {
+        stage(V, 0, nx, [&](int k, int r) { return a.x0[k * a.x0_rs + I.x0 + r]; });
+        __syncthreads();
+        // the root's x is x0: written out too (lanes past nx store nothing)
+        for (int k = threadIdx.x / kWave; k < kPanel; k += kWg)
+            for (int r = threadIdx.x & (kWave - 1); r < nx; r += kWave) x_ptr(a, I, k, 0)[r] = V[r * kLdv + k];
+    } else {
+        stage(V, 0, nx, [&](int k, int r) { return 0.0; });
+        for (int k = threadIdx.x / kWave; k < kPanel; k += kWg)
+            for (int r = threadIdx.x & (kWave - 1); r < nx; r += kWave) x_ptr(a, I, k, 0)[r] = 0.0;
+    }
     __syncthreads();
 }
 
@@ -316,7 +417,7 @@ __device__ __forceinline__ bool panel_skipped(const SweepArgs &a, int inst)
 }
 
 template <int TPW>
-__global__ void __launch_bounds__(kWave *kWg, 2) bwd_trunk64_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave *kWg, kMinWavesBwd<TPW>) bwd_trunk64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
@@ -327,7 +428,7 @@ __global__ void __launch_bounds__(kWave *kWg, 2) bwd_trunk64_kernel(SweepArgs a)
 }
 
 template <int TPW>
-__global__ void __launch_bounds__(kWave *kWg, 2) fwd_trunk64_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave *kWg, kMinWavesFwd<TPW>) fwd_trunk64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
@@ -338,9 +439,19 @@ __global__ void __launch_bounds__(kWave *kWg, 2) fwd_trunk64_kernel(SweepArgs a)
     fwd_node64<TPW>(a, I, it.idx, lds, false, wave, lane);
 }
 
+// The lane and wavefront ids as values the compiler cannot see through: the
+// chain loops pass these so that the per-lane addresses of a node step are
+// formed inside the step instead of being hoisted out of the loop and held
+// in registers across it.
+__device__ __forceinline__ void opaque_ids(int &wave, int &lane)
+{
+    asm volatile("" : "+s"(wave));
+    asm volatile("" : "+v"(lane));
+}
+
 // Chains below s*: one workgroup per chain (items: instance, chain).
 template <int TPW>
-__global__ void __launch_bounds__(kWave *kWg, 2) bwd_chain64_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave *kWg, kMinWavesBwd<TPW>) bwd_chain64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
@@ -348,12 +459,15 @@ __global__ void __launch_bounds__(kWave *kWg, 2) bwd_chain64_kernel(SweepArgs a)
     const InstDesc I = a.inst[it.inst];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
     const int *sp = a.sp + I.sp;
-    for (int t = I.N - 1; t >= I.sstar; --t)
-        bwd_node64<TPW>(a, I, sp[t] + it.idx, lds, t != I.N - 1, t == I.sstar && t > 0, wave, lane);
+    for (int t = I.N - 1; t >= I.sstar; --t) {
+        int w = wave, l = lane;
+        opaque_ids(w, l);
+        bwd_node64<TPW>(a, I, sp[t] + it.idx, lds, t != I.N - 1, t == I.sstar && t > 0, w, l);
+    }
 }
 
 template <int TPW>
-__global__ void __launch_bounds__(kWave *kWg, 2) fwd_chain64_kernel(SweepArgs a)
+__global__ void __launch_bounds__(kWave *kWg, kMinWavesFwd<TPW>) fwd_chain64_kernel(SweepArgs a)
 {
     extern __shared__ double lds[];
     const Item it = a.items[blockIdx.x];
@@ -362,8 +476,11 @@ __global__ void __launch_bounds__(kWave *kWg, 2) fwd_chain64_kernel(SweepArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
     const int *sp = a.sp + I.sp;
     load_x64(a, I, sp[I.sstar] + it.idx, lds);
-    for (int t = I.sstar; t < I.N; ++t)
-        fwd_node64<TPW>(a, I, sp[t] + it.idx, lds, t + 1 < I.N, wave, lane);
+    for (int t = I.sstar; t < I.N; ++t) {
+        int w = wave, l = lane;
+        opaque_ids(w, l);
+        fwd_node64<TPW>(a, I, sp[t] + it.idx, lds, t + 1 < I.N, w, l);
+    }
 }
 
 }  // namespace
