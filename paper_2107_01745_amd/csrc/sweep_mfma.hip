@@ -215,11 +215,11 @@ __device__ __forceinline__ void stage(double *V, int r0, int n, Src src)
 // Backward step of non-leaf node i (Algorithm 3 / 4 body) for the panel.  On
 // entry, if child_in_lds, rows [0, nx) of V hold qhat of the single child; on
 // exit they hold qhat_i.  k_i goes to kbuf; qhat_i to the global buffer if
-// store_q.  Rows [nx, nx + nu), idle during the children's products, take
-// s_i y^u + pi r (sig) while those run; after them rows [0, nx) take
-// s_i y^x + chat_i; each lane then adds its own product entries, giving
-// sum A'qhat + s_i y^x + chat_i (completed to qhat_i after the second
-// product) and g_i.
+// store_q.  The accumulators of the children's products start at
+// s_i y_i + (chat_i; pi r = sig) of their slots, loaded together with the
+// first factor batch, so they end as sum A'qhat + s_i y^x + chat_i (rows
+// [0, nx), completed to qhat_i after the second product) and g_i (rows
+// [nx, nx + nu), the input of the second product).
 template <int TPW>
 __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double *V, bool child_in_lds,
                            bool store_q, int wave, int lane)
@@ -229,21 +229,41 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
     const Tasks tk{tiles(nx), tiles(nu)};
     const int ncols[2] = {nx, nu};
     const double si = a.sc ? a.sc[I.sc + i] : 1.0;
-    const double *ch = a.chat + I.chat + (long long)i * nx;
-    const double *sg = a.sig + I.sig + (long long)i * nu;
-    const bool aff = a.affine;
-    if (aff)
-        stage(V, nx, nu, [&](int k, int r) { return si * y_ptr(a, I, k, i)[nx + r] + sg[r]; });
-    else
-        stage(V, nx, nu, [&](int k, int r) { return si * y_ptr(a, I, k, i)[nx + r]; });
     v4d S[TPW][2];
-    zero(S);
+    {
+        // rows past a part read its last row; slots of unowned tasks are never stored
+        const double *ch = a.chat + I.chat + (long long)i * nx;
+        const double *sg = a.sig + I.sig + (long long)i * nu;
+        const bool aff = a.affine;
+#pragma unroll
+        for (int s = 0; s < TPW; ++s)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                    const int row = o.row < ncols[o.part] ? o.row : ncols[o.part] - 1;
+                    S[s][h][e] = si * y_ptr(a, I, o.rhs, i)[o.part ? nx + row : row];
+                }
+        if (aff) {
+#pragma unroll
+            for (int s = 0; s < TPW; ++s)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                        const int row = o.row < ncols[o.part] ? o.row : ncols[o.part] - 1;
+                        S[s][h][e] += o.part ? sg[row] : ch[o.rhs * a.chat_rs + row];
+                    }
+        }
+    }
     for (int j = cp[i]; j < cp[i + 1]; ++j) {
         if (!child_in_lds) {
             if (j >= I.Vnl) {
                 const double sj = a.sc ? a.sc[I.sc + j] : 1.0;
                 const double *cj = a.chat + I.chat + (long long)j * nx;
-                if (aff)
+                if (a.affine)
                     stage(V, 0, nx,
                           [&](int k, int r) { return sj * y_ptr(a, I, k, j)[r] + cj[k * a.chat_rs + r]; });
                 else
@@ -258,12 +278,6 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
         product(p, tk, nx, V, S, wave, lane);
         __syncthreads();   // every wavefront is done with the child panel
     }
-    // rows [0, nx): sum A'qhat + s_i y^x + chat_i; rows [nx, nx + nu): g = sum B'qhat + s_i y^u + pi r
-    if (aff)
-        stage(V, 0, nx, [&](int k, int r) { return si * y_ptr(a, I, k, i)[r] + ch[k * a.chat_rs + r]; });
-    else
-        stage(V, 0, nx, [&](int k, int r) { return si * y_ptr(a, I, k, i)[r]; });
-    __syncthreads();
 #pragma unroll
     for (int s = 0; s < TPW; ++s)
 #pragma unroll
@@ -271,7 +285,7 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const Slot o = slot(tk, ncols, s, h, e, wave, lane);
-                if (o.valid) V[(o.part ? nx + o.row : o.row) * kLdv + o.rhs] += S[s][h][e];
+                if (o.valid) V[(o.part ? nx + o.row : o.row) * kLdv + o.rhs] = S[s][h][e];
             }
     __syncthreads();
     // [K' g ; -R~^{-1} g]
@@ -304,8 +318,9 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
 
 // Forward step of non-leaf node i with x_i in panel rows [0, nx).  Writes u_i
 // and the children's x_j; for a single-child chain (keep_child) the child's x
-// replaces x_i in the panel.  k_i is staged into rows [nx, nx + nu) (idle
-// during K x_i) and completed there to u_i.
+// replaces x_i in the panel.  The accumulators start at k_i (for u_i = K_i x_i
+// + k_i) and at c_j (for x_j = A_j x_i + B_j u_i + c_j), loaded with the first
+// factor batch.
 template <int TPW>
 __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double *V, bool keep_child, int wave,
                            int lane)
@@ -313,14 +328,22 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
     const int nx = I.nx, nu = I.nu, W = nx + nu;
     const int *cp = a.cp + I.cp;
     const int ncols[2] = {nx, nu};
-    stage(V, nx, nu, [&](int k, int r) { return kbuf_ptr(a, I, k, i)[r]; });
     {
         const Tasks tk{0, tiles(nu)};
         v4d U[TPW][2];
-        zero(U);
+        // rows past nu read row nu - 1; slots of unowned tasks are never stored
+#pragma unroll
+        for (int s = 0; s < TPW; ++s)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                    U[s][h][e] = kbuf_ptr(a, I, o.rhs, i)[o.row < nu ? o.row : nu - 1];
+                }
         const Part p[2] = {{nullptr, 0, 0, 0}, {a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nu}};
         product(p, tk, nx, V, U, wave, lane);
-        __syncthreads();   // the staged k_i rows are visible
+        // rows [nx, W) are not read by K x_i: u_i goes there directly
 #pragma unroll
         for (int s = 0; s < TPW; ++s)
 #pragma unroll
@@ -329,37 +352,30 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
                 for (int e = 0; e < 4; ++e) {
                     const Slot o = slot(tk, ncols, s, h, e, wave, lane);
                     if (!o.valid) continue;
-                    const double uv = U[s][h][e] + V[(nx + o.row) * kLdv + o.rhs];
-                    u_ptr(a, I, o.rhs, i)[o.row] = uv;
-                    V[(nx + o.row) * kLdv + o.rhs] = uv;
+                    u_ptr(a, I, o.rhs, i)[o.row] = U[s][h][e];
+                    V[(nx + o.row) * kLdv + o.rhs] = U[s][h][e];
                 }
         __syncthreads();
     }
     const Tasks tk{tiles(nx), 0};
     v4d X[TPW][2];
     for (int j = cp[i]; j < cp[i + 1]; ++j) {
-        zero(X);
-        const Part p[2] = {{a.Mf + I.Mf + (long long)j * W * I.ldx, I.ldx, 0, nx}, {nullptr, 0, 0, 0}};
-        product(p, tk, W, V, X, wave, lane);
         if (a.affine) {
-            // c_j of a task's eight slots first (rows past nx read row nx - 1), then the sums
             const double *cj = a.cvec + I.c + (long long)j * nx;
 #pragma unroll
-            for (int s = 0; s < TPW; ++s) {
-                double cv[2][4];
+            for (int s = 0; s < TPW; ++s)
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const Slot o = slot(tk, ncols, s, h, e, wave, lane);
-                        cv[h][e] = cj[o.rhs * a.c_rs + (o.row < nx ? o.row : nx - 1)];
+                        X[s][h][e] = cj[o.rhs * a.c_rs + (o.row < nx ? o.row : nx - 1)];
                     }
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) X[s][h][e] += cv[h][e];
-            }
+        } else {
+            zero(X);
         }
+        const Part p[2] = {{a.Mf + I.Mf + (long long)j * W * I.ldx, I.ldx, 0, nx}, {nullptr, 0, 0, 0}};
+        product(p, tk, W, V, X, wave, lane);
 #pragma unroll
         for (int s = 0; s < TPW; ++s)
 #pragma unroll
@@ -496,7 +512,21 @@ int panel_tpw(const tree_factors *f)
     return t <= kTpwMax ? t : 0;
 }
 
-template <int TPW>
+// Tasks per wavefront of the forward products alone (K x: 2 tiles(nu) tasks,
+// [A B][x; u]: 2 tiles(nx)); at most panel_tpw.
+static int panel_tpw_fwd(const tree_factors *f)
+{
+    int t = 1;
+    for (const InstDesc &I : f->inst) {
+        const int tl = tiles(I.nx) > tiles(I.nu) ? tiles(I.nx) : tiles(I.nu);
+        const int need = (2 * tl + kWg - 1) / kWg;
+        t = need > t ? need : t;
+    }
+    return t;
+}
+
+// TB tasks per wavefront in the backward kernels, TF in the forward ones.
+template <int TB, int TF>
 static void launch_panel(const tree_factors *f, const SweepArgs &a, size_t lds, hipStream_t st)
 {
     const dim3 blk(kWave * kWg);
@@ -504,20 +534,20 @@ static void launch_panel(const tree_factors *f, const SweepArgs &a, size_t lds, 
     ca.items = f->panel_chain_items;
     ca.nitems = f->npanel_chain_items;
     const std::vector<LevelPlan> &levels = f->shared > 1 ? f->panel_levels : f->levels;
-    if (ca.nitems > 0) hipLaunchKernelGGL(bwd_chain64_kernel<TPW>, dim3(ca.nitems), blk, lds, st, ca);
+    if (ca.nitems > 0) hipLaunchKernelGGL(bwd_chain64_kernel<TB>, dim3(ca.nitems), blk, lds, st, ca);
     for (int k = (int)levels.size() - 1; k >= 0; --k) {
         SweepArgs la = a;
         la.items = levels[k].items;
         la.nitems = levels[k].count;
-        if (la.nitems > 0) hipLaunchKernelGGL(bwd_trunk64_kernel<TPW>, dim3(la.nitems), blk, lds, st, la);
+        if (la.nitems > 0) hipLaunchKernelGGL(bwd_trunk64_kernel<TB>, dim3(la.nitems), blk, lds, st, la);
     }
     for (size_t k = 0; k < levels.size(); ++k) {
         SweepArgs la = a;
         la.items = levels[k].items;
         la.nitems = levels[k].count;
-        if (la.nitems > 0) hipLaunchKernelGGL(fwd_trunk64_kernel<TPW>, dim3(la.nitems), blk, lds, st, la);
+        if (la.nitems > 0) hipLaunchKernelGGL(fwd_trunk64_kernel<TF>, dim3(la.nitems), blk, lds, st, la);
     }
-    if (ca.nitems > 0) hipLaunchKernelGGL(fwd_chain64_kernel<TPW>, dim3(ca.nitems), blk, lds, st, ca);
+    if (ca.nitems > 0) hipLaunchKernelGGL(fwd_chain64_kernel<TF>, dim3(ca.nitems), blk, lds, st, ca);
 }
 
 hipError_t launch_panel_sweep(const tree_factors *f, const SweepArgs &a, hipStream_t st)
@@ -525,11 +555,16 @@ hipError_t launch_panel_sweep(const tree_factors *f, const SweepArgs &a, hipStre
     int W = 2;
     for (const InstDesc &I : f->inst) W = W > I.nx + I.nu ? W : I.nx + I.nu;
     const size_t lds = sizeof(double) * (size_t)W * kLdv;
-    switch (panel_tpw(f)) {
-    case 1: launch_panel<1>(f, a, lds, st); break;
-    case 2: launch_panel<2>(f, a, lds, st); break;
-    case 3: launch_panel<3>(f, a, lds, st); break;
-    case 4: launch_panel<4>(f, a, lds, st); break;
+    const int tb = panel_tpw(f), tf = panel_tpw_fwd(f);
+    switch (tb * 8 + tf) {
+    case 1 * 8 + 1: launch_panel<1, 1>(f, a, lds, st); break;
+    case 2 * 8 + 1: launch_panel<2, 1>(f, a, lds, st); break;
+    case 2 * 8 + 2: launch_panel<2, 2>(f, a, lds, st); break;
+    case 3 * 8 + 2: launch_panel<3, 2>(f, a, lds, st); break;
+    case 3 * 8 + 3: launch_panel<3, 3>(f, a, lds, st); break;
+    case 4 * 8 + 2: launch_panel<4, 2>(f, a, lds, st); break;
+    case 4 * 8 + 3: launch_panel<4, 3>(f, a, lds, st); break;
+    case 4 * 8 + 4: launch_panel<4, 4>(f, a, lds, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
