@@ -66,51 +66,71 @@ struct Tasks {
 
 __host__ __device__ inline int tiles(int n) { return (n + 15) >> 4; }
 
-// acc[s][h] (+)= product for task w + kWg*s of wavefront w (owned while
-// below the task count); V is the LDS input panel (R rows of kLdv).  Every
-// task of a wavefront has half (w & 1), so they share the B operand.  Whole
-// batches of 16 rows run with the factor loads of the next batch issued
-// before the matrix operations of the current one (two register buffers);
-// the last R mod 16 rows are a tail whose rows past R read a valid row and
-// are zeroed (the panel needs no padding rows).  Every load is unconditional
-// (a task past the count re-reads the first columns, a cache hit), so the
-// loads of a batch are all in flight together; only the matrix operations of
-// unowned tasks are skipped, on a wavefront-uniform test.
+// The factor side of one product for wavefront w: column pointers of its
+// tasks w + kWg*s (owned while below the task count; advanced batch by batch)
+// and the first batch of 16 rows, which stream_open loads so that it can be
+// issued ahead of the point where stream_run multiplies.
 template <int TPW>
-__device__ __forceinline__ void product(const Part (&p)[2], const Tasks &tk, int R, const double *V,
-                                        v4d (&acc)[TPW][2], int wave, int lane)
-{
-    const int n = tk.count();
-    const int lr = lane >> 4, lc = lane & 15;
-    const double *vb = V + lr * kLdv + (wave & 1) * 32 + lc;   // this lane's B entry of row lr
+struct FactorStream {
     const double *ap[TPW];
     long long ld[TPW];
     bool own[TPW];
+    double a0[kKu][TPW];
+};
+
+template <int TPW>
+__device__ __forceinline__ void stream_load(FactorStream<TPW> &f, double (&a)[kKu][TPW])
+{
+#pragma unroll
+    for (int u = 0; u < kKu; ++u)
+#pragma unroll
+        for (int s = 0; s < TPW; ++s) a[u][s] = f.ap[s][4 * u * f.ld[s]];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) f.ap[s] += 4 * kKu * f.ld[s];
+}
+
+// Every load is unconditional (a task past the count re-reads the first
+// columns, a cache hit; columns past a part re-read its first column, whose
+// rows of D are never stored), so the loads of a batch are all in flight
+// together; only the matrix operations of unowned tasks are skipped, on a
+// wavefront-uniform test.
+template <int TPW>
+__device__ __forceinline__ void stream_open(FactorStream<TPW> &f, const Part (&p)[2], const Tasks &tk, int R,
+                                            int wave, int lane)
+{
+    const int n = tk.count();
+    const int lr = lane >> 4, lc = lane & 15;
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
         const int task = wave + kWg * s;
-        own[s] = task < n;
-        const int tile = (own[s] ? task : 0) >> 1;
+        f.own[s] = task < n;
+        const int tile = (f.own[s] ? task : 0) >> 1;
         const int part = tile < tk.t0 ? 0 : 1;
         const int c = (part ? tile - tk.t0 : tile) * 16 + lc;
-        // columns past the part re-read its first column; their rows of D are never stored
-        ap[s] = p[part].M + p[part].col0 + (c < p[part].ncols ? c : 0) + (long long)lr * p[part].ld;
-        ld[s] = p[part].ld;
+        f.ap[s] = p[part].M + p[part].col0 + (c < p[part].ncols ? c : 0) + (long long)lr * p[part].ld;
+        f.ld[s] = p[part].ld;
     }
-    auto load = [&](double (&a)[kKu][TPW]) {
-#pragma unroll
-        for (int u = 0; u < kKu; ++u)
-#pragma unroll
-            for (int s = 0; s < TPW; ++s) a[u][s] = ap[s][4 * u * ld[s]];
-#pragma unroll
-        for (int s = 0; s < TPW; ++s) ap[s] += 4 * kKu * ld[s];
-    };
+    if (R >= 4 * kKu) stream_load(f, f.a0);
+}
+
+// acc[s][h] (+)= the product of task s with the LDS input panel V (R rows of
+// kLdv).  Every task of a wavefront has half (w & 1), so they share the B
+// operand.  Whole batches of 16 rows run with the factor loads of the next
+// batch issued before the matrix operations of the current one (two register
+// buffers); the last R mod 16 rows are a tail whose rows past R read a valid
+// row and are zeroed (the panel needs no padding rows).
+template <int TPW>
+__device__ __forceinline__ void stream_run(FactorStream<TPW> &f, int R, const double *V, v4d (&acc)[TPW][2],
+                                           int wave, int lane)
+{
+    const int lr = lane >> 4, lc = lane & 15;
+    const double *vb = V + lr * kLdv + (wave & 1) * 32 + lc;   // this lane's B entry of row lr
     auto mma = [&](const double (&a)[kKu][TPW], const double (&b)[kKu][2]) {
 #pragma unroll
         for (int u = 0; u < kKu; ++u)
 #pragma unroll
             for (int s = 0; s < TPW; ++s)
-                if (own[s]) {
+                if (f.own[s]) {
                     acc[s][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b[u][0], acc[s][0], 0, 0, 0);
                     acc[s][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b[u][1], acc[s][1], 0, 0, 0);
                 }
@@ -123,20 +143,19 @@ __device__ __forceinline__ void product(const Part (&p)[2], const Tasks &tk, int
         }
     };
     const int nfull = R / (4 * kKu);
-    double a0[kKu][TPW], a1[kKu][TPW], b[kKu][2];
+    double a1[kKu][TPW], b[kKu][2];
     int q = 0;
-    if (nfull > 0) load(a0);
     for (; q + 2 <= nfull; q += 2) {
-        load(a1);
+        stream_load(f, a1);
         bload(b, q * 4 * kKu);
-        mma(a0, b);
-        if (q + 2 < nfull) load(a0);
+        mma(f.a0, b);
+        if (q + 2 < nfull) stream_load(f, f.a0);
         bload(b, (q + 1) * 4 * kKu);
         mma(a1, b);
     }
     if (q < nfull) {
         bload(b, q * 4 * kKu);
-        mma(a0, b);
+        mma(f.a0, b);
     }
     const int k0 = nfull * 4 * kKu;
     if (k0 < R) {
@@ -148,15 +167,25 @@ __device__ __forceinline__ void product(const Part (&p)[2], const Tasks &tk, int
             const int d = (in ? 4 * u + lr : last) - lr;
 #pragma unroll
             for (int s = 0; s < TPW; ++s) {
-                const double v = ap[s][d * ld[s]];
-                a0[u][s] = in ? v : 0.0;
+                const double v = f.ap[s][d * f.ld[s]];
+                f.a0[u][s] = in ? v : 0.0;
             }
             const double v0 = vb[(k0 + d) * kLdv], v1 = vb[(k0 + d) * kLdv + 16];
             b[u][0] = in ? v0 : 0.0;
             b[u][1] = in ? v1 : 0.0;
         }
-        mma(a0, b);      // the steps past R add zero products
+        mma(f.a0, b);    // the steps past R add zero products
     }
+}
+
+
+template <int TPW>
+__device__ __forceinline__ void product(const Part (&p)[2], const Tasks &tk, int R, const double *V,
+                                        v4d (&acc)[TPW][2], int wave, int lane)
+{
+    FactorStream<TPW> f;
+    stream_open(f, p, tk, R, wave, lane);
+    stream_run(f, R, V, acc, wave, lane);
 }
 
 template <int TPW>
@@ -276,8 +305,16 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
         const double *Mb = a.Mb + I.Mb + (long long)j * nx * I.ldM;
         const Part p[2] = {{Mb, I.ldM, 0, nx}, {Mb, I.ldM, nx, nu}};
         product(p, tk, nx, V, S, wave, lane);
-        __syncthreads();   // every wavefront is done with the child panel
+        if (j + 1 < cp[i + 1]) __syncthreads();   // every wavefront is done with the child panel
     }
+    // first batch of [K' ; -R~^{-1}] in flight across the barriers
+    FactorStream<TPW> f2;
+    {
+        const Part p[2] = {{a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nx},
+                           {a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu}};
+        stream_open(f2, p, tk, nu, wave, lane);
+    }
+    __syncthreads();       // every wavefront is done with the child panel
 #pragma unroll
     for (int s = 0; s < TPW; ++s)
 #pragma unroll
@@ -291,11 +328,7 @@ __device__ void bwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
     // [K' g ; -R~^{-1} g]
     v4d T[TPW][2];
     zero(T);
-    {
-        const Part p[2] = {{a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nx},
-                           {a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu}};
-        product(p, tk, nu, V + nx * kLdv, T, wave, lane);
-    }
+    stream_run(f2, nu, V + nx * kLdv, T, wave, lane);
     // each lane completes its own entries of rows [0, nx); the g rows are not written
 #pragma unroll
     for (int s = 0; s < TPW; ++s)
@@ -328,6 +361,9 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
     const int nx = I.nx, nu = I.nu, W = nx + nu;
     const int *cp = a.cp + I.cp;
     const int ncols[2] = {nx, nu};
+    const Tasks tkx{tiles(nx), 0};
+    const int j0 = cp[i], j1 = cp[i + 1];
+    FactorStream<TPW> fx;     // the first child's [A B], opened before the u_i barrier
     {
         const Tasks tk{0, tiles(nu)};
         v4d U[TPW][2];
@@ -355,11 +391,12 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
                     u_ptr(a, I, o.rhs, i)[o.row] = U[s][h][e];
                     V[(nx + o.row) * kLdv + o.rhs] = U[s][h][e];
                 }
+        const Part px[2] = {{a.Mf + I.Mf + (long long)j0 * W * I.ldx, I.ldx, 0, nx}, {nullptr, 0, 0, 0}};
+        stream_open(fx, px, tkx, W, wave, lane);
         __syncthreads();
     }
-    const Tasks tk{tiles(nx), 0};
     v4d X[TPW][2];
-    for (int j = cp[i]; j < cp[i + 1]; ++j) {
+    for (int j = j0; j < j1; ++j) {
         if (a.affine) {
             const double *cj = a.cvec + I.c + (long long)j * nx;
 #pragma unroll
@@ -368,21 +405,24 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                        const Slot o = slot(tkx, ncols, s, h, e, wave, lane);
                         X[s][h][e] = cj[o.rhs * a.c_rs + (o.row < nx ? o.row : nx - 1)];
                     }
         } else {
             zero(X);
         }
-        const Part p[2] = {{a.Mf + I.Mf + (long long)j * W * I.ldx, I.ldx, 0, nx}, {nullptr, 0, 0, 0}};
-        product(p, tk, W, V, X, wave, lane);
+        if (j > j0) {
+            const Part p[2] = {{a.Mf + I.Mf + (long long)j * W * I.ldx, I.ldx, 0, nx}, {nullptr, 0, 0, 0}};
+            stream_open(fx, p, tkx, W, wave, lane);
+        }
+        stream_run(fx, W, V, X, wave, lane);
 #pragma unroll
         for (int s = 0; s < TPW; ++s)
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                    const Slot o = slot(tkx, ncols, s, h, e, wave, lane);
                     if (o.valid) x_ptr(a, I, o.rhs, j)[o.row] = X[s][h][e];
                 }
     }
@@ -394,7 +434,7 @@ __device__ void fwd_node64(const SweepArgs &a, const InstDesc &I, int i, double 
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const Slot o = slot(tk, ncols, s, h, e, wave, lane);
+                    const Slot o = slot(tkx, ncols, s, h, e, wave, lane);
                     if (o.valid) V[o.row * kLdv + o.rhs] = X[s][h][e];
                 }
         __syncthreads();
