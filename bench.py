@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the dual-gradient hot path on one MI355X.
 
-Workload (config 1): one scenario tree with nx=50, nu=30, horizon N=20,
+Workload (the large tree): one scenario tree with nx=50, nu=30, horizon N=20,
 branching 4 at stages 0-5 then 1 (4,096 scenarios, 62,805 nodes, 4.90M primal
 and 4.90M dual variables), FP64 factors and solves, synthetic seeded data.
 
@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 KERNEL_SOURCES = ("paper_2107_01745_amd/csrc/sweep.hip", "paper_2107_01745_amd/csrc/sweep_common.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_cfg1.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_large_tree.md")
 
 
 def kernel_sources_sha1():
@@ -156,7 +156,7 @@ def cpu_baseline(prob, seconds=10.0):
 
 
 def batched_leg(stotree, torch, steps, warmup, cache):
-    """Config 2: 256 independent trees (nx ~ U{8..32}, nu = nx/2, N ~ U{10..30},
+    """Uneven batch: 256 independent trees (nx ~ U{8..32}, nu = nx/2, N ~ U{10..30},
     16..1024 scenarios, first-stage branching 2..8) in one handle.  The
     schedule is autotuned on the device (or read from the cache), the
     dual-gradient sweep of all 256 trees is recorded once as a HIP graph, and
@@ -173,7 +173,7 @@ def batched_leg(stotree, torch, steps, warmup, cache):
     t0 = time.perf_counter()
     tf = stotree.tree_factor_batch(probs, precondition=True)
     factor_s = time.perf_counter() - t0
-    log(f"config 2: {len(probs)} trees, {tf.V} nodes, drawn in {gen_s:.1f} s, factored in {factor_s:.1f} s, "
+    log(f"uneven batch: {len(probs)} trees, {tf.V} nodes, drawn in {gen_s:.1f} s, factored in {factor_s:.1f} s, "
         f"{tf.device_bytes / 1e9:.1f} GB on device")
     nbytes, flops = 0, 0.0
     for p, d in zip(probs, tf.instances):
@@ -182,7 +182,7 @@ def batched_leg(stotree, torch, steps, warmup, cache):
     t0 = time.perf_counter()
     tune = stotree.sweep_autotune(tf, nrhs=1, reps=3, cache=cache)
     tune_s = time.perf_counter() - t0
-    log(f"config 2 schedule {tune['knobs']} ({'cached' if tune['cached'] else 'tuned'} in {tune_s:.1f} s)")
+    log(f"uneven batch schedule {tune['knobs']} ({'cached' if tune['cached'] else 'tuned'} in {tune_s:.1f} s)")
     rng = np.random.default_rng(12)
     y = torch.tensor(rng.standard_normal(tf.m), dtype=torch.float64, device=dev)
     x0 = torch.tensor(np.concatenate([p.x0 for p in probs]), dtype=torch.float64, device=dev)
@@ -227,7 +227,7 @@ def batched_leg(stotree, torch, steps, warmup, cache):
     graph.free()
     tf.free()
     gbs = nbytes / (graph_ms * 1e-3) / 1e9
-    rep = {"workload": "config 2: 256 uneven trees (seed 1002), one handle, one graph replay per step",
+    rep = {"workload": "uneven batch: 256 uneven trees (seed 1002), one handle, one graph replay per step",
            "trees": 256, "nodes": int(tf.V), "m": int(tf.m), "generation_s": gen_s, "factor_s": factor_s,
            "schedule": tune, "tune_s": tune_s, "ms_per_step_graph": graph_ms, "ms_per_step_eager": eager_ms,
            "instance_sweeps_per_s": 256 * 1000.0 / graph_ms, "batched_sweeps_per_s": 1000.0 / graph_ms,
@@ -235,7 +235,7 @@ def batched_leg(stotree, torch, steps, warmup, cache):
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS},
            "phases_eager_ms": phases, "inner_kkt_residual_sampled": worst}
-    log(f"config 2: graph {graph_ms:.3f} ms/step, eager {eager_ms:.3f} ms ({256e3 / graph_ms:.0f} "
+    log(f"uneven batch: graph {graph_ms:.3f} ms/step, eager {eager_ms:.3f} ms ({256e3 / graph_ms:.0f} "
         f"instance sweeps/s, {gbs:.0f} GB/s = {100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak); "
         f"phases {phases}; KKT residual {worst:.1e}")
     return rep
@@ -258,7 +258,7 @@ def panel_bytes(prob, sstar, nrhs):
 
 
 def panel_leg(stotree, torch, steps, warmup):
-    """Config 4: nx=64, nu=32, N=20, branching 4 at stages 0-6 (16384
+    """Shared tree: nx=64, nu=32, N=20, branching 4 at stages 0-6 (16384
     scenarios, 234,837 nodes); 64 instances share the tree's factors and
     differ in x0.  A step is one x(y) sweep of all 64 instances, i.e. one
     64-right-hand-side panel pass on the FP64 matrix cores.  Also timed: the
@@ -268,7 +268,7 @@ def panel_leg(stotree, torch, steps, warmup):
     from gpu_cases import inner_kkt_residual
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    prob = treegen.make_config(4)
+    prob = treegen.make_workload("shared")
     gen_s = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -276,7 +276,7 @@ def panel_leg(stotree, torch, steps, warmup):
     torch.cuda.synchronize()
     factor_s = time.perf_counter() - t0
     sstar = tf.sstar
-    log(f"config 4: V={prob.tree.V}, m={prob.m}, drawn in {gen_s:.1f} s, factor step {factor_s:.1f} s, "
+    log(f"shared tree: V={prob.tree.V}, m={prob.m}, drawn in {gen_s:.1f} s, factor step {factor_s:.1f} s, "
         f"{tf.device_bytes / 1e9:.1f} GB on device")
     rng = np.random.default_rng(13)
     X0 = rng.uniform(-3, 3, (64, prob.nx))
@@ -330,7 +330,7 @@ def panel_leg(stotree, torch, steps, warmup):
     flops = 64 * sweep_flops(prob)
     gbs = nbytes / (panel_ms * 1e-3) / 1e9
     tfs = flops / (panel_ms * 1e-3) / 1e12
-    rep = {"workload": ("config 4: nx=64, nu=32, N=20, branching 4 at stages 0-6 (16384 scenarios, 234837 "
+    rep = {"workload": ("shared tree: nx=64, nu=32, N=20, branching 4 at stages 0-6 (16384 scenarios, 234837 "
                         "nodes); 64 instances sharing the factors, different x0; step = x(y) of all 64"),
            "generation_s": gen_s, "factor_s": factor_s, "ms_per_step_panel": panel_ms,
            "ms_per_64_pair_sweeps": pair_ms, "speedup_panel_vs_pairs": pair_ms / panel_ms,
@@ -339,14 +339,14 @@ def panel_leg(stotree, torch, steps, warmup):
                         "frac": gbs / HBM_PEAK_GBS},
            "mfma": {"achieved": tfs, "peak": 78.6, "unit": "TFLOP/s", "frac": tfs / 78.6},
            "inner_kkt_residual_sampled": worst}
-    log(f"config 4: panel {panel_ms:.2f} ms per 64 sweeps, pairs {pair_ms:.2f} ms "
+    log(f"shared tree: panel {panel_ms:.2f} ms per 64 sweeps, pairs {pair_ms:.2f} ms "
         f"({pair_ms / panel_ms:.2f}x); {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% HBM), "
         f"{tfs:.1f} TFLOP/s ({100 * tfs / 78.6:.1f}% FP64 MFMA); KKT residual {worst:.1e}")
     return rep
 
 
 def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
-    """Config 4 solves: 64 instances sharing the tree (x0 ~ U[-3,3]^64), |u|
+    """Shared-tree solves: 64 instances sharing the tree (x0 ~ U[-3,3]^64), |u|
     <= ubox so that the boxes bind.  The node-wise MLP is retrained on this
     tree from n_batches x 64 batched NAMA solves (rows subsampled), then 64
     held-out draws are solved (a) one at a time from a cold start on a plain
@@ -356,7 +356,7 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     checks of the warm start."""
     from paper_2107_01745_amd import warmstart as ws
     dev = torch.device("cuda:0")
-    prob = treegen.with_boxes(treegen.make_config(4), 5.0, ubox)
+    prob = treegen.with_boxes(treegen.make_workload("shared"), 5.0, ubox)
     nx = prob.nx
     rng = np.random.default_rng(404)
     draws = lambda: torch.tensor(rng.uniform(-3, 3, (64, nx)).ravel(), dtype=torch.float64, device=dev)
@@ -372,11 +372,11 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
         solo_it.append(info[0]["iters"])
     tf1.free()
     torch.cuda.empty_cache()
-    log(f"config 4 solve: lambda {lam:.4g}; cold per-instance {solo_s / n_solo:.2f} s, iters {solo_it}")
+    log(f"shared-tree solve: lambda {lam:.4g}; cold per-instance {solo_s / n_solo:.2f} s, iters {solo_it}")
     tfs = stotree.tree_factor_shared(prob, 64, precondition=True)
     t0 = time.perf_counter()
     tune = stotree.sweep_autotune(tfs, nrhs=1, reps=1)
-    log(f"config 4 solve: schedule {tune['knobs']} tuned in {time.perf_counter() - t0:.1f} s")
+    log(f"shared-tree solve: schedule {tune['knobs']} tuned in {time.perf_counter() - t0:.1f} s")
     model = ws.WarmStartMLP(nx, prob.nu, prob.tree.N, dh=128, seed=0)
     Xs, Ts, Ms = [], [], []
     gen_s, gen_it = 0.0, []
@@ -412,7 +412,7 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     train_s = time.perf_counter() - t0
     del X, T, M
     torch.cuda.empty_cache()
-    log(f"config 4 solve: {n_batches * 64} training solves in {gen_s:.1f} s (mean iters {np.mean(gen_it):.1f}); "
+    log(f"shared-tree solve: {n_batches * 64} training solves in {gen_s:.1f} s (mean iters {np.mean(gen_it):.1f}); "
         f"{epochs} epochs in {train_s:.1f} s, masked MSE {hist[0]:.3e} -> {hist[-1]:.3e}")
     # (b) cold, batched
     _, _, info_c, cold_s = ws.solve_batch(test_x0, lam, eps=1e-6, tf=tfs, mem=mem, max_iter=500)
@@ -427,7 +427,7 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     del yw
     torch.cuda.empty_cache()
     solo_total = solo_s / n_solo * 64
-    rep = {"workload": "config 4 with |u| <= %g: 64 instances sharing the tree, x0 ~ U[-3,3]" % ubox,
+    rep = {"workload": "shared tree (nx=64, nu=32, N=20, 16384 scenarios) with |u| <= %g: 64 instances sharing the tree, x0 ~ U[-3,3]" % ubox,
            "lambda": lam, "mem": mem, "schedule": tune["knobs"], "training_solves": n_batches * 64, "training_rows": int(keep_rows * n_batches),
            "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]], "training_generation_s": gen_s,
            "train_s": train_s,
@@ -441,7 +441,7 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
                             "converged": int(sum(i["status"] == 0 for i in info_w))},
            "speedup_warm_batched_vs_cold_per_instance": solo_total / (pred_s + warm_s),
            "speedup_cold_batched_vs_cold_per_instance": solo_total / cold_s}
-    log(f"config 4 solve: cold per-instance {solo_total:.1f} s (64, est.), cold batched {cold_s:.2f} s "
+    log(f"shared-tree solve: cold per-instance {solo_total:.1f} s (64, est.), cold batched {cold_s:.2f} s "
         f"(iters {rep['cold_batched']['iters_mean']:.1f}), warm batched {pred_s + warm_s:.2f} s "
         f"(iters {rep['warm_batched']['iters_mean']:.1f} incl. the refining one, kept {sum(keep)}) -> "
         f"{rep['speedup_warm_batched_vs_cold_per_instance']:.1f}x")
@@ -493,7 +493,7 @@ def screen_feasible(stotree, ws, base, probs, lam, batch, tune, max_iter=400):
 
 
 def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
-    """Config 3 (nx=20, nu=10, N=15, branching 3 at stages 0-4; |u| <= 0.2 so
+    """Warm-start tree (nx=20, nu=10, N=15, branching 3 at stages 0-4; |u| <= 0.2 so
     that the boxes bind): train the warm-start MLP on solver-generated duals
     of n_train draws (x0, disturbance path; draws the solver cannot solve are
     masked out), then compare on n_test held-out feasible draws the plain
@@ -502,7 +502,7 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     side includes prediction, the refining iteration and the residual checks)."""
     from paper_2107_01745_amd import warmstart as ws
     dev = torch.device("cuda:0")
-    base = treegen.with_boxes(treegen.make_config(3), 5.0, 0.2)
+    base = treegen.with_boxes(treegen.make_workload("warm"), 5.0, 0.2)
     tf0 = stotree.tree_factor(base, precondition=True)
     lam = 1.0 / (1.1 * stotree.dual_lipschitz(tf0, 200))
     tf0.free()
@@ -576,7 +576,7 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
         it_solo.append(info[0]["iters"])
         tf.free()
     solo_total = solo_s / max(1, n_solo) * n_test
-    rep = {"tree": "config 3 (2794 nodes), |u| <= 0.2", "lambda": lam, "n_train": n_train,
+    rep = {"tree": "warm-start tree (nx=20, nu=10, N=15, 2794 nodes), |u| <= 0.2", "lambda": lam, "n_train": n_train,
            "n_train_solved": int(gen_ok), "n_test_drawn": len(drawn), "n_test_feasible": n_test,
            "batch": batch, "schedule": tune.get("knobs"), "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]],
            "y_scale": model.y_scale, "data_generation_s": gen_s, "train_s": train_s,
@@ -610,11 +610,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-panel", action="store_true")
     ap.add_argument("--no-panel-solve", action="store_true")
-    ap.add_argument("--c4-ubox", type=float, default=0.1)
-    ap.add_argument("--c4-batches", type=int, default=2)
-    ap.add_argument("--c4-epochs", type=int, default=8)
-    ap.add_argument("--c4-solo", type=int, default=2)
-    ap.add_argument("--c4-mem", type=int, default=3)
+    ap.add_argument("--shared-ubox", type=float, default=0.1)
+    ap.add_argument("--shared-batches", type=int, default=2)
+    ap.add_argument("--shared-epochs", type=int, default=8)
+    ap.add_argument("--shared-solo", type=int, default=2)
+    ap.add_argument("--shared-mem", type=int, default=3)
     ap.add_argument("--tune-cache", default=None, help="JSON cache of tuned schedules (default: tune)")
     ap.add_argument("--warm-train", type=int, default=1024)
     ap.add_argument("--warm-test", type=int, default=256)
@@ -631,8 +631,8 @@ def main():
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    prob = treegen.make_config(1)
-    log(f"config 1 generated in {time.perf_counter() - t0:.1f} s: V={prob.tree.V}, m={prob.m}")
+    prob = treegen.make_workload("large")
+    log(f"large tree generated in {time.perf_counter() - t0:.1f} s: V={prob.tree.V}, m={prob.m}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tf = stotree.tree_factor(prob, precondition=True)
@@ -707,7 +707,7 @@ def main():
     if not args.no_solve:
         import dataclasses
         solve_rep = {}
-        # config 1 as read (|u| <= 1: the unconstrained optimum is feasible, y* = 0) and with
+        # the large tree as read (|u| <= 1: the unconstrained optimum is feasible, y* = 0) and with
         # |u| <= 0.1, where about 4% of the inputs are active at the solution
         variants = [("as_specified", tf, prob)]
         tight = dataclasses.replace(prob, umin=np.full_like(prob.umin, -args.tight_u),
@@ -746,8 +746,8 @@ def main():
         panel_rep = guarded("panel", panel_leg, stotree, torch, min(args.steps, 20), min(args.warmup, 2))
     panel_solve_rep = None
     if not args.no_panel_solve:
-        panel_solve_rep = guarded("panel solve", panel_solve_leg, stotree, torch, args.c4_ubox, args.c4_batches,
-                                  args.c4_epochs, args.c4_solo, args.c4_mem)
+        panel_solve_rep = guarded("panel solve", panel_solve_leg, stotree, torch, args.shared_ubox, args.shared_batches,
+                                  args.shared_epochs, args.shared_solo, args.shared_mem)
 
     warm_rep = None
     if not args.no_warm:
@@ -764,7 +764,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "dual-grad evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": ("config 1: single scenario tree, nx=50, nu=30, N=20, branching 4 at "
+        "config": {"workload": ("large tree: single scenario tree, nx=50, nu=30, N=20, branching 4 at "
                                 "stages 0-5 then 1 (4096 scenarios, 62805 nodes, 4.90M primal / "
                                 "4.90M dual variables); step = one FP64 dual-gradient sweep x(y)"),
                    "nodes": prob.tree.V, "m": prob.m, "precondition": True,

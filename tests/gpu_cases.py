@@ -29,10 +29,15 @@ def row_scale(prob, precondition=True):
     return np.repeat(np.sqrt(t.prob), w)
 
 
+# Seeds of cases whose draws are pinned to the ones the tests were first
+# written against (a case's seed is otherwise the CRC of its name).
+_SEEDS = {"large_blocks": 3302201992, "shared_blocks": 2532029743, "warm_blocks": 1397525409}
+
+
 def case(name):
     """Named test instances of different shapes."""
-    rng = np.random.default_rng(zlib.crc32(name.encode()))
-    if name == "tiny":            # config-0 shape
+    rng = np.random.default_rng(_SEEDS.get(name, zlib.crc32(name.encode())))
+    if name == "tiny":            # tiny-workload shape
         return treegen.draw_problem(treegen.uniform_tree([2, 2, 2, 1, 1]), 4, 2, rng)
     if name == "odd_ragged":      # odd nx, nu; uneven branching; S, q, r, p present
         counts, n = [], 1
@@ -41,7 +46,7 @@ def case(name):
             counts.append(ct.tolist())
             n = int(ct.sum())
         return treegen.draw_problem(treegen.tree_from_counts(counts), 5, 3, rng, cross_terms=True)
-    if name == "cfg1_shape":      # config-1 blocks (nx=50, nu=30) on a small tree
+    if name == "large_blocks":      # large-tree blocks (nx=50, nu=30) on a small tree
         return treegen.draw_problem(treegen.uniform_tree([4, 4, 1, 1, 1]), 50, 30, rng,
                                     qdiag=(0.5, 2.0), rdiag=(0.05, 0.5))
     if name == "wide":            # nx + nu > 128: two 128-column chunks per lane
@@ -50,20 +55,20 @@ def case(name):
         return treegen.draw_problem(treegen.uniform_tree([1] * 12), 7, 3, rng)
     if name == "no_chain":        # branching at every stage (s* = N)
         return treegen.draw_problem(treegen.uniform_tree([2, 3, 2]), 6, 4, rng)
-    if name == "capped":          # config-2 style uneven fan-out
+    if name == "capped":          # uneven-batch style fan-out
         return treegen.draw_problem(treegen.capped_tree(9, 23, 3), 9, 4, rng)
     if name == "mid_width":       # nx + nu in (32, 64]: two chains per wavefront; 13 chains
         return treegen.draw_problem(treegen.capped_tree(8, 13, 3), 24, 12, rng)
-    if name == "cfg4_shape":      # config-4 blocks (nx=64, nu=32) on a small tree
+    if name == "shared_blocks":      # shared-tree blocks (nx=64, nu=32) on a small tree
         return treegen.draw_problem(treegen.uniform_tree([4, 4, 1, 1, 1]), 64, 32, rng)
-    if name == "cfg3_shape":
+    if name == "warm_blocks":
         return treegen.draw_problem(treegen.uniform_tree([3, 3, 1, 1, 1, 1]), 20, 10, rng,
                                     x0_range=3.0)
     raise KeyError(name)
 
 
-SWEEP_CASES = ["tiny", "odd_ragged", "cfg1_shape", "wide", "single_path", "no_chain", "capped",
-               "mid_width", "cfg3_shape"]
+SWEEP_CASES = ["tiny", "odd_ragged", "large_blocks", "wide", "single_path", "no_chain", "capped",
+               "mid_width", "warm_blocks"]
 
 
 def with_tight_boxes(prob, xbox, ubox):

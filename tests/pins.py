@@ -41,7 +41,7 @@ def feasible(prob) -> bool:
 
 
 def tight_tiny(seed=7):
-    """Config-0 shape with boxes tight enough that constraints bind; the first
+    """Tiny-workload shape with boxes tight enough that constraints bind; the first
     LP-feasible draw at or after ``seed``."""
     for s in range(seed, seed + 200):
         pr = treegen.draw_problem(treegen.uniform_tree([2, 2, 2, 1, 1]), 4, 2,

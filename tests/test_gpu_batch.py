@@ -27,7 +27,7 @@ def _t(a):
 
 
 def forest_cases():
-    probs = [case(n) for n in ("odd_ragged", "capped", "single_path", "no_chain", "tiny", "cfg3_shape")]
+    probs = [case(n) for n in ("odd_ragged", "capped", "single_path", "no_chain", "tiny", "warm_blocks")]
     probs += treegen.draw_batch_instances(6, seed=77, scale=0.05, N_range=(6, 12))
     return probs
 
@@ -83,7 +83,7 @@ def test_batched_lipschitz_per_instance(st):
 
 
 def solver_forest():
-    return [pins.tight_tiny(), pins.ragged_cross(), with_tight_boxes(case("cfg3_shape"), 3.0, 0.4),
+    return [pins.tight_tiny(), pins.ragged_cross(), with_tight_boxes(case("warm_blocks"), 3.0, 0.4),
             pins.tight_tiny(seed=40)]
 
 

@@ -10,7 +10,7 @@ from gpu_cases import TOL_GRAD, case, row_scale
 
 pytestmark = pytest.mark.gpu
 
-PANEL_CASES = ["tiny", "odd_ragged", "cfg1_shape", "cfg4_shape", "mid_width", "cfg3_shape", "capped",
+PANEL_CASES = ["tiny", "odd_ragged", "large_blocks", "shared_blocks", "mid_width", "warm_blocks", "capped",
                "single_path", "no_chain", "wide"]
 
 
@@ -63,7 +63,7 @@ def test_panel_matches_single_sweeps_and_oracle(st, name, homogeneous):
 
 
 def test_panel_on_batched_handle(st):
-    probs = [case(n) for n in ("odd_ragged", "capped", "cfg3_shape", "mid_width")]
+    probs = [case(n) for n in ("odd_ragged", "capped", "warm_blocks", "mid_width")]
     probs += treegen.draw_batch_instances(4, seed=5, scale=0.03, N_range=(5, 8))
     tf = st.tree_factor_batch(probs, precondition=True)
     rng = np.random.default_rng(9)
@@ -89,7 +89,7 @@ def test_shared_handle_sweeps_match_solo(st, count, pmin):
     count is a multiple of 64) against each instance's own handle."""
     import dataclasses
     import torch
-    base = case("cfg4_shape") if count == 64 else case("odd_ragged")
+    base = case("shared_blocks") if count == 64 else case("odd_ragged")
     tf = st.tree_factor_shared(base, count, precondition=True)
     assert tf.ninst == count and tf.m == count * base.m
     st.sweep_schedule(tf, (8, 1, 16, 0, pmin))   # 65 > count: the copies on lane groups

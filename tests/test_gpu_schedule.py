@@ -31,7 +31,7 @@ def _t(a):
 def mixed_forest():
     """Widths nx+nu from 6 to 142: every lane-group width and both column
     chunkings, ragged chain counts."""
-    probs = [case(n) for n in ("tiny", "odd_ragged", "mid_width", "cfg3_shape", "capped", "wide",
+    probs = [case(n) for n in ("tiny", "odd_ragged", "mid_width", "warm_blocks", "capped", "wide",
                                "single_path", "no_chain")]
     probs += treegen.draw_batch_instances(5, seed=91, scale=0.04, N_range=(5, 9))
     return probs

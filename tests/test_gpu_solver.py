@@ -28,7 +28,7 @@ def solver_cases():
     return {
         "tight_tiny": pins.tight_tiny,
         "ragged_cross": pins.ragged_cross,
-        "cfg3_tight": lambda: with_tight_boxes(case("cfg3_shape"), 3.0, 0.4),
+        "warm_tight": lambda: with_tight_boxes(case("warm_blocks"), 3.0, 0.4),
     }
 
 
@@ -44,7 +44,7 @@ def _gpu_solve(st, tf, prob, method, lam, y0=None, **kw):
 
 
 @pytest.mark.parametrize("method", ["minfbe", "nama"])
-@pytest.mark.parametrize("name", ["tight_tiny", "ragged_cross", "cfg3_tight"])
+@pytest.mark.parametrize("name", ["tight_tiny", "ragged_cross", "warm_tight"])
 def test_solution_matches_oracle(st, method, name):
     prob = solver_cases()[name]()
     print(f"{method} {name}", flush=True)
@@ -117,9 +117,9 @@ def test_warm_start_at_solution_stops_immediately(st):
 
 
 @pytest.mark.parametrize("method", ["minfbe", "nama"])
-def test_config0_as_specified(st, method):
+def test_tiny_workload_as_specified(st, method):
     import treegen
-    prob = treegen.make_config(0)
+    prob = treegen.make_workload("tiny")
     tf = st.tree_factor(prob, precondition=True)
     rc, info, y, x, u = _gpu_solve(st, tf, prob, method, 0.0, eps=1e-6)
     assert rc == 0 and info["res_scaled_inf"] <= 1e-6

@@ -1,6 +1,6 @@
 """GPU parity of the factor step and the sweeps (Algorithms 3 and 4) through
 the C ABI, against the CPU oracle element by element, and at the full size of
-the config-1 workload against the inner problem's optimality conditions."""
+the large-tree workload against the inner problem's optimality conditions."""
 import numpy as np
 import pytest
 
@@ -89,7 +89,7 @@ def test_zero_dual_edge_case(st):
 
 
 def test_deterministic_repeat(st):
-    prob = case("cfg1_shape")
+    prob = case("large_blocks")
     tf = st.tree_factor(prob, precondition=True)
     y = np.random.default_rng(2).standard_normal(tf.m)
     a = _run(st, tf, prob.x0, y, False)
@@ -108,12 +108,12 @@ def test_not_positive_definite_is_reported(st):
     assert ei.value.code == -3
 
 
-def test_config1_full_size_kkt(st):
-    """Config-1 tree at full size (62,805 nodes, nx=50, nu=30): the GPU x(y)
+def test_large_tree_full_size_kkt(st):
+    """Large tree at full size (62,805 nodes, nx=50, nu=30): the GPU x(y)
     satisfies the dynamics and the stationarity conditions of the inner
     problem at a random dual; x-hat(r) likewise for the homogeneous problem."""
-    prob = treegen.make_config(1)
-    print("config 1 generated", flush=True)
+    prob = treegen.make_workload("large")
+    print("large tree generated", flush=True)
     tf = st.tree_factor(prob, precondition=True)
     rng = np.random.default_rng(5)
     sc = row_scale(prob)

@@ -30,11 +30,11 @@ def _built():
 
 
 PROBLEMS = {"tiny": pins.tight_tiny, "ragged": pins.ragged_cross,
-            "cfg0": lambda: treegen.make_config(0)}
+            "tiny_workload": lambda: treegen.make_workload("tiny")}
 
 
 def test_tree_invariants():
-    trees = [treegen.uniform_tree(treegen.CONFIG_SHAPES[k]["branching"]) for k in (0, 1, 3)]
+    trees = [treegen.uniform_tree(treegen.WORKLOAD_SHAPES[k]["branching"]) for k in ("tiny", "large", "warm")]
     trees += [pins.ragged_cross().tree, treegen.capped_tree(12, 37, 3), treegen.capped_tree(10, 1024, 2)]
     for t in trees:
         V, N = t.V, t.N
@@ -49,14 +49,14 @@ def test_tree_invariants():
         assert t.child_ptr[t.Vnl] == V
         # leaves all at stage N
         assert t.stage_ptr[N] == t.Vnl
-    t1 = treegen.uniform_tree(treegen.CONFIG_SHAPES[1]["branching"])
+    t1 = treegen.uniform_tree(treegen.WORKLOAD_SHAPES["large"]["branching"])
     assert (t1.V, t1.Vnl, t1.Vl) == (62805, 58709, 4096)
     t = treegen.capped_tree(12, 37, 3)
     sizes = np.diff(t.stage_ptr)
     assert list(sizes[:5]) == [1, 3, 9, 27, 37] and (sizes[4:] == 37).all()
 
 
-@pytest.mark.parametrize("name", ["tiny", "ragged", "cfg0"])
+@pytest.mark.parametrize("name", ["tiny", "ragged", "tiny_workload"])
 def test_sweep_matches_dense_kkt(name):
     assert pins.pin_kkt_affine(PROBLEMS[name]()) < PIN_TOL["kkt_affine"]
 
@@ -219,7 +219,7 @@ def test_lbfgs_secant_and_dense_recursion():
     assert np.array_equal(oracle.lbfgs_direction([], [], g), -g)
 
 
-def test_minfbe_and_nama_agree_with_each_other_on_cfg0_shape():
+def test_minfbe_and_nama_agree_with_each_other_on_tiny_workload():
     prob = pins.tight_tiny(seed=3)
     pb, fac = oracle.factor(prob)
     L = oracle.power_iteration(pb, fac, True, 400)

@@ -33,8 +33,8 @@ import numpy as np
 
 __all__ = [
     "Tree", "Problem", "tree_from_counts", "uniform_tree", "capped_tree",
-    "draw_problem", "make_config", "draw_batch_instances", "random_dual",
-    "CONFIG_SHAPES",
+    "draw_problem", "make_workload", "draw_batch_instances", "random_dual",
+    "WORKLOAD_SHAPES",
 ]
 
 
@@ -227,35 +227,40 @@ def draw_problem(tree: Tree, nx: int, nu: int, rng: np.random.Generator, *,
                    S=S, q=q, r=r, p=p, name=name)
 
 
-# Shapes of the five workloads; the tree of config 2 is drawn per instance.
-CONFIG_SHAPES = {
-    0: dict(nx=4, nu=2, branching=[2, 2, 2, 1, 1]),
-    1: dict(nx=50, nu=30, branching=[4] * 6 + [1] * 14),
-    3: dict(nx=20, nu=10, branching=[3] * 5 + [1] * 10),
-    4: dict(nx=64, nu=32, branching=[4] * 7 + [1] * 13),
+# Shapes of the single-tree workloads (the uneven batch draws one tree per
+# instance, draw_batch_instances):
+#   tiny    nx=4,  nu=2,  N=5,  branching 2 at stages 0-2 (8 scenarios)
+#   large   nx=50, nu=30, N=20, branching 4 at stages 0-5 (4096 scenarios)
+#   warm    nx=20, nu=10, N=15, branching 3 at stages 0-4 (243 scenarios)
+#   shared  nx=64, nu=32, N=20, branching 4 at stages 0-6 (16384 scenarios)
+WORKLOAD_SHAPES = {
+    "tiny": dict(nx=4, nu=2, branching=[2, 2, 2, 1, 1], seed=1000),
+    "large": dict(nx=50, nu=30, branching=[4] * 6 + [1] * 14, seed=1001),
+    "warm": dict(nx=20, nu=10, branching=[3] * 5 + [1] * 10, seed=1003),
+    "shared": dict(nx=64, nu=32, branching=[4] * 7 + [1] * 13, seed=1004),
 }
 
 
-def make_config(k: int, seed: int | None = None) -> Problem:
-    """The single-tree workloads 0, 1, 3 and 4 (seed default 1000 + k)."""
-    if k not in CONFIG_SHAPES:
-        raise ValueError(f"config {k} is not a single-tree workload")
-    rng = np.random.default_rng(1000 + k if seed is None else seed)
-    sh = CONFIG_SHAPES[k]
+def make_workload(name: str, seed: int | None = None) -> Problem:
+    """One of the single-tree workloads of WORKLOAD_SHAPES (its own default seed)."""
+    if name not in WORKLOAD_SHAPES:
+        raise ValueError(f"{name!r} is not a single-tree workload")
+    sh = WORKLOAD_SHAPES[name]
+    rng = np.random.default_rng(sh["seed"] if seed is None else seed)
     tree = uniform_tree(sh["branching"])
     kw = {}
-    if k == 1:
+    if name == "large":
         kw = dict(qdiag=(0.5, 2.0), rdiag=(0.05, 0.5))
-    if k in (3, 4):
+    if name in ("warm", "shared"):
         kw = dict(x0_range=3.0)
-    return draw_problem(tree, sh["nx"], sh["nu"], rng, name=f"cfg{k}", **kw)
+    return draw_problem(tree, sh["nx"], sh["nu"], rng, name=name, **kw)
 
 
 def draw_batch_instances(count: int = 256, seed: int = 1002, *,
                          nx_range=(8, 32), N_range=(10, 30),
                          S_range=(16, 1024), b0_range=(2, 8),
                          scale: float = 1.0) -> list:
-    """Uneven batch of independent instances (workload 2).
+    """Uneven batch of independent instances (the uneven-batch workload).
 
     Per instance: nx ~ U{nx_range}, nu = nx // 2, N ~ U{N_range},
     scenarios S ~ U{S_range} (times ``scale``, for reduced test sizes),
@@ -279,7 +284,7 @@ def draw_batch_instances(count: int = 256, seed: int = 1002, *,
     def one(b):
         nx, nu, N, S, b0 = shapes[b]
         return draw_problem(capped_tree(N, S, b0), nx, nu, np.random.default_rng([seed, b]),
-                            name=f"cfg2[{b}]", threads=1)
+                            name=f"batch[{b}]", threads=1)
 
     nthreads = min(16, os.cpu_count() or 1)
     if count < 4 or nthreads == 1:
