@@ -638,6 +638,11 @@ def main():
     tf = stotree.tree_factor(prob, precondition=True)
     factor_s = time.perf_counter() - t0
     log(f"factor step {factor_s:.2f} s, device bytes {tf.device_bytes / 1e9:.2f} GB, s*={tf.sstar}")
+    # the library's autotuner picks the sweep schedule (timed sweeps, well under a second)
+    t0 = time.perf_counter()
+    tune = stotree.sweep_autotune(tf, nrhs=1, reps=5, cache=args.tune_cache)
+    log(f"schedule {tune['knobs']} ({'cached' if tune['cached'] else 'tuned'} in "
+        f"{time.perf_counter() - t0:.1f} s)")
 
     rng = np.random.default_rng(11)
     y = torch.tensor(rng.standard_normal(tf.m), dtype=torch.float64, device=dev)
@@ -768,7 +773,7 @@ def main():
                                 "stages 0-5 then 1 (4096 scenarios, 62805 nodes, 4.90M primal / "
                                 "4.90M dual variables); step = one FP64 dual-gradient sweep x(y)"),
                    "nodes": prob.tree.V, "m": prob.m, "precondition": True,
-                   "factor_seconds": factor_s},
+                   "factor_seconds": factor_s, "schedule": tune["knobs"]},
         "roofline": roofline,
         "phases": phase_rep,
         "cpu_baseline": cpu,
