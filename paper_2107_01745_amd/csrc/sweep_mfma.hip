@@ -17,10 +17,14 @@
 // of a product is cut into 16-row tiles of the x part and of the u part, each
 // tile in two halves of 32 right-hand sides; the (tile, half) tasks are dealt
 // round-robin to the wavefronts, and every task keeps its two 16x16 result
-// blocks in registers.  Backward: the x tiles of sum A'qhat and of K'g land on
-// the same wavefront and lanes, so qhat_i is formed in registers; g goes to LDS
-// as the input of [K; -R~^{-1}] g.  Sums over the K dimension run in a fixed
-// order (deterministic results).
+// blocks in registers.  The result accumulators start at the node's own
+// vector terms (s_i y_i + chat_i / sig_i backward, k_i and c_j forward); the
+// finished blocks go to the LDS panel, where they are the input of the next
+// product (g for [K; -R~^{-1}] g, [x; u] for the children), and each lane
+// completes its own entries of qhat_i there.  No load sits under a branch:
+// the factor rows of a batch are all in flight together, and the next batch
+// is loaded before the current one is multiplied.  Sums over the K dimension
+// run in a fixed order (deterministic results).
 //
 // Operand layout of v_mfma_f64_16x16x4f64 (D = A B + C, A 16x4, B 4x16):
 // lane l holds A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4e][l%16], e < 4
