@@ -40,6 +40,7 @@ namespace {
 
 constexpr int kMemMax = 16;   // L-BFGS memory supported on the device
 constexpr int kNuCap = 30;    // largest nu_max
+constexpr int kNuDefault = 10; // default nu_max
 constexpr int kVB = 256;      // threads per block of the vector kernels
 
 // reduction slots
@@ -282,7 +283,9 @@ __global__ void __launch_bounds__(kVB) combine_kernel(VecArgs a)
 }
 
 // All trial steps in one pass; slot nu holds sum over rows of the change of
-// the FBE at w(tau_nu) relative to y.
+// the FBE at w(tau_nu) relative to y.  NUC: the largest nu_max the variant
+// serves (its accumulators, and so its register demand, scale with it).
+template <int NUC>
 __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
 {
     const BlockRows br = block_rows(a);
@@ -291,9 +294,9 @@ __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
     const double lam = c->lam;
     const int numax = c->nu_max;
     const bool nama = a.method == 1;
-    double acc[kNuCap + 2];
+    double acc[NUC + 1];
 #pragma unroll
-    for (int v = 0; v < kNuCap + 2; ++v) acc[v] = 0.0;
+    for (int v = 0; v < NUC + 1; ++v) acc[v] = 0.0;
     FOR_BLOCK_ROWS(br, kl, k) {
         const double s = row_scale(a, br, kl);
         const double lo = s * a.lo[br.I.box + kl], hi = s * a.hi[br.I.box + kl];
@@ -304,7 +307,7 @@ __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
         const double ey = yk * (rk + ah) - 0.5 * lam * rk * rk;
         double tau = 1.0;
 #pragma unroll
-        for (int nu = 0; nu <= kNuCap; ++nu) {
+        for (int nu = 0; nu <= NUC; ++nu) {
             if (nu <= numax) {
                 const double cr = nama ? -(1.0 - tau) * lam : 0.0;
                 const double dl = cr * rk + tau * dk;     // w - y
@@ -318,12 +321,12 @@ __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
         }
     }
     // slots [0, kNMax) are the max-reduced ones; the sums follow them
-    double packed[kNuCap + 2 + kNMax];
+    double packed[kNMax + NUC + 1];
 #pragma unroll
     for (int v = 0; v < kNMax; ++v) packed[v] = 0.0;
 #pragma unroll
-    for (int v = 0; v < kNuCap + 2; ++v) packed[kNMax + v] = acc[v];
-    block_store<kNuCap + 2 + kNMax>(packed, kNMax + kNuCap + 1, a.part, a.nblocks);
+    for (int v = 0; v < NUC + 1; ++v) packed[kNMax + v] = acc[v];
+    block_store<kNMax + NUC + 1>(packed, kNMax + NUC + 1, a.part, a.nblocks);
 }
 
 __global__ void __launch_bounds__(kVB) update_kernel(VecArgs a)
@@ -616,7 +619,7 @@ SweepArgs dual_layout_sweep(const tree_factors *f, int affine, const double *x0,
     return a;
 }
 
-template <int MEMCAP>
+template <int MEMCAP, int NUC>
 hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *ybuf[2], int k, int method,
                              int active, hipStream_t st)
 {
@@ -664,7 +667,7 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
     VecArgs la = vec_args(f);
     la.method = method;
     la.y = y; la.rp = r; la.d = w.d; la.hx = w.hx; la.hr = hr; la.hd = hd; la.yn = yn;
-    hipLaunchKernelGGL(ls_kernel, grid, blk, 0, st, la);
+    hipLaunchKernelGGL(ls_kernel<NUC>, grid, blk, 0, st, la);
     hipLaunchKernelGGL(fin_ls_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks);
     hipLaunchKernelGGL(update_kernel, grid, blk, 0, st, la);
     return hipGetLastError();
@@ -672,11 +675,20 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
 
 using IterFn = hipError_t (*)(const tree_factors *, const double *, double *[2], int, int, int, hipStream_t);
 
-IterFn pick_iter(int mem)
+// Variant for the L-BFGS memory (accumulators per pair slot) and the number
+// of line-search trials; the default options (mem 5, nu_max 10) have their own.
+template <int NUC>
+IterFn pick_iter_mem(int mem)
 {
-    if (mem <= 4) return enqueue_iteration<4>;
-    if (mem <= 8) return enqueue_iteration<8>;
-    return enqueue_iteration<16>;
+    if (mem <= 4) return enqueue_iteration<4, NUC>;
+    if (mem == 5) return enqueue_iteration<5, NUC>;
+    if (mem <= 8) return enqueue_iteration<8, NUC>;
+    return enqueue_iteration<16, NUC>;
+}
+
+IterFn pick_iter(int mem, int nu_max)
+{
+    return nu_max <= kNuDefault ? pick_iter_mem<kNuDefault>(mem) : pick_iter_mem<kNuCap>(mem);
 }
 
 // Power iteration on every instance (per-instance normalisation); leaves
@@ -773,7 +785,7 @@ int solve(const tree_factors *fc, const double *x0, const solver_opts *opts_in, 
     STOTREE_HIP(hipMemcpyAsync(dctl, h.data(), sizeof(Ctl) * h.size(), hipMemcpyHostToDevice, st));
     STOTREE_HIP(hipMemsetAsync(w.ndone, 0, sizeof(int), st));
     double *ybuf[2] = {y_io, w.y[1]};
-    IterFn iter = pick_iter(o.mem);
+    IterFn iter = pick_iter(o.mem, o.nu_max);
     int k = 0, ndone = 0;
     while (ndone < f->ninst && k <= o.max_iter) {
         // instances finished by the last check are skipped by the sweeps (the
