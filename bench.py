@@ -718,6 +718,7 @@ def main():
         tight = dataclasses.replace(prob, umin=np.full_like(prob.umin, -args.tight_u),
                                     umax=np.full_like(prob.umax, args.tight_u))
         tf_t = stotree.tree_factor(tight, precondition=True)
+        stotree.sweep_autotune(tf_t, nrhs=1, reps=5, cache=args.tune_cache)
         variants.append((f"u_box_{args.tight_u:g}", tf_t, tight))
         for vname, tfv, pv in variants:
             L = stotree.dual_lipschitz(tfv, 100)
