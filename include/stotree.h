@@ -184,7 +184,12 @@ int tree_instance_dims(const tree_factors *f, int b, int64_t *out);
  * batched handle, the concatenated sizes of tree_dims).
  * nrhs >= 1; right-hand sides are swept 64 at a time on the FP64 matrix
  * cores while at least 64 remain (when every nx + nu <= 128), the rest two at
- * a time, each group sharing one streaming of the factors.  Errors: ERR_ARG, ERR_OOM (workspace growth), ERR_DEVICE.
+ * a time, each group sharing one streaming of the factors.  On a shared
+ * handle (tree_factor_shared) whose copies form whole panels of 64, each
+ * right-hand side sweeps its copies as panels when the copy count reaches
+ * the schedule's panel minimum (sweep_schedule knobs[4]); otherwise, and on
+ * other shared handles, the right-hand sides go two at a time.
+ * Errors: ERR_ARG, ERR_OOM (workspace growth), ERR_DEVICE.
  */
 int dual_grad(const tree_factors *f, const double *x0, const double *y, int homogeneous,
               int nrhs, double *x, double *u, void *hip_stream);
