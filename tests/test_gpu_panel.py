@@ -253,3 +253,33 @@ def test_shared_handle_route_switch_keeps_solutions(st):
     for pmin in (16, 65):
         assert abs(out[pmin][1].mean() - its.mean()) <= 1.0, (pmin, out[pmin][1], its)
         assert np.abs(out[pmin][0] - out[1][0]).max() / s < 1e-6, pmin
+
+
+def test_two_panels_finishing_apart(st):
+    """128 copies (two panels) kept on the matrix cores throughout (panel
+    minimum 1): the second panel's copies start far from the first's, so one
+    panel finishes while the other still iterates and its sweeps are skipped;
+    every copy matches the same copies solved on lane groups only."""
+    import torch
+    base = _shared_base()
+    rng = np.random.default_rng(31)
+    X0 = np.concatenate([rng.uniform(-0.2, 0.2, (64, base.nx)), rng.uniform(-1.5, 1.5, (64, base.nx))])
+    pb, fac = oracle.factor(base)
+    lam = 1.0 / (1.1 * oracle.power_iteration(pb, fac, True, 300))
+    out = {}
+    for pmin in (1, 129):
+        tf = st.tree_factor_shared(base, 128, precondition=True)
+        st.sweep_schedule(tf, (8, 1, 16, 0, pmin))
+        y = _t(np.zeros(tf.m))
+        x = torch.zeros(tf.x_len, dtype=torch.float64, device="cuda:0")
+        u = torch.zeros(tf.u_len, dtype=torch.float64, device="cuda:0")
+        rc, _ = st.nama_solve(tf, _t(X0.ravel()), y, x, u, st.make_opts(lam=lam, eps=1e-8, max_iter=3000))
+        infos = st.solve_info_batch(tf)
+        assert rc == 0 and all(i["status"] == 0 and i["res_scaled_inf"] <= 1e-8 for i in infos), pmin
+        out[pmin] = (x.cpu().numpy(), np.array([i["iters"] for i in infos]))
+        tf.free()
+    its = out[1][1]
+    assert its[:64].max() < its[64:].max()      # the first panel finishes first
+    s = max(1.0, np.abs(out[129][0]).max())
+    assert np.abs(out[1][0] - out[129][0]).max() / s < 1e-6
+    assert abs(its.mean() - out[129][1].mean()) <= 1.0
