@@ -548,7 +548,7 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     del X, T, M
     drawn = treegen.draw_warm_instances(base, n_test + n_test // 4, seed=2004)
     test = screen_feasible(stotree, ws, base, drawn, lam, batch, tune)
-    n_test = min(n_test, len(test) // batch * batch)    # whole 64-draw panels
+    n_test = min(n_test, len(test) // batch * batch)    # whole batches of 64-draw panels
     test = test[:n_test]
     cold_b, warm_b, it_c, it_w, kept, ok_w = 0.0, 0.0, [], [], 0, 0
     for s in range(0, n_test, batch):
@@ -620,6 +620,7 @@ def main():
     ap.add_argument("--warm-test", type=int, default=256)
     ap.add_argument("--warm-solo", type=int, default=32)
     ap.add_argument("--warm-epochs", type=int, default=40)
+    ap.add_argument("--warm-batch", type=int, default=256, help="draws per shared handle (a multiple of 64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design "
@@ -758,7 +759,7 @@ def main():
     warm_rep = None
     if not args.no_warm:
         warm_rep = guarded("warm start", warm_leg, stotree, torch, args.warm_train, args.warm_test,
-                           args.warm_solo, 64, args.warm_epochs)
+                           args.warm_solo, args.warm_batch, args.warm_epochs)
 
     cpu = None
     if not args.no_cpu:
