@@ -150,3 +150,39 @@ def test_batch_instances_stop_independently(st):
     infos = st.solve_info_batch(tf)
     assert rc == 0 and infos[0]["iters"] == 0 and infos[1]["iters"] > 0
     tf.free()
+
+
+def test_uneven_batch_full_size_kkt(st):
+    """The uneven batch at full size (256 trees, about 2.2M nodes), in the
+    benchmark's launch configuration (autotuned schedule, one graph replay):
+    the x(y) of sampled instances (the smallest, the largest and two more)
+    satisfies the dynamics and stationarity of each instance's inner problem
+    at a random dual."""
+    import torch
+    from gpu_cases import inner_kkt_residual
+    probs = treegen.draw_batch_instances(256)
+    print("uneven batch generated", flush=True)
+    tf = st.tree_factor_batch(probs, precondition=True)
+    rec = st.sweep_autotune(tf, nrhs=1, reps=3)
+    print(f"schedule {rec['knobs']}", flush=True)
+    rng = np.random.default_rng(17)
+    ybar = rng.standard_normal(tf.m)
+    x0 = _t(np.concatenate([p.x0 for p in probs]))
+    y = _t(ybar)
+    x = torch.full((tf.x_len,), np.nan, dtype=torch.float64, device="cuda:0")
+    u = torch.full((tf.u_len,), np.nan, dtype=torch.float64, device="cuda:0")
+    graph = st.SweepGraph(tf, x0, y, False, x, u)
+    graph.launch()
+    torch.cuda.synchronize()
+    xh, uh = x.cpu().numpy(), u.cpu().numpy()
+    sizes = [p.tree.V for p in probs]
+    for b in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 200}):
+        p, d = probs[b], tf.instances[b]
+        xb = xh[d["x_off"]:d["x_off"] + d["V"] * d["nx"]].reshape(d["V"], d["nx"])
+        ub = uh[d["u_off"]:d["u_off"] + d["Vnl"] * d["nu"]].reshape(d["Vnl"], d["nu"])
+        yb = row_scale(p) * ybar[d["y_off"]:d["y_off"] + d["m"]]
+        dyn, stat = inner_kkt_residual(p, yb, xb, ub, p.x0)
+        print(f"instance {b} (V={d['V']}, nx={d['nx']}): dynamics {dyn:.2e}, stationarity {stat:.2e}", flush=True)
+        assert dyn < TOL_GRAD and stat < TOL_GRAD, b
+    graph.free()
+    tf.free()

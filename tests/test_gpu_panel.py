@@ -283,3 +283,37 @@ def test_two_panels_finishing_apart(st):
     s = max(1.0, np.abs(out[129][0]).max())
     assert np.abs(out[1][0] - out[129][0]).max() / s < 1e-6
     assert abs(its.mean() - out[129][1].mean()) <= 1.0
+
+
+def test_shared_tree_full_size_kkt(st):
+    """The shared tree at full size (234,837 nodes, nx=64, nu=32), 64 copies
+    with their own x0 swept as one panel per right-hand side on the matrix
+    cores, as the benchmark times it: the x(y) of copies 0 and 63 satisfies the
+    dynamics and stationarity of the inner problem at random duals (drawn on
+    the device; only the checked copies come back)."""
+    import dataclasses
+    import torch
+    from gpu_cases import inner_kkt_residual
+    prob = treegen.make_workload("shared")
+    print("shared tree generated", flush=True)
+    tf = st.tree_factor_shared(prob, 64, precondition=True)
+    rng = np.random.default_rng(13)
+    X0 = rng.uniform(-3, 3, (64, prob.nx))
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(13)
+    y = torch.randn(tf.m, dtype=torch.float64, device="cuda:0", generator=gen)
+    x = torch.empty(tf.x_len, dtype=torch.float64, device="cuda:0")
+    u = torch.empty(tf.u_len, dtype=torch.float64, device="cuda:0")
+    st.dual_grad(tf, _t(X0.ravel()), y, False, x, u)
+    torch.cuda.synchronize()
+    print("panel sweep done", flush=True)
+    sc = row_scale(prob)
+    for k in (0, 63):
+        d = tf.instances[k]
+        xb = x[d["x_off"]:d["x_off"] + d["V"] * d["nx"]].cpu().numpy().reshape(d["V"], d["nx"])
+        ub = u[d["u_off"]:d["u_off"] + d["Vnl"] * d["nu"]].cpu().numpy().reshape(d["Vnl"], d["nu"])
+        yb = sc * y[d["y_off"]:d["y_off"] + d["m"]].cpu().numpy()
+        dyn, stat = inner_kkt_residual(dataclasses.replace(prob, x0=X0[k]), yb, xb, ub, X0[k])
+        print(f"copy {k}: dynamics {dyn:.2e}, stationarity {stat:.2e}", flush=True)
+        assert dyn < TOL_GRAD and stat < TOL_GRAD, k
+    tf.free()
