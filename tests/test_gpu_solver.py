@@ -127,3 +127,33 @@ def test_tiny_workload_as_specified(st, method):
     ev = oracle.evaluate(pb, fac, y, info["lam"], True)
     assert np.abs(ev["R"]).max() <= TOL_RES
     tf.free()
+
+
+def test_large_tree_solves_full_size(st):
+    """The large tree at full size with abs(u) <= 0.1 (the benchmark's solve),
+    NAMA and MINFBE from a cold start to a 1e-6 residual on the GPU; the CPU
+    oracle, factored independently, recomputes the residual at the GPU's final
+    dual (<= 1e-6) and x(y) there (the GPU's returned primal)."""
+    import dataclasses
+    import treegen
+    prob = treegen.make_workload("large")
+    tight = dataclasses.replace(prob, umin=np.full_like(prob.umin, -0.1), umax=np.full_like(prob.umax, 0.1))
+    print("large tree generated", flush=True)
+    tf = st.tree_factor(tight, precondition=True)
+    lam = 1.0 / (1.1 * st.dual_lipschitz(tf, 100))
+    sols = {}
+    for method in ("nama", "minfbe"):
+        rc, info, y, x, u = _gpu_solve(st, tf, tight, method, lam, eps=1e-6, max_iter=2000)
+        print(f"{method}: rc {rc}, iterations {info['iters']}, residual {info['res_scaled_inf']:.2e}", flush=True)
+        assert rc == 0 and info["res_scaled_inf"] <= 1e-6
+        sols[method] = (y, x, u)
+    tf.free()
+    pb, fac = oracle.factor(tight)
+    print("oracle factored", flush=True)
+    for method, (y, x, u) in sols.items():
+        ev = oracle.evaluate(pb, fac, y, lam, True)
+        res = np.abs(ev["R"]).max()
+        scale = max(1.0, np.abs(ev["x"]).max())
+        print(f"{method}: oracle residual {res:.2e}", flush=True)
+        assert res <= TOL_RES
+        assert np.abs(x - ev["x"]).max() / scale < 1e-9 and np.abs(u - ev["u"]).max() / scale < 1e-9
