@@ -239,8 +239,8 @@ def tree_factor_shared(prob, count: int, precondition: bool = True, c=None, stre
 def tree_factor_batch(probs, precondition: bool = True, stream=None) -> TreeFactors:
     """Factor step on a list of treegen.Problem instances (one handle)."""
     keep = []
-    tds, pds = zip(*[_descs(p, keep) for p in probs])
     n = len(probs)
+    tds, pds = zip(*[_descs(p, keep) for p in probs]) if n else ((), ())
     tarr = (TreeDesc * n)(*tds)
     parr = (ProblemData * n)(*pds)
     h = C.c_void_p()

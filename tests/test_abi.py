@@ -97,6 +97,16 @@ def test_rejects_sizes(st):
     _expect(st, p, -1)
 
 
+def test_rejects_degenerate_sizes(st):
+    """No inputs (nu = 0), a tree that is only its root (N = 0) and an empty
+    batch are rejected with ERR_ARG before any device work."""
+    _expect(st, treegen.draw_problem(treegen.uniform_tree([2, 1, 1]), 3, 0, np.random.default_rng(0)), -1)
+    _expect(st, treegen.draw_problem(treegen.uniform_tree([]), 3, 2, np.random.default_rng(0)), -1)
+    with pytest.raises(st.StotreeError) as ei:
+        st.tree_factor_batch([])
+    assert ei.value.code == -1
+
+
 def test_schedule_graph_calls_reject_null_on_host(st):
     import ctypes as C
     L = st.lib()
