@@ -51,6 +51,10 @@ def case(name):
                                     qdiag=(0.5, 2.0), rdiag=(0.05, 0.5))
     if name == "wide":            # nx + nu > 128: two 128-column chunks per lane
         return treegen.draw_problem(treegen.uniform_tree([3, 1, 1]), 97, 45, rng)
+    if name == "widest":          # nx + nu = 256, the largest width the sweeps take
+        return treegen.draw_problem(treegen.uniform_tree([2, 1, 1]), 170, 86, rng)
+    if name == "panel_wide":      # nx + nu = 124: four tasks per wavefront in the 64-RHS backward step
+        return treegen.draw_problem(treegen.uniform_tree([3, 1, 1]), 80, 44, rng)
     if name == "single_path":     # the whole tree is one chain (s* = 0)
         return treegen.draw_problem(treegen.uniform_tree([1] * 12), 7, 3, rng)
     if name == "no_chain":        # branching at every stage (s* = N)
@@ -67,7 +71,7 @@ def case(name):
     raise KeyError(name)
 
 
-SWEEP_CASES = ["tiny", "odd_ragged", "large_blocks", "wide", "single_path", "no_chain", "capped",
+SWEEP_CASES = ["tiny", "odd_ragged", "large_blocks", "wide", "widest", "single_path", "no_chain", "capped",
                "mid_width", "warm_blocks"]
 
 

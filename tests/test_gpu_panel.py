@@ -10,7 +10,7 @@ from gpu_cases import TOL_GRAD, case, row_scale
 
 pytestmark = pytest.mark.gpu
 
-PANEL_CASES = ["tiny", "odd_ragged", "large_blocks", "shared_blocks", "mid_width", "warm_blocks", "capped",
+PANEL_CASES = ["tiny", "odd_ragged", "large_blocks", "shared_blocks", "panel_wide", "mid_width", "warm_blocks", "capped",
                "single_path", "no_chain", "wide"]
 
 
