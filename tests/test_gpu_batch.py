@@ -152,6 +152,34 @@ def test_batch_instances_stop_independently(st):
     tf.free()
 
 
+@pytest.mark.parametrize("method", ["nama", "minfbe"])
+def test_polling_interval_changes_no_iterate(st, method):
+    """Polling the stop counter every 5 iterations instead of every one
+    changes no bit of the result: finished instances are skipped on the
+    device, so the extra iterations the host enqueues do nothing."""
+    import torch
+    probs = solver_forest()
+    lams = []
+    for p in probs:
+        pb, fac = oracle.factor(p)
+        lams.append(1.0 / (1.1 * oracle.power_iteration(pb, fac, True, 300)))
+    lam = min(lams)
+    tf = st.tree_factor_batch(probs, precondition=True)
+    x0 = _t(np.concatenate([p.x0 for p in probs]))
+    out = []
+    for every in (1, 5):
+        y = _t(np.zeros(tf.m))
+        x = torch.zeros(tf.x_len, dtype=torch.float64, device="cuda:0")
+        u = torch.zeros(tf.u_len, dtype=torch.float64, device="cuda:0")
+        fn = st.nama_solve if method == "nama" else st.minfbe_solve
+        rc, _ = fn(tf, x0, y, x, u, st.make_opts(lam=lam, eps=1e-8, check_every=every))
+        assert rc == 0
+        out.append((y.cpu().numpy(), x.cpu().numpy(), [i["iters"] for i in st.solve_info_batch(tf)]))
+    assert out[0][2] == out[1][2] and len(set(out[0][2])) > 1      # instances stop at different iterations
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    tf.free()
+
+
 def test_uneven_batch_full_size_kkt(st):
     """The uneven batch at full size (256 trees, about 2.2M nodes), in the
     benchmark's launch configuration (autotuned schedule, one graph replay):
