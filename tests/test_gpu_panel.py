@@ -169,7 +169,8 @@ def test_shared_handle_with_own_disturbances(st, count):
     tf.free()
 
 
-def test_shared_handle_with_own_disturbances_solves(st):
+@pytest.mark.parametrize("method", ["nama", "minfbe"])
+def test_shared_handle_with_own_disturbances_solves(st, method):
     """64 copies with their own x0 and c solved together (panels) against the
     oracle solution of each copy."""
     import torch
@@ -181,14 +182,15 @@ def test_shared_handle_with_own_disturbances_solves(st):
     y = _t(np.zeros(tf.m))
     x = torch.zeros(tf.x_len, dtype=torch.float64, device="cuda:0")
     u = torch.zeros(tf.u_len, dtype=torch.float64, device="cuda:0")
-    rc, agg = st.nama_solve(tf, _t(np.concatenate([p.x0 for p in draws])), y, x, u,
-                            st.make_opts(lam=lam, eps=1e-8, max_iter=3000))
+    fn = st.nama_solve if method == "nama" else st.minfbe_solve
+    rc, agg = fn(tf, _t(np.concatenate([p.x0 for p in draws])), y, x, u,
+                 st.make_opts(lam=lam, eps=1e-8, max_iter=3000))
     infos = st.solve_info_batch(tf)
     xh = x.cpu().numpy()
     checked = 0
     for k in (0, 9, 40, 63):
         pk, fk = oracle.factor(draws[k])
-        ref = oracle.solve(pk, fk, "nama", lam, eps=1e-10, max_iter=5000)
+        ref = oracle.solve(pk, fk, method, lam, eps=1e-10, max_iter=5000)
         if ref["status"] != 0:
             continue          # a draw without a feasible point: nothing to compare
         assert infos[k]["status"] == 0 and infos[k]["res_scaled_inf"] <= 1e-8, infos[k]
@@ -316,4 +318,29 @@ def test_shared_tree_full_size_kkt(st):
         dyn, stat = inner_kkt_residual(dataclasses.replace(prob, x0=X0[k]), yb, xb, ub, X0[k])
         print(f"copy {k}: dynamics {dyn:.2e}, stationarity {stat:.2e}", flush=True)
         assert dyn < TOL_GRAD and stat < TOL_GRAD, k
+    tf.free()
+
+
+def test_graph_replay_of_panel_sweep(st):
+    """A shared handle's dual_grad (one 64-copy panel per right-hand side on
+    the matrix cores) recorded as a HIP graph: replays with new duals at the
+    bound address, and eager work in between, equal eager sweeps bit for bit."""
+    import torch
+    base = case("shared_blocks")
+    tf = st.tree_factor_shared(base, 64, precondition=True)
+    rng = np.random.default_rng(19)
+    x0 = _t(rng.uniform(-2, 2, 64 * base.nx))
+    y = _t(rng.standard_normal(tf.m))
+    x = torch.zeros(tf.x_len, dtype=torch.float64, device="cuda:0")
+    u = torch.zeros(tf.u_len, dtype=torch.float64, device="cuda:0")
+    g = st.SweepGraph(tf, x0, y, False, x, u)
+    for rep in range(4):
+        y.copy_(_t(rng.standard_normal(tf.m)))
+        x.fill_(np.nan)
+        u.fill_(np.nan)
+        g.launch()
+        torch.cuda.synchronize()
+        xe, ue = _many(st, tf, x0, y, False, 1)
+        assert np.array_equal(x.cpu().numpy(), xe[0]) and np.array_equal(u.cpu().numpy(), ue[0]), rep
+    g.free()
     tf.free()
