@@ -112,6 +112,59 @@ __device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, 
     if (b < nbt) fma_rows<NRHS, CH>(m0, v, ldv, r0 + b * kRowBatch, cnt(b), acc);
 }
 
+// The product of gemv_rows split in two so that its loads can be issued
+// before the vector exists: stream_open<D> loads the range's first D (1 or
+// 2) batches of rows (the rows only depend on the node), stream_run
+// multiplies them once v is in LDS and streams the rest double-buffered.
+// Used where a node's latency, not its bandwidth, bounds the step: the
+// stages above s*.  An open stream holds D*kRowBatch*CH double2 registers.
+template <int CH>
+struct RowStream {
+    const double *M;
+    int ld, r0, n;
+    int col[CH];
+    double2 m0[kRowBatch][CH], m1[kRowBatch][CH];
+};
+
+template <int CH>
+__device__ __forceinline__ int stream_cnt(const RowStream<CH> &s, int b)
+{
+    return s.n - b * kRowBatch < kRowBatch ? s.n - b * kRowBatch : kRowBatch;
+}
+
+template <int D, int CH>
+__device__ __forceinline__ void stream_open(RowStream<CH> &s, const double *__restrict__ M, int ld, int r0, int r1,
+                                            int W, int lane)
+{
+    s.M = M;
+    s.ld = ld;
+    s.r0 = r0;
+    s.n = r1 > r0 ? r1 - r0 : 0;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c0 = 2 * lane + 2 * kWave * ch;
+        s.col[ch] = c0 < W ? c0 : 0;
+    }
+    if (s.n > 0) load_rows<CH>(s.m0, M, ld, r0, stream_cnt(s, 0), s.col);
+    if (D == 2 && s.n > kRowBatch) load_rows<CH>(s.m1, M, ld, r0 + kRowBatch, stream_cnt(s, 1), s.col);
+}
+
+template <int D, int NRHS, int CH>
+__device__ __forceinline__ void stream_run(RowStream<CH> &s, const double *v, int ldv, double (&acc)[NRHS][CH][2])
+{
+    const int nbt = (s.n + kRowBatch - 1) / kRowBatch;
+    if (D == 1 && nbt > 1) load_rows<CH>(s.m1, s.M, s.ld, s.r0 + kRowBatch, stream_cnt(s, 1), s.col);
+    for (int b = 0; b < nbt; b += 2) {
+        fma_rows<NRHS, CH>(s.m0, v, ldv, s.r0 + b * kRowBatch, stream_cnt(s, b), acc);
+        if (b + 2 < nbt) load_rows<CH>(s.m0, s.M, s.ld, s.r0 + (b + 2) * kRowBatch, stream_cnt(s, b + 2), s.col);
+        if (b + 1 < nbt) {
+            fma_rows<NRHS, CH>(s.m1, v, ldv, s.r0 + (b + 1) * kRowBatch, stream_cnt(s, b + 1), acc);
+            if (b + 3 < nbt)
+                load_rows<CH>(s.m1, s.M, s.ld, s.r0 + (b + 3) * kRowBatch, stream_cnt(s, b + 3), s.col);
+        }
+    }
+}
+
 // The same product for W <= G columns on a lane group of G lanes: each load
 // instruction brings in two rows per group, the even rows of the range in the
 // lower half of the group and the odd rows in the upper half (lane l of a
@@ -439,18 +492,57 @@ __device__ void bwd_trunk_node(const SweepArgs &a, const InstDesc &I, int i, int
 {
     const int nx = I.nx, nu = I.nu, W = nx + nu, ldq = I.ldx, ldM = I.ldM;
     const int *cp = a.cp + I.cp;
-    const int CB = child_batch(NRHS, ldq);
+    // batches of [A_j B_j] rows requested up front (two where the registers allow)
+    constexpr int kDepth = CH == 1 && NW <= 8 ? 2 : 1;
+    const int CB = child_batch(NRHS, ldq), ldv = CB * ldq;
     extern __shared__ double lds[];
-    double *qs = lds;                          // [CB][NRHS][ldq]
-    double *red = qs + CB * NRHS * ldq;        // [NW][NRHS][ldM]
-    double *as = red + NW * NRHS * ldM;        // [NRHS][ldM]
-    double *gs = as + NRHS * ldM;              // [NRHS][ldu]
+    double *qs = lds;                          // [NRHS][ldv]: a batch's children's qhat, child after child
+    double *red = qs + NRHS * ldv;             // [NW][NRHS][ldM]
+    double *as = red + NW * NRHS * ldM;        // [NRHS][ldM]: [sum A'q ; g_i] plus the node's own terms
     const int j0 = cp[i], nch = cp[i + 1] - j0;
+    // Everything that depends on node i alone is requested before the
+    // children's qhat: the wavefront's rows of -R~^{-1} and K_i (split over
+    // the 2nu rows as below) and, on wavefront 0, the node's own terms
+    // s_i y_i + [chat_i ; sigma_i], which seed its accumulator.
+    // (With two column chunks or 16 wavefronts the registers of all three
+    // streams would not fit: those rows are then requested after the
+    // children's product.)
+    RowStream<CH> rk, rq;
+    auto open_rk = [&]() {
+        const int R = 2 * nu, r0 = R * w / NW, r1 = R * (w + 1) / NW;
+        stream_open<1, CH>(rk, a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, r0, r1 < nu ? r1 : nu, nu, lane);
+        stream_open<1, CH>(rq, a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, (r0 > nu ? r0 : nu) - nu, r1 - nu,
+                           nx, lane);
+    };
+    if (CH == 1 && NW <= 8) open_rk();
     double acc[NRHS][CH][2];
     zero(acc);
+    if (w == 0) {
+        const double si = a.sc ? a.sc[I.sc + i] : 1.0;
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int c = 2 * lane + 2 * kWave * ch + e, cw = c < W ? c : W - 1;
+                double t = 0.0;
+                if (a.affine) {
+                    const int cx = cw < nx ? cw : nx - 1, cu = cw < nx ? 0 : cw - nx;
+                    const double ch_ = a.chat[I.chat + (long long)i * nx + cx];
+                    const double sg = a.sig[I.sig + (long long)i * nu + cu];
+                    t = cw < nx ? ch_ : sg;
+                }
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) acc[k][ch][e] = si * y_ptr(a, I, k, i)[cw] + t;
+            }
+    }
     for (int cb = 0; cb < nch; cb += CB) {
         const int nb = nch - cb < CB ? nch - cb : CB;
-        for (int e = threadIdx.x; e < nb * nx; e += blockDim.x) {
+        // the batch's rows of [A_j B_j] are contiguous (children are
+        // consecutive nodes): one range of R rows split over the wavefronts
+        const int R = nb * nx, r0 = (int)((long long)R * w / NW), r1 = (int)((long long)R * (w + 1) / NW);
+        RowStream<CH> mb;
+        stream_open<kDepth, CH>(mb, a.Mb + I.Mb + (long long)(j0 + cb) * nx * ldM, ldM, r0, r1, W, lane);
+        for (int e = threadIdx.x; e < R; e += blockDim.x) {
             const int c = e / nx, r = e - c * nx, j = j0 + cb + c;
 #pragma unroll
             for (int k = 0; k < NRHS; ++k) {
@@ -461,21 +553,14 @@ __device__ void bwd_trunk_node(const SweepArgs &a, const InstDesc &I, int i, int
                 } else {
                     q = qhat_ptr(a, I, k, j)[r];
                 }
-                qs[(c * NRHS + k) * ldq + r] = q;
+                qs[k * ldv + e] = q;
             }
         }
         __syncthreads();
-        const int R = nb * nx;
-        const int r0 = (int)((long long)R * w / NW), r1 = (int)((long long)R * (w + 1) / NW);
-        for (int c = r0 / nx; c < nb && c * nx < r1; ++c) {
-            const int lo = (r0 > c * nx ? r0 : c * nx) - c * nx;
-            const int hi = (r1 < (c + 1) * nx ? r1 : (c + 1) * nx) - c * nx;
-            if (lo < hi)
-                gemv_rows<NRHS, CH>(a.Mb + I.Mb + (long long)(j0 + cb + c) * nx * ldM, ldM, lo, hi, W,
-                                    qs + c * NRHS * ldq, ldq, acc, lane);
-        }
-        __syncthreads();
+        stream_run<kDepth, NRHS, CH>(mb, qs, ldv, acc);
+        if (cb + CB < nch) __syncthreads();   // qs is refilled
     }
+    if (!(CH == 1 && NW <= 8)) open_rk();
     store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, W, acc, lane);
     __syncthreads();
     for (int e = threadIdx.x; e < NRHS * W; e += blockDim.x) {
@@ -485,26 +570,12 @@ __device__ void bwd_trunk_node(const SweepArgs &a, const InstDesc &I, int i, int
         as[k * ldM + c] = s;
     }
     __syncthreads();
-    const double si = a.sc ? a.sc[I.sc + i] : 1.0;
-    for (int e = threadIdx.x; e < NRHS * nu; e += blockDim.x) {
-        const int k = e / nu, c = e - k * nu;
-        gs[k * I.ldu + c] = as[k * ldM + nx + c] + si * y_ptr(a, I, k, i)[nx + c] +
-                            (a.affine ? a.sig[I.sig + (long long)i * nu + c] : 0.0);
-    }
-    __syncthreads();
+    // g_i = as[nx:]: k_i = -R~^{-1} g_i and K_i' g_i
     double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
     zero(kacc);
     zero(qacc);
-    {
-        const int R = 2 * nu;
-        const int r0 = R * w / NW, r1 = R * (w + 1) / NW;
-        if (r0 < nu)
-            gemv_rows<NRHS, CH>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, r0, r1 < nu ? r1 : nu, nu, gs,
-                                I.ldu, kacc, lane);
-        if (r1 > nu)
-            gemv_rows<NRHS, CH>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, (r0 > nu ? r0 : nu) - nu,
-                                r1 - nu, nx, gs, I.ldu, qacc, lane);
-    }
+    stream_run<1, NRHS, CH>(rk, as + nx, ldM, kacc);
+    stream_run<1, NRHS, CH>(rq, as + nx, ldM, qacc);
     store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nu, kacc, lane);
     store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, nu, nx, qacc, lane);
     __syncthreads();
@@ -512,13 +583,10 @@ __device__ void bwd_trunk_node(const SweepArgs &a, const InstDesc &I, int i, int
         const int k = e / W, c = e - k * W;
         double s = 0.0;
         for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + c];
-        if (c < nu) {
+        if (c < nu)
             kbuf_ptr(a, I, k, i)[c] = s;
-        } else {
-            const int cx = c - nu;
-            qhat_ptr(a, I, k, i)[cx] = as[k * ldM + cx] + si * y_ptr(a, I, k, i)[cx] +
-                                       (a.affine ? a.chat[I.chat + (long long)i * nx + cx] : 0.0) + s;
-        }
+        else
+            qhat_ptr(a, I, k, i)[c - nu] = as[k * ldM + c - nu] + s;
     }
 }
 
@@ -569,6 +637,20 @@ __global__ void __launch_bounds__(kWave *NW) bwd_trunk_tree_kernel(SweepArgs a, 
     }
 }
 
+// The lane's entries of c_j (zero without disturbances): they seed the
+// accumulator of the wavefront that owns x_j's first rows.
+template <int CH>
+__device__ __forceinline__ void load_cvec(const SweepArgs &a, const InstDesc &I, int j, int lane, double (&cv)[CH][2])
+{
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int c = 2 * lane + 2 * kWave * ch + e;
+            cv[ch][e] = a.affine ? a.cvec[I.c + (long long)j * I.nx + (c < I.nx ? c : I.nx - 1)] : 0.0;
+        }
+}
+
 template <int NRHS, int CH, int NW>
 __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a)
 {
@@ -582,74 +664,108 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a)
     extern __shared__ double lds[];
     double *xs = lds;                 // [NRHS][ldM]: x_i then u_i
     double *red = xs + NRHS * ldM;    // [NW][NRHS][ldM]
-    for (int e = threadIdx.x; e < NRHS * nx; e += blockDim.x) {
-        const int k = e / nx, c = e - k * nx;
-        double v;
-        if (i == 0) {
-            v = a.affine ? a.x0[k * a.x0_rs + I.x0 + c] : 0.0;
-            x_ptr(a, I, k, 0)[c] = v;
-        } else {
-            v = x_ptr(a, I, k, i)[c];
-        }
-        xs[k * ldM + c] = v;
-    }
-    __syncthreads();
+    // batches of [A_j B_j]' rows requested up front (two where the registers allow)
+    constexpr int kDepth = CH == 1 && NW <= 8 ? 2 : 1;
+    const int j0 = cp[i], nch = cp[i + 1] - j0;
+    const int RB = nch >= NW ? 1 : NW / nch;
+    // Requested before x_i: the wavefront's rows of K_i' (k_i seeds
+    // wavefront 0's sum) and its first rows of a child's [A_j B_j]' with
+    // c_j; children go round-robin to the wavefronts, or, with fewer children
+    // than wavefronts, each child's rows are split into RB blocks.
+    RowStream<CH> kf, mf;
     double uacc[NRHS][CH][2];
     zero(uacc);
     {
         const int r0 = nx * w / NW, r1 = nx * (w + 1) / NW;
-        if (r0 < r1)
-            gemv_rows<NRHS, CH>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, r0, r1, nu, xs, ldM, uacc, lane);
+        stream_open<1, CH>(kf, a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, r0, r1, nu, lane);
+        if (w == 0)
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int c = 2 * lane + 2 * kWave * ch + e;
+#pragma unroll
+                    for (int k = 0; k < NRHS; ++k) uacc[k][ch][e] = kbuf_ptr(a, I, k, i)[c < nu ? c : nu - 1];
+                }
     }
+    int c = RB == 1 ? w : w / RB;
+    const int blk = RB == 1 ? 0 : w - c * RB;
+    double cv[CH][2];
+    if (c < nch) {
+        const int rr0 = W * blk / RB, rr1 = W * (blk + 1) / RB;
+        stream_open<kDepth, CH>(mf, a.Mf + I.Mf + (long long)(j0 + c) * W * I.ldx, I.ldx, rr0, rr1, nx, lane);
+        load_cvec<CH>(a, I, j0 + c, lane, cv);
+    }
+    for (int e = threadIdx.x; e < NRHS * nx; e += blockDim.x) {
+        const int k = e / nx, cc = e - k * nx;
+        double v;
+        if (i == 0) {
+            v = a.affine ? a.x0[k * a.x0_rs + I.x0 + cc] : 0.0;
+            x_ptr(a, I, k, 0)[cc] = v;
+        } else {
+            v = x_ptr(a, I, k, i)[cc];
+        }
+        xs[k * ldM + cc] = v;
+    }
+    __syncthreads();
+    stream_run<1, NRHS, CH>(kf, xs, ldM, uacc);
     store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nu, uacc, lane);
     __syncthreads();
     for (int e = threadIdx.x; e < NRHS * nu; e += blockDim.x) {
-        const int k = e / nu, c = e - k * nu;
-        double s = kbuf_ptr(a, I, k, i)[c];
-        for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + c];
-        u_ptr(a, I, k, i)[c] = s;
-        xs[k * ldM + nx + c] = s;
+        const int k = e / nu, cc = e - k * nu;
+        double s = 0.0;
+        for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + cc];
+        u_ptr(a, I, k, i)[cc] = s;
+        xs[k * ldM + nx + cc] = s;
     }
     __syncthreads();
-    const int j0 = cp[i], nch = cp[i + 1] - j0;
-    const int RB = nch >= NW ? 1 : NW / nch;
     if (RB == 1) {
-        for (int c = w; c < nch; c += NW) {
-            const int j = j0 + c;
+        for (; c < nch; c += NW) {
             double xacc[NRHS][CH][2];
-            zero(xacc);
-            gemv_rows<NRHS, CH>(a.Mf + I.Mf + (long long)j * W * I.ldx, I.ldx, 0, W, nx, xs, ldM, xacc, lane);
 #pragma unroll
-            for (int ch = 0; ch < CH; ++ch) {
-                const int c0 = 2 * lane + 128 * ch;
+            for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+                for (int ch = 0; ch < CH; ++ch) {
+                    xacc[k][ch][0] = cv[ch][0];
+                    xacc[k][ch][1] = cv[ch][1];
+                }
+            stream_run<kDepth, NRHS, CH>(mf, xs, ldM, xacc);
+            const int j = j0 + c;
+            if (c + NW < nch) {   // the next child's rows are in flight while x_j is stored
+                stream_open<kDepth, CH>(mf, a.Mf + I.Mf + (long long)(j + NW) * W * I.ldx, I.ldx, 0, W, nx, lane);
+                load_cvec<CH>(a, I, j + NW, lane, cv);
+            }
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch)
 #pragma unroll
                 for (int e2 = 0; e2 < 2; ++e2) {
-                    const int col = c0 + e2;
+                    const int col = 2 * lane + 2 * kWave * ch + e2;
                     if (col < nx)
 #pragma unroll
-                        for (int k = 0; k < NRHS; ++k)
-                            x_ptr(a, I, k, j)[col] =
-                                xacc[k][ch][e2] + (a.affine ? a.cvec[I.c + (long long)j * nx + col] : 0.0);
+                        for (int k = 0; k < NRHS; ++k) x_ptr(a, I, k, j)[col] = xacc[k][ch][e2];
                 }
-            }
         }
     } else {
         double xacc[NRHS][CH][2];
         zero(xacc);
-        if (w < nch * RB) {
-            const int c = w / RB, blk = w - c * RB;
-            const int rr0 = W * blk / RB, rr1 = W * (blk + 1) / RB;
-            gemv_rows<NRHS, CH>(a.Mf + I.Mf + (long long)(j0 + c) * W * I.ldx, I.ldx, rr0, rr1, nx, xs, ldM,
-                                xacc, lane);
+        if (c < nch) {
+            if (blk == 0)
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+                    for (int ch = 0; ch < CH; ++ch) {
+                        xacc[k][ch][0] = cv[ch][0];
+                        xacc[k][ch][1] = cv[ch][1];
+                    }
+            stream_run<kDepth, NRHS, CH>(mf, xs, ldM, xacc);
         }
         store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nx, xacc, lane);
         __syncthreads();
         for (int e = threadIdx.x; e < nch * NRHS * nx; e += blockDim.x) {
-            const int c = e / (NRHS * nx), rem = e - c * NRHS * nx, k = rem / nx, col = rem - k * nx;
-            const int j = j0 + c;
-            double s = a.affine ? a.cvec[I.c + (long long)j * nx + col] : 0.0;
-            for (int blk = 0; blk < RB; ++blk) s += red[((c * RB + blk) * NRHS + k) * ldM + col];
-            x_ptr(a, I, k, j)[col] = s;
+            const int cc = e / (NRHS * nx), rem = e - cc * NRHS * nx, k = rem / nx, col = rem - k * nx;
+            double s = 0.0;
+            for (int b = 0; b < RB; ++b) s += red[((cc * RB + b) * NRHS + k) * ldM + col];
+            x_ptr(a, I, k, j0 + cc)[col] = s;
         }
     }
 }
@@ -873,8 +989,7 @@ static void launch_trunk_nw(bool backward, SweepArgs a, const LevelPlan &lv, int
     a.t = lv.t;
     if (backward) {
         // max_qs: largest child_batch(NRHS, ldx) * ldx over the instances
-        const size_t lds = sizeof(double) * ((size_t)max_qs * NRHS + (size_t)(NW + 1) * NRHS * max_ldM +
-                                             (size_t)NRHS * max_ldu);
+        const size_t lds = sizeof(double) * ((size_t)max_qs * NRHS + (size_t)(NW + 1) * NRHS * max_ldM);
         hipLaunchKernelGGL((bwd_trunk_kernel<NRHS, CH, NW>), dim3(lv.count), dim3(kWave * NW), lds, st, a);
     } else {
         const size_t lds = sizeof(double) * (size_t)(NW + 1) * NRHS * max_ldM;
@@ -887,7 +1002,8 @@ static void launch_trunk(bool backward, const SweepArgs &a, const LevelPlan &lv,
                          int max_ldu, hipStream_t st)
 {
     switch (lv.nw) {
-    case 16: launch_trunk_nw<NRHS, CH, 16>(backward, a, lv, max_ldM, max_qs, max_ldu, st); break;
+    // rows wider than 128 entries (CH = 2) never get more than 8 wavefronts
+    case 16: launch_trunk_nw<NRHS, CH, CH == 1 ? 16 : 8>(backward, a, lv, max_ldM, max_qs, max_ldu, st); break;
     case 8: launch_trunk_nw<NRHS, CH, 8>(backward, a, lv, max_ldM, max_qs, max_ldu, st); break;
     case 4: launch_trunk_nw<NRHS, CH, 4>(backward, a, lv, max_ldM, max_qs, max_ldu, st); break;
     case 2: launch_trunk_nw<NRHS, CH, 2>(backward, a, lv, max_ldM, max_qs, max_ldu, st); break;
@@ -901,8 +1017,7 @@ static void launch_trunk_tree_nw(SweepArgs a, const tree_factors *f, int max_ldM
 {
     a.items = f->trunk_entry.items;
     a.nitems = f->trunk_entry.count;
-    const size_t lds = sizeof(double) * ((size_t)max_qs * NRHS + (size_t)(NW + 1) * NRHS * max_ldM +
-                                         (size_t)NRHS * max_ldu);
+    const size_t lds = sizeof(double) * ((size_t)max_qs * NRHS + (size_t)(NW + 1) * NRHS * max_ldM);
     hipLaunchKernelGGL((bwd_trunk_tree_kernel<NRHS, CH, NW>), dim3(a.nitems), dim3(kWave * NW), lds, st, a,
                        f->trunk_cnt);
 }
@@ -912,7 +1027,7 @@ static void launch_trunk_tree(const SweepArgs &a, const tree_factors *f, int max
                               hipStream_t st)
 {
     switch (f->trunk_entry.nw) {
-    case 16: launch_trunk_tree_nw<NRHS, CH, 16>(a, f, max_ldM, max_qs, max_ldu, st); break;
+    case 16: launch_trunk_tree_nw<NRHS, CH, CH == 1 ? 16 : 8>(a, f, max_ldM, max_qs, max_ldu, st); break;
     case 8: launch_trunk_tree_nw<NRHS, CH, 8>(a, f, max_ldM, max_qs, max_ldu, st); break;
     case 4: launch_trunk_tree_nw<NRHS, CH, 4>(a, f, max_ldM, max_qs, max_ldu, st); break;
     case 2: launch_trunk_tree_nw<NRHS, CH, 2>(a, f, max_ldM, max_qs, max_ldu, st); break;

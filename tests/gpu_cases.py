@@ -59,6 +59,9 @@ def case(name):
         return treegen.draw_problem(treegen.uniform_tree([1] * 12), 7, 3, rng)
     if name == "no_chain":        # branching at every stage (s* = N)
         return treegen.draw_problem(treegen.uniform_tree([2, 3, 2]), 6, 4, rng)
+    if name == "fanout":          # 20 children at the root: several child batches backward,
+        # several children per wavefront forward
+        return treegen.draw_problem(treegen.uniform_tree([20, 2, 1, 1]), 21, 9, rng)
     if name == "capped":          # uneven-batch style fan-out
         return treegen.draw_problem(treegen.capped_tree(9, 23, 3), 9, 4, rng)
     if name == "mid_width":       # nx + nu in (32, 64]: two chains per wavefront; 13 chains
@@ -72,7 +75,7 @@ def case(name):
 
 
 SWEEP_CASES = ["tiny", "odd_ragged", "large_blocks", "wide", "widest", "single_path", "no_chain", "capped",
-               "mid_width", "warm_blocks"]
+               "mid_width", "warm_blocks", "fanout"]
 
 
 def with_tight_boxes(prob, xbox, ubox):

@@ -58,8 +58,9 @@ def test_dual_grad_matches_oracle(st, name, precondition):
 
 
 @pytest.mark.parametrize("nrhs", [2, 3, 5])
-def test_dual_grad_several_rhs(st, nrhs):
-    prob = case("odd_ragged")
+@pytest.mark.parametrize("name", ["odd_ragged", "fanout"])
+def test_dual_grad_several_rhs(st, name, nrhs):
+    prob = case(name)
     tf = st.tree_factor(prob, precondition=True)
     pb, fac = oracle.factor(prob)
     rng = np.random.default_rng(nrhs)
