@@ -272,20 +272,83 @@ __device__ __forceinline__ WaveLds wave_lds(int ldq, int nrhs, int slot)
     return w;
 }
 
+// The raw values behind the lane's entries of node i's own terms
+// s_i y_i + [chat_i ; sigma_i] (columns 2*lane + 2*G*ch + e, clamped to the
+// row), requested at the start of the node's backward step and combined only
+// where they are added to its children's product, once that is done: no
+// load of them waits before the product.  (A select or a branch on a loaded
+// value, or seeding the accumulator with it, made the compiler wait for the
+// loads right away.)  chat and sigma are allocated for every handle, so the
+// loads carry no condition; without disturbances their values are not used.
+template <int NRHS, int CH>
+struct NodeTerms {
+    double si;
+    double y[NRHS][CH][2];
+    double h[CH][2];
+};
+
+template <int NRHS, int CH, int G>
+__device__ __forceinline__ void node_terms(const SweepArgs &a, const InstDesc &I, int i, int lane,
+                                           NodeTerms<NRHS, CH> &t)
+{
+    const int nx = I.nx, nu = I.nu, W = nx + nu;
+    t.si = a.sc ? a.sc[I.sc + i] : 1.0;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int c = 2 * lane + 2 * G * ch + e, cw = c < W ? c : W - 1;
+            const double *h = cw < nx ? a.chat + I.chat + (long long)i * nx + cw
+                                      : a.sig + I.sig + (long long)i * nu + (cw - nx);
+            t.h[ch][e] = *h;
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) t.y[k][ch][e] = y_ptr(a, I, k, i)[cw];
+        }
+}
+
+// acc += s_i y_i + [chat_i ; sigma_i] (the last term only with disturbances)
+template <int NRHS, int CH>
+__device__ __forceinline__ void add_node_terms(const SweepArgs &a, double (&acc)[NRHS][CH][2],
+                                               const NodeTerms<NRHS, CH> &t)
+{
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                acc[k][ch][e] += t.si * t.y[k][ch][e] + (a.affine ? t.h[ch][e] : 0.0);
+}
+
+template <int NRHS, int CH>
+__device__ __forceinline__ void add_to(double (&acc)[NRHS][CH][2], const double (&v)[NRHS][CH][2])
+{
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+            acc[k][ch][0] += v[k][ch][0];
+            acc[k][ch][1] += v[k][ch][1];
+        }
+}
+
 // Backward step of non-leaf node i of instance I by one wavefront.  If
 // child_in_lds, qhat of the (single) child is already in L.qx; otherwise each
 // child's qhat is staged from the leaf data or from the global qhat buffer.
-// The result qhat_i is left in L.qx and, if store_q, written to the global
-// buffer; k_i always goes to kbuf.
-template <int NRHS, int CH, int G>
+// For a chain node (kChain) jc is the index of its only child; otherwise the
+// children are read from the child pointers.  The result qhat_i is left in
+// L.qx and, if store_q, written to the global buffer; k_i always goes to kbuf.
+template <int NRHS, int CH, int G, bool kChain = false>
 __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const WaveLds &L,
-                         bool child_in_lds, bool store_q, int lane)
+                         bool child_in_lds, bool store_q, int lane, int jc = -1)
 {
     const int nx = I.nx, nu = I.nu, W = nx + nu;
     const int *cp = a.cp + I.cp;
+    NodeTerms<NRHS, CH> nt;
+    node_terms<NRHS, CH, G>(a, I, i, lane, nt);
     double acc[NRHS][CH][2];
     zero(acc);
-    const int j0 = cp[i], j1 = cp[i + 1];
+    const int j0 = kChain ? jc : cp[i], j1 = kChain ? jc + 1 : cp[i + 1];
     for (int j = j0; j < j1; ++j) {
         if (!child_in_lds) {
             if (j >= I.Vnl) {
@@ -305,29 +368,25 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
         gemv_rows<NRHS, CH, G>(a.Mb + I.Mb + (long long)j * nx * I.ldM, I.ldM, 0, nx, W, L.qx, L.ldq, acc, lane);
         wave_sync();
     }
-    store_acc<NRHS, CH, G>(L.as, L.ldq, 0, W, acc, lane);  // [sum A'q ; sum B'q]
+    // L.as = [sum A'q + s_i y_i^x + chat_i ; g_i], g_i = sum B'q + s_i y_i^u + sigma_i
+    add_node_terms(a, acc, nt);
+    store_acc<NRHS, CH, G>(L.as, L.ldq, 0, W, acc, lane);
     wave_sync();
-    const double si = a.sc ? a.sc[I.sc + i] : 1.0;
-    for (int c = lane; c < nu; c += G)
-#pragma unroll
-        for (int k = 0; k < NRHS; ++k)
-            L.gs[k * L.ldq + c] = L.as[k * L.ldq + nx + c] + si * y_ptr(a, I, k, i)[nx + c] +
-                                  (a.affine ? a.sig[I.sig + (long long)i * nu + c] : 0.0);
-    wave_sync();
+    const double *gs = L.as + nx;
     double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
     zero(kacc);
     zero(qacc);
     if constexpr (CH == 1) {
         if (nx <= G && nu >= 2) {
-            gemv_pairs<NRHS, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
-            gemv_pairs<NRHS, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
+            gemv_pairs<NRHS, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, gs, L.ldq, kacc, lane);
+            gemv_pairs<NRHS, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, gs, L.ldq, qacc, lane);
         } else {
-            gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
-            gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
+            gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, gs, L.ldq, kacc, lane);
+            gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, gs, L.ldq, qacc, lane);
         }
     } else {
-        gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, L.gs, L.ldq, kacc, lane);
-        gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, L.gs, L.ldq, qacc, lane);
+        gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, gs, L.ldq, kacc, lane);
+        gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, gs, L.ldq, qacc, lane);
     }
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
@@ -339,7 +398,7 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
             if (c0 + 1 < nu) kb[c0 + 1] = kacc[k][ch][1];
         }
     }
-    // qhat_i = [sum A'q]_c + s_i y_i^x + chat_i + (K_i' g_i)
+    // qhat_i = [sum A'q + s_i y_i^x + chat_i]_c + (K_i' g_i)
     double qv[NRHS][CH][2];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
@@ -348,13 +407,7 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
         for (int e = 0; e < 2; ++e) {
             const int c = c0 + e;
 #pragma unroll
-            for (int k = 0; k < NRHS; ++k) {
-                double v = 0.0;
-                if (c < nx)
-                    v = L.as[k * L.ldq + c] + si * y_ptr(a, I, k, i)[c] +
-                        (a.affine ? a.chat[I.chat + (long long)i * nx + c] : 0.0) + qacc[k][ch][e];
-                qv[k][ch][e] = v;
-            }
+            for (int k = 0; k < NRHS; ++k) qv[k][ch][e] = c < nx ? L.as[k * L.ldq + c] + qacc[k][ch][e] : 0.0;
         }
     }
     wave_sync();  // every lane has finished reading L.qx / L.as
@@ -378,15 +431,26 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
 
 // Forward step of non-leaf node i with x_i in L.qx[0..nx).  Writes u_i and the
 // children's x_j to the outputs; for a single-child chain the child's x is
-// left in L.qx.
-template <int NRHS, int CH, int G>
+// left in L.qx.  For a chain node (kChain) jc is the index of its only
+// child; otherwise the children are read from the child pointers.  k_i and
+// each c_j are requested before the product they are added to.
+template <int NRHS, int CH, int G, bool kChain = false>
 __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const WaveLds &L, bool keep_child,
-                         int lane)
+                         int lane, int jc = -1)
 {
     const int nx = I.nx, nu = I.nu;
     const int *cp = a.cp + I.cp;
-    double uacc[NRHS][CH][2];
+    double kv[NRHS][CH][2], uacc[NRHS][CH][2];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int c = 2 * lane + 2 * G * ch + e;
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) kv[k][ch][e] = kbuf_ptr(a, I, k, i)[c < nu ? c : nu - 1];
+        }
     zero(uacc);
+    const int j0 = kChain ? jc : cp[i], j1 = kChain ? jc + 1 : cp[i + 1];
     if constexpr (CH == 1) {
         if (nu <= G && nx >= 2)
             gemv_pairs<NRHS, G>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
@@ -395,6 +459,14 @@ __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     } else {
         gemv_rows<NRHS, CH, G>(a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, 0, nx, nu, L.qx, L.ldq, uacc, lane);
     }
+    // both of a lane's entries are formed before either is stored (the empty
+    // asm keeps the compiler from sinking each sum into its store's branch,
+    // where the second reused the first store's registers and waited on it)
+    add_to(uacc, kv);
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) asm volatile("" : "+v"(uacc[k][ch][0]), "+v"(uacc[k][ch][1]));
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
         const int c0 = 2 * lane + 2 * G * ch;
@@ -404,19 +476,24 @@ __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
             if (c < nu) {
 #pragma unroll
                 for (int k = 0; k < NRHS; ++k) {
-                    const double uval = uacc[k][ch][e] + kbuf_ptr(a, I, k, i)[c];
-                    u_ptr(a, I, k, i)[c] = uval;
-                    L.qx[k * L.ldq + nx + c] = uval;
+                    u_ptr(a, I, k, i)[c] = uacc[k][ch][e];
+                    L.qx[k * L.ldq + nx + c] = uacc[k][ch][e];
                 }
             }
         }
     }
     wave_sync();
-    const int j0 = cp[i], j1 = cp[i + 1];
     double keep[NRHS][CH][2];
     zero(keep);
     for (int j = j0; j < j1; ++j) {
-        double xacc[NRHS][CH][2];
+        double xacc[NRHS][CH][2], cv[CH][2];
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int c = 2 * lane + 2 * G * ch + e;
+                cv[ch][e] = a.cvec[I.c + (long long)j * nx + (c < nx ? c : nx - 1)];   // allocated always
+            }
         zero(xacc);
         if constexpr (CH == 1) {
             if (nx <= G)
@@ -438,7 +515,7 @@ __device__ void fwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
                 if (c < nx) {
 #pragma unroll
                     for (int k = 0; k < NRHS; ++k) {
-                        const double xv = xacc[k][ch][e] + (a.affine ? a.cvec[I.c + (long long)j * nx + c] : 0.0);
+                        const double xv = xacc[k][ch][e] + (a.affine ? cv[ch][e] : 0.0);
                         x_ptr(a, I, k, j)[c] = xv;
                         keep[k][ch][e] = xv;
                     }
@@ -502,8 +579,8 @@ __device__ void bwd_trunk_node(const SweepArgs &a, const InstDesc &I, int i, int
     const int j0 = cp[i], nch = cp[i + 1] - j0;
     // Everything that depends on node i alone is requested before the
     // children's qhat: the wavefront's rows of -R~^{-1} and K_i (split over
-    // the 2nu rows as below) and, on wavefront 0, the node's own terms
-    // s_i y_i + [chat_i ; sigma_i], which seed its accumulator.
+    // the 2nu rows as below) and the node's own terms s_i y_i + [chat_i ;
+    // sigma_i], which wavefront 0 adds to its partial sum.
     // (With two column chunks or 16 wavefronts the registers of all three
     // streams would not fit: those rows are then requested after the
     // children's product.)
@@ -515,26 +592,10 @@ __device__ void bwd_trunk_node(const SweepArgs &a, const InstDesc &I, int i, int
                            nx, lane);
     };
     if (CH == 1 && NW <= 8) open_rk();
+    NodeTerms<NRHS, CH> nt;
+    node_terms<NRHS, CH, kWave>(a, I, i, lane, nt);
     double acc[NRHS][CH][2];
     zero(acc);
-    if (w == 0) {
-        const double si = a.sc ? a.sc[I.sc + i] : 1.0;
-#pragma unroll
-        for (int ch = 0; ch < CH; ++ch)
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int c = 2 * lane + 2 * kWave * ch + e, cw = c < W ? c : W - 1;
-                double t = 0.0;
-                if (a.affine) {
-                    const int cx = cw < nx ? cw : nx - 1, cu = cw < nx ? 0 : cw - nx;
-                    const double ch_ = a.chat[I.chat + (long long)i * nx + cx];
-                    const double sg = a.sig[I.sig + (long long)i * nu + cu];
-                    t = cw < nx ? ch_ : sg;
-                }
-#pragma unroll
-                for (int k = 0; k < NRHS; ++k) acc[k][ch][e] = si * y_ptr(a, I, k, i)[cw] + t;
-            }
-    }
     for (int cb = 0; cb < nch; cb += CB) {
         const int nb = nch - cb < CB ? nch - cb : CB;
         // the batch's rows of [A_j B_j] are contiguous (children are
@@ -561,6 +622,7 @@ __device__ void bwd_trunk_node(const SweepArgs &a, const InstDesc &I, int i, int
         if (cb + CB < nch) __syncthreads();   // qs is refilled
     }
     if (!(CH == 1 && NW <= 8)) open_rk();
+    if (w == 0) add_node_terms(a, acc, nt);
     store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, W, acc, lane);
     __syncthreads();
     for (int e = threadIdx.x; e < NRHS * W; e += blockDim.x) {
@@ -637,8 +699,9 @@ __global__ void __launch_bounds__(kWave *NW) bwd_trunk_tree_kernel(SweepArgs a, 
     }
 }
 
-// The lane's entries of c_j (zero without disturbances): they seed the
-// accumulator of the wavefront that owns x_j's first rows.
+// The lane's entries of c_j (allocated for every handle; used only with
+// disturbances), added to the partial sum of the wavefront that owns x_j's
+// first rows.
 template <int CH>
 __device__ __forceinline__ void load_cvec(const SweepArgs &a, const InstDesc &I, int j, int lane, double (&cv)[CH][2])
 {
@@ -647,7 +710,7 @@ __device__ __forceinline__ void load_cvec(const SweepArgs &a, const InstDesc &I,
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int c = 2 * lane + 2 * kWave * ch + e;
-            cv[ch][e] = a.affine ? a.cvec[I.c + (long long)j * I.nx + (c < I.nx ? c : I.nx - 1)] : 0.0;
+            cv[ch][e] = a.cvec[I.c + (long long)j * I.nx + (c < I.nx ? c : I.nx - 1)];
         }
 }
 
@@ -668,25 +731,25 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a)
     constexpr int kDepth = CH == 1 && NW <= 8 ? 2 : 1;
     const int j0 = cp[i], nch = cp[i + 1] - j0;
     const int RB = nch >= NW ? 1 : NW / nch;
-    // Requested before x_i: the wavefront's rows of K_i' (k_i seeds
-    // wavefront 0's sum) and its first rows of a child's [A_j B_j]' with
-    // c_j; children go round-robin to the wavefronts, or, with fewer children
-    // than wavefronts, each child's rows are split into RB blocks.
+    // Requested before x_i: the wavefront's rows of K_i' and k_i (which
+    // wavefront 0 adds to its partial sum), and its first rows of a child's
+    // [A_j B_j]' with c_j; children go round-robin to the wavefronts, or,
+    // with fewer children than wavefronts, each child's rows are split into
+    // RB blocks.
     RowStream<CH> kf, mf;
-    double uacc[NRHS][CH][2];
+    double kv[NRHS][CH][2], uacc[NRHS][CH][2];
     zero(uacc);
     {
         const int r0 = nx * w / NW, r1 = nx * (w + 1) / NW;
         stream_open<1, CH>(kf, a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, r0, r1, nu, lane);
-        if (w == 0)
 #pragma unroll
-            for (int ch = 0; ch < CH; ++ch)
+        for (int ch = 0; ch < CH; ++ch)
 #pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const int c = 2 * lane + 2 * kWave * ch + e;
+            for (int e = 0; e < 2; ++e) {
+                const int c = 2 * lane + 2 * kWave * ch + e;
 #pragma unroll
-                    for (int k = 0; k < NRHS; ++k) uacc[k][ch][e] = kbuf_ptr(a, I, k, i)[c < nu ? c : nu - 1];
-                }
+                for (int k = 0; k < NRHS; ++k) kv[k][ch][e] = kbuf_ptr(a, I, k, i)[c < nu ? c : nu - 1];
+            }
     }
     int c = RB == 1 ? w : w / RB;
     const int blk = RB == 1 ? 0 : w - c * RB;
@@ -709,6 +772,7 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a)
     }
     __syncthreads();
     stream_run<1, NRHS, CH>(kf, xs, ldM, uacc);
+    if (w == 0) add_to(uacc, kv);
     store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nu, uacc, lane);
     __syncthreads();
     for (int e = threadIdx.x; e < NRHS * nu; e += blockDim.x) {
@@ -722,14 +786,15 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a)
     if (RB == 1) {
         for (; c < nch; c += NW) {
             double xacc[NRHS][CH][2];
+            zero(xacc);
+            stream_run<kDepth, NRHS, CH>(mf, xs, ldM, xacc);
 #pragma unroll
             for (int k = 0; k < NRHS; ++k)
 #pragma unroll
                 for (int ch = 0; ch < CH; ++ch) {
-                    xacc[k][ch][0] = cv[ch][0];
-                    xacc[k][ch][1] = cv[ch][1];
+                    xacc[k][ch][0] += a.affine ? cv[ch][0] : 0.0;
+                    xacc[k][ch][1] += a.affine ? cv[ch][1] : 0.0;
                 }
-            stream_run<kDepth, NRHS, CH>(mf, xs, ldM, xacc);
             const int j = j0 + c;
             if (c + NW < nch) {   // the next child's rows are in flight while x_j is stored
                 stream_open<kDepth, CH>(mf, a.Mf + I.Mf + (long long)(j + NW) * W * I.ldx, I.ldx, 0, W, nx, lane);
@@ -749,15 +814,15 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a)
         double xacc[NRHS][CH][2];
         zero(xacc);
         if (c < nch) {
+            stream_run<kDepth, NRHS, CH>(mf, xs, ldM, xacc);
             if (blk == 0)
 #pragma unroll
                 for (int k = 0; k < NRHS; ++k)
 #pragma unroll
                     for (int ch = 0; ch < CH; ++ch) {
-                        xacc[k][ch][0] = cv[ch][0];
-                        xacc[k][ch][1] = cv[ch][1];
+                        xacc[k][ch][0] += a.affine ? cv[ch][0] : 0.0;
+                        xacc[k][ch][1] += a.affine ? cv[ch][1] : 0.0;
                     }
-            stream_run<kDepth, NRHS, CH>(mf, xs, ldM, xacc);
         }
         store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nx, xacc, lane);
         __syncthreads();
@@ -792,8 +857,14 @@ __device__ __forceinline__ void bwd_chain_body(const SweepArgs &a, const Item *i
     if (chain >= I.nchains) return;
     const int *sp = a.sp + I.sp;
     const WaveLds L = wave_lds(ldq, NRHS, wave * kGroups + grp);
-    for (int t = I.N - 1; t >= I.sstar; --t)
-        bwd_node<NRHS, CH, G>(a, I, sp[t] + chain, L, t != I.N - 1, t == I.sstar && t > 0, lane);
+    // every stage from s* on holds the nchains chain nodes in chain order:
+    // the chain's node of stage t is sp[s*] + chain + (t - s*) nchains, and
+    // its child is nchains further on
+    const int head = sp[I.sstar] + chain;
+    for (int t = I.N - 1; t >= I.sstar; --t) {
+        const int i = head + (t - I.sstar) * I.nchains;
+        bwd_node<NRHS, CH, G, true>(a, I, i, L, t != I.N - 1, t == I.sstar && t > 0, lane, i + I.nchains);
+    }
 }
 
 template <int NRHS, int CH, int G>
@@ -812,7 +883,12 @@ __device__ __forceinline__ void fwd_chain_body(const SweepArgs &a, const Item *i
     const int *sp = a.sp + I.sp;
     const WaveLds L = wave_lds(ldq, NRHS, wave * kGroups + grp);
     load_x<NRHS, G>(a, I, sp[I.sstar] + chain, L, lane);
-    for (int t = I.sstar; t < I.N; ++t) fwd_node<NRHS, CH, G>(a, I, sp[t] + chain, L, t + 1 < I.N, lane);
+    // the chain's node of stage t and its child, as in the backward pass
+    const int head = sp[I.sstar] + chain;
+    for (int t = I.sstar; t < I.N; ++t) {
+        const int i = head + (t - I.sstar) * I.nchains;
+        fwd_node<NRHS, CH, G, true>(a, I, i, L, t + 1 < I.N, lane, i + I.nchains);
+    }
 }
 
 // Chains of one lane-group width (G = 64).
