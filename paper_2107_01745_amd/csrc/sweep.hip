@@ -344,8 +344,12 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
 {
     const int nx = I.nx, nu = I.nu, W = nx + nu;
     const int *cp = a.cp + I.cp;
+    // Narrow lane groups request the node's own terms up front (their
+    // chains gain from it); 64-lane groups load them after the product, as
+    // a coalesced pass per vector, which measured faster for them.
+    constexpr bool kEarly = G < kWave;
     NodeTerms<NRHS, CH> nt;
-    node_terms<NRHS, CH, G>(a, I, i, lane, nt);
+    if constexpr (kEarly) node_terms<NRHS, CH, G>(a, I, i, lane, nt);
     double acc[NRHS][CH][2];
     zero(acc);
     const int j0 = kChain ? jc : cp[i], j1 = kChain ? jc + 1 : cp[i + 1];
@@ -368,11 +372,22 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
         gemv_rows<NRHS, CH, G>(a.Mb + I.Mb + (long long)j * nx * I.ldM, I.ldM, 0, nx, W, L.qx, L.ldq, acc, lane);
         wave_sync();
     }
-    // L.as = [sum A'q + s_i y_i^x + chat_i ; g_i], g_i = sum B'q + s_i y_i^u + sigma_i
-    add_node_terms(a, acc, nt);
+    // early: L.as = [sum A'q + s_i y_i^x + chat_i ; g_i], g_i = sum B'q + s_i y_i^u + sigma_i;
+    // otherwise L.as = [sum A'q ; sum B'q] and g_i is formed in L.gs
+    if constexpr (kEarly) add_node_terms(a, acc, nt);
     store_acc<NRHS, CH, G>(L.as, L.ldq, 0, W, acc, lane);
     wave_sync();
     const double *gs = L.as + nx;
+    const double si = kEarly ? 0.0 : (a.sc ? a.sc[I.sc + i] : 1.0);
+    if constexpr (!kEarly) {
+        for (int c = lane; c < nu; c += G)
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k)
+                L.gs[k * L.ldq + c] = L.as[k * L.ldq + nx + c] + si * y_ptr(a, I, k, i)[nx + c] +
+                                      (a.affine ? a.sig[I.sig + (long long)i * nu + c] : 0.0);
+        wave_sync();
+        gs = L.gs;
+    }
     double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
     zero(kacc);
     zero(qacc);
@@ -398,7 +413,7 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
             if (c0 + 1 < nu) kb[c0 + 1] = kacc[k][ch][1];
         }
     }
-    // qhat_i = [sum A'q + s_i y_i^x + chat_i]_c + (K_i' g_i)
+    // qhat_i = [sum A'q]_c + s_i y_i^x + chat_i + (K_i' g_i)
     double qv[NRHS][CH][2];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
@@ -407,7 +422,17 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
         for (int e = 0; e < 2; ++e) {
             const int c = c0 + e;
 #pragma unroll
-            for (int k = 0; k < NRHS; ++k) qv[k][ch][e] = c < nx ? L.as[k * L.ldq + c] + qacc[k][ch][e] : 0.0;
+            for (int k = 0; k < NRHS; ++k) {
+                double v = 0.0;
+                if constexpr (kEarly) {
+                    if (c < nx) v = L.as[k * L.ldq + c] + qacc[k][ch][e];
+                } else {
+                    if (c < nx)
+                        v = L.as[k * L.ldq + c] + si * y_ptr(a, I, k, i)[c] +
+                            (a.affine ? a.chat[I.chat + (long long)i * nx + c] : 0.0) + qacc[k][ch][e];
+                }
+                qv[k][ch][e] = v;
+            }
         }
     }
     wave_sync();  // every lane has finished reading L.qx / L.as
@@ -863,7 +888,7 @@ __device__ __forceinline__ void bwd_chain_body(const SweepArgs &a, const Item *i
     const int head = sp[I.sstar] + chain;
     for (int t = I.N - 1; t >= I.sstar; --t) {
         const int i = head + (t - I.sstar) * I.nchains;
-        bwd_node<NRHS, CH, G, true>(a, I, i, L, t != I.N - 1, t == I.sstar && t > 0, lane, i + I.nchains);
+        bwd_node<NRHS, CH, G, (G < kWave)>(a, I, i, L, t != I.N - 1, t == I.sstar && t > 0, lane, i + I.nchains);
     }
 }
 
