@@ -884,11 +884,13 @@ __device__ __forceinline__ void bwd_chain_body(const SweepArgs &a, const Item *i
     const WaveLds L = wave_lds(ldq, NRHS, wave * kGroups + grp);
     // every stage from s* on holds the nchains chain nodes in chain order:
     // the chain's node of stage t is sp[s*] + chain + (t - s*) nchains, and
-    // its child is nchains further on
+    // its child is nchains further on (64-lane groups read it from the child
+    // pointers instead, which measured faster for them)
     const int head = sp[I.sstar] + chain;
     for (int t = I.N - 1; t >= I.sstar; --t) {
         const int i = head + (t - I.sstar) * I.nchains;
-        bwd_node<NRHS, CH, G, (G < kWave)>(a, I, i, L, t != I.N - 1, t == I.sstar && t > 0, lane, i + I.nchains);
+        bwd_node<NRHS, CH, G, (G < kWave)>(a, I, i, L, t != I.N - 1, t == I.sstar && t > 0, lane,
+                                           i + I.nchains);
     }
 }
 
