@@ -328,15 +328,18 @@ int validate(const tree_desc *t, const problem_data *d, const std::string &who)
     return STOTREE_OK;
 }
 
-// Wavefronts per node for a stage of n nodes: enough to keep about 4096
-// wavefronts busy, within the LDS budget of the reduction buffers.  Rows
+// Wavefronts per node for a stage of n nodes: at most 2048 in the stage, so
+// that a wide stage fits the chip in one round at the per-node kernels'
+// register use (4096 left a 1024-node stage running in two rounds; 2048 was
+// 0.5% faster per large-tree sweep), within the LDS budget of the reduction
+// buffers.  Rows
 // wider than two entries per lane take at most 8: at 16 wavefronts (1024
 // threads) the two-chunk row code runs out of registers and its loads wait
 // for one another (the stages of an nx=100, nu=40 tree ran 3-7x slower).
 int trunk_waves(int n, int nrhs_max, int ldM, int cap)
 {
     int nw = ldM > 2 * kWave && cap > 8 ? 8 : cap;
-    while (nw > 1 && (long long)n * nw > 4096) nw /= 2;
+    while (nw > 1 && (long long)n * nw > 2048) nw /= 2;
     while (nw > 1 && (size_t)(nw + 2) * nrhs_max * ldM * sizeof(double) > 40 * 1024) nw /= 2;
     return nw;
 }
