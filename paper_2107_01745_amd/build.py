@@ -1,16 +1,23 @@
-"""Compile the HIP library libstotree.so for gfx950 (in-tree)."""
+"""Compile the HIP library libstotree.so for gfx950 (in-tree).
+
+Each source is compiled to an object of its own, in parallel, then the
+objects are linked into one shared library.  No kernel calls across
+translation units, so the objects need no relocatable device code.
+"""
 from __future__ import annotations
 
 import glob
 import os
 import subprocess
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libstotree.so")
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -22,15 +29,28 @@ def sources() -> list:
                   glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
 
 
-def build(verbose: bool = False) -> str:
-    """Always recompiles; writes libstotree.so next to this file."""
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), "-o", tmp, *sources()]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Always recompiles every source; writes libstotree.so next to this file."""
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    with tempfile.TemporaryDirectory(prefix="stotree_build_") as tmpdir:
+        objs, cmds = [], []
+        for src in sources():
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            objs.append(obj)
+            cmds.append(["hipcc", *HIPCC_FLAGS, *inc, "-c", "-o", obj, src])
+
+        def run(cmd):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.check_call(cmd)
+
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            for fut in [ex.submit(run, c) for c in cmds]:
+                fut.result()
+        tmp = LIB + ".tmp"
+        run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+        os.replace(tmp, LIB)
     return LIB
 
 

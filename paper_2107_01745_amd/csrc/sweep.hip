@@ -707,9 +707,13 @@ __global__ void __launch_bounds__(kWave *NW) bwd_trunk_tree_kernel(SweepArgs a, 
         bwd_trunk_node<NRHS, CH, NW>(a, I, i, w, lane);
         if (i == 0) break;
         const int p = a.anc[I.sc + i];
-        __syncthreads();   // every store of node i has been issued
+        // Every wavefront releases its own stores of node i's qhat and k
+        // device-wide (the fence waits for them and writes them back past
+        // this XCD's L2) before the barrier; a fence on one wavefront would
+        // cover only that wavefront's stores.
+        __threadfence();
+        __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence();   // release node i's qhat and k device-wide
             const int nch = a.cp[I.cp + p + 1] - a.cp[I.cp + p];
             const int last = atomicAdd(&counters[I.node0 + p], 1) == nch - 1;
             if (last) {
