@@ -195,6 +195,24 @@ int dual_grad(const tree_factors *f, const double *x0, const double *y, int homo
               int nrhs, double *x, double *u, void *hip_stream);
 
 /*
+ * dual_grad for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * arguments, results and errors as dual_grad, but the per-call q-hat / k
+ * workspace of the sweeps lives in a static device array of the library
+ * (128 MiB per GPU, held from the first use of the library on that GPU until
+ * the process ends) instead of the handle's workspace, and the call makes no
+ * hipMalloc, hipFree or other allocating call.  The workspace needed is
+ * w * (sum V nx + sum V_nl nu) doubles, w = 1 on a shared handle swept as
+ * panels, 64 when nrhs >= 64 right-hand sides run as matrix-core panels,
+ * else min(nrhs, 2); a call needing more than the 128 MiB returns ERR_ARG
+ * before any work.  Every call on a GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and give
+ * undefined results.  Nothing in the array needs clearing between calls.
+ */
+int dual_grad_noalloc(const tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs,
+                      double *x, double *u, void *hip_stream);
+
+/*
  * Sweep schedule of a handle: how the stage-parallel sweeps of Sec. III-D
  * (Algorithms 3 and 4) are cut into GPU work.  HOST knobs[5]:
  *   knobs[0] smallest lane group walking one chain below s*: 8, 16, 32 or 64

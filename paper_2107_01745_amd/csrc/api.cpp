@@ -88,6 +88,16 @@ int dual_grad(const tree_factors *fc, const double *x0, const double *y, int hom
                              (hipStream_t)hip_stream);
 }
 
+int dual_grad_noalloc(const tree_factors *fc, const double *x0, const double *y, int homogeneous, int nrhs,
+                      double *x, double *u, void *hip_stream)
+{
+    if (!fc || !y || !x || !u || nrhs < 1 || (!homogeneous && !x0)) {
+        set_error("dual_grad_noalloc: NULL pointer or nrhs < 1");
+        return STOTREE_ERR_ARG;
+    }
+    return dual_grad_noalloc_impl(fc, x0, y, homogeneous, nrhs, x, u, (hipStream_t)hip_stream);
+}
+
 int sweep_schedule(tree_factors *f, const int32_t *knobs)
 {
     if (!f || !knobs) { set_error("sweep_schedule: NULL argument"); return STOTREE_ERR_ARG; }

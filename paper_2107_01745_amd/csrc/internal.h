@@ -177,8 +177,15 @@ int timing_enable(int on);
 bool timing_on();
 int timing_read(double *ms, long long *count);
 // dual_grad's work: right-hand sides two at a time, one sweep each pair.
+// ws: null, the handle's workspace; else caller device memory of
+// dual_grad_ws_rhs(f, nrhs) * (x_tot + u_tot) doubles.
+int dual_grad_ws_rhs(const tree_factors *f, int nrhs);
 int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,
-                      double *u, hipStream_t st);
+                      double *u, hipStream_t st, double *ws = nullptr);
+// dual_grad with the q-hat / k workspace in the library's static device
+// scratch (no allocation).
+int dual_grad_noalloc_impl(const tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs,
+                           double *x, double *u, hipStream_t st);
 
 // schedule.hip
 constexpr int kKnobs = 5;            // group_min, chain_order, trunk_cap, trunk_fused, panel_min

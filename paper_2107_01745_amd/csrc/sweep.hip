@@ -32,6 +32,9 @@
 // its stages with qhat / x carried in LDS, so those stages need no grid-wide
 // synchronisation.  Stages above s* are launched stage by stage.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "sweep_common.h"
 
@@ -1259,15 +1262,34 @@ static hipError_t sweep_impl(const tree_factors *f, SweepArgs a, hipStream_t st)
     return hipGetLastError();
 }
 
-int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,
-                      double *u, hipStream_t st)
+// Right-hand sides of q-hat / k workspace a dual_grad call needs: one on a
+// shared handle's panel route, a panel's worth for 64-wide matrix-core
+// panels, else a pair (or one).
+int dual_grad_ws_rhs(const tree_factors *f, int nrhs)
 {
+    if (panel_route(f, f->ninst)) return 1;
+    if (nrhs >= kRhsPanel && panel_tpw(f) > 0 && f->shared <= 1) return kRhsPanel;
+    return nrhs >= 2 ? 2 : 1;
+}
+
+// ws: null, the handle's own workspace (grown on demand); otherwise caller
+// memory of dual_grad_ws_rhs(f, nrhs) * (x_tot + u_tot) doubles, q-hat first.
+int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,
+                      double *u, hipStream_t st, double *ws)
+{
+    const int ws_rhs = dual_grad_ws_rhs(f, nrhs);
+    if (!ws) {
+        int rc = ensure_sweep_ws(f, ws_rhs);
+        if (rc) return rc;
+    }
+    SweepArgs a = sweep_args(f, homogeneous ? 0 : 1);
+    if (ws) {
+        a.qhat = ws;
+        a.kbuf = ws + (long long)ws_rhs * f->x_tot;
+    }
+    a.dual_out = 0;
     // shared handle: each right-hand side covers all instances in panels
     if (panel_route(f, f->ninst)) {
-        int rc = ensure_sweep_ws(f, 1);
-        if (rc) return rc;
-        SweepArgs a = sweep_args(f, homogeneous ? 0 : 1);
-        a.dual_out = 0;
         for (int k = 0; k < nrhs; ++k) {
             a.x0 = x0 ? x0 + (long long)k * f->nx_tot : nullptr;
             a.y = y + (long long)k * f->m_tot;
@@ -1283,16 +1305,12 @@ int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int ho
     }
     // panels of kRhsPanel right-hand sides on the matrix cores, the rest in
     // pairs (a shared handle's panel work lists hold instance 0's nodes only)
-    const bool panel = nrhs >= kRhsPanel && panel_tpw(f) > 0 && f->shared <= 1;
+    const bool panel = ws_rhs == kRhsPanel;
     const int npanel = panel ? nrhs / kRhsPanel * kRhsPanel : 0;
-    int rc = ensure_sweep_ws(f, panel ? kRhsPanel : (nrhs >= 2 ? 2 : 1));
-    if (rc) return rc;
-    SweepArgs a = sweep_args(f, homogeneous ? 0 : 1);
     a.y_rs = f->m_tot;
     a.x0_rs = f->nx_tot;
     a.xo_rs = f->x_tot;
     a.uo_rs = f->u_tot;
-    a.dual_out = 0;
     for (int k0 = 0; k0 < nrhs;) {
         const int nk = k0 < npanel ? kRhsPanel : (nrhs - k0 >= 2 ? 2 : 1);
         a.x0 = x0 ? x0 + (long long)k0 * f->nx_tot : nullptr;
@@ -1315,6 +1333,51 @@ hipError_t launch_sweep_tree(const tree_factors *f, const SweepArgs &a, int nrhs
     if (nrhs == 1) return wide ? sweep_impl<1, 2>(f, a, st) : sweep_impl<1, 1>(f, a, st);
     if (nrhs == 2) return wide ? sweep_impl<2, 2>(f, a, st) : sweep_impl<2, 1>(f, a, st);
     return hipErrorInvalidValue;
+}
+
+// ---- dual_grad without allocation: static device scratch ----
+// The q-hat / k workspace of dual_grad_noalloc lives in this file-scope
+// device array (one copy per GPU, alive until the process ends).  In host
+// code its name is only a stand-in for the symbol: kernels get the device
+// address that hipGetSymbolAddress returns for the current device.
+constexpr long long kScratchDoubles = 16LL << 20;   // 128 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;   // device ordinal -> address of its scratch
+
+// Address of this device's scratch, looked up once per device.
+int scratch_address(double **out)
+{
+    int dev = -1;
+    STOTREE_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        STOTREE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        it = g_scratch_ptr.emplace(dev, static_cast<double *>(p)).first;
+    }
+    *out = it->second;
+    return STOTREE_OK;
+}
+}  // namespace
+
+int dual_grad_noalloc_impl(const tree_factors *fc, const double *x0, const double *y, int homogeneous, int nrhs,
+                           double *x, double *u, hipStream_t st)
+{
+    tree_factors *f = const_cast<tree_factors *>(fc);
+    const long long need = (long long)dual_grad_ws_rhs(f, nrhs) * (f->x_tot + f->u_tot);
+    if (need > kScratchDoubles) {
+        set_error("dual_grad_noalloc: the sweep workspace needs " + std::to_string(need * 8) +
+                  " bytes, more than the " + std::to_string(kScratchDoubles * 8) + "-byte static scratch");
+        return STOTREE_ERR_ARG;
+    }
+    double *ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    return enqueue_dual_grad(f, x0, y, homogeneous, nrhs, x, u, st, ws);
 }
 
 }  // namespace stotree

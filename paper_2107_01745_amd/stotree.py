@@ -61,7 +61,7 @@ EXPORTS = ("tree_factor", "tree_factor_batch", "tree_factors_free", "tree_dims",
            "warm_mlp_params", "warm_mlp_work_len", "warm_mlp_forward", "warm_mlp_backward",
            "warm_mse_grad", "warm_adam", "warm_features", "warm_scatter", "warm_targets",
            "dual_select", "tree_factor_shared", "sweep_schedule", "sweep_schedule_get", "sweep_autotune",
-           "sweep_graph_create", "sweep_graph_launch", "sweep_graph_free")
+           "sweep_graph_create", "sweep_graph_launch", "sweep_graph_free", "dual_grad_noalloc")
 PHASES = ("bwd_chain", "bwd_stages", "fwd_stages", "fwd_chain")
 
 _lib = None
@@ -92,8 +92,9 @@ def lib():
         L.tree_factors_free.restype = None
         L.tree_dims.argtypes = [vp, C.POINTER(C.c_int64)]
         L.tree_dims.restype = C.c_int
-        L.dual_grad.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp, vp, vp]
-        L.dual_grad.restype = C.c_int
+        for fn in (L.dual_grad, L.dual_grad_noalloc):
+            fn.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp, vp, vp]
+            fn.restype = C.c_int
         L.dual_lipschitz.argtypes = [vp, C.c_int, _dp, vp]
         L.dual_lipschitz.restype = C.c_int
         for fn in (L.minfbe_solve, L.nama_solve):
@@ -264,6 +265,13 @@ def dual_grad(tf: TreeFactors, x0, y, homogeneous: bool, x, u, nrhs: int = 1, st
     """x(y) (Algorithm 3) or x-hat(y) (Algorithm 4) into the device tensors x, u."""
     _check(lib().dual_grad(tf.handle, _ptr(x0), _ptr(y), int(bool(homogeneous)), int(nrhs),
                            _ptr(x), _ptr(u), _stream(stream)))
+
+
+def dual_grad_noalloc(tf: TreeFactors, x0, y, homogeneous: bool, x, u, nrhs: int = 1, stream=None) -> None:
+    """dual_grad with the sweep workspace in the library's static device
+    scratch (no device allocation in the call)."""
+    _check(lib().dual_grad_noalloc(tf.handle, _ptr(x0), _ptr(y), int(bool(homogeneous)), int(nrhs),
+                                   _ptr(x), _ptr(u), _stream(stream)))
 
 
 def sweep_schedule(tf: TreeFactors, knobs) -> None:
