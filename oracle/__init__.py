@@ -37,7 +37,9 @@ class _Problem(C.Structure):
                 ("prob", _dp), ("A", _dp), ("B", _dp), ("c", _dp),
                 ("Q", _dp), ("R", _dp), ("S", _dp), ("q", _dp), ("r", _dp),
                 ("P", _dp), ("p", _dp),
-                ("xmin", _dp), ("xmax", _dp), ("umin", _dp), ("umax", _dp)]
+                ("xmin", _dp), ("xmax", _dp), ("umin", _dp), ("umax", _dp),
+                ("nc", C.c_int), ("ncN", C.c_int), ("F", _dp), ("G", _dp), ("FN", _dp),
+                ("zmin", _dp), ("zmax", _dp), ("wgt", _dp), ("hub", _dp)]
 
 
 class _Factors(C.Structure):
@@ -48,7 +50,9 @@ class _Factors(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("lam", C.c_double), ("eps", C.c_double), ("eps_curv", C.c_double),
                 ("mem", C.c_int), ("nu_max", C.c_int), ("max_iter", C.c_int),
-                ("precondition", C.c_int), ("method", C.c_int)]
+                ("precondition", C.c_int), ("method", C.c_int), ("backtrack", C.c_int),
+                ("div_window", C.c_int), ("bt_param", C.c_double), ("trace", _dp),
+                ("trace_iters", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -56,7 +60,12 @@ class _Info(C.Structure):
                 ("ls_trials", C.c_int), ("lbfgs_push", C.c_int), ("lbfgs_skip", C.c_int),
                 ("status", C.c_int), ("res_scaled_inf", C.c_double),
                 ("res_unscaled_inf", C.c_double), ("phi", C.c_double),
-                ("tau_hist", C.c_int * 32)]
+                ("tau_hist", C.c_int * 32), ("backtracks", C.c_int), ("lambda_final", C.c_double)]
+
+
+TRACE_COLS = 40     # trace row: lambda, ||R||_inf, accepted nu, nu_max, pairs used, dphi[nu]...
+TRACE_PHI = 5
+METHODS = {"minfbe": 0, "nama": 1, "gpad": 2}
 
 
 _lib = None
@@ -80,7 +89,13 @@ def lib():
         L.or_dual_dim.argtypes = [P]
         L.or_dual_dim.restype = C.c_int
         L.or_eval.argtypes = [P, F, _dp, C.c_double, C.c_int, _dp,
-                              _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+                              _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_con_dim.argtypes = [P]
+        L.or_con_dim.restype = C.c_int
+        L.or_apply_H.argtypes = [P, _dp, _dp, _dp]
+        L.or_apply_H.restype = None
+        L.or_apply_Ht.argtypes = [P, _dp, _dp]
+        L.or_apply_Ht.restype = None
         L.or_eval.restype = C.c_double
         L.or_hess_neg.argtypes = [P, F, C.c_int, _dp, _dp]
         L.or_hess_neg.restype = None
@@ -137,8 +152,16 @@ class Problem:
                 ("xmin", prob.xmin, np.float64, _dp), ("xmax", prob.xmax, np.float64, _dp),
                 ("umin", prob.umin, np.float64, _dp), ("umax", prob.umax, np.float64, _dp)]:
             setattr(s, name, _ptr(arr(name, a, dt), dt, ct))
+        if prob.F is not None:
+            s.nc, s.ncN = prob.nc, prob.ncN
+            for name in ("F", "G", "FN", "zmin", "zmax"):
+                setattr(s, name, _ptr(arr(name, getattr(prob, name))))
+        if prob.wgt is not None:
+            s.wgt = _ptr(arr("wgt", prob.wgt))
+            s.hub = _ptr(arr("hub", np.zeros(prob.m) if prob.hub is None else prob.hub))
         self.s = s
-        self.m = lib().or_dual_dim(C.byref(s))
+        self.m_xu = lib().or_dual_dim(C.byref(s))     # (x, u) layout of the sweeps
+        self.m = lib().or_con_dim(C.byref(s))         # constraint (dual) layout
         self.x0 = np.ascontiguousarray(prob.x0, dtype=np.float64)
 
 
@@ -174,9 +197,11 @@ def factor(prob) -> tuple:
 
 
 def sweep(pb: Problem, fac: Factors, y, homogeneous=False, x0=None):
-    """Algorithm 3 (homogeneous=False) or 4 on the unscaled dual y; (x, u)."""
+    """Algorithm 3 (homogeneous=False) or 4 on the unscaled dual y given in the
+    (x, u) layout (length m_xu; the constraint layout maps there by apply_Ht);
+    returns (x, u)."""
     y = np.ascontiguousarray(y, dtype=np.float64)
-    assert y.shape == (pb.m,)
+    assert y.shape == (pb.m_xu,)
     p = pb.x0 if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
     x = np.zeros((pb.V, pb.nx))
     u = np.zeros((pb.Vnl, pb.nu))
@@ -190,8 +215,24 @@ def cost(pb: Problem, x, u) -> float:
 
 
 def Hx(pb: Problem, x, u) -> np.ndarray:
-    out = np.zeros(pb.m)
+    """(x, u) in the (x, u) layout."""
+    out = np.zeros(pb.m_xu)
     lib().or_Hx(C.byref(pb.s), _ptr(np.ascontiguousarray(x)), _ptr(np.ascontiguousarray(u)), _ptr(out))
+    return out
+
+
+def apply_H(pb: Problem, x, u) -> np.ndarray:
+    """z = H(x, u) in the constraint layout (Sec. II-B)."""
+    out = np.zeros(pb.m)
+    lib().or_apply_H(C.byref(pb.s), _ptr(np.ascontiguousarray(x)), _ptr(np.ascontiguousarray(u)),
+                     _ptr(out))
+    return out
+
+
+def apply_Ht(pb: Problem, y) -> np.ndarray:
+    """H' y: constraint-layout dual -> (x, u) layout."""
+    out = np.zeros(pb.m_xu)
+    lib().or_apply_Ht(C.byref(pb.s), _ptr(np.ascontiguousarray(y, dtype=np.float64)), _ptr(out))
     return out
 
 
@@ -204,10 +245,12 @@ def evaluate(pb: Problem, fac: Factors, yb, lam: float, precondition: bool = Tru
     out["x"] = np.zeros((pb.V, pb.nx))
     out["u"] = np.zeros((pb.Vnl, pb.nu))
     gp = np.zeros(pb.m) if grad else None
+    extra = np.zeros(2)
     phi = lib().or_eval(C.byref(pb.s), C.byref(fac.s), _ptr(p), float(lam), int(bool(precondition)),
                         _ptr(yb), _ptr(out["x"]), _ptr(out["u"]), _ptr(out["Hbx"]), _ptr(out["z"]),
-                        _ptr(out["R"]), _ptr(out["T"]), _ptr(gp))
+                        _ptr(out["R"]), _ptr(out["T"]), _ptr(gp), _ptr(extra))
     out["phi"] = phi
+    out["fhat"], out["g"] = float(extra[0]), float(extra[1])
     if grad:
         out["grad_phi"] = gp
     return out
@@ -245,12 +288,18 @@ def lbfgs_direction(S: list, Qs: list, g) -> np.ndarray:
 
 def solve(pb: Problem, fac: Factors, method: str, lam: float, *, eps: float = 1e-6,
           mem: int = 5, nu_max: int = 10, max_iter: int = 1000, eps_curv: float = 1e-12,
-          precondition: bool = True, y0=None, x0=None) -> dict:
-    """Algorithm 1 (method='minfbe') or Algorithm 2 ('nama')."""
+          precondition: bool = True, y0=None, x0=None, backtrack: int = 0, bt_param: float = 0.0,
+          div_window: int = 50, trace_iters: int = 0) -> dict:
+    """Algorithm 1 (method='minfbe'), Algorithm 2 ('nama') or GPAD ('gpad');
+    backtrack 1 / 2 halves lambda by the two tests of Sec. III-B; with
+    trace_iters > 0 the result holds a per-update trace (TRACE_COLS columns,
+    every line-search trial evaluated)."""
+    trace = np.full((max(trace_iters, 1), TRACE_COLS), np.nan)
     o = _Opts(lam=float(lam), eps=float(eps), eps_curv=float(eps_curv), mem=int(mem),
               nu_max=int(nu_max), max_iter=int(max_iter),
-              precondition=int(bool(precondition)),
-              method={"minfbe": 0, "nama": 1}[method])
+              precondition=int(bool(precondition)), method=METHODS[method],
+              backtrack=int(backtrack), div_window=int(div_window), bt_param=float(bt_param),
+              trace=_ptr(trace) if trace_iters > 0 else _dp(), trace_iters=int(trace_iters))
     y = np.zeros(pb.m) if y0 is None else np.array(y0, dtype=np.float64, copy=True)
     p = pb.x0 if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
     x = np.zeros((pb.V, pb.nx))
@@ -262,4 +311,5 @@ def solve(pb: Problem, fac: Factors, method: str, lam: float, *, eps: float = 1e
                 sweeps_hom=info.sweeps_hom, ls_trials=info.ls_trials,
                 lbfgs_push=info.lbfgs_push, lbfgs_skip=info.lbfgs_skip,
                 res_scaled_inf=info.res_scaled_inf, res_unscaled_inf=info.res_unscaled_inf,
-                phi=info.phi, tau_hist=list(info.tau_hist))
+                phi=info.phi, tau_hist=list(info.tau_hist), backtracks=info.backtracks,
+                lambda_final=info.lambda_final, trace=trace[:trace_iters] if trace_iters > 0 else None)

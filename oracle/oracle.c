@@ -48,6 +48,18 @@ typedef struct {
     const double *P, *p;              /* [Vl][nx][nx], [Vl][nx] (p NULL ok) */
     const double *xmin, *xmax;        /* [V][nx]                             */
     const double *umin, *umax;        /* [Vnl][nu]                           */
+    /* Sec. II-B constraint map: z_i = F x_i + G u_i at non-leaf nodes and
+     * z_j = FN x_j at leaves, the same matrices at every node.  F == NULL
+     * selects the rows (x_i, u_i) and x_j themselves, bounded by the boxes
+     * above; otherwise the rows are bounded by zmin/zmax. */
+    int nc, ncN;
+    const double *F, *G, *FN;         /* [nc][nx], [nc][nu], [ncN][nx]      */
+    const double *zmin, *zmax;        /* [m] constraint-row bounds (F set)  */
+    /* Sec. II-B soft rows (NULL: every row hard): row k of node i adds
+     * pi_i wgt_k psi(dist(z_k, [lo_k, hi_k])) to the cost, psi the Huber
+     * function of threshold hub_k (0: the distance itself, an l1-type
+     * penalty); wgt_k = +inf keeps the row a hard bound. */
+    const double *wgt, *hub;          /* [m]                                 */
 } or_problem;
 
 typedef struct {
@@ -63,13 +75,30 @@ typedef struct {
 
 typedef struct {
     double lambda, eps, eps_curv;
-    int mem, nu_max, max_iter, precondition, method; /* method 0 MINFBE, 1 NAMA */
+    int mem, nu_max, max_iter, precondition;
+    int method;        /* 0 MINFBE (Alg. 1), 1 NAMA (Alg. 2), 2 GPAD (Sec. III-F) */
+    int backtrack;     /* 0 fixed lambda; 1 the decrease test of Sec. III-B
+                          (beta = bt_param); 2 the Linesearch-1 test
+                          (eps'' = bt_param)                                   */
+    int div_window;    /* divergence test every div_window updates (<= 0 off) */
+    double bt_param;
+    double *trace;     /* NULL or [trace_iters][OR_TRACE_COLS] per update      */
+    int trace_iters;
 } or_opts;
+
+/* trace row of update k: lambda, ||R(y^k)||_inf, accepted nu (-1: tau = 0),
+ * nu_max, L-BFGS pairs used by the direction, then phi(w_nu) - phi(y^k) for
+ * every trial nu = 0..nu_max (all evaluated in trace mode). */
+#define OR_TRACE_COLS 40
+#define OR_TRACE_PHI 5
+#define OR_BT_MAX 50       /* halvings of lambda before giving up */
 
 typedef struct {
     int iters, sweeps_affine, sweeps_hom, ls_trials, lbfgs_push, lbfgs_skip, status;
     double res_scaled_inf, res_unscaled_inf, phi;
     int tau_hist[32];
+    int backtracks;
+    double lambda_final;
 } or_info;
 
 /* Deliberate-mistake switch used only by the tests that show the pins have
@@ -79,7 +108,8 @@ int or_mutation = 0;
 /* ---------------------------- small helpers ---------------------------- */
 static int dual_off(const or_problem *pb, int i)
 {
-    /* Dual vector layout: non-leaf i holds (x-rows, u-rows); leaves follow. */
+    /* (x, u) layout of the sweeps: non-leaf i holds (x-rows, u-rows); leaves
+     * follow with their x-rows. */
     if (i < pb->Vnl) return i * (pb->nx + pb->nu);
     return pb->Vnl * (pb->nx + pb->nu) + (i - pb->Vnl) * pb->nx;
 }
@@ -92,6 +122,27 @@ int or_dual_dim(const or_problem *pb)
 static int node_rows(const or_problem *pb, int i)
 {
     return i < pb->Vnl ? pb->nx + pb->nu : pb->nx;
+}
+
+/* Constraint (dual) layout of Sec. II-C: the rows z_i of node i, non-leaf
+ * nodes first.  Without a constraint map it is the (x, u) layout. */
+static int con_rows(const or_problem *pb, int i)
+{
+    if (!pb->F) return node_rows(pb, i);
+    return i < pb->Vnl ? pb->nc : pb->ncN;
+}
+
+static int con_off(const or_problem *pb, int i)
+{
+    if (!pb->F) return dual_off(pb, i);
+    if (i < pb->Vnl) return i * pb->nc;
+    return pb->Vnl * pb->nc + (i - pb->Vnl) * pb->ncN;
+}
+
+int or_con_dim(const or_problem *pb)
+{
+    if (!pb->F) return or_dual_dim(pb);
+    return pb->Vnl * pb->nc + (pb->V - pb->Vnl) * pb->ncN;
 }
 
 /* Cholesky factor L (lower) of the n x n SPD matrix M; returns 0 or -1. */
@@ -427,9 +478,72 @@ void or_Hx(const or_problem *pb, const double *x, const double *u, double *hx)
     }
 }
 
-/* Per-row lower/upper box in the dual layout (unscaled). */
+/* The constraint map of Sec. II-B: z = H(x, u) in the constraint layout
+ * (identity rows without F). */
+void or_apply_H(const or_problem *pb, const double *x, const double *u, double *z)
+{
+    const int nx = pb->nx, nu = pb->nu;
+    if (!pb->F) { or_Hx(pb, x, u, z); return; }
+    for (int i = 0; i < pb->V; ++i) {
+        double *zi = z + con_off(pb, i);
+        const double *xi = x + (size_t)i * nx;
+        if (i < pb->Vnl) {
+            const double *ui = u + (size_t)i * nu;
+            for (int a = 0; a < pb->nc; ++a) {
+                double s = 0.0;
+                for (int b = 0; b < nx; ++b) s += pb->F[a * nx + b] * xi[b];
+                for (int b = 0; b < nu; ++b) s += pb->G[a * nu + b] * ui[b];
+                zi[a] = s;
+            }
+        } else {
+            for (int a = 0; a < pb->ncN; ++a) {
+                double s = 0.0;
+                for (int b = 0; b < nx; ++b) s += pb->FN[a * nx + b] * xi[b];
+                zi[a] = s;
+            }
+        }
+    }
+}
+
+/* Its adjoint: a constraint-layout dual y -> H' y in the (x, u) layout the
+ * sweeps take (the term <y, Hx> of the inner problem is <H'y, (x, u)>). */
+void or_apply_Ht(const or_problem *pb, const double *y, double *v)
+{
+    const int nx = pb->nx, nu = pb->nu;
+    if (!pb->F) { memcpy(v, y, sizeof(double) * or_dual_dim(pb)); return; }
+    for (int i = 0; i < pb->V; ++i) {
+        const double *yi = y + con_off(pb, i);
+        double *vi = v + dual_off(pb, i);
+        if (i < pb->Vnl) {
+            for (int b = 0; b < nx; ++b) {
+                double s = 0.0;
+                for (int a = 0; a < pb->nc; ++a) s += pb->F[a * nx + b] * yi[a];
+                vi[b] = s;
+            }
+            for (int b = 0; b < nu; ++b) {
+                double s = 0.0;
+                for (int a = 0; a < pb->nc; ++a) s += pb->G[a * nu + b] * yi[a];
+                vi[nx + b] = s;
+            }
+        } else {
+            for (int b = 0; b < nx; ++b) {
+                double s = 0.0;
+                for (int a = 0; a < pb->ncN; ++a) s += pb->FN[a * nx + b] * yi[a];
+                vi[b] = s;
+            }
+        }
+    }
+}
+
+/* Per-row lower/upper bound in the constraint layout (unscaled). */
 static void box_rows(const or_problem *pb, double *lo, double *hi)
 {
+    if (pb->F) {
+        const int m = or_con_dim(pb);
+        memcpy(lo, pb->zmin, sizeof(double) * m);
+        memcpy(hi, pb->zmax, sizeof(double) * m);
+        return;
+    }
     for (int i = 0; i < pb->V; ++i) {
         const int o = dual_off(pb, i);
         for (int a = 0; a < pb->nx; ++a) {
@@ -445,15 +559,50 @@ static void box_rows(const or_problem *pb, double *lo, double *hi)
 }
 
 /* Per-row scale of the preconditioning of Sec. III-E: sqrt(pi_i) for every row
- * of node i (1 when not preconditioning). */
-static void row_scale(const or_problem *pb, int precondition, double *sc)
+ * of node i (1 when not preconditioning); pr receives pi_i per row. */
+static void row_scale(const or_problem *pb, int precondition, double *sc, double *pr)
 {
     for (int i = 0; i < pb->V; ++i) {
         double s = 1.0;
         if (precondition) s = (or_mutation == 8) ? pb->prob[i] : sqrt(pb->prob[i]);
-        const int o = dual_off(pb, i);
-        for (int a = 0; a < node_rows(pb, i); ++a) sc[o + a] = s;
+        const int o = con_off(pb, i);
+        for (int a = 0; a < con_rows(pb, i); ++a) {
+            sc[o + a] = s;
+            pr[o + a] = pb->prob[i];
+        }
     }
+}
+
+/* ------------------------------ row penalties --------------------------- */
+/* Huber function of threshold d (d = 0: the identity) at a distance t >= 0. */
+static double huber(double t, double d)
+{
+    if (d > 0.0 && t <= d) return t * t / (2.0 * d);
+    return t - 0.5 * d;
+}
+
+/*
+ * One row of the prox of Sec. II-D, z = prox_{g/lambda}(v): minimise
+ * g(z) + (lambda/2)(z - v)^2 for g(z) = w psi_d(dist(z, [lo, hi])), with
+ * w = +inf meaning the indicator of [lo, hi] (projection).  Outside the
+ * interval the distance t = v - hi (or lo - v) shrinks to the minimiser s of
+ * w psi_d(s) + (lambda/2)(s - t)^2: s = t/(1 + w/(lambda d)) on the quadratic
+ * part of psi (s <= d), else s = t - w/lambda, never below 0.  *gz = g(z).
+ */
+static double row_prox(double v, double lo, double hi, double w, double d, double lam, double *gz)
+{
+    *gz = 0.0;
+    if (!(w < INFINITY)) return v < lo ? lo : (v > hi ? hi : v);
+    double t, side;
+    if (v > hi) { t = v - hi; side = 1.0; }
+    else if (v < lo) { t = lo - v; side = -1.0; }
+    else return v;
+    const double wl = w / lam;
+    double sh;
+    if (d > 0.0 && t <= d + wl) sh = t / (1.0 + wl / ((or_mutation == 10) ? 1.0 : d));
+    else sh = t - wl > 0.0 ? t - wl : 0.0;
+    *gz = w * huber(sh, d);
+    return side > 0.0 ? hi + sh : lo - sh;
 }
 
 /* ------------------------- evaluation at a dual point ------------------- */
@@ -462,9 +611,9 @@ typedef struct {
     const or_factors *f;
     const double *p;       /* x0 */
     double lambda;
-    int m, precondition;
-    double *sc, *lo, *hi;  /* per-row scale and (unscaled) box */
-    double *ytmp, *x, *u, *hx;
+    int m, mxu, precondition;
+    double *sc, *pr, *lo, *hi;  /* per row: scale, pi, unscaled bounds */
+    double *ytmp, *yxu, *x, *u, *hx;
     int sweeps_affine, sweeps_hom;
 } or_ctx;
 
@@ -473,65 +622,94 @@ static void ctx_init(or_ctx *c, const or_problem *pb, const or_factors *f,
 {
     c->pb = pb; c->f = f; c->p = p; c->lambda = lambda;
     c->precondition = precondition;
-    c->m = or_dual_dim(pb);
+    c->m = or_con_dim(pb);
+    c->mxu = or_dual_dim(pb);
     c->sc = malloc(sizeof(double) * c->m);
+    c->pr = malloc(sizeof(double) * c->m);
     c->lo = malloc(sizeof(double) * c->m);
     c->hi = malloc(sizeof(double) * c->m);
     c->ytmp = malloc(sizeof(double) * c->m);
     c->hx = malloc(sizeof(double) * c->m);
+    c->yxu = malloc(sizeof(double) * c->mxu);
     c->x = malloc(sizeof(double) * (size_t)pb->V * pb->nx);
     c->u = malloc(sizeof(double) * (size_t)pb->Vnl * pb->nu);
-    row_scale(pb, precondition, c->sc);
+    row_scale(pb, precondition, c->sc, c->pr);
     box_rows(pb, c->lo, c->hi);
     c->sweeps_affine = c->sweeps_hom = 0;
 }
 
 static void ctx_free(or_ctx *c)
 {
-    free(c->sc); free(c->lo); free(c->hi); free(c->ytmp); free(c->hx);
-    free(c->x); free(c->u);
+    free(c->sc); free(c->pr); free(c->lo); free(c->hi); free(c->ytmp); free(c->hx);
+    free(c->yxu); free(c->x); free(c->u);
+}
+
+/* Scaled penalty of row k: in the variables zb = s z of Sec. III-E the row
+ * function pi w psi_d(dist(zb / s, [lo, hi])) equals w' psi_d'(dist(zb,
+ * [s lo, s hi])) with w' = pi w / s and d' = s d. */
+static void row_params(const or_ctx *c, int k, double *lo, double *hi, double *w, double *d)
+{
+    const double s = c->sc[k];
+    *lo = s * c->lo[k];
+    *hi = s * c->hi[k];
+    *w = INFINITY;
+    *d = 0.0;
+    if (c->pb->wgt && c->pb->wgt[k] < INFINITY) {
+        *w = c->pr[k] * c->pb->wgt[k] / s;
+        *d = s * c->pb->hub[k];
+    }
 }
 
 /*
- * At the (scaled) dual point yb: x = x(sc*yb) (Algorithm 3), Hbx = sc*H x,
- * z = proj_{sc*Y}(yb/lambda + Hbx), R = z - Hbx (Sec. II-D), and the FBE
- *   phi = -f(x) + <yb, R> - (lambda/2) ||R||^2,
+ * At the (scaled) dual point yb: x = x(H'(sc*yb)) (Algorithm 3 on the
+ * (x, u)-layout dual), Hbx = sc * H x, z = prox_{g/lambda}(yb/lambda + Hbx),
+ * R = z - Hbx (Sec. II-D), and the FBE
+ *   phi = -f(x) + <yb, R> - (lambda/2) ||R||^2 - g(z),
  * which equals f-hat + g*(T) - lambda <grad f-hat, R> + (lambda/2)||R||^2 of
- * Sec. III-A because g*(T) = <T, z> for a box (Fenchel-Young equality at the
- * projection).  Outputs Hbx, R (each may be NULL) and returns phi.
+ * Sec. III-A because g*(T) = <T, z> - g(z) (Fenchel-Young equality at the
+ * prox point, T = lambda (v - z) being a subgradient of g at z).  Outputs Hbx,
+ * R (each may be NULL), f-hat(yb) = -f(x) - <yb, Hbx> and g(z) (NULL ok);
+ * returns phi.
  */
-static double ctx_eval(or_ctx *c, const double *yb, double *Hbx, double *R)
+static double ctx_eval(or_ctx *c, const double *yb, double *Hbx, double *R, double *fhat, double *gsum)
 {
     const int m = c->m;
     for (int k = 0; k < m; ++k) c->ytmp[k] = c->sc[k] * yb[k];
-    or_sweep(c->pb, c->f, c->ytmp, c->p, 0, c->x, c->u);
+    or_apply_Ht(c->pb, c->ytmp, c->yxu);
+    or_sweep(c->pb, c->f, c->yxu, c->p, 0, c->x, c->u);
     c->sweeps_affine++;
-    or_Hx(c->pb, c->x, c->u, c->hx);
-    double inner = 0.0, nrm2 = 0.0;
+    or_apply_H(c->pb, c->x, c->u, c->hx);
+    double inner = 0.0, nrm2 = 0.0, gs = 0.0, yh = 0.0;
     for (int k = 0; k < m; ++k) {
         const double h = c->sc[k] * c->hx[k];
         const double v = yb[k] / c->lambda + h;
-        const double lo = c->sc[k] * c->lo[k], hi = c->sc[k] * c->hi[k];
-        const double z = v < lo ? lo : (v > hi ? hi : v);
+        double lo, hi, w, d, gz;
+        row_params(c, k, &lo, &hi, &w, &d);
+        const double z = row_prox(v, lo, hi, w, d, c->lambda, &gz);
         const double r = z - h;
         if (Hbx) Hbx[k] = h;
         if (R) R[k] = r;
         inner += yb[k] * r;
         nrm2 += r * r;
+        gs += gz;
+        yh += yb[k] * h;
     }
     const double fx = or_cost(c->pb, c->x, c->u);
-    if (or_mutation == 6) return -fx + inner + 0.5 * c->lambda * nrm2;
-    return -fx + inner - 0.5 * c->lambda * nrm2;
+    if (fhat) *fhat = -fx - yh;
+    if (gsum) *gsum = gs;
+    if (or_mutation == 6) return -fx + inner + 0.5 * c->lambda * nrm2 - gs;
+    return -fx + inner - 0.5 * c->lambda * nrm2 - gs;
 }
 
-/* Hb x-hat(sc * v): the linear part (Algorithm 4), scaled back; the Hessian
- * of the (scaled) dual function applied to v is minus this. */
+/* Hb x-hat(H'(sc * v)): the linear part (Algorithm 4), scaled back; the
+ * Hessian of the (scaled) dual function applied to v is minus this. */
 static void ctx_hom(or_ctx *c, const double *v, double *out)
 {
     for (int k = 0; k < c->m; ++k) c->ytmp[k] = c->sc[k] * v[k];
-    or_sweep(c->pb, c->f, c->ytmp, c->p, 1, c->x, c->u);
+    or_apply_Ht(c->pb, c->ytmp, c->yxu);
+    or_sweep(c->pb, c->f, c->yxu, c->p, 1, c->x, c->u);
     c->sweeps_hom++;
-    or_Hx(c->pb, c->x, c->u, c->hx);
+    or_apply_H(c->pb, c->x, c->u, c->hx);
     for (int k = 0; k < c->m; ++k) out[k] = c->sc[k] * c->hx[k];
 }
 
@@ -539,18 +717,21 @@ static void ctx_hom(or_ctx *c, const double *v, double *out)
  * Exported evaluation: given a (scaled) dual point, return x, u (unscaled
  * primal, Algorithm 3), Hbx, z, R, T = y - lambda R, and grad_phi =
  * (I - lambda Hess f-hat) R = R + lambda Hb x-hat(sc R) (Sec. III-A).
- * Any output pointer may be NULL.  Returns phi.
+ * extra[0] = f-hat(yb), extra[1] = g(z).  Any output pointer may be NULL.
+ * Returns phi.
  */
 double or_eval(const or_problem *pb, const or_factors *f, const double *p,
                double lambda, int precondition, const double *yb,
                double *x, double *u, double *Hbx, double *z, double *R,
-               double *T, double *grad_phi)
+               double *T, double *grad_phi, double *extra)
 {
     or_ctx c;
     ctx_init(&c, pb, f, p, lambda, precondition);
     const int m = c.m;
     double *h = malloc(sizeof(double) * m), *r = malloc(sizeof(double) * m);
-    const double phi = ctx_eval(&c, yb, h, r);
+    double fh, gs;
+    const double phi = ctx_eval(&c, yb, h, r, &fh, &gs);
+    if (extra) { extra[0] = fh; extra[1] = gs; }
     if (x) memcpy(x, c.x, sizeof(double) * (size_t)pb->V * pb->nx);
     if (u) memcpy(u, c.u, sizeof(double) * (size_t)pb->Vnl * pb->nu);
     for (int k = 0; k < m; ++k) {
@@ -570,7 +751,7 @@ double or_eval(const or_problem *pb, const or_factors *f, const double *p,
     return phi;
 }
 
-/* v -> Hb x-hat(sc v), exported for the Hessian pins (the Hessian of the
+/* v -> Hb x-hat(H'(sc v)), exported for the Hessian pins (the Hessian of the
  * scaled dual function is minus this map). */
 void or_hess_neg(const or_problem *pb, const or_factors *f, int precondition,
                  const double *v, double *out)
@@ -702,6 +883,8 @@ static void lb_direction(or_lbfgs *b, const double *g, double *d)
                        (const double *const *)b->qo, g, d);
 }
 
+static void lb_clear(or_lbfgs *b) { b->cnt = 0; b->head = 0; }
+
 /* --------------------------- Algorithms 1 and 2 -------------------------- */
 static double dot(int m, const double *a, const double *b)
 {
@@ -718,23 +901,159 @@ static double inf_norm(int m, const double *a)
 }
 
 /*
- * Dual MINFBE (Algorithm 1, opts->method == 0) or NAMA (Algorithm 2,
- * method == 1) on the (scaled, if opts->precondition) dual.  y_inout holds the
- * initial dual on entry and the last iterate on exit; x, u receive x(y).
+ * Divergence test.  The problem is assumed feasible (Sec. II-C); when it is
+ * not, the dual function F = f-hat + g* is unbounded below and the iterates
+ * run off along a direction d with (i) H'd orthogonal to the directions of
+ * the dynamics, so that f-hat is affine along d (its Hessian, minus the
+ * Algorithm-4 map, annihilates d), and (ii) F decreasing linearly along d:
+ *   sigma_Y(d) - <d, H x(y)> < 0,
+ * sigma_Y the support function of the (scaled) boxes; such a d certifies
+ * that no x satisfies the dynamics and the boxes (Farkas).  Every div_window
+ * updates the increment d = y^k - y^{k - div_window} is tested:
+ *   lambda ||Hb x-hat(sc d)||_inf <= eps_div ||d||_inf  and
+ *   sigma(d) - <d, Hb x(y^k)> <= -eps_div ||d||_inf ||R(y^k)||_inf,
+ * with eps_div = 1e-3; rows with an infinite bound (and soft rows, whose g*
+ * has a bounded domain) must carry no part of d (|d_k| <= 1e-9 ||d||_inf).
+ * Returns 1 on divergence.  One Algorithm-4 sweep per test.
+ */
+#define OR_EPS_DIV 1e-3
+typedef struct { int last; double *yck; } or_divtest;
+
+static int div_check(or_ctx *c, or_divtest *t, int window, int k, const double *y, const double *Hbx,
+                     const double *R)
+{
+    const int m = c->m;
+    if (window <= 0 || k % window != 0 || k == t->last) return 0;
+    int diverged = 0;
+    if (t->last >= 0) {
+        double *d = malloc(sizeof(double) * m), *hv = malloc(sizeof(double) * m);
+        double dn = 0.0, rn = 0.0;
+        for (int kk = 0; kk < m; ++kk) {
+            d[kk] = y[kk] - t->yck[kk];
+            dn = fmax(dn, fabs(d[kk]));
+            rn = fmax(rn, fabs(R[kk]));
+        }
+        if (dn > 0.0) {
+            ctx_hom(c, d, hv);
+            double hn = 0.0, lin = 0.0;
+            int dom = 1;
+            for (int kk = 0; kk < m; ++kk) {
+                hn = fmax(hn, fabs(hv[kk]));
+                if (d[kk] == 0.0) continue;
+                double lo, hi, w, dd;
+                row_params(c, kk, &lo, &hi, &w, &dd);
+                const int tiny = fabs(d[kk]) <= 1e-9 * dn;
+                if (w < INFINITY || (d[kk] > 0.0 && !(hi < INFINITY)) || (d[kk] < 0.0 && !(lo > -INFINITY))) {
+                    if (!tiny) dom = 0;
+                    lin -= d[kk] * Hbx[kk];
+                    continue;
+                }
+                lin += (d[kk] > 0.0 ? hi * d[kk] : lo * d[kk]) - d[kk] * Hbx[kk];
+            }
+            diverged = dom && c->lambda * hn <= OR_EPS_DIV * dn && lin <= -OR_EPS_DIV * dn * rn;
+        }
+        free(d); free(hv);
+    }
+    memcpy(t->yck, y, sizeof(double) * m);
+    t->last = k;
+    return diverged;
+}
+
+/*
+ * Accelerated dual proximal gradient (GPAD), the warm start of Sec. III-F and
+ * the comparison method of Sec. IV-A: from y^0 = y^{-1} = y_inout and
+ * theta_0 = theta_{-1} = 1, update k takes the forward-backward step at the
+ * extrapolated point
+ *   w^k = y^k + theta_k (1/theta_{k-1} - 1) (y^k - y^{k-1}),
+ *   y^{k+1} = T_lambda(w^k),
+ *   theta_{k+1} = (sqrt(theta_k^4 + 4 theta_k^2) - theta_k^2) / 2.
+ * One Algorithm-3 sweep per update.  The termination test of the other
+ * methods is applied to R_lambda(w^k); the last evaluated point w^k is
+ * returned in y_inout (max_iter = k stops after k steps with w^k).
+ */
+static int gpad(const or_problem *pb, const or_factors *f, const double *p,
+                const or_opts *o, double *y_inout, double *x, double *u, or_info *info)
+{
+    or_ctx c;
+    const double lam = o->lambda;
+    ctx_init(&c, pb, f, p, lam, o->precondition);
+    const int m = c.m;
+    double *y = malloc(sizeof(double) * m), *yp = malloc(sizeof(double) * m);
+    double *w = y_inout, *R = malloc(sizeof(double) * m);
+    memcpy(y, y_inout, sizeof(double) * m);
+    memcpy(yp, y_inout, sizeof(double) * m);
+    double th = 1.0, thp = 1.0;
+    double *hb = malloc(sizeof(double) * m);
+    or_divtest dt = {-1, malloc(sizeof(double) * m)};
+    int status = 1, k = 0;
+    double phi = 0.0;
+    for (;;) {
+        const double beta = (or_mutation == 9) ? th * (thp - 1.0) : th * (1.0 / thp - 1.0);
+        for (int kk = 0; kk < m; ++kk) w[kk] = y[kk] + beta * (y[kk] - yp[kk]);
+        phi = ctx_eval(&c, w, hb, R, NULL, NULL);
+        const double rn = inf_norm(m, R);
+        if (!isfinite(rn)) { status = -5; break; }
+        if (rn <= o->eps) { status = 0; break; }
+        if (div_check(&c, &dt, o->div_window, k, w, hb, R)) { status = -6; break; }
+        if (k >= o->max_iter) { status = 1; break; }
+        for (int kk = 0; kk < m; ++kk) {
+            yp[kk] = y[kk];
+            y[kk] = w[kk] - lam * R[kk];
+        }
+        thp = th;
+        th = 0.5 * (sqrt(th * th * th * th + 4.0 * th * th) - th * th);
+        ++k;
+    }
+    memcpy(x, c.x, sizeof(double) * (size_t)pb->V * pb->nx);
+    memcpy(u, c.u, sizeof(double) * (size_t)pb->Vnl * pb->nu);
+    double unsc = 0.0;
+    for (int kk = 0; kk < m; ++kk) unsc = fmax(unsc, fabs(R[kk] / c.sc[kk]));
+    info->iters = k;
+    info->sweeps_affine = c.sweeps_affine;
+    info->status = status;
+    info->res_scaled_inf = inf_norm(m, R);
+    info->res_unscaled_inf = unsc;
+    info->phi = phi;
+    info->lambda_final = lam;
+    free(y); free(yp); free(R); free(hb); free(dt.yck);
+    ctx_free(&c);
+    return status;
+}
+
+/*
+ * Dual MINFBE (Algorithm 1, opts->method == 0), NAMA (Algorithm 2, method
+ * 1) or GPAD (method 2) on the (scaled, if opts->precondition) dual.  y_inout
+ * holds the initial dual on entry and the last iterate on exit; x, u receive
+ * x(y).
  *
  * Readings: the line search takes the LARGEST step tau = 2^-nu, nu = 0..nu_max,
  * with phi(w) <= phi(y) (nu = 0 first), and falls back to tau = 0 after nu_max
  * failures; MINFBE's update is y+ = T(w); NAMA's trial point is
  * w = y - (1 - tau) lambda r + tau d, so tau = 0 gives the forward-backward
  * step T(y), and y+ = T(w); the stopping test is ||R||_inf <= eps in the
- * solver's variables.  Returns 0 (converged), 1 (max_iter reached) or -5
- * (non-finite values).
+ * solver's variables.
+ *
+ * Backtracking on lambda (Sec. III-B), both tests with the L-BFGS buffer
+ * emptied whenever lambda is halved, after which the update is taken again
+ * from the same y^k with the new lambda (it does not count as an update):
+ *   backtrack = 1: after y+ = T(w), halve lambda when
+ *     f-hat(y+) > f-hat(w) - lambda <grad f-hat(w), R(w)>
+ *                 + ((1 - beta) lambda / 2) ||R(w)||^2,   beta = bt_param
+ *     (read at the point w the forward-backward step was taken from; w = y
+ *     when tau = 0 in MINFBE);
+ *   backtrack = 2: before the direction, halve lambda when
+ *     lambda ||grad f-hat(T(y)) - grad f-hat(y)|| > eps'' ||T(y) - y||,
+ *     eps'' = bt_param; both gradients are evaluated directly.
+ * Returns 0 (converged), 1 (max_iter reached), -5 (non-finite values or more
+ * than OR_BT_MAX halvings) or -6 (divergence test).
  */
 int or_solve(const or_problem *pb, const or_factors *f, const double *p,
              const or_opts *o, double *y_inout, double *x, double *u, or_info *info)
 {
+    memset(info, 0, sizeof(*info));
+    if (o->method == 2) return gpad(pb, f, p, o, y_inout, x, u, info);
     or_ctx c;
-    const double lam = o->lambda;
+    double lam = o->lambda;
     ctx_init(&c, pb, f, p, lam, o->precondition);
     const int m = c.m;
     double *y = y_inout;
@@ -743,73 +1062,144 @@ int or_solve(const or_problem *pb, const or_factors *f, const double *p,
     double *Rw = malloc(sizeof(double) * m), *yn = malloc(sizeof(double) * m);
     double *Rn = malloc(sizeof(double) * m), *gn = malloc(sizeof(double) * m);
     double *s = malloc(sizeof(double) * m), *qv = malloc(sizeof(double) * m);
-    double *hv = malloc(sizeof(double) * m);
+    double *hv = malloc(sizeof(double) * m), *hw = malloc(sizeof(double) * m);
+    double *yt = malloc(sizeof(double) * m), *Rt = malloc(sizeof(double) * m);
     or_lbfgs lb;
     lb_init(&lb, o->mem, m);
-    memset(info, 0, sizeof(*info));
     int status = 1;
+    double fh = 0.0;
+    double *hb = malloc(sizeof(double) * m), *hbn = malloc(sizeof(double) * m);
+    or_divtest dt = {-1, malloc(sizeof(double) * m)};
 
-    double phi = ctx_eval(&c, y, NULL, R);
-    if (o->method == 0) {                           /* grad phi = R + lam Hb xhat(sc R) */
-        ctx_hom(&c, R, hv);
-        for (int k = 0; k < m; ++k) g[k] = R[k] + lam * hv[k];
-    }
+    /* phi, R (and grad phi for MINFBE) at y with the current lambda */
+#define EVAL_AT_Y()                                                          \
+    do {                                                                     \
+        phi = ctx_eval(&c, y, hb, R, &fh, NULL);                             \
+        if (o->method == 0) {                                                \
+            ctx_hom(&c, R, hv);                                              \
+            for (int kk = 0; kk < m; ++kk) g[kk] = R[kk] + lam * hv[kk];     \
+        }                                                                    \
+    } while (0)
+    double phi;
+    EVAL_AT_Y();
     int k = 0;
     for (;;) {
         const double rn = inf_norm(m, R);
         if (!isfinite(rn) || !isfinite(phi)) { status = -5; break; }
         if (rn <= o->eps) { status = 0; break; }
+        if (div_check(&c, &dt, o->div_window, k, y, hb, R)) { status = -6; break; }
         if (k >= o->max_iter) { status = 1; break; }
 
-        const double *dir_src = (o->method == 0) ? g : R;
-        lb_direction(&lb, dir_src, d);
+        int halve = 0;
+        if (o->backtrack == 2) {
+            /* T(y) and the dual gradient there, both directly */
+            for (int kk = 0; kk < m; ++kk) yt[kk] = y[kk] - lam * R[kk];
+            double *h0 = malloc(sizeof(double) * m);
+            ctx_eval(&c, y, h0, NULL, NULL, NULL);
+            ctx_eval(&c, yt, hw, Rt, NULL, NULL);
+            double gd2 = 0.0, st2 = 0.0;
+            for (int kk = 0; kk < m; ++kk) {
+                const double gd = -(hw[kk] - h0[kk]);    /* grad f-hat = -Hb x */
+                gd2 += gd * gd;
+                st2 += (yt[kk] - y[kk]) * (yt[kk] - y[kk]);
+            }
+            free(h0);
+            halve = lam * sqrt(gd2) > o->bt_param * sqrt(st2);
+        }
+        if (!halve) {
+            const double *dir_src = (o->method == 0) ? g : R;
+            const int used = lb.cnt;
+            lb_direction(&lb, dir_src, d);
 
-        int accepted = -1;
-        double phiw = phi;
-        for (int nu = 0; nu <= o->nu_max; ++nu) {
-            const double tau = ldexp(1.0, -nu);
+            int accepted = -1;
+            double phiw = phi;
+            double *row = (o->trace && k < o->trace_iters) ? o->trace + (size_t)k * OR_TRACE_COLS : NULL;
+            if (row) {
+                for (int cc = 0; cc < OR_TRACE_COLS; ++cc) row[cc] = NAN;
+                row[0] = lam; row[1] = rn; row[3] = o->nu_max; row[4] = used;
+            }
+            for (int nu = 0; nu <= o->nu_max; ++nu) {
+                const double tau = ldexp(1.0, -nu);
+                for (int kk = 0; kk < m; ++kk)
+                    w[kk] = (o->method == 0) ? y[kk] + tau * d[kk]
+                                             : y[kk] - (1.0 - tau) * lam * R[kk] + tau * d[kk];
+                phiw = ctx_eval(&c, w, NULL, Rw, NULL, NULL);
+                if (accepted < 0) info->ls_trials++;
+                if (row && OR_TRACE_PHI + nu < OR_TRACE_COLS) row[OR_TRACE_PHI + nu] = phiw - phi;
+                if (accepted < 0 && phiw <= phi) {
+                    accepted = nu;
+                    if (!row) break;
+                }
+            }
+            if (row) row[2] = accepted;
+            /* w and its residual at the accepted trial */
+            if (accepted < 0) {                         /* tau = 0 */
+                for (int kk = 0; kk < m; ++kk)
+                    w[kk] = (o->method == 0) ? y[kk] : y[kk] - lam * R[kk];
+            } else {
+                const double tau = ldexp(1.0, -accepted);
+                for (int kk = 0; kk < m; ++kk)
+                    w[kk] = (o->method == 0) ? y[kk] + tau * d[kk]
+                                             : y[kk] - (1.0 - tau) * lam * R[kk] + tau * d[kk];
+            }
+            ctx_eval(&c, w, hw, Rw, NULL, NULL);
             for (int kk = 0; kk < m; ++kk)
-                w[kk] = (o->method == 0) ? y[kk] + tau * d[kk]
-                                         : y[kk] - (1.0 - tau) * lam * R[kk] + tau * d[kk];
-            phiw = ctx_eval(&c, w, NULL, Rw);
-            info->ls_trials++;
-            if (phiw <= phi) { accepted = nu; break; }
-        }
-        if (accepted < 0) {                         /* tau = 0 */
-            for (int kk = 0; kk < m; ++kk)
-                w[kk] = (o->method == 0) ? y[kk] : y[kk] - lam * R[kk];
-            if (o->method == 0) memcpy(Rw, R, sizeof(double) * m);
-            else ctx_eval(&c, w, NULL, Rw);
-            info->tau_hist[31]++;
-        } else {
-            info->tau_hist[accepted < 31 ? accepted : 30]++;
-        }
-        for (int kk = 0; kk < m; ++kk)
-            yn[kk] = (or_mutation == 5) ? w[kk] + lam * Rw[kk] : w[kk] - lam * Rw[kk];
+                yn[kk] = (or_mutation == 5) ? w[kk] + lam * Rw[kk] : w[kk] - lam * Rw[kk];
 
-        phi = ctx_eval(&c, yn, NULL, Rn);
-        if (o->method == 0) {
-            ctx_hom(&c, Rn, hv);
-            for (int kk = 0; kk < m; ++kk) gn[kk] = Rn[kk] + lam * hv[kk];
+            const double phin = ctx_eval(&c, yn, hbn, Rn, NULL, NULL);
+            if (o->backtrack == 1) {
+                /* f-hat is quadratic, so with delta = y+ - w = -lambda R(w)
+                 * its increment is exactly
+                 *   f-hat(y+) - f-hat(w) = <grad f-hat(w), delta>
+                 *                          - (1/2) <delta, Hb x-hat(sc delta)>,
+                 * the second term from one Algorithm-4 sweep.  The first term
+                 * is the test's -lambda <grad f-hat(w), R(w)>, present on both
+                 * sides, so the test compares the remaining terms (evaluating
+                 * f-hat(y+) and f-hat(w) and subtracting would lose the test
+                 * in rounding once ||R|| is small). */
+                for (int kk = 0; kk < m; ++kk) s[kk] = yn[kk] - w[kk];
+                ctx_hom(&c, s, qv);
+                const double curv = -0.5 * dot(m, s, qv);
+                const double bound = 0.5 * (1.0 - o->bt_param) * lam * dot(m, Rw, Rw);
+                halve = curv > bound;
+            }
+            if (!halve) {
+                if (accepted < 0) info->tau_hist[31]++;
+                else info->tau_hist[accepted < 31 ? accepted : 30]++;
+                phi = phin;
+                if (o->method == 0) {
+                    ctx_hom(&c, Rn, hv);
+                    for (int kk = 0; kk < m; ++kk) gn[kk] = Rn[kk] + lam * hv[kk];
+                }
+                /* curvature-guarded push of (s, q) */
+                const double *gold = (o->method == 0) ? g : R;
+                const double *gnew = (o->method == 0) ? gn : Rn;
+                for (int kk = 0; kk < m; ++kk) { s[kk] = yn[kk] - y[kk]; qv[kk] = gnew[kk] - gold[kk]; }
+                const double sq = dot(m, s, qv);
+                if (sq > o->eps_curv * dot(m, s, s) * dot(m, gold, gold)) {
+                    lb_push(&lb, s, qv);
+                    info->lbfgs_push++;
+                } else {
+                    info->lbfgs_skip++;
+                }
+                memcpy(y, yn, sizeof(double) * m);
+                memcpy(R, Rn, sizeof(double) * m);
+                memcpy(hb, hbn, sizeof(double) * m);
+                if (o->method == 0) memcpy(g, gn, sizeof(double) * m);
+                ++k;
+                continue;
+            }
         }
-        /* curvature-guarded push of (s, q) */
-        const double *gold = (o->method == 0) ? g : R;
-        const double *gnew = (o->method == 0) ? gn : Rn;
-        for (int kk = 0; kk < m; ++kk) { s[kk] = yn[kk] - y[kk]; qv[kk] = gnew[kk] - gold[kk]; }
-        const double sq = dot(m, s, qv);
-        if (sq > o->eps_curv * dot(m, s, s) * dot(m, gold, gold)) {
-            lb_push(&lb, s, qv);
-            info->lbfgs_push++;
-        } else {
-            info->lbfgs_skip++;
-        }
-        memcpy(y, yn, sizeof(double) * m);
-        memcpy(R, Rn, sizeof(double) * m);
-        if (o->method == 0) memcpy(g, gn, sizeof(double) * m);
-        ++k;
+        /* halve lambda, empty the buffer, evaluate again at the same y */
+        if (++info->backtracks > OR_BT_MAX) { status = -5; break; }
+        lam *= 0.5;
+        c.lambda = lam;
+        if (or_mutation != 11) lb_clear(&lb);
+        EVAL_AT_Y();
     }
+#undef EVAL_AT_Y
     /* final primal x(y) and residuals */
-    phi = ctx_eval(&c, y, NULL, R);
+    phi = ctx_eval(&c, y, NULL, R, NULL, NULL);
     memcpy(x, c.x, sizeof(double) * (size_t)pb->V * pb->nx);
     memcpy(u, c.u, sizeof(double) * (size_t)pb->Vnl * pb->nu);
     double unsc = 0.0;
@@ -821,9 +1211,10 @@ int or_solve(const or_problem *pb, const or_factors *f, const double *p,
     info->res_scaled_inf = inf_norm(m, R);
     info->res_unscaled_inf = unsc;
     info->phi = phi;
+    info->lambda_final = lam;
     lb_free(&lb);
     free(R); free(g); free(d); free(w); free(Rw); free(yn); free(Rn); free(gn);
-    free(s); free(qv); free(hv);
+    free(s); free(qv); free(hv); free(hw); free(yt); free(Rt); free(hb); free(hbn); free(dt.yck);
     ctx_free(&c);
     return status;
 }

@@ -114,21 +114,11 @@ class DenseQP:
         return x, u
 
     def H_linear(self, y):
-        """(h, hconst): <y, H x> = h' X + hconst for the stacked variables."""
-        nx = self.nx
-        h = np.zeros(self.n)
-        hc = 0.0
-        blocks, m = self.dual_blocks()
-        assert y.shape == (m,)
-        for i, o in blocks:
-            yx = y[o:o + nx]
-            if i == 0:
-                hc += yx @ self.p
-            else:
-                h[self.xi(i)] += yx
-            if i < self.Vnl:
-                h[self.ui(i)] += y[o + nx:o + nx + self.nu]
-        return h, hc
+        """(h, hconst): <y, H x> = h' X + hconst for the stacked variables
+        (y in the constraint layout; the map of ``constraint_matrix``)."""
+        Hd, hcv = constraint_matrix(self)
+        assert y.shape == (Hd.shape[0],)
+        return Hd.T @ y, float(hcv @ y)
 
     def inner(self, y, homogeneous=False):
         """x(y) by a dense KKT solve of min f(X) + <y, HX> s.t. EX = e.
@@ -300,3 +290,166 @@ def active_set_bruteforce(G, g, E, e, lb, ub, tol=1e-10):
             if best is None or obj < best[1] - 1e-12:
                 best = (X, obj)
     return best
+
+
+# ---------------------- constraint map and soft rows ---------------------- #
+def constraint_matrix(dq):
+    """The map of Sec. II-B written out densely: z = Hd X + hc in the dual
+    (constraint) layout, Hd [m][n], from the problem statement (F, G, FN at
+    every node, or the rows (x_i, u_i) and x_j themselves).  x_0 = p is data,
+    so the root's state part goes to the constant hc."""
+    prob = dq.prob
+    nx, nu, V, Vnl = dq.nx, dq.nu, dq.V, dq.Vnl
+    if prob.F is None:
+        F, G, FN = (np.vstack([np.eye(nx), np.zeros((nu, nx))]),
+                    np.vstack([np.zeros((nx, nu)), np.eye(nu)]), np.eye(nx))
+    else:
+        F, G, FN = prob.F, prob.G, prob.FN
+    rows = []
+    for i in range(V):
+        rows.append(F.shape[0] if i < Vnl else FN.shape[0])
+    m = int(sum(rows))
+    Hd = np.zeros((m, dq.n))
+    hc = np.zeros(m)
+    o = 0
+    for i in range(V):
+        r = rows[i]
+        Fi = F if i < Vnl else FN
+        if i == 0:
+            hc[o:o + r] = Fi @ dq.p
+        else:
+            Hd[o:o + r, dq.xi(i)] = Fi
+        if i < Vnl:
+            Hd[o:o + r, dq.ui(i)] = G
+        o += r
+    return Hd, hc
+
+
+def row_bounds(prob):
+    """Lower / upper bound of every constraint row (dual layout)."""
+    if prob.F is not None:
+        return np.asarray(prob.zmin, float), np.asarray(prob.zmax, float)
+    t = prob.tree
+    lo, hi = [], []
+    for i in range(t.V):
+        lo += list(prob.xmin[i])
+        hi += list(prob.xmax[i])
+        if i < t.Vnl:
+            lo += list(prob.umin[i])
+            hi += list(prob.umax[i])
+    return np.array(lo), np.array(hi)
+
+
+def row_prob(prob):
+    """Probability of the node owning each constraint row."""
+    t = prob.tree
+    out = []
+    for i in range(t.V):
+        r = prob.nc if i < t.Vnl else prob.ncN
+        out += [t.prob[i]] * r
+    return np.array(out)
+
+
+def soft_qp(prob):
+    """The whole problem with a general constraint map and soft rows as one
+    QP for ``ipm``: variables (X, z, slacks) with z = Hd X + hc; a hard row
+    bounds z directly; a soft row k (weight w, Huber threshold d, node
+    probability pi) costs pi w (e + q^2 / (2 d)) with e, q >= 0 (no q when
+    d = 0) and z - hi = e + q + a (a <= 0), z - lo = b - e - q (b >= 0): at
+    the optimum e + q is the distance of z to [lo, hi] and the cost its Huber
+    function (min of e + q^2/(2d) over e + q >= t is t^2/(2d) for t <= d,
+    else t - d/2).  Returns (G, g, k, E, e, lb, ub, n, dq) with n the size of
+    X."""
+    dq = DenseQP(prob)
+    Hd, hc = constraint_matrix(dq)
+    lo, hi = row_bounds(prob)
+    m, n = Hd.shape
+    pi = row_prob(prob)
+    wgt = prob.wgt if prob.wgt is not None else np.full(m, np.inf)
+    hub = prob.hub if prob.hub is not None else np.zeros(m)
+    # every bound sits on the z rows (with the identity map too), so X is free
+    lbs, ubs, diag, lin = [-np.inf] * n, [np.inf] * n, [0.0] * n, list(dq.g)
+
+    def new_var(lo_, hi_, quad=0.0, cost=0.0):
+        lbs.append(lo_)
+        ubs.append(hi_)
+        diag.append(quad)
+        lin.append(cost)
+        return len(lbs) - 1
+
+    eq = []          # (dict var -> coefficient, rhs)
+    for r in range(dq.E.shape[0]):
+        eq.append(({j: dq.E[r, j] for j in np.nonzero(dq.E[r])[0]}, dq.e[r]))
+    for k in range(m):
+        soft = np.isfinite(wgt[k])
+        z = new_var(-np.inf if soft else lo[k], np.inf if soft else hi[k])
+        row = {j: -Hd[k, j] for j in np.nonzero(Hd[k])[0]}
+        row[z] = 1.0
+        eq.append((row, hc[k]))
+        if not soft:
+            continue
+        w, d = wgt[k] * pi[k], hub[k]
+        e = new_var(0.0, np.inf, cost=w)
+        q = new_var(0.0, np.inf, quad=w / d) if d > 0 else None
+        if np.isfinite(hi[k]):
+            a = new_var(-np.inf, 0.0)
+            row = {z: 1.0, e: -1.0, a: -1.0}
+            if q is not None:
+                row[q] = -1.0
+            eq.append((row, hi[k]))
+        if np.isfinite(lo[k]):
+            b = new_var(0.0, np.inf)
+            row = {z: 1.0, e: 1.0, b: -1.0}
+            if q is not None:
+                row[q] = 1.0
+            eq.append((row, lo[k]))
+    N = len(lbs)
+    Gm = np.zeros((N, N))
+    Gm[:n, :n] = dq.G
+    Gm[np.arange(n, N), np.arange(n, N)] = diag[n:]
+    E = np.zeros((len(eq), N))
+    ev = np.zeros(len(eq))
+    for r, (row, rhs) in enumerate(eq):
+        for j, v in row.items():
+            E[r, j] = v
+        ev[r] = rhs
+    return Gm, np.array(lin), dq.k, E, ev, np.array(lbs), np.array(ubs), n, dq
+
+
+def fista_dense(prob, lam, iters, precondition=True):
+    """Textbook FISTA (Beck and Teboulle 2009, the t_k form) on the dual
+    min f-hat(y) + g*(y) in the scaled variables, with hard rows only:
+    the gradient -Hb x(y) comes from the dense KKT solve of the inner problem
+    and the prox of lam g* from the Moreau decomposition
+    prox_{lam g*}(v) = v - lam proj_box(v / lam).  Returns the extrapolated
+    points y_1 .. y_{iters+1} of that form (y_1 = 0)."""
+    dq = DenseQP(prob)
+    Hd, hc = constraint_matrix(dq)
+    lo, hi = row_bounds(prob)
+    s = np.sqrt(row_prob(prob)) if precondition else np.ones(Hd.shape[0])
+    n, me = dq.n, dq.E.shape[0]
+    K = np.zeros((n + me, n + me))
+    K[:n, :n] = dq.G
+    K[:n, n:] = dq.E.T
+    K[n:, :n] = dq.E
+    Kinv = np.linalg.inv(K)
+
+    def grad(yb):
+        # x(y) minimises f(X) + <y, Hd X + hc> s.t. EX = e, y = s * yb
+        rhs = np.concatenate([-(dq.g + Hd.T @ (s * yb)), dq.e])
+        X = (Kinv @ rhs)[:n]
+        return -(s * (Hd @ X + hc))
+
+    m = Hd.shape[0]
+    yk = np.zeros(m)          # the extrapolated point
+    x_prev = np.zeros(m)
+    t = 1.0
+    out = [yk.copy()]
+    for _ in range(iters):
+        v = yk - lam * grad(yk)
+        x_new = v - lam * np.clip(v / lam, s * lo, s * hi)
+        t_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
+        yk = x_new + ((t - 1.0) / t_new) * (x_new - x_prev)
+        x_prev, t = x_new, t_new
+        out.append(yk.copy())
+    return out

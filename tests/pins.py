@@ -32,12 +32,13 @@ PIN_TOL = {
 
 def feasible(prob) -> bool:
     """LP feasibility of the whole problem (Sec. II assumes it; the generator
-    does not guarantee it, so test instances are certified)."""
+    does not guarantee it, so test instances are certified).  Covers a
+    general constraint map and soft rows (through the slack form)."""
     from scipy.optimize import linprog
-    dq = DenseQP(prob)
-    bounds = list(zip(np.where(np.isfinite(dq.lb), dq.lb, None),
-                      np.where(np.isfinite(dq.ub), dq.ub, None)))
-    return linprog(np.zeros(dq.n), A_eq=dq.E, b_eq=dq.e, bounds=bounds).status == 0
+    from dense import soft_qp
+    G, g, k, E, e, lb, ub, n, dq = soft_qp(prob)
+    bounds = list(zip(np.where(np.isfinite(lb), lb, None), np.where(np.isfinite(ub), ub, None)))
+    return linprog(np.zeros(G.shape[0]), A_eq=E, b_eq=e, bounds=bounds).status == 0
 
 
 def tight_tiny(seed=7):
@@ -72,12 +73,57 @@ def row_scale(prob):
     t = prob.tree
     sc = []
     for i in range(t.V):
-        w = prob.nx + prob.nu if i < t.Vnl else prob.nx
+        w = prob.nc if i < t.Vnl else prob.ncN
         sc += [np.sqrt(t.prob[i])] * w
     return np.array(sc)
 
 
+def general_map(seed=13, nc=3, ncN=2):
+    """Tiny-shape problem bounded through a general constraint map
+    z_i = F x_i + G u_i (|z| <= 0.8) and z_j = FN x_j (|z| <= 1.5): the first
+    LP-feasible draw at or after ``seed``."""
+    for s in range(seed, seed + 200):
+        rng = np.random.default_rng(s)
+        pr = treegen.draw_problem(treegen.uniform_tree([2, 2, 2, 1, 1]), 4, 2, rng, x0_range=1.5)
+        F = rng.standard_normal((nc, pr.nx)) * 0.5
+        G = rng.standard_normal((nc, pr.nu))
+        FN = rng.standard_normal((ncN, pr.nx)) * 0.5
+        pr = treegen.with_constraint_map(pr, F, G, FN, -0.8, 0.8, -1.5, 1.5)
+        if feasible(pr):
+            return pr
+    raise RuntimeError("no feasible draw")
+
+
+def soft_rows(prob, seed=17, frac=0.5):
+    """``prob`` with about ``frac`` of its finite rows made soft: weights
+    U[0.5, 3], half of them with a Huber threshold U[0.05, 0.5], and every
+    input row of the first non-leaf stage turned into an l1 penalty on u
+    (bounds [0, 0])."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    lo, hi = box_rows(prob) if prob.F is None else (prob.zmin.copy(), prob.zmax.copy())
+    m = prob.m
+    wgt = np.full(m, np.inf)
+    hub = np.zeros(m)
+    fin = np.isfinite(lo) | np.isfinite(hi)
+    pick = fin & (rng.random(m) < frac)
+    wgt[pick] = rng.uniform(0.5, 3.0, pick.sum())
+    hub[pick] = np.where(rng.random(pick.sum()) < 0.5, 0.0, rng.uniform(0.05, 0.5, pick.sum()))
+    out = prob
+    if prob.F is None:
+        umin, umax = prob.umin.copy(), prob.umax.copy()
+        umin[0], umax[0] = 0.0, 0.0
+        out = dataclasses.replace(prob, umin=umin, umax=umax)
+        nx, nu = prob.nx, prob.nu
+        rows = nx + np.arange(nu)           # node 0's input rows
+        wgt[rows] = 1.5
+        hub[rows] = 0.0
+    return treegen.with_soft_rows(out, wgt, hub)
+
+
 def box_rows(prob):
+    if prob.F is not None:
+        return prob.zmin.copy(), prob.zmax.copy()
     t = prob.tree
     lo, hi = [], []
     for i in range(t.V):

@@ -1,0 +1,326 @@
+"""The CPU oracle's accelerated gradient (GPAD), lambda backtracking,
+divergence test, line-search trace, soft / Huber / l1 rows and general
+constraint map, each pinned to something other than the oracle itself:
+textbook FISTA on the dense dual, the O(1/k^2) rate bound, the descent lemma,
+an LP infeasibility certificate, brute-force scalar minimisation of the
+prox, the conjugate form of the FBE, and an interior-point solution of the
+slack reformulation (no GPU)."""
+import numpy as np
+import pytest
+from scipy.optimize import minimize_scalar
+
+import oracle
+import pins
+import treegen
+from dense import DenseQP, constraint_matrix, fista_dense, ipm, row_bounds, row_prob, soft_qp
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+    oracle.set_mutation(0)
+    yield
+    oracle.set_mutation(0)
+
+
+def _lam(prob, precondition=True):
+    pb, fac = oracle.factor(prob)
+    L = oracle.power_iteration(pb, fac, precondition, 600)
+    return pb, fac, L
+
+
+def _ipm_soft(prob):
+    G, g, k, E, e, lb, ub, n, dq = soft_qp(prob)
+    X, nu, ll, lu, cert = ipm(G, g, E, e, lb, ub)
+    assert max(cert.values()) < 1e-8, cert
+    x, u = dq.split(X[:n])
+    return x, u, 0.5 * X @ G @ X + g @ X + k
+
+
+def _dual_objective(prob, pb, fac, yb, lam):
+    """f-hat(y) + g*(y) in the scaled variables, hard rows only: f-hat from the
+    dense objective at x(y) and g* the support function of the scaled box
+    (y must vanish on rows with an infinite bound)."""
+    ev = oracle.evaluate(pb, fac, yb, lam, True)
+    dq = DenseQP(prob)
+    Hd, hc = constraint_matrix(dq)
+    s = np.sqrt(row_prob(prob))
+    X = np.concatenate([ev["u"].ravel(), ev["x"][1:].ravel()])
+    y = s * yb
+    fhat = -dq.objective(X) - y @ (Hd @ X + hc)
+    lo, hi = row_bounds(prob)
+    fin = np.isfinite(lo) & np.isfinite(hi)
+    assert np.abs(yb[~fin]).max(initial=0.0) < 1e-9 * max(1.0, np.abs(yb).max())
+    return fhat + np.sum(np.maximum(y[fin] * lo[fin], y[fin] * hi[fin]))
+
+
+# ------------------------------------ GPAD --------------------------------- #
+@pytest.mark.parametrize("name", ["tiny", "general"])
+def test_gpad_equals_textbook_fista_on_the_dense_dual(name):
+    prob = pins.tight_tiny() if name == "tiny" else pins.general_map()
+    pb, fac, L = _lam(prob)
+    lam = 1.0 / L
+    ref = fista_dense(prob, lam, 60)
+    for K in (0, 1, 2, 5, 20, 60):
+        r = oracle.solve(pb, fac, "gpad", lam, eps=0.0, max_iter=K, div_window=0)
+        assert r["iters"] == K
+        err = np.abs(r["y"] - ref[K]).max() / max(1.0, np.abs(ref[K]).max())
+        assert err < 1e-9, (K, err)
+
+
+def test_gpad_rate_bound():
+    """F(y^k) - F* <= 2 ||y^0 - y*||^2 / (lambda (k+1)^2) for the dual
+    objective F = f-hat + g* (the accelerated-gradient bound with step
+    lambda <= 1/L), F* = -(primal optimum) by strong duality."""
+    prob = pins.tight_tiny()
+    pb, fac, L = _lam(prob)
+    lam = 1.0 / L
+    dq = DenseQP(prob)
+    X, *_, cert = ipm(dq.G, dq.g, dq.E, dq.e, dq.lb, dq.ub)
+    Fstar = -dq.objective(X)
+    ystar = oracle.solve(pb, fac, "nama", 1 / (1.1 * L), eps=1e-12, max_iter=5000)["y"]
+    # y* is optimal: zero residual and dual objective = -(primal optimum)
+    assert abs(_dual_objective(prob, pb, fac, ystar, lam) - Fstar) < 1e-8 * max(1, abs(Fstar))
+    r2 = ystar @ ystar
+    for k in range(1, 80):
+        w = oracle.solve(pb, fac, "gpad", lam, eps=0.0, max_iter=k - 1, div_window=0)["y"]
+        yk = oracle.evaluate(pb, fac, w, lam, True)["T"]
+        gap = _dual_objective(prob, pb, fac, yk, lam) - Fstar
+        assert gap <= 2 * r2 / (lam * (k + 1) ** 2) * (1 + 1e-9) + 1e-10, (k, gap)
+
+
+@pytest.mark.parametrize("name", ["tiny", "general"])
+def test_gpad_reaches_interior_point_solution(name):
+    prob = pins.tight_tiny() if name == "tiny" else pins.general_map()
+    pb, fac, L = _lam(prob)
+    r = oracle.solve(pb, fac, "gpad", 1.0 / L, eps=1e-9, max_iter=20000)
+    assert r["status"] == 0
+    x, u, opt = _ipm_soft(prob)
+    assert max(np.abs(r["x"] - x).max(), np.abs(r["u"] - u).max()) < 1e-6
+
+
+# ------------------------------- backtracking ------------------------------ #
+@pytest.mark.parametrize("method", ["minfbe", "nama"])
+@pytest.mark.parametrize("rule,param", [(1, 0.1), (2, 0.4)])
+def test_backtracking_from_a_large_step(method, rule, param):
+    """Started at lambda_0 = 64 / (1.1 L) >> 1/L, both tests of Sec. III-B
+    bring lambda down and the solve still reaches the interior-point
+    solution; a halving needs lambda L > 1 - beta (the descent lemma) or
+    lambda L > eps'' (||Hess r|| <= L ||r||), so the final lambda stays above
+    half of that threshold."""
+    prob = pins.tight_tiny()
+    pb, fac, L = _lam(prob)
+    lam0 = 64.0 / (1.1 * L)
+    r = oracle.solve(pb, fac, method, lam0, eps=1e-9, max_iter=3000, backtrack=rule, bt_param=param)
+    assert r["status"] == 0 and r["backtracks"] >= 1
+    thr = (1.0 - param) if rule == 1 else param
+    assert thr / (2 * L) * (1 - 1e-9) < r["lambda_final"] <= lam0
+    assert np.isclose(r["lambda_final"], lam0 * 0.5 ** r["backtracks"])
+    x, u, opt = _ipm_soft(prob)
+    assert max(np.abs(r["x"] - x).max(), np.abs(r["u"] - u).max()) < 1e-6
+
+
+def test_no_halving_below_the_descent_lemma_threshold():
+    prob = pins.tight_tiny()
+    pb, fac, L = _lam(prob)
+    beta = 0.1
+    for method in ("minfbe", "nama"):
+        r = oracle.solve(pb, fac, method, 0.95 * (1 - beta) / L, eps=1e-9, backtrack=1, bt_param=beta)
+        assert r["status"] == 0 and r["backtracks"] == 0
+
+
+def _halving_rows(tr):
+    lam = tr[:, 0]
+    return [k for k in range(1, len(tr)) if lam[k] < lam[k - 1]]
+
+
+@pytest.mark.parametrize("method", ["minfbe", "nama"])
+def test_halving_empties_the_lbfgs_buffer(method):
+    """The trace column 'pairs used by the direction' is 0 at the first update
+    after every halving of lambda, including halvings that happen once the
+    buffer holds pairs."""
+    prob = pins.tight_tiny()
+    pb, fac, L = _lam(prob)
+    seen_full = False
+    for scale in (1.6, 2.5, 4.0, 8.0):
+        r = oracle.solve(pb, fac, method, scale / L, eps=1e-9, backtrack=1, bt_param=0.1, trace_iters=400)
+        tr = r["trace"][:r["iters"]]
+        for k in _halving_rows(tr):
+            assert tr[k, 4] == 0, (scale, k, tr[k, 4])
+            seen_full |= tr[k - 1, 4] > 0
+    assert seen_full, "no halving happened with pairs in the buffer: the pin would be vacuous"
+
+
+# ------------------------------- divergence -------------------------------- #
+@pytest.mark.parametrize("method", ["minfbe", "nama", "gpad"])
+def test_infeasible_problem_is_reported_diverged(method):
+    prob = treegen.with_boxes(pins.tight_tiny(), xbox=0.05, ubox=0.05)
+    assert not pins.feasible(prob)          # LP certificate of infeasibility
+    pb, fac, L = _lam(prob)
+    r = oracle.solve(pb, fac, method, 1 / (1.1 * L), eps=1e-9, max_iter=2000, div_window=50)
+    assert r["status"] == -6 and r["iters"] % 50 == 0
+    off = oracle.solve(pb, fac, method, 1 / (1.1 * L), eps=1e-9, max_iter=300, div_window=0)
+    # without the test the dual keeps growing: at 300 updates well past its size at the detection
+    assert off["status"] == 1 and np.abs(off["y"]).max() > 2 * np.abs(r["y"]).max()
+
+
+@pytest.mark.parametrize("method", ["minfbe", "nama", "gpad"])
+def test_feasible_problems_are_not_flagged(method):
+    for prob in (pins.tight_tiny(), pins.ragged_cross(), pins.general_map()):
+        pb, fac, L = _lam(prob)
+        r = oracle.solve(pb, fac, method, 1 / (1.1 * L), eps=1e-8, max_iter=20000, div_window=50)
+        assert r["status"] == 0
+
+
+# ---------------------------------- trace ---------------------------------- #
+@pytest.mark.parametrize("method", ["minfbe", "nama"])
+@pytest.mark.parametrize("nu_max", [0, 1, 10])
+def test_trace_records_every_trial(method, nu_max):
+    prob = pins.tight_tiny()
+    pb, fac, L = _lam(prob)
+    r = oracle.solve(pb, fac, method, 1 / (1.1 * L), eps=1e-9, nu_max=nu_max, trace_iters=200)
+    tr = r["trace"][:r["iters"]]
+    assert r["status"] == 0 and len(tr) == r["iters"]
+    fallback = 0
+    for row in tr:
+        dphi = row[oracle.TRACE_PHI:oracle.TRACE_PHI + nu_max + 1]
+        assert np.isfinite(dphi).all() and row[3] == nu_max
+        ok = np.nonzero(dphi <= 0)[0]
+        assert row[2] == (ok[0] if ok.size else -1)
+        fallback += row[2] < 0
+    assert r["ls_trials"] == sum(int(a) + 1 if a >= 0 else nu_max + 1 for a in tr[:, 2])
+    if nu_max == 0:
+        assert fallback > 0          # the tau = 0 step is exercised
+
+
+# --------------------------- soft rows and the prox ------------------------ #
+def _soft_cases():
+    return {"tiny_soft": pins.soft_rows(pins.tight_tiny()), "general": pins.general_map(),
+            "general_soft": pins.soft_rows(pins.general_map())}
+
+
+def _row_fn(prob, k, s):
+    """The scaled row function zb -> g_k(zb / s), g_k(z) = pi w huber_d(dist(z,
+    [lo, hi])), from the problem statement (hard rows: None)."""
+    if prob.wgt is None or not np.isfinite(prob.wgt[k]):
+        return None
+    lo, hi = row_bounds(prob)
+    pi = row_prob(prob)[k]
+    w, d = prob.wgt[k], prob.hub[k]
+
+    def g(zb):
+        z = zb / s
+        t = max(lo[k] - z, 0.0, z - hi[k])
+        return pi * w * (t * t / (2 * d) if (d > 0 and t <= d) else t - d / 2)
+    return g
+
+
+@pytest.mark.parametrize("name", ["tiny_soft", "general_soft"])
+def test_soft_prox_by_scalar_minimisation(name):
+    prob = _soft_cases()[name]
+    pb, fac, L = _lam(prob)
+    lam = 0.9 / L
+    s = pins.row_scale(prob)
+    rng = np.random.default_rng(5)
+    checked = 0
+    for _ in range(3):
+        yb = 3.0 * rng.standard_normal(pb.m)
+        ev = oracle.evaluate(pb, fac, yb, lam, True)
+        v = yb / lam + ev["Hbx"]
+        for k in range(pb.m):
+            g = _row_fn(prob, k, s[k])
+            if g is None:
+                continue
+            a, b = min(v[k], ev["z"][k]) - 5.0, max(v[k], ev["z"][k]) + 5.0
+            res = minimize_scalar(lambda z: g(z) + 0.5 * lam * (z - v[k]) ** 2, bounds=(a, b),
+                                  method="bounded", options={"xatol": 1e-12})
+            obj = lambda z: g(z) + 0.5 * lam * (z - v[k]) ** 2      # noqa: E731
+            assert obj(ev["z"][k]) <= obj(res.x) + 1e-10 * max(1.0, abs(obj(res.x)))
+            assert abs(ev["z"][k] - res.x) < 1e-5 * max(1.0, abs(res.x))
+            checked += 1
+    assert checked > 50
+
+
+@pytest.mark.parametrize("name", ["tiny_soft", "general", "general_soft"])
+def test_soft_fbe_conjugate_form(name):
+    """phi = f-hat(y) + g*(T) - lam <grad f-hat, R> + lam/2 ||R||^2 with the
+    conjugate of each scaled row function zb -> pi w huber_d(dist(zb/s,
+    [lo, hi])): s * support(s t) + d s^2 t^2 / (2 pi w) for |s t| <= pi w
+    (support of [lo, hi] only, for a hard row)."""
+    prob = _soft_cases()[name]
+    pb, fac, L = _lam(prob)
+    lam = 0.9 / L
+    dq = DenseQP(prob)
+    Hd, hc = constraint_matrix(dq)
+    s = pins.row_scale(prob)
+    lo, hi = row_bounds(prob)
+    pi = row_prob(prob)
+    wgt = prob.wgt if prob.wgt is not None else np.full(pb.m, np.inf)
+    hub = prob.hub if prob.hub is not None else np.zeros(pb.m)
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        yb = rng.standard_normal(pb.m)
+        ev = oracle.evaluate(pb, fac, yb, lam, True)
+        X = np.concatenate([ev["u"].ravel(), ev["x"][1:].ravel()])
+        fhat = -dq.objective(X) - (s * yb) @ (Hd @ X + hc)
+        T, R = ev["T"], ev["R"]
+        t = s * T
+        gstar = 0.0
+        for k in range(pb.m):
+            if np.isfinite(lo[k]) or np.isfinite(hi[k]):
+                sup = max(t[k] * lo[k] if np.isfinite(lo[k]) else -np.inf,
+                          t[k] * hi[k] if np.isfinite(hi[k]) else -np.inf)
+            else:
+                sup = 0.0
+            if np.isfinite(wgt[k]):
+                W = pi[k] * wgt[k]
+                assert abs(t[k]) <= W * (1 + 1e-12)
+                if not (np.isfinite(lo[k]) and np.isfinite(hi[k])):
+                    sup = max(sup, 0.0) if np.isfinite(lo[k]) or np.isfinite(hi[k]) else 0.0
+                gstar += sup + hub[k] * t[k] ** 2 / (2 * W)
+            else:
+                if not (np.isfinite(lo[k]) and np.isfinite(hi[k])):
+                    assert abs(t[k]) < 1e-9
+                    continue
+                gstar += sup
+        phi2 = fhat + gstar + lam * ev["Hbx"] @ R + 0.5 * lam * R @ R
+        assert abs(phi2 - ev["phi"]) < 1e-10 * max(1.0, abs(phi2)), (phi2, ev["phi"])
+
+
+@pytest.mark.parametrize("method", ["minfbe", "nama", "gpad"])
+@pytest.mark.parametrize("name", ["tiny_soft", "general", "general_soft"])
+def test_soft_and_general_solves_match_interior_point(method, name):
+    prob = _soft_cases()[name]
+    pb, fac, L = _lam(prob)
+    lam = (1.0 if method == "gpad" else 1 / 1.1) / L
+    r = oracle.solve(pb, fac, method, lam, eps=1e-9, max_iter=20000)
+    assert r["status"] == 0
+    x, u, opt = _ipm_soft(prob)
+    scale = max(1.0, np.abs(x).max(), np.abs(u).max())
+    assert max(np.abs(r["x"] - x).max(), np.abs(r["u"] - u).max()) / scale < 1e-6
+    if method != "gpad":     # strong duality: phi(y*) = -(primal optimum)
+        assert abs(r["phi"] + opt) < 1e-7 * max(1.0, abs(opt))
+
+
+def test_general_map_inner_problem_and_adjoint():
+    """x(y) for a constraint-layout dual equals the dense KKT solve with the
+    term <y, Hd X + hc>; apply_H is Hd X + hc and apply_Ht its adjoint."""
+    prob = pins.general_map()
+    pb, fac = oracle.factor(prob)
+    dq = DenseQP(prob)
+    Hd, hc = constraint_matrix(dq)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        y = rng.standard_normal(pb.m)
+        x, u = oracle.sweep(pb, fac, oracle.apply_Ht(pb, y))
+        xd, ud = dq.inner(y)
+        assert max(np.abs(x - xd).max(), np.abs(u - ud).max()) < 1e-10 * max(1, np.abs(xd).max())
+        X = np.concatenate([u.ravel(), x[1:].ravel()])
+        assert np.abs(oracle.apply_H(pb, x, u) - (Hd @ X + hc)).max() < 1e-12 * max(1, np.abs(X).max())
+        v = rng.standard_normal(pb.m_xu)
+        xv = v[:0]
+        # <y, H(x,u)> = <H'y, (x,u)> for arbitrary (x, u)
+        xr, ur = rng.standard_normal((pb.V, pb.nx)), rng.standard_normal((pb.Vnl, pb.nu))
+        lhs = y @ oracle.apply_H(pb, xr, ur)
+        rhs = oracle.apply_Ht(pb, y) @ oracle.Hx(pb, xr, ur)
+        assert abs(lhs - rhs) < 1e-12 * max(1, abs(lhs)), (lhs, rhs, xv)

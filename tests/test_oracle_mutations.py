@@ -73,3 +73,29 @@ def test_mutation_is_caught(k):
     finally:
         oracle.set_mutation(0)
     assert fails, f"mutation {k} ({MUTATIONS[k]}) passed every pin"
+
+
+# Mistakes in the accelerated gradient, the soft-row prox and the
+# backtracking, each caught by the pin written for that part.
+def _targeted():
+    import test_oracle_methods as tm
+    return {
+        9: ("GPAD momentum theta (theta_prev - 1) instead of theta (1/theta_prev - 1)",
+            lambda: tm.test_gpad_equals_textbook_fista_on_the_dense_dual("tiny")),
+        10: ("Huber prox with the threshold dropped from the shrink factor",
+             lambda: tm.test_soft_prox_by_scalar_minimisation("tiny_soft")),
+        11: ("lambda halved without emptying the L-BFGS buffer",
+             lambda: tm.test_halving_empties_the_lbfgs_buffer("nama")),
+    }
+
+
+@pytest.mark.parametrize("k", [9, 10, 11])
+def test_targeted_mutation_is_caught(k):
+    desc, pin = _targeted()[k]
+    pin()                                   # passes on the correct oracle
+    oracle.set_mutation(k)
+    try:
+        with np.errstate(all="ignore"), pytest.raises(AssertionError):
+            pin()
+    finally:
+        oracle.set_mutation(0)

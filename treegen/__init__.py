@@ -80,12 +80,39 @@ class Problem:
     r: np.ndarray | None = None   # [Vnl][nu]
     p: np.ndarray | None = None   # [Vl][nx]
     name: str = ""
+    # optional constraint map of Sec. II-B, the same at every node:
+    # z_i = F x_i + G u_i (non-leaf), z_j = FN x_j (leaf), bounded by
+    # zmin <= z <= zmax in the dual layout; F None: the rows (x_i, u_i), x_j
+    F: np.ndarray | None = None      # [nc][nx]
+    G: np.ndarray | None = None      # [nc][nu]
+    FN: np.ndarray | None = None     # [ncN][nx]
+    zmin: np.ndarray | None = None   # [m]
+    zmax: np.ndarray | None = None   # [m]
+    # optional soft rows (dual layout): row k of node i costs
+    # pi_i wgt[k] huber_{hub[k]}(dist(z_k, [lo_k, hi_k])); wgt = inf: hard
+    wgt: np.ndarray | None = None    # [m]
+    hub: np.ndarray | None = None    # [m]
+
+    @property
+    def nc(self) -> int:
+        return self.nx + self.nu if self.F is None else int(self.F.shape[0])
+
+    @property
+    def ncN(self) -> int:
+        return self.nx if self.F is None else int(self.FN.shape[0])
+
+    @property
+    def m_xu(self) -> int:
+        """Length of the (x, u) layout: (nx+nu) rows per non-leaf node, nx per leaf."""
+        t = self.tree
+        return t.Vnl * (self.nx + self.nu) + t.Vl * self.nx
 
     @property
     def m(self) -> int:
-        """Dual dimension: (nx+nu) rows per non-leaf node, nx per leaf."""
+        """Dual dimension: the constraint rows, nc per non-leaf node and ncN
+        per leaf ((nx+nu) and nx without a constraint map)."""
         t = self.tree
-        return t.Vnl * (self.nx + self.nu) + t.Vl * self.nx
+        return t.Vnl * self.nc + t.Vl * self.ncN
 
 
 def tree_from_counts(counts: list) -> Tree:
@@ -326,3 +353,119 @@ def with_boxes(prob: Problem, xbox: float | None = None, ubox: float | None = No
         umin = np.full_like(prob.umin, -ubox)
         umax = np.full_like(prob.umax, ubox)
     return dataclasses.replace(prob, xmin=xmin, xmax=xmax, umin=umin, umax=umax)
+
+
+def with_constraint_map(prob: Problem, F: np.ndarray, G: np.ndarray, FN: np.ndarray,
+                        lo: float | np.ndarray, hi: float | np.ndarray,
+                        loN: float | np.ndarray, hiN: float | np.ndarray) -> Problem:
+    """The same problem constrained by z_i = F x_i + G u_i in [lo, hi] at every
+    non-leaf node and z_j = FN x_j in [loN, hiN] at every leaf (Sec. II-B);
+    the box arrays are kept but no longer bound anything."""
+    t = prob.tree
+    nc, ncN = F.shape[0], FN.shape[0]
+    zmin = np.concatenate([np.broadcast_to(lo, (t.Vnl, nc)).ravel(),
+                           np.broadcast_to(loN, (t.Vl, ncN)).ravel()]).astype(np.float64)
+    zmax = np.concatenate([np.broadcast_to(hi, (t.Vnl, nc)).ravel(),
+                           np.broadcast_to(hiN, (t.Vl, ncN)).ravel()]).astype(np.float64)
+    return dataclasses.replace(prob, F=np.ascontiguousarray(F, dtype=np.float64),
+                               G=np.ascontiguousarray(G, dtype=np.float64),
+                               FN=np.ascontiguousarray(FN, dtype=np.float64), zmin=zmin, zmax=zmax,
+                               wgt=None, hub=None)
+
+
+def with_soft_rows(prob: Problem, wgt: np.ndarray, hub: np.ndarray | None = None) -> Problem:
+    """Soft rows (dual layout): row k costs pi wgt[k] huber_{hub[k]}(distance of
+    z_k to its bounds); wgt[k] = inf keeps row k hard."""
+    wgt = np.ascontiguousarray(wgt, dtype=np.float64)
+    hub = np.zeros_like(wgt) if hub is None else np.ascontiguousarray(hub, dtype=np.float64)
+    assert wgt.shape == (prob.m,) and hub.shape == (prob.m,)
+    return dataclasses.replace(prob, wgt=wgt, hub=hub)
+
+
+# --------------------- spring-mass-damper array (Sec. IV-A) --------------------- #
+def spring_mass_dynamics(M: int = 5, mass: float = 5.0, ks: float = 1.0, bd: float = 0.1,
+                         Ts: float = 0.5):
+    """(A, B) of the array of M masses between two walls: M + 1 springs
+    (stiffness ks) and dampers (coefficient bd), M - 1 actuators, the one
+    between masses j and j + 1 pushing them apart with force u_j.  State
+    (p_1..p_M, v_1..v_M); Newton's law in continuous time, then a
+    zero-order hold with sampling time Ts (the exponential of the augmented
+    matrix [[Ac, Bc], [0, 0]] Ts)."""
+    from scipy.linalg import expm
+    T = 2.0 * np.eye(M) - np.eye(M, k=1) - np.eye(M, k=-1)   # wall-to-wall coupling
+    Bu = np.zeros((M, M - 1))
+    for j in range(M - 1):
+        Bu[j, j] = -1.0
+        Bu[j + 1, j] = 1.0
+    Ac = np.block([[np.zeros((M, M)), np.eye(M)], [-ks / mass * T, -bd / mass * T]])
+    Bc = np.vstack([np.zeros((M, M - 1)), Bu / mass])
+    n, m = 2 * M, M - 1
+    aug = np.zeros((n + m, n + m))
+    aug[:n, :n] = Ac
+    aug[:n, n:] = Bc
+    E = expm(aug * Ts)
+    return E[:n, :n].copy(), E[:n, n:].copy()
+
+
+def markov_tree(N: int, p0=(0.5, 0.5), Pc=((0.1, 0.9), (0.9, 0.1))):
+    """Scenario tree of a two-mode Markov chain: every node has one child per
+    mode; the root's children take the initial distribution p0, later
+    children the transition probabilities Pc[mode of the parent]; child k of
+    a node is mode k.  Returns (tree, mode of every node; -1 at the root)."""
+    nm = len(p0)
+    t = uniform_tree([nm] * N)
+    mode = np.full(t.V, -1, dtype=np.int64)
+    prob = np.zeros(t.V)
+    prob[0] = 1.0
+    for i in range(t.Vnl):
+        for k, j in enumerate(range(t.child_ptr[i], t.child_ptr[i + 1])):
+            mode[j] = k
+            prob[j] = prob[i] * (p0[k] if i == 0 else Pc[mode[i]][k])
+    return dataclasses.replace(t, prob=prob), mode
+
+
+def spring_mass_problem(x0: np.ndarray | None = None, *, N: int = 11, M: int = 5,
+                        umax: float = 2.0, vmax: float = 5.0, pmax: float = 2.0,
+                        c_mode=(0.0, 0.1), seed: int = 1005, x0_pos: float = 1.0,
+                        x0_vel: float = 1.0, name: str = "spring") -> Problem:
+    """The stochastic optimal control problem of Sec. IV-A: M = 5 masses of
+    5 kg, ks = 1 N/m, bd = 0.1 Ns/m, Ts = 0.5 s, horizon N = 11, |u| <= 2 N,
+    |v| <= 5 m/s, positions |p| <= pmax (not given in the paper), stage cost
+    x'(5 I)x + u'(2 I)u, terminal cost x'(100 I)x, and the disturbance c of
+    the two-mode Markov chain (p0 = (0.5, 0.5), transitions [[0.1, 0.9],
+    [0.9, 0.1]]): every state entry is c_mode[k] in mode k.  x0 (default:
+    positions U[-x0_pos, x0_pos], velocities U[-x0_vel, x0_vel], drawn from
+    default_rng(seed))."""
+    tree, mode = markov_tree(N)
+    A1, B1 = spring_mass_dynamics(M)
+    nx, nu = 2 * M, M - 1
+    V, Vnl, Vl = tree.V, tree.Vnl, tree.Vl
+    A = np.zeros((V, nx, nx))
+    B = np.zeros((V, nx, nu))
+    c = np.zeros((V, nx))
+    A[1:] = A1
+    B[1:] = B1
+    c[1:] = np.asarray(c_mode)[mode[1:]][:, None]
+    Q = np.broadcast_to(5.0 * np.eye(nx), (Vnl, nx, nx)).copy()
+    R = np.broadcast_to(2.0 * np.eye(nu), (Vnl, nu, nu)).copy()
+    P = np.broadcast_to(100.0 * np.eye(nx), (Vl, nx, nx)).copy()
+    lim = np.concatenate([np.full(M, pmax), np.full(M, vmax)])
+    xmin = np.broadcast_to(-lim, (V, nx)).copy()
+    xmax = np.broadcast_to(lim, (V, nx)).copy()
+    xmin[0], xmax[0] = -np.inf, np.inf
+    umin = np.full((Vnl, nu), -umax)
+    umax_ = np.full((Vnl, nu), umax)
+    if x0 is None:
+        rng = np.random.default_rng(seed)
+        x0 = np.concatenate([rng.uniform(-x0_pos, x0_pos, M), rng.uniform(-x0_vel, x0_vel, M)])
+    return Problem(tree=tree, nx=nx, nu=nu, A=A, B=B, c=c, Q=Q, R=R, P=P, xmin=xmin, xmax=xmax,
+                   umin=umin, umax=umax_, x0=np.asarray(x0, dtype=np.float64), name=name)
+
+
+def spring_mass_x0(count: int, seed: int = 1005, *, x0_pos: float = 1.0, x0_vel: float = 1.0,
+                   M: int = 5) -> np.ndarray:
+    """count initial states, positions U[-x0_pos, x0_pos], velocities
+    U[-x0_vel, x0_vel] (the draws of the Sec. IV-A study), [count][2M]."""
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.uniform(-x0_pos, x0_pos, (count, M)),
+                           rng.uniform(-x0_vel, x0_vel, (count, M))], axis=1)
