@@ -83,6 +83,23 @@ typedef struct {
     const double *p;     /* [V-V_nl][nx] or NULL                             */
     const double *xmin, *xmax;  /* [V][nx], +-INFINITY allowed              */
     const double *umin, *umax;  /* [V_nl][nu], +-INFINITY allowed           */
+    /* Optional constraint map of Sec. II-B, the same at every node: rows
+     * z_i = F x_i + G u_i at non-leaf nodes, z_j = FN x_j at leaves.  F NULL
+     * (default): the rows are (x_i, u_i) and x_j themselves with the boxes
+     * above.  Otherwise the dual has nc rows per non-leaf node and ncN per
+     * leaf (m = V_nl nc + (V - V_nl) ncN, same node order), bounded by
+     * zmin <= z <= zmax given in that layout, and the box arrays above are
+     * not read (they may be NULL).  Not for tree_factor_shared. */
+    int32_t nc, ncN;            /* rows per non-leaf node / leaf (nc >= 1)  */
+    const double *F, *G, *FN;   /* [nc][nx], [nc][nu], [ncN][nx]             */
+    const double *zmin, *zmax;  /* [m], +-INFINITY allowed                   */
+    /* Optional soft rows (Sec. II-B: a distance-to-set function in place of
+     * the indicator), in the dual layout; NULL: every row hard.  Row k of node
+     * i adds pi_i wgt[k] psi(dist(z_k, [lo_k, hi_k])) to the cost, psi the
+     * Huber function of threshold hub[k] (t^2/(2 hub) below hub, t - hub/2
+     * above; hub = 0: the distance itself, an l1 penalty when lo = hi = 0);
+     * wgt[k] = +INFINITY keeps row k a hard bound.  wgt > 0, hub >= 0. */
+    const double *wgt, *hub;    /* [m] or NULL                               */
 } problem_data;
 
 typedef struct {
@@ -95,14 +112,40 @@ typedef struct {
                             (default 10, at most 30)                        */
     int32_t max_iter;    /* default 1000                                     */
     int32_t check_every; /* host reads the stop flag every k iterations (1)  */
+    /* lambda backtracking (Sec. III-B), MINFBE and NAMA; each halving empties
+     * the L-BFGS memory and takes the update again from the same y:
+     *   0  fixed lambda (default);
+     *   1  halve when f-hat(T(w)) > f-hat(w) - lambda <grad f-hat(w), R(w)>
+     *      + (1 - beta) lambda/2 ||R(w)||^2 at the point w the step was taken
+     *      from, beta = bt_param in [0, 1);
+     *   2  halve when lambda ||grad f-hat(T(y)) - grad f-hat(y)||
+     *      > eps'' ||T(y) - y||, eps'' = bt_param in (0, 1/2).
+     * With backtracking and lambda = 0 the start is 1/L from 5 power
+     * iterations (an L from below, so a step at least 1/L). */
+    int32_t backtrack;
+    /* infeasibility test every div_window iterations (0: 50; < 0: off): the
+     * change of the dual over the window certifies that no point satisfies
+     * the dynamics and the constraints (it is annihilated by the dual
+     * Hessian and the dual objective falls linearly along it); the instance
+     * then stops with ERR_DIVERGED. */
+    int32_t div_window;
+    double bt_param;
+    /* DEVICE [instances][trace_iters][40] or NULL: row k of an instance
+     * holds lambda, ||R(y^k)||_inf, the accepted nu (-1: tau = 0), nu_max, the
+     * L-BFGS pairs of the direction, then phi(w_nu) - phi(y^k) for every
+     * trial nu = 0..nu_max of update k (MINFBE and NAMA). */
+    double *trace;
+    int32_t trace_iters, reserved;
 } solver_opts;
 
 typedef struct {
     int32_t iters, sweeps_affine, sweeps_hom, ls_trials, lbfgs_push, lbfgs_skip, status;
     double res_scaled_inf;    /* ||R||_inf in the solver's (scaled) units    */
     double res_unscaled_inf;  /* ||z - Hx||_inf in the problem's units       */
-    double lambda;            /* step used                                   */
+    double lambda;            /* step used (the last one with backtracking)  */
     double seconds;           /* host wall time of the call                  */
+    int32_t backtracks;       /* halvings of lambda                          */
+    int32_t reserved;
 } solver_info;
 
 typedef struct tree_factors tree_factors;  /* opaque; owns device memory */
@@ -299,8 +342,9 @@ int dual_lipschitz(const tree_factors *f, int iters, double *L_out, void *hip_st
  * test in the same launches, and stops independently; lambda = 0 gives each
  * instance 1/(1.1 L_b); info summarises (iters = largest, status = worst) and
  * solve_info_batch gives the per-instance records.  Returns OK,
- * NOT_CONVERGED, ERR_NUMERIC (NaN/Inf in the iterates), ERR_ARG, ERR_OOM,
- * ERR_DEVICE.
+ * NOT_CONVERGED, ERR_NUMERIC (NaN/Inf in the iterates, or more than 50 halvings
+ * of lambda), ERR_DIVERGED (the infeasibility test of solver_opts fired),
+ * ERR_ARG, ERR_OOM, ERR_DEVICE.
  */
 int minfbe_solve(const tree_factors *f, const double *x0, const solver_opts *opts,
                  double *y_inout, double *x, double *u, solver_info *info, void *hip_stream);
@@ -315,6 +359,22 @@ int minfbe_solve(const tree_factors *f, const double *x0, const solver_opts *opt
  */
 int nama_solve(const tree_factors *f, const double *x0, const solver_opts *opts,
                double *y_inout, double *x, double *u, solver_info *info, void *hip_stream);
+
+/*
+ * Accelerated dual proximal gradient (GPAD): the warm start of Sec. III-F
+ * and the comparison method of Sec. IV-A.  From y^0 = y^{-1} = y_inout and
+ * theta_0 = theta_{-1} = 1, update k takes the forward-backward step at the
+ * extrapolated point w^k = y^k + theta_k (1/theta_{k-1} - 1)(y^k - y^{k-1}):
+ * y^{k+1} = T_lambda(w^k), theta_{k+1} = (sqrt(theta_k^4 + 4 theta_k^2) -
+ * theta_k^2)/2; one affine sweep (Algorithm 3) per update.  The stop test is
+ * ||R_lambda(w^k)||_inf <= eps; y_inout receives the last point evaluated,
+ * w^k (so max_iter = 5 is the paper's five-iteration warm start, ending
+ * with w^5).  lambda must lie in (0, 1/L]; lambda = 0 takes 1/(1.1 L).  The
+ * L-BFGS, line-search and backtracking options are ignored.  Arguments,
+ * outputs and errors as minfbe_solve.
+ */
+int gpad_solve(const tree_factors *f, const double *x0, const solver_opts *opts, double *y_inout, double *x,
+               double *u, solver_info *info, void *hip_stream);
 
 /*
  * Learned warm start (the warm-start slot of Sec. III-F, filled by a node-wise

@@ -84,8 +84,9 @@ int dual_grad(const tree_factors *fc, const double *x0, const double *y, int hom
         set_error("dual_grad: NULL pointer or nrhs < 1");
         return STOTREE_ERR_ARG;
     }
-    return enqueue_dual_grad(const_cast<tree_factors *>(fc), x0, y, homogeneous, nrhs, x, u,
-                             (hipStream_t)hip_stream);
+    tree_factors *f = const_cast<tree_factors *>(fc);
+    if (f->cmap) return dual_grad_mapped(f, x0, y, homogeneous, nrhs, x, u, (hipStream_t)hip_stream);
+    return enqueue_dual_grad(f, x0, y, homogeneous, nrhs, x, u, (hipStream_t)hip_stream);
 }
 
 int dual_grad_noalloc(const tree_factors *fc, const double *x0, const double *y, int homogeneous, int nrhs,
@@ -127,6 +128,10 @@ int sweep_graph_create(const tree_factors *f, const double *x0, const double *y,
         set_error("sweep_graph_create: NULL pointer or nrhs not in {1, 2}");
         return STOTREE_ERR_ARG;
     }
+    if (f->cmap) {
+        set_error("sweep_graph_create: handles with a constraint map are not supported");
+        return STOTREE_ERR_ARG;
+    }
     return graph_create(const_cast<tree_factors *>(f), x0, y, homogeneous, nrhs, x, u, out);
 }
 
@@ -166,6 +171,12 @@ int nama_solve(const tree_factors *f, const double *x0, const solver_opts *opts,
                double *x, double *u, solver_info *info, void *hip_stream)
 {
     return run_solver(f, x0, opts, y_inout, x, u, info, hip_stream, 1);
+}
+
+int gpad_solve(const tree_factors *f, const double *x0, const solver_opts *opts, double *y_inout, double *x,
+               double *u, solver_info *info, void *hip_stream)
+{
+    return run_solver(f, x0, opts, y_inout, x, u, info, hip_stream, 2);
 }
 
 int solve_info_batch(const tree_factors *f, solver_info *infos)
@@ -229,19 +240,19 @@ int warm_adam(int64_t n, float *params, const float *grad, float *m, float *v, f
 
 int warm_features(const tree_factors *f, const double *x0, float c_scale, float *X, void *hip_stream)
 {
-    if (!f || !x0 || !X || !(c_scale > 0.0f)) { set_error("warm_features: bad argument"); return STOTREE_ERR_ARG; }
+    if (!f || !x0 || !X || !(c_scale > 0.0f) || f->cmap) { set_error("warm_features: bad argument (or a constraint map)"); return STOTREE_ERR_ARG; }
     return warm_features_impl(f, x0, c_scale, X, (hipStream_t)hip_stream);
 }
 
 int warm_scatter(const tree_factors *f, const float *Y, float y_scale, double *y, void *hip_stream)
 {
-    if (!f || !Y || !y) { set_error("warm_scatter: bad argument"); return STOTREE_ERR_ARG; }
+    if (!f || !Y || !y || f->cmap) { set_error("warm_scatter: bad argument (or a constraint map)"); return STOTREE_ERR_ARG; }
     return warm_scatter_impl(f, Y, y_scale, y, (hipStream_t)hip_stream);
 }
 
 int warm_targets(const tree_factors *f, const double *y, float y_scale, float *T, float *mask, void *hip_stream)
 {
-    if (!f || !y || !T || !mask || !(y_scale > 0.0f)) { set_error("warm_targets: bad argument"); return STOTREE_ERR_ARG; }
+    if (!f || !y || !T || !mask || !(y_scale > 0.0f) || f->cmap) { set_error("warm_targets: bad argument (or a constraint map)"); return STOTREE_ERR_ARG; }
     return warm_targets_impl(f, y, y_scale, T, mask, (hipStream_t)hip_stream);
 }
 

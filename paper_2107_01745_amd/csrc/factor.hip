@@ -256,9 +256,16 @@ int validate(const tree_desc *t, const problem_data *d, const std::string &who)
         set_error(who + ": need nx>=1, nu>=1, N>=1, V>=2 and nx+nu<=256");
         return STOTREE_ERR_ARG;
     }
+    const bool cmap = d->F != nullptr;
     if (!t->stage_ptr || !t->ancestor || !t->child_ptr || !t->prob || !d->A || !d->B || !d->c ||
-        !d->Q || !d->R || !d->P || !d->xmin || !d->xmax || !d->umin || !d->umax) {
+        !d->Q || !d->R || !d->P ||
+        (!cmap && (!d->xmin || !d->xmax || !d->umin || !d->umax)) ||
+        (cmap && (!d->G || !d->zmin || !d->zmax || (d->ncN > 0 && !d->FN)))) {
         set_error(who + ": a required array is NULL");
+        return STOTREE_ERR_ARG;
+    }
+    if (cmap && (d->nc < 1 || d->ncN < 0 || d->nc > 4 * kMaxWidth || d->ncN > 4 * kMaxWidth)) {
+        set_error(who + ": constraint map needs 1 <= nc and 0 <= ncN (at most 1024 rows per node)");
         return STOTREE_ERR_ARG;
     }
     const int *sp = t->stage_ptr;
@@ -315,15 +322,38 @@ int validate(const tree_desc *t, const problem_data *d, const std::string &who)
             set_error(who + ": non-finite entry in " + c.name);
             return STOTREE_ERR_NUMERIC;
         }
-    for (size_t k = 0; k < (size_t)V * nx; ++k)
-        if (std::isnan(d->xmin[k]) || std::isnan(d->xmax[k]) || d->xmin[k] > d->xmax[k]) {
-            set_error(who + ": state box with lo > hi (or NaN)");
-            return STOTREE_ERR_BOX;
+    size_t m = (size_t)Vnl * (nx + nu) + Vl * nx;
+    if (cmap) {
+        m = (size_t)Vnl * d->nc + Vl * d->ncN;
+        if (!all_finite(d->F, (size_t)d->nc * nx) || !all_finite(d->G, (size_t)d->nc * nu) ||
+            (d->ncN > 0 && !all_finite(d->FN, (size_t)d->ncN * nx))) {
+            set_error(who + ": non-finite entry in the constraint map");
+            return STOTREE_ERR_NUMERIC;
         }
-    for (size_t k = 0; k < (size_t)Vnl * nu; ++k)
-        if (std::isnan(d->umin[k]) || std::isnan(d->umax[k]) || d->umin[k] > d->umax[k]) {
-            set_error(who + ": input box with lo > hi (or NaN)");
-            return STOTREE_ERR_BOX;
+        for (size_t k = 0; k < m; ++k)
+            if (std::isnan(d->zmin[k]) || std::isnan(d->zmax[k]) || d->zmin[k] > d->zmax[k]) {
+                set_error(who + ": constraint row with lo > hi (or NaN)");
+                return STOTREE_ERR_BOX;
+            }
+    } else {
+        for (size_t k = 0; k < (size_t)V * nx; ++k)
+            if (std::isnan(d->xmin[k]) || std::isnan(d->xmax[k]) || d->xmin[k] > d->xmax[k]) {
+                set_error(who + ": state box with lo > hi (or NaN)");
+                return STOTREE_ERR_BOX;
+            }
+        for (size_t k = 0; k < (size_t)Vnl * nu; ++k)
+            if (std::isnan(d->umin[k]) || std::isnan(d->umax[k]) || d->umin[k] > d->umax[k]) {
+                set_error(who + ": input box with lo > hi (or NaN)");
+                return STOTREE_ERR_BOX;
+            }
+    }
+    if (d->wgt)
+        for (size_t k = 0; k < m; ++k) {
+            const double hb = d->hub ? d->hub[k] : 0.0;
+            if (!(d->wgt[k] > 0.0) || !(hb >= 0.0) || !std::isfinite(hb)) {
+                set_error(who + ": soft rows need wgt > 0 (or +inf) and a finite hub >= 0");
+                return STOTREE_ERR_ARG;
+            }
         }
     return STOTREE_OK;
 }
@@ -362,8 +392,10 @@ void free_tree(tree_factors *f)
     for (void *p : {(void *)f->d_inst, (void *)f->d_sp, (void *)f->d_cp, (void *)f->d_anc, (void *)f->Mb, (void *)f->Mf,
                     (void *)f->Kb, (void *)f->Kf, (void *)f->Rn, (void *)f->chat, (void *)f->sig,
                     (void *)f->cvec, (void *)f->sc, (void *)f->lo, (void *)f->hi, (void *)f->qhat,
-                    (void *)f->kbuf, (void *)f->sws.buf})
+                    (void *)f->kbuf, (void *)f->sws.buf, (void *)f->pw, (void *)f->hub, (void *)f->Fm,
+                    (void *)f->map_ws})
         if (p) (void)hipFree(p);
+    if (f->d_inst_xu && f->d_inst_xu != f->d_inst) (void)hipFree(f->d_inst_xu);
     for (auto &cp : f->chains)
         if (cp.items) (void)hipFree(cp.items);
     for (auto &lv : f->levels) free_level(lv);
@@ -564,6 +596,7 @@ __global__ void copy_affine_kernel(const double *Pcal, const double *chat0, cons
 int replicate_instances(tree_factors *f, int count, const double *c_host, hipStream_t st)
 {
     if (f->ninst != 1 || count < 1) { set_error("tree_factor_shared: bad instance count"); return STOTREE_ERR_ARG; }
+    if (f->cmap) { set_error("tree_factor_shared: a constraint map is not supported on shared handles"); return STOTREE_ERR_ARG; }
     const InstDesc I0 = f->inst[0];
     const long long xl = (long long)I0.V * I0.nx, ul = (long long)I0.Vnl * I0.nu;
     if (c_host) {
@@ -619,6 +652,8 @@ int replicate_instances(tree_factors *f, int count, const double *c_host, hipStr
     f->d_inst = nullptr;
     STOTREE_HIP(hipMalloc(&f->d_inst, sizeof(InstDesc) * count));
     STOTREE_HIP(hipMemcpy(f->d_inst, f->inst.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice));
+    f->d_inst_xu = f->d_inst;
+    f->mxu_tot = f->m_tot;
     f->last_info.assign(count, solver_info{});
     return build_schedule(f);
 }
@@ -645,7 +680,8 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
     f->inst.resize(count);
     std::vector<RawDesc> raw(count);
     long long oMb = 0, oMf = 0, oKb = 0, oKf = 0, oRn = 0, ochat = 0, osig = 0, osc = 0, oy = 0, ox = 0,
-              ou = 0, ox0 = 0, onode = 0;
+              ou = 0, ox0 = 0, onode = 0, oF = 0, oxu = 0;
+    bool anyW = false;
     RawDesc ro{};
     int osp = 0, ocp = 0;
     bool anyS = false, anyq = false, anyr = false, anyp = false;
@@ -665,7 +701,15 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
         I.Mb = oMb; I.Mf = oMf; I.Kb = oKb; I.Kf = oKf; I.Rn = oRn;
         I.chat = ochat; I.c = ochat; I.sig = osig; I.sc = osc;
         I.y = oy; I.x = ox; I.u = ou; I.x0 = ox0; I.box = oy; I.node0 = onode;
-        I.m = (long long)I.Vnl * (I.nx + I.nu) + (long long)(I.V - I.Vnl) * I.nx;
+        I.cmap = d.F != nullptr;
+        I.nc = I.cmap ? d.nc : I.nx + I.nu;
+        I.ncN = I.cmap ? d.ncN : I.nx;
+        I.Fo = oF;
+        if (I.cmap) oF += (long long)d.nc * (I.nx + I.nu) + (long long)d.ncN * I.nx;
+        I.m = (long long)I.Vnl * I.nc + (long long)(I.V - I.Vnl) * I.ncN;
+        oxu += (long long)I.Vnl * (I.nx + I.nu) + (long long)(I.V - I.Vnl) * I.nx;
+        f->cmap |= I.cmap;
+        anyW |= d.wgt != nullptr;
         const long long V = I.V, Vnl = I.Vnl, Vl = I.V - I.Vnl, nx = I.nx, nu = I.nu;
         oMb += V * nx * I.ldM; oMf += V * (nx + nu) * I.ldx; oKb += Vnl * nu * I.ldx;
         oKf += Vnl * nx * I.ldu; oRn += Vnl * nu * I.ldu; ochat += V * nx; osig += Vnl * nu; osc += V;
@@ -682,7 +726,7 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
         f->n_tot += Vnl * nu + (V - 1) * nx;
         f->V_tot += V;
     }
-    f->m_tot = oy; f->x_tot = ox; f->u_tot = ou; f->nx_tot = ox0;
+    f->m_tot = oy; f->x_tot = ox; f->u_tot = ou; f->nx_tot = ox0; f->mxu_tot = oxu;
     // host pools of the stage/child pointers
     f->sp_pool.resize(osp);
     std::vector<int> cp_pool(ocp);
@@ -705,6 +749,55 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
         (rc = dalloc(&f->lo, oy)) || (rc = dalloc(&f->hi, oy)))
         return rc;
     STOTREE_HIP(hipMemcpy(f->d_inst, f->inst.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice));
+    f->d_inst_xu = f->d_inst;
+    if (f->cmap) {
+        // the sweeps read and write the (x, u) layout: their descriptors
+        // place each instance in that layout
+        std::vector<InstDesc> ixu = f->inst;
+        long long o = 0;
+        for (InstDesc &I : ixu) {
+            I.y = o;
+            I.m = (long long)I.Vnl * (I.nx + I.nu) + (long long)(I.V - I.Vnl) * I.nx;
+            o += I.m;
+        }
+        STOTREE_HIP(hipMalloc(&f->d_inst_xu, sizeof(InstDesc) * count));
+        f->bytes += sizeof(InstDesc) * count;
+        STOTREE_HIP(hipMemcpy(f->d_inst_xu, ixu.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice));
+        std::vector<double> Fm((size_t)std::max(1LL, oF));
+        for (int b = 0; b < count; ++b) {
+            const InstDesc &I = f->inst[b];
+            if (!I.cmap) continue;
+            const problem_data &d = datas[b];
+            double *dst = Fm.data() + I.Fo;
+            std::memcpy(dst, d.F, sizeof(double) * I.nc * I.nx);
+            std::memcpy(dst + (size_t)I.nc * I.nx, d.G, sizeof(double) * I.nc * I.nu);
+            if (I.ncN > 0)
+                std::memcpy(dst + (size_t)I.nc * (I.nx + I.nu), d.FN, sizeof(double) * I.ncN * I.nx);
+        }
+        if ((rc = dalloc(&f->Fm, oF))) return rc;
+        STOTREE_HIP(hipMemcpy(f->Fm, Fm.data(), sizeof(double) * oF, hipMemcpyHostToDevice));
+    }
+    if (anyW) {
+        // soft rows: pi_i * wgt (+inf: hard) and the Huber thresholds
+        std::vector<double> pw((size_t)oy), hb((size_t)oy, 0.0);
+        for (int b = 0; b < count; ++b) {
+            const InstDesc &I = f->inst[b];
+            const problem_data &d = datas[b];
+            for (int i = 0; i < I.V; ++i) {
+                const int rows = i < I.Vnl ? I.nc : I.ncN;
+                const long long o = i < I.Vnl ? (long long)i * I.nc
+                                              : (long long)I.Vnl * I.nc + (long long)(i - I.Vnl) * I.ncN;
+                for (int a = 0; a < rows; ++a) {
+                    const size_t k = (size_t)(I.y + o + a), kl = (size_t)(o + a);
+                    pw[k] = d.wgt ? trees[b].prob[i] * d.wgt[kl] : INFINITY;
+                    hb[k] = (d.wgt && d.hub) ? d.hub[kl] : 0.0;
+                }
+            }
+        }
+        if ((rc = dalloc(&f->pw, oy)) || (rc = dalloc(&f->hub, oy))) return rc;
+        STOTREE_HIP(hipMemcpy(f->pw, pw.data(), sizeof(double) * oy, hipMemcpyHostToDevice));
+        STOTREE_HIP(hipMemcpy(f->hub, hb.data(), sizeof(double) * oy, hipMemcpyHostToDevice));
+    }
     STOTREE_HIP(hipMemcpy(f->d_sp, f->sp_pool.data(), sizeof(int) * osp, hipMemcpyHostToDevice));
     STOTREE_HIP(hipMemcpy(f->d_cp, cp_pool.data(), sizeof(int) * ocp, hipMemcpyHostToDevice));
     for (int b = 0; b < count; ++b)
@@ -716,6 +809,11 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
         for (int b = 0; b < count; ++b) {
             const InstDesc &I = f->inst[b];
             const problem_data &d = datas[b];
+            if (I.cmap) {
+                std::memcpy(&lo[I.y], d.zmin, sizeof(double) * I.m);
+                std::memcpy(&hi[I.y], d.zmax, sizeof(double) * I.m);
+                continue;
+            }
             for (int i = 0; i < I.V; ++i) {
                 const size_t o = I.y + (i < I.Vnl ? (size_t)i * (I.nx + I.nu) : (size_t)I.Vnl * I.nu + (size_t)i * I.nx);
                 std::memcpy(&lo[o], d.xmin + (size_t)i * I.nx, sizeof(double) * I.nx);

@@ -38,6 +38,12 @@ struct InstDesc {
     long long m;                     // dual rows of the instance
     long long box;                   // first row of the instance's boxes in lo / hi
     long long node0;                 // first node of the instance in node-indexed work arrays
+    // dual (constraint) layout: nc rows per non-leaf node, ncN per leaf; with
+    // cmap the rows are z = [F G] (x, u) / FN x (matrices at Fo in the cmap
+    // pool: F [nc][nx], G [nc][nu], FN [ncN][nx]); otherwise nc = nx + nu,
+    // ncN = nx and the rows are (x, u) themselves
+    int nc, ncN, cmap;
+    long long Fo;
 };
 
 struct Item {
@@ -96,6 +102,10 @@ struct SolverWS {
     double *buf = nullptr;
     size_t bytes = 0;
     double *y[2], *r[2], *hx, *hr2, *d, *S, *Qv, *g[2];
+    double *yck = nullptr;           // iterate at the last infeasibility test (then the change since)
+    double *Rw = nullptr, *hw = nullptr;  // backtracking test 1: R(w) and H x(w) of the last update
+    double *xu = nullptr;            // constraint-map handles: [2][mxu] inputs and [2][mxu] outputs of the sweeps
+    bool has_div = false, has_bt = false;
     double *partials;                // [kNVMax][nblocks]
     void *ctl;                       // device array of per-instance control blocks
     int *blk;                        // device: per block {instance, local block, blocks of the instance}
@@ -114,6 +124,15 @@ struct tree_factors {
     double *Mb = nullptr, *Mf = nullptr, *Kb = nullptr, *Kf = nullptr, *Rn = nullptr;
     double *chat = nullptr, *sig = nullptr, *cvec = nullptr, *sc = nullptr;
     double *lo = nullptr, *hi = nullptr;    // unscaled box rows in the dual layout
+    double *pw = nullptr, *hub = nullptr;   // soft rows: pi * weight (+inf: hard) and Huber threshold, or null
+    double *Fm = nullptr;                   // constraint-map matrices (instances with cmap)
+    // descriptors the sweeps use: the (x, u) layout of the duals they read and
+    // of the H x they write (the same array as d_inst without a constraint map)
+    stotree::InstDesc *d_inst_xu = nullptr;
+    long long mxu_tot = 0;                  // length of the (x, u) layout (= m_tot without a map)
+    bool cmap = false;                      // some instance has a constraint map
+    double *map_ws = nullptr;               // dual_grad's (x, u)-layout inputs (constraint-map handles)
+    long long map_ws_len = 0;
     double *Pcal = nullptr;                 // value-function Hessians [V][nx][nx] (kept only on request)
     long long m_tot = 0, n_tot = 0, x_tot = 0, u_tot = 0, nx_tot = 0, V_tot = 0;
     int max_width = 0;                      // max nx+nu over instances
@@ -210,6 +229,15 @@ int adam_impl(long long n, float *p, const float *g, float *m, float *v, float l
 int warm_features_impl(const tree_factors *f, const double *x0, float c_scale, float *X, hipStream_t st);
 int warm_scatter_impl(const tree_factors *f, const float *Y, float y_scale, double *y, hipStream_t st);
 int warm_targets_impl(const tree_factors *f, const double *y, float y_scale, float *T, float *mask, hipStream_t st);
+
+// cmap.hip: the constraint map of Sec. II-B around the sweeps (no-ops
+// without a map).  to_xu: out[k] = H' y[k] in the (x, u) layout (mxu_tot
+// per right-hand side); from_xu: out[k] = H xu[k] in the dual layout.
+hipError_t map_to_xu(const tree_factors *f, const double *y, long long y_rs, double *out, int nrhs, hipStream_t st);
+hipError_t map_from_xu(const tree_factors *f, const double *xu, double *out, long long o_rs, int nrhs,
+                       hipStream_t st);
+int dual_grad_mapped(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,
+                     double *u, hipStream_t st);
 
 // solver.hip
 int solve(const tree_factors *f, const double *x0, const solver_opts *opts, double *y,

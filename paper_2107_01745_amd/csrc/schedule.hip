@@ -91,10 +91,10 @@ int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms
             if (e1) (void)hipEventDestroy(e1);
         }
     } cleanup{y, x, u, e0, e1};
-    STOTREE_HIP(hipMalloc(&y, sizeof(double) * (size_t)nrhs * f->m_tot));
+    STOTREE_HIP(hipMalloc(&y, sizeof(double) * (size_t)nrhs * f->mxu_tot));
     STOTREE_HIP(hipMalloc(&x, sizeof(double) * (size_t)nrhs * f->x_tot));
     STOTREE_HIP(hipMalloc(&u, sizeof(double) * (size_t)nrhs * f->u_tot));
-    STOTREE_HIP(hipMemsetAsync(y, 0, sizeof(double) * (size_t)nrhs * f->m_tot, st));
+    STOTREE_HIP(hipMemsetAsync(y, 0, sizeof(double) * (size_t)nrhs * f->mxu_tot, st));
     STOTREE_HIP(hipEventCreate(&e0));
     STOTREE_HIP(hipEventCreate(&e1));
     const bool timing_was = timing_on();

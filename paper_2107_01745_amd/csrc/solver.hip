@@ -27,6 +27,13 @@
 //           phi(w) - phi(y) is accumulated row by row (Sec. III-B, the
 //           tau-independent quantities of the line-search reformulation).
 //   update  y+ = T_lambda(w) = w - lambda R(w).
+//
+// Also here: the accelerated dual proximal gradient GPAD (the warm start of
+// Sec. III-F and the comparison method of Sec. IV-A), the two lambda
+// backtracking tests of Sec. III-B, a primal-infeasibility test, soft rows
+// (a weighted Huber function of the distance to the row's interval in
+// place of the hard bound, Sec. II-B), and the constraint map z = [F G] (x, u)
+// around the sweeps (cmap.hip).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -43,32 +50,42 @@ constexpr int kNuCap = 30;    // largest nu_max
 constexpr int kNuDefault = 10; // default nu_max
 constexpr int kVB = 256;      // threads per block of the vector kernels
 
+constexpr int kBtMax = 50;     // halvings of lambda before an instance gives up
+constexpr int kTraceCols = 40; // trace row: lambda, res, accepted nu, nu_max, pairs, dphi[nu]...
+constexpr int kTracePhi = 5;
+constexpr double kEpsDiv = 1e-3;  // tolerance of the infeasibility test
+
 // reduction slots
-constexpr int R_MAX = 0, R_MAXU = 1, R_SS = 2, R_BAD = 3, PB = 4;
-constexpr int kNMax = 2;  // slots [0, kNMax) are max-reduced, the rest summed
+constexpr int R_MAX = 0, R_MAXU = 1, R_MAX3 = 2, R_SS = 3, R_BAD = 4, PB = 5;
+constexpr int kNMax = 3;  // slots [0, kNMax) are max-reduced, the rest summed
 constexpr int nv_pair(int memcap) { return PB + 6 + 5 * memcap; }
-constexpr int kNVMax = nv_pair(kMemMax) > kNuCap + 2 ? nv_pair(kMemMax) : kNuCap + 2;
+constexpr int kNVMax = nv_pair(kMemMax) > kNuCap + 3 + kNMax ? nv_pair(kMemMax) : kNuCap + 3 + kNMax;
 
 struct Ctl {
     int done, status, iter, have_pair;
-    int first_blk, nblk, pad0, pad1;
+    int first_blk, nblk, skip, redo;      // skip: update undone by test 1; redo: see update_kernel
     int cnt, free_slot, pushes, skips;
     int ls_trials, sweeps_aff, sweeps_hom, accepted_nu;
     int max_iter, mem, nu_max, method;
+    int buf, bt_pending, backtracks, backtrack;
+    int ck_set, div_now, div_store, nodiv;
     int order[kMemMax];
     double lam, eps, eps_curv, tau, cr;
     double res, resu, rr, gg_prev, gamma;
-    double L, inv_norm;
+    double L, inv_norm, bt_param, hh;
+    double theta, beta;                   // GPAD: theta_k and the next extrapolation weight
     double SY[kMemMax + 1][kMemMax + 1];  // s_a . q_b by slot
     double QQ[kMemMax + 1][kMemMax + 1];  // q_a . q_b by slot
     double coefS[kMemMax], coefQ[kMemMax];
     double ls_val[kNuCap + 1];
 };
+constexpr int kCtlInts = (int)(sizeof(Ctl) / sizeof(int));
 
 struct VecArgs {
     const InstDesc *inst;
     const int *blk;  // per block: instance, block within the instance, blocks of the instance
     const double *sc, *lo, *hi;
+    const double *pw, *hub;  // soft rows (pi * weight, Huber threshold) or null: all hard
     Ctl *ctl;
     int *ndone;
     long long m_tot;
@@ -76,6 +93,8 @@ struct VecArgs {
     int nblocks, method;
     const double *y, *yp, *hx, *rp, *gp, *hr, *hd, *d;
     double *r, *g, *S, *Q, *yn;
+    double *Rw, *hw;         // backtracking test 1: R(w), s H x(w) of the update (null: not kept)
+    double *yck;             // infeasibility test: iterate at the last test, then the change since
 };
 
 // The rows a block visits: rows lb*kVB + tid + n*nblk*kVB of its instance.
@@ -92,18 +111,66 @@ __device__ __forceinline__ BlockRows block_rows(const VecArgs &a)
     br.lb = a.blk[3 * blockIdx.x + 1];
     br.nb = a.blk[3 * blockIdx.x + 2];
     br.I = a.inst[br.b];
-    br.nlr = (unsigned)((long long)br.I.Vnl * (br.I.nx + br.I.nu));
+    br.nlr = (unsigned)((long long)br.I.Vnl * br.I.nc);
     return br;
 }
 
-// sqrt(pi) of the node owning local row k (1 without preconditioning).
+// sqrt(pi) of the node owning local row k (1 without preconditioning); the
+// dual layout has nc rows per non-leaf node and ncN per leaf.
 __device__ __forceinline__ double row_scale(const VecArgs &a, const BlockRows &br, long long k)
 {
     if (!a.sc) return 1.0;
     const unsigned kk = (unsigned)k;
-    const unsigned node = kk < br.nlr ? kk / (unsigned)(br.I.nx + br.I.nu)
-                                      : (unsigned)br.I.Vnl + (kk - br.nlr) / (unsigned)br.I.nx;
+    const unsigned node = kk < br.nlr ? kk / (unsigned)br.I.nc
+                                      : (unsigned)br.I.Vnl + (kk - br.nlr) / (unsigned)br.I.ncN;
     return a.sc[br.I.sc + node];
+}
+
+// Bounds and penalty of local row kl in the scaled variables of Sec. III-E:
+// the row function pi w psi_d(dist(z / s, [lo, hi])) equals
+// w' psi_d'(dist(zb, [s lo, s hi])) with w' = pi w / s and d' = s d.
+struct RowG {
+    double lo, hi, w, d;   // w = +inf: hard row
+};
+__device__ __forceinline__ RowG row_g(const VecArgs &a, const BlockRows &br, long long kl, double s)
+{
+    RowG g;
+    g.lo = s * a.lo[br.I.box + kl];
+    g.hi = s * a.hi[br.I.box + kl];
+    g.w = INFINITY;
+    g.d = 0.0;
+    if (a.pw) {
+        const double pw = a.pw[br.I.box + kl];
+        if (pw < INFINITY) {
+            g.w = pw / s;
+            g.d = s * a.hub[br.I.box + kl];
+        }
+    }
+    return g;
+}
+
+// Row prox of Sec. II-D, z = argmin g(z) + (lambda/2)(z - v)^2: the
+// projection on [lo, hi] for a hard row; for a soft row the distance t to
+// the interval shrinks to t / (1 + w / (lambda d)) on the quadratic part of
+// the Huber function (shrunk distance <= d) and to max(t - w/lambda, 0)
+// beyond it.  gz receives g(z) (0 for a hard row).
+__device__ __forceinline__ double row_prox(double v, const RowG &g, double lam, double &gz)
+{
+    gz = 0.0;
+    if (!(g.w < INFINITY)) return v < g.lo ? g.lo : (v > g.hi ? g.hi : v);
+    const bool above = v > g.hi;
+    if (!above && !(v < g.lo)) return v;
+    const double t = above ? v - g.hi : g.lo - v;
+    const double wl = g.w / lam;
+    double sh;
+    if (g.d > 0.0 && t <= g.d + wl) {
+        sh = t / (1.0 + wl / g.d);
+        gz = g.w * sh * sh / (2.0 * g.d);
+    } else {
+        sh = t - wl > 0.0 ? t - wl : 0.0;
+        gz = g.w * (sh - 0.5 * g.d);
+    }
+    return above ? g.hi + sh : g.lo - sh;
 }
 
 #define FOR_BLOCK_ROWS(br, kl, k)                                                             \
@@ -195,13 +262,15 @@ __device__ __forceinline__ void pair_dots(const VecArgs &a, long long k, double 
     }
 }
 
+__device__ __forceinline__ bool idle(const Ctl *c) { return c->done || c->skip; }
+
 // Residual pass.  PAIR (NAMA): g = R and the L-BFGS pair/dots.
 template <bool PAIR, int MEMCAP>
 __global__ void __launch_bounds__(kVB) resid_kernel(VecArgs a)
 {
     const BlockRows br = block_rows(a);
     const Ctl *c = a.ctl + br.b;
-    if (c->done) return;
+    if (idle(c)) return;
     constexpr int NV = PAIR ? nv_pair(MEMCAP) : PB;
     double acc[nv_pair(MEMCAP)];
 #pragma unroll
@@ -216,7 +285,8 @@ __global__ void __launch_bounds__(kVB) resid_kernel(VecArgs a)
         const double s = row_scale(a, br, kl);
         const double h = s * a.hx[k];
         const double yk = a.y[k];
-        const double z = clampd(yk / lam + h, s * a.lo[br.I.box + kl], s * a.hi[br.I.box + kl]);
+        double gz;
+        const double z = row_prox(yk / lam + h, row_g(a, br, kl, s), lam, gz);
         const double R = z - h;
         a.r[k] = R;
         const double aR = fabs(R);
@@ -233,13 +303,14 @@ __global__ void __launch_bounds__(kVB) resid_kernel(VecArgs a)
     block_store<nv_pair(MEMCAP)>(acc, NV, a.part, a.nblocks);
 }
 
-// MINFBE gradient of the FBE and the L-BFGS pair/dots.
+// MINFBE gradient of the FBE and the L-BFGS pair/dots; slot R_SS collects
+// ||s H xhat(s R)||^2 for backtracking test 2.
 template <int MEMCAP>
 __global__ void __launch_bounds__(kVB) grad_kernel(VecArgs a)
 {
     const BlockRows br = block_rows(a);
     const Ctl *c = a.ctl + br.b;
-    if (c->done) return;
+    if (idle(c)) return;
     double acc[nv_pair(MEMCAP)];
 #pragma unroll
     for (int v = 0; v < nv_pair(MEMCAP); ++v) acc[v] = 0.0;
@@ -251,8 +322,10 @@ __global__ void __launch_bounds__(kVB) grad_kernel(VecArgs a)
     for (int j = 0; j < MEMCAP; ++j) order[j] = c->order[j];
     FOR_BLOCK_ROWS(br, kl, k) {
         const double s = row_scale(a, br, kl);
-        const double g = a.r[k] + lam * s * a.hr[k];
+        const double shr = s * a.hr[k];
+        const double g = a.r[k] + lam * shr;
         a.g[k] = g;
+        acc[R_SS] += shr * shr;
         const double sv = have_pair ? a.y[k] - a.yp[k] : 0.0;
         const double qv = have_pair ? g - a.gp[k] : 0.0;
         pair_dots<MEMCAP>(a, k, sv, qv, g, have_pair, cnt, fslot, order, acc);
@@ -265,7 +338,7 @@ __global__ void __launch_bounds__(kVB) combine_kernel(VecArgs a)
 {
     const BlockRows br = block_rows(a);
     const Ctl *c = a.ctl + br.b;
-    if (c->done) return;
+    if (idle(c)) return;
     const int cnt = c->cnt;
     const double gam = c->gamma;
     int order[MEMCAP > 0 ? MEMCAP : 1];
@@ -283,28 +356,35 @@ __global__ void __launch_bounds__(kVB) combine_kernel(VecArgs a)
 }
 
 // All trial steps in one pass; slot nu holds sum over rows of the change of
-// the FBE at w(tau_nu) relative to y.  NUC: the largest nu_max the variant
-// serves (its accumulators, and so its register demand, scale with it).
+// the FBE at w(tau_nu) relative to y, with phi = f-hat + <y, z> -
+// (lambda/2) ||R||^2 - g(z).  NUC: the largest nu_max the variant serves
+// (its accumulators, and so its register demand, scale with it).  For NAMA
+// the slot after the last trial collects ||s H xhat(s r)||^2 (backtracking
+// test 2).
 template <int NUC>
 __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
 {
     const BlockRows br = block_rows(a);
     const Ctl *c = a.ctl + br.b;
-    if (c->done) return;
+    if (idle(c)) return;
     const double lam = c->lam;
     const int numax = c->nu_max;
     const bool nama = a.method == 1;
     double acc[NUC + 1];
+    double hh = 0.0;
 #pragma unroll
     for (int v = 0; v < NUC + 1; ++v) acc[v] = 0.0;
     FOR_BLOCK_ROWS(br, kl, k) {
         const double s = row_scale(a, br, kl);
-        const double lo = s * a.lo[br.I.box + kl], hi = s * a.hi[br.I.box + kl];
+        const RowG rg = row_g(a, br, kl, s);
         const double yk = a.y[k], rk = a.rp[k], dk = a.d[k];
         const double ah = s * a.hx[k];
         const double brk = nama ? s * a.hr[k] : 0.0;
+        hh += brk * brk;
         const double bd = s * a.hd[k];
-        const double ey = yk * (rk + ah) - 0.5 * lam * rk * rk;
+        double gy;
+        (void)row_prox(yk / lam + ah, rg, lam, gy);   // g at z(y) = R + s H x
+        const double ey = yk * (rk + ah) - 0.5 * lam * rk * rk - gy;
         double tau = 1.0;
 #pragma unroll
         for (int nu = 0; nu <= NUC; ++nu) {
@@ -313,27 +393,38 @@ __global__ void __launch_bounds__(kVB) ls_kernel(VecArgs a)
                 const double dl = cr * rk + tau * dk;     // w - y
                 const double hd = cr * brk + tau * bd;    // s H xhat(w - y)
                 const double w = yk + dl, hw = ah + hd;
-                const double zw = clampd(w / lam + hw, lo, hi);
+                double gw;
+                const double zw = row_prox(w / lam + hw, rg, lam, gw);
                 const double Rw = zw - hw;
-                acc[nu] += -ah * dl - 0.5 * dl * hd + w * zw - 0.5 * lam * Rw * Rw - ey;
+                acc[nu] += -ah * dl - 0.5 * dl * hd + w * zw - 0.5 * lam * Rw * Rw - gw - ey;
             }
             tau *= 0.5;
         }
     }
-    // slots [0, kNMax) are the max-reduced ones; the sums follow them
-    double packed[kNMax + NUC + 1];
+    // slots [0, kNMax) are the max-reduced ones; the sums follow them, then hh
+    double packed[kNMax + NUC + 2];
 #pragma unroll
     for (int v = 0; v < kNMax; ++v) packed[v] = 0.0;
 #pragma unroll
-    for (int v = 0; v < NUC + 1; ++v) packed[kNMax + v] = acc[v];
-    block_store<kNMax + NUC + 1>(packed, kNMax + NUC + 1, a.part, a.nblocks);
+    for (int v = 0; v < NUC + 2; ++v)
+        packed[kNMax + v] = v <= numax ? (v < NUC + 1 ? acc[v] : 0.0) : (v == numax + 1 ? hh : 0.0);
+    block_store<kNMax + NUC + 2>(packed, kNMax + NUC + 2, a.part, a.nblocks);
 }
 
+// y+ = T(w) at the accepted step (tau = c->tau); with a.Rw kept, R(w) and
+// s H x(w) for backtracking test 1.  A redone update (redo = 1: lambda
+// halved by test 2) copies y; a skipped one (redo = 2: test 1 undid the
+// previous update) leaves y+ as it is, since it already holds the iterate
+// the next update starts from.
 __global__ void __launch_bounds__(kVB) update_kernel(VecArgs a)
 {
     const BlockRows br = block_rows(a);
     const Ctl *c = a.ctl + br.b;
-    if (c->done) return;
+    if (idle(c) || c->redo == 2) return;
+    if (c->redo == 1) {
+        FOR_BLOCK_ROWS(br, kl, k) a.yn[k] = a.y[k];
+        return;
+    }
     const double lam = c->lam, tau = c->tau, cr = c->cr;
     const bool nama = a.method == 1;
     FOR_BLOCK_ROWS(br, kl, k) {
@@ -341,14 +432,106 @@ __global__ void __launch_bounds__(kVB) update_kernel(VecArgs a)
         const double dl = cr * a.rp[k] + tau * a.d[k];
         const double hd = (nama ? cr * s * a.hr[k] : 0.0) + tau * s * a.hd[k];
         const double w = a.y[k] + dl, hw = s * a.hx[k] + hd;
-        const double zw = clampd(w / lam + hw, s * a.lo[br.I.box + kl], s * a.hi[br.I.box + kl]);
+        double gw;
+        const double zw = row_prox(w / lam + hw, row_g(a, br, kl, s), lam, gw);
         a.yn[k] = w - lam * (zw - hw);
+        if (a.Rw) {
+            a.Rw[k] = zw - hw;
+            a.hw[k] = hw;
+        }
     }
+}
+
+// Backtracking test 1 at the start of the update after y+ = T(w): with
+// H x(y+) from this update's affine sweep, sums <R(w), s H x(y+) - s H x(w)>
+// and ||R(w)||^2 (f-hat is quadratic, so f-hat(y+) - f-hat(w) minus the
+// linear term of the test is -(1/2) <y+ - w, s H xhat(y+ - w)>, and
+// s H xhat(y+ - w) = s H x(y+) - s H x(w) with y+ - w = -lambda R(w)).
+__global__ void __launch_bounds__(kVB) bt_kernel(VecArgs a)
+{
+    const BlockRows br = block_rows(a);
+    const Ctl *c = a.ctl + br.b;
+    if (c->done || !c->bt_pending) return;
+    double acc[kNMax + 2] = {};
+    FOR_BLOCK_ROWS(br, kl, k) {
+        const double s = row_scale(a, br, kl);
+        const double Rw = a.Rw[k];
+        acc[kNMax + 0] += Rw * (s * a.hx[k] - a.hw[k]);
+        acc[kNMax + 1] += Rw * Rw;
+    }
+    block_store<kNMax + 2>(acc, kNMax + 2, a.part, a.nblocks);
+}
+
+// Infeasibility test, first pass: yck becomes y - yck (the change since the
+// last test), or y itself at the first test.
+__global__ void __launch_bounds__(kVB) div_prep_kernel(VecArgs a)
+{
+    const BlockRows br = block_rows(a);
+    const Ctl *c = a.ctl + br.b;
+    if (idle(c) || !c->div_store) return;
+    if (c->div_now) {
+        FOR_BLOCK_ROWS(br, kl, k) a.yck[k] = a.y[k] - a.yck[k];
+    } else {
+        FOR_BLOCK_ROWS(br, kl, k) a.yck[k] = a.y[k];
+    }
+}
+
+// Second pass, after the homogeneous sweep of the change d (in a.hd): max |d|,
+// max |s H xhat(s d)|, max |d| on rows whose g* is +inf along d (an infinite
+// bound on the side d points to, or a soft row), and sigma(d) - <d, s H x(y)>;
+// then yck = y.
+__global__ void __launch_bounds__(kVB) div_kernel(VecArgs a)
+{
+    const BlockRows br = block_rows(a);
+    const Ctl *c = a.ctl + br.b;
+    if (idle(c) || !c->div_now) return;
+    double acc[kNMax + 1] = {};
+    FOR_BLOCK_ROWS(br, kl, k) {
+        const double s = row_scale(a, br, kl);
+        const double d = a.yck[k];
+        const double ad = fabs(d);
+        acc[0] = fmax(acc[0], ad);
+        acc[1] = fmax(acc[1], fabs(s * a.hd[k]));
+        if (d != 0.0) {
+            const RowG rg = row_g(a, br, kl, s);
+            const double bound = d > 0.0 ? rg.hi : rg.lo;
+            if (rg.w < INFINITY || !isfinite(bound)) acc[2] = fmax(acc[2], ad);
+            else acc[kNMax] += bound * d;
+            acc[kNMax] -= d * s * a.hx[k];
+        }
+        a.yck[k] = a.y[k];
+    }
+    block_store<kNMax + 1>(acc, kNMax + 1, a.part, a.nblocks);
+}
+
+// GPAD update: y^{k+1} = T(w^k) = w^k - lambda R(w^k) into y (the main
+// sequence, a.yn), w^{k+1} = y^{k+1} + beta (y^{k+1} - y^k) into w (a.r is
+// R, a.g the evaluation point w, updated in place).
+__global__ void __launch_bounds__(kVB) gpad_update_kernel(VecArgs a)
+{
+    const BlockRows br = block_rows(a);
+    const Ctl *c = a.ctl + br.b;
+    if (c->done) return;
+    const double lam = c->lam, beta = c->beta;
+    FOR_BLOCK_ROWS(br, kl, k) {
+        const double yold = a.yn[k];
+        const double ynew = a.g[k] - lam * a.r[k];
+        a.yn[k] = ynew;
+        a.g[k] = ynew + beta * (ynew - yold);
+    }
+}
+
+__global__ void __launch_bounds__(kVB) copy_kernel(VecArgs a)
+{
+    const BlockRows br = block_rows(a);
+    FOR_BLOCK_ROWS(br, kl, k) a.yn[k] = a.y[k];
 }
 
 // ---------------------------- finalize kernels ---------------------------
 // One block per instance; lane 0 of the block takes the scalar decisions.
-__device__ void finish_residual(Ctl *c, const double *red, int *ndone)
+// div_due: this update runs the infeasibility test (which then takes the
+// max_iter decision after it, as the test comes first).
+__device__ void finish_residual(Ctl *c, const double *red, int *ndone, int div_due)
 {
     c->sweeps_aff++;
     c->res = red[R_MAX];
@@ -356,10 +539,12 @@ __device__ void finish_residual(Ctl *c, const double *red, int *ndone)
     c->rr = red[R_SS];
     if (red[R_BAD] > 0.0 || !isfinite(red[R_SS])) { c->done = 1; c->status = STOTREE_ERR_NUMERIC; }
     else if (red[R_MAX] <= c->eps) { c->done = 1; c->status = STOTREE_OK; }
-    else if (c->iter >= c->max_iter) { c->done = 1; c->status = STOTREE_NOT_CONVERGED; }
+    else if (c->iter >= c->max_iter && !(div_due && c->ck_set)) { c->done = 1; c->status = STOTREE_NOT_CONVERGED; }
     if (c->done) atomicAdd(ndone, 1);
+    c->div_store = div_due && !c->done;
+    c->div_now = c->div_store && c->ck_set;
+    c->nodiv = !c->div_now;
 }
-
 // Cautious push of the candidate pair (Li and Fukushima: push when
 // <s,q> > eps' ||s||^2 ||g_prev||^2) and the compact-form coefficients of
 // d = -B g = -(gamma g + S p1 + gamma Q p2).
@@ -444,47 +629,170 @@ __device__ void lbfgs_update(Ctl *c, const double *red)
     c->gamma = gam;
 }
 
+// Empties the L-BFGS memory (lambda changed); the next pass forms no pair.
+__device__ void lbfgs_clear(Ctl *c)
+{
+    c->cnt = 0;
+    c->free_slot = 0;
+    c->have_pair = 0;
+    c->gamma = 1.0;
+}
+
+// Halving of lambda by a backtracking test; false (and the instance stops
+// with ERR_NUMERIC) after kBtMax halvings.
+__device__ bool halve_lambda(Ctl *c, int *ndone)
+{
+    if (++c->backtracks > kBtMax) {
+        c->done = 1;
+        c->status = STOTREE_ERR_NUMERIC;
+        atomicAdd(ndone, 1);
+        return false;
+    }
+    c->lam *= 0.5;
+    lbfgs_clear(c);
+    return true;
+}
+
 __global__ void __launch_bounds__(kVB) fin_resid_kernel(Ctl *ctl, const double *part, int nblocks,
-                                                        int with_pair, int *ndone)
+                                                        int with_pair, int *ndone, int div_due)
 {
     Ctl *c = ctl + blockIdx.x;
-    if (c->done) return;
+    if (idle(c)) return;
     __shared__ double red[kNVMax];
     reduce_partials(part, nblocks, c->first_blk, c->nblk, with_pair ? nv_pair(c->mem) : PB, red);
     if (threadIdx.x != 0) return;
-    finish_residual(c, red, ndone);
+    finish_residual(c, red, ndone, div_due);
     if (!c->done && with_pair) lbfgs_update(c, red);
 }
 
 __global__ void __launch_bounds__(kVB) fin_grad_kernel(Ctl *ctl, const double *part, int nblocks)
 {
     Ctl *c = ctl + blockIdx.x;
-    if (c->done) return;
+    if (idle(c)) return;
     __shared__ double red[kNVMax];
     reduce_partials(part, nblocks, c->first_blk, c->nblk, nv_pair(c->mem), red);
     if (threadIdx.x != 0) return;
     c->sweeps_hom++;
+    c->hh = red[R_SS];
     lbfgs_update(c, red);
 }
 
-__global__ void __launch_bounds__(kVB) fin_ls_kernel(Ctl *ctl, const double *part, int nblocks)
+// Line-search decision (the largest tau = 2^-nu with phi(w) <= phi(y), else
+// tau = 0), the trace row, backtracking test 2, and the end of the update:
+// the iteration counter, the buffer that holds the next iterate, and the
+// flag that arms test 1 for the next update.  A skipped update (test 1
+// undid the previous one) only moves to the other buffer.
+__global__ void __launch_bounds__(kVB) fin_ls_kernel(Ctl *ctl, const double *part, int nblocks, int *ndone,
+                                                     double *trace, int trace_iters)
 {
-    Ctl *c = ctl + blockIdx.x;
-    if (c->done) return;
+    const int b = blockIdx.x;
+    Ctl *c = ctl + b;
+    const bool done = c->done, skip = c->skip;
+    __syncthreads();   // every thread has read the flags before lane 0 changes them
+    if (done) return;
+    if (skip) {
+        // redo = 2: the update kernel leaves y+ as it is
+        if (threadIdx.x == 0) { c->skip = 0; c->buf ^= 1; c->redo = 2; }
+        return;
+    }
     __shared__ double red[kNVMax];
-    reduce_partials(part, nblocks, c->first_blk, c->nblk, kNMax + c->nu_max + 1, red);
+    reduce_partials(part, nblocks, c->first_blk, c->nblk, kNMax + c->nu_max + 2, red);
     if (threadIdx.x != 0) return;
     int acc = -1;
     for (int nu = 0; nu <= c->nu_max; ++nu) {
         const double dphi = red[kNMax + nu];
         c->ls_val[nu] = dphi;
-        if (isfinite(dphi) && dphi <= 0.0) { acc = nu; break; }
+        if (acc < 0 && isfinite(dphi) && dphi <= 0.0) acc = nu;
+    }
+    if (trace && c->iter < trace_iters) {
+        double *row = trace + ((long long)b * trace_iters + c->iter) * kTraceCols;
+        for (int k = 0; k < kTraceCols; ++k) row[k] = NAN;
+        row[0] = c->lam;
+        row[1] = c->res;
+        row[2] = acc;
+        row[3] = c->nu_max;
+        row[4] = c->cnt;
+        for (int nu = 0; nu <= c->nu_max && kTracePhi + nu < kTraceCols; ++nu) row[kTracePhi + nu] = c->ls_val[nu];
+    }
+    c->sweeps_hom += c->method == 1 ? 2 : 1;
+    c->buf ^= 1;
+    c->redo = 0;
+    if (c->backtrack == 2) {
+        // test 2: lambda ||s H xhat(s R)|| > eps'' ||R|| (the gradients of
+        // f-hat at T(y) and y differ by lambda s H xhat(s R), T(y) - y = -lambda R)
+        const double hh = c->method == 1 ? red[kNMax + c->nu_max + 1] : c->hh;
+        if (c->lam * sqrt(hh) > c->bt_param * sqrt(c->rr)) {
+            if (halve_lambda(c, ndone)) c->redo = 1;
+            c->bt_pending = 0;
+            return;
+        }
     }
     c->accepted_nu = acc;
     c->tau = acc >= 0 ? ldexp(1.0, -acc) : 0.0;
     c->cr = c->method == 1 ? -(1.0 - c->tau) * c->lam : 0.0;
     c->ls_trials += acc >= 0 ? acc + 1 : c->nu_max + 1;
-    c->sweeps_hom += c->method == 1 ? 2 : 1;
+    c->bt_pending = c->backtrack == 1;
+    c->iter++;
+}
+
+// Test 1: halve lambda when <R(w), s H x(y+) - s H x(w)> > (1 - beta) ||R(w)||^2;
+// the update that produced y+ is then undone (this update is skipped and
+// the next one starts again from y^k, which the buffer of y+ of this update
+// still holds).
+__global__ void __launch_bounds__(kVB) fin_bt_kernel(Ctl *ctl, const double *part, int nblocks, int *ndone)
+{
+    Ctl *c = ctl + blockIdx.x;
+    if (c->done || !c->bt_pending) return;
+    __shared__ double red[kNVMax];
+    reduce_partials(part, nblocks, c->first_blk, c->nblk, kNMax + 2, red);
+    if (threadIdx.x != 0) return;
+    c->bt_pending = 0;
+    if (red[kNMax + 0] > (1.0 - c->bt_param) * red[kNMax + 1]) {
+        c->sweeps_aff++;
+        if (halve_lambda(c, ndone)) {
+            c->skip = 1;
+            c->iter--;
+        }
+    }
+}
+
+// Infeasibility decision (see div_kernel), then the max_iter test it deferred.
+__global__ void __launch_bounds__(kVB) fin_div_kernel(Ctl *ctl, const double *part, int nblocks, int *ndone)
+{
+    Ctl *c = ctl + blockIdx.x;
+    if (idle(c) || !c->div_store) return;
+    __shared__ double red[kNVMax];
+    if (c->div_now) reduce_partials(part, nblocks, c->first_blk, c->nblk, kNMax + 1, red);
+    if (threadIdx.x != 0) return;
+    c->div_store = 0;
+    if (!c->div_now) {
+        c->ck_set = 1;
+        return;
+    }
+    c->div_now = 0;
+    c->nodiv = 1;
+    c->sweeps_hom++;
+    const double dn = red[0], hn = red[1], dbad = red[2], lin = red[kNMax];
+    if (dn > 0.0 && dbad <= 1e-9 * dn && c->lam * hn <= kEpsDiv * dn && lin <= -kEpsDiv * dn * c->res) {
+        c->done = 1;
+        c->status = STOTREE_ERR_DIVERGED;
+    } else if (c->iter >= c->max_iter) {
+        c->done = 1;
+        c->status = STOTREE_NOT_CONVERGED;
+    }
+    if (c->done) atomicAdd(ndone, 1);
+}
+
+// GPAD end of update: theta_{k+1} = (sqrt(theta^4 + 4 theta^2) - theta^2)/2
+// and the extrapolation weight theta_{k+1} (1/theta_k - 1) of w^{k+1}.
+__global__ void __launch_bounds__(kVB) fin_gpad_kernel(Ctl *ctl)
+{
+    Ctl *c = ctl + blockIdx.x;
+    if (c->done || threadIdx.x != 0) return;
+    const double th = c->theta;
+    const double tn = 0.5 * (sqrt(th * th * th * th + 4.0 * th * th) - th * th);
+    c->beta = tn * (1.0 / th - 1.0);
+    c->theta = tn;
     c->iter++;
 }
 
@@ -493,7 +801,7 @@ __global__ void __launch_bounds__(kVB) fin_ls_kernel(Ctl *ctl, const double *par
 __global__ void __launch_bounds__(kVB) gather_final_kernel(VecArgs a)
 {
     const BlockRows br = block_rows(a);
-    if (!(a.ctl[br.b].iter & 1)) return;
+    if (!a.ctl[br.b].buf) return;
     FOR_BLOCK_ROWS(br, kl, k) a.yn[k] = a.y[k];
 }
 
@@ -539,12 +847,28 @@ __global__ void __launch_bounds__(kVB) power_scale_kernel(VecArgs a)
 }
 
 // ------------------------------- host side -------------------------------
-// need_g: the two FBE-gradient vectors (MINFBE only).
-int ensure_solver_ws(tree_factors *f, int mem, bool need_g)
+struct WsNeed {
+    int mem;
+    bool g, div, bt;
+};
+
+// need.g: the two FBE-gradient vectors (MINFBE only); need.div: the iterate
+// of the infeasibility test; need.bt: R(w), H x(w) for backtracking test 1.
+int ensure_solver_ws(tree_factors *f, WsNeed need)
 {
     SolverWS &w = f->sws;
-    if (w.buf && w.mem >= mem && (w.has_g || !need_g)) return STOTREE_OK;
-    if (w.buf) { (void)hipFree(w.buf); w.buf = nullptr; w.bytes = 0; }
+    if (w.buf && w.mem >= need.mem && (w.has_g || !need.g) && (w.has_div || !need.div) && (w.has_bt || !need.bt))
+        return STOTREE_OK;
+    if (w.buf) {
+        // keep what the old workspace offered
+        need.mem = std::max(need.mem, w.mem);
+        need.g |= w.has_g;
+        need.div |= w.has_div;
+        need.bt |= w.has_bt;
+        (void)hipFree(w.buf);
+        w.buf = nullptr;
+        w.bytes = 0;
+    }
     // blocks per instance: one per 1024 rows, at most 1024
     std::vector<int> blk;
     w.blk_first.assign(f->ninst, 0);
@@ -556,29 +880,41 @@ int ensure_solver_ws(tree_factors *f, int mem, bool need_g)
     }
     const int nblocks = (int)(blk.size() / 3);
     const long long m = f->m_tot;
-    const long long nvec = (need_g ? 9 : 7) + 2LL * (mem + 1);
-    const size_t vec_bytes = sizeof(double) * ((size_t)nvec * m + (size_t)kNVMax * nblocks);
+    const long long nvec = (need.g ? 9 : 7) + 2LL * (need.mem + 1) + (need.div ? 1 : 0) + (need.bt ? 2 : 0);
+    const long long nxu = f->cmap ? 4 * f->mxu_tot : 0;
+    const size_t vec_bytes = sizeof(double) * ((size_t)nvec * m + (size_t)nxu + (size_t)kNVMax * nblocks);
     const size_t ctl_bytes = sizeof(Ctl) * (size_t)f->ninst;
     const size_t bytes = vec_bytes + ctl_bytes + sizeof(int) * (blk.size() + 1) + 512;
     STOTREE_HIP(hipMalloc(&w.buf, bytes));
     w.bytes = bytes;
-    w.mem = mem;
+    w.mem = need.mem;
     w.nblocks = nblocks;
     double *p = w.buf;
     w.y[1] = p; p += m;
     w.r[0] = p; p += m;
     w.r[1] = p; p += m;
-    w.has_g = need_g;
+    w.has_g = need.g;
     w.g[0] = w.g[1] = nullptr;
-    if (need_g) {
+    if (need.g) {
         w.g[0] = p; p += m;
         w.g[1] = p; p += m;
     }
     w.hx = p; p += m;
     w.hr2 = p; p += 2 * m;  // hr, hd
     w.d = p; p += m;
-    w.S = p; p += (long long)(mem + 1) * m;
-    w.Qv = p; p += (long long)(mem + 1) * m;
+    w.S = p; p += (long long)(need.mem + 1) * m;
+    w.Qv = p; p += (long long)(need.mem + 1) * m;
+    w.has_div = need.div;
+    w.yck = nullptr;
+    if (need.div) { w.yck = p; p += m; }
+    w.has_bt = need.bt;
+    w.Rw = w.hw = nullptr;
+    if (need.bt) {
+        w.Rw = p; p += m;
+        w.hw = p; p += m;
+    }
+    w.xu = nullptr;
+    if (nxu) { w.xu = p; p += nxu; }
     w.partials = p; p += (size_t)kNVMax * nblocks;
     w.ctl = p;
     char *q = reinterpret_cast<char *>(p) + ctl_bytes;
@@ -596,64 +932,115 @@ VecArgs vec_args(const tree_factors *f)
     a.sc = f->precondition ? f->sc : nullptr;
     a.lo = f->lo;
     a.hi = f->hi;
+    a.pw = f->pw;
+    a.hub = f->hub;
     a.ctl = reinterpret_cast<Ctl *>(f->sws.ctl);
     a.ndone = f->sws.ndone;
     a.m_tot = f->m_tot;
     a.part = f->sws.partials;
     a.nblocks = f->sws.nblocks;
+    a.yck = f->sws.yck;
     return a;
 }
 
-// Sweep arguments writing H x (dual layout) for right-hand sides whose
-// inputs/outputs are at (y, y + y_rs) and (out, out + o_rs).
-SweepArgs dual_layout_sweep(const tree_factors *f, int affine, const double *x0, const double *y,
-                            long long y_rs, double *out, long long o_rs, const Ctl *ctl)
+// A sweep of nrhs in {1, 2} right-hand sides whose duals are at (y, y + y_rs)
+// in the dual layout, writing H x there at (out, out + o_rs); instances whose
+// flag (an int of each control block, flag_of(ctl)) is set are skipped.  With
+// a constraint map the duals go through to_xu and the sweep's (x, u) output
+// through from_xu.
+hipError_t dual_sweep(const tree_factors *f, int affine, const double *x0, const double *y, long long y_rs,
+                      double *out, long long o_rs, const int *flags, int nrhs, hipStream_t st, int active = -1)
 {
     SweepArgs a = sweep_args(f, affine);
     a.x0 = x0; a.x0_rs = 0;
-    a.y = y; a.y_rs = y_rs;
-    a.xo = out; a.xo_rs = o_rs;
     a.dual_out = 1;
-    a.done = ctl ? &ctl->done : nullptr;
-    a.done_stride = (int)(sizeof(Ctl) / sizeof(int));
-    return a;
+    a.done = flags;
+    a.done_stride = kCtlInts;
+    if (!f->cmap) {
+        a.y = y; a.y_rs = y_rs;
+        a.xo = out; a.xo_rs = o_rs;
+        return launch_sweep_any(f, a, nrhs, st, active);
+    }
+    double *vin = f->sws.xu, *vout = f->sws.xu + 2 * f->mxu_tot;
+    hipError_t e = map_to_xu(f, y, y_rs, vin, nrhs, st);
+    if (e != hipSuccess) return e;
+    a.y = vin; a.y_rs = f->mxu_tot;
+    a.xo = vout; a.xo_rs = f->mxu_tot;
+    if ((e = launch_sweep_any(f, a, nrhs, st, active)) != hipSuccess) return e;
+    return map_from_xu(f, vout, out, o_rs, nrhs, st);
 }
 
-template <int MEMCAP, int NUC>
-hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *ybuf[2], int k, int method,
-                             int active, hipStream_t st)
+const int *done_flags(const Ctl *ctl) { return ctl ? &ctl->done : nullptr; }
+const int *div_flags(const Ctl *ctl) { return &ctl->nodiv; }
+
+struct IterArgs {
+    const double *x0;
+    double *ybuf[2];
+    int k, method, active;
+    int div_due, backtrack;
+    double *trace;
+    int trace_iters;
+};
+
+// Infeasibility test of the iterate y (after fin_resid): the change since
+// the last test, its homogeneous sweep into hd, the reductions and the
+// decision.
+hipError_t enqueue_div_test(const tree_factors *f, const double *y, hipStream_t st)
 {
     const SolverWS &w = f->sws;
     VecArgs a = vec_args(f);
-    a.method = method;
     Ctl *ctl = a.ctl;
     const dim3 grid(a.nblocks), blk(kVB), fgrid(f->ninst);
-    double *y = ybuf[k & 1], *yn = ybuf[(k + 1) & 1];
+    double *hd = w.hr2 + f->m_tot;
+    a.y = y; a.hx = w.hx; a.hd = hd;
+    hipLaunchKernelGGL(div_prep_kernel, grid, blk, 0, st, a);
+    hipError_t e = dual_sweep(f, 0, nullptr, w.yck, 0, hd, 0, div_flags(ctl), 1, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(div_kernel, grid, blk, 0, st, a);
+    hipLaunchKernelGGL(fin_div_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, a.ndone);
+    return hipGetLastError();
+}
+
+template <int MEMCAP, int NUC>
+hipError_t enqueue_iteration(const tree_factors *f, const IterArgs &it, hipStream_t st)
+{
+    const SolverWS &w = f->sws;
+    VecArgs a = vec_args(f);
+    a.method = it.method;
+    Ctl *ctl = a.ctl;
+    const int k = it.k, method = it.method, active = it.active;
+    const dim3 grid(a.nblocks), blk(kVB), fgrid(f->ninst);
+    double *y = it.ybuf[k & 1], *yn = it.ybuf[(k + 1) & 1];
     double *r = w.r[k & 1], *rp = w.r[(k + 1) & 1];
     double *g = w.g[k & 1], *gp = w.g[(k + 1) & 1];
     double *hr = w.hr2, *hd = w.hr2 + f->m_tot;
     hipError_t e;
     // x(y) -> H x
-    if ((e = launch_sweep_any(f, dual_layout_sweep(f, 1, x0, y, 0, w.hx, 0, ctl), 1, st, active))) return e;
+    if ((e = dual_sweep(f, 1, it.x0, y, 0, w.hx, 0, done_flags(ctl), 1, st, active))) return e;
+    if (it.backtrack == 1) {
+        VecArgs ba = a;
+        ba.hx = w.hx; ba.Rw = w.Rw; ba.hw = w.hw;
+        hipLaunchKernelGGL(bt_kernel, grid, blk, 0, st, ba);
+        hipLaunchKernelGGL(fin_bt_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, a.ndone);
+    }
     a.y = y; a.yp = yn; a.hx = w.hx; a.rp = rp; a.r = r;
     a.S = w.S; a.Q = w.Qv;
     if (method == 1) {
         hipLaunchKernelGGL((resid_kernel<true, MEMCAP>), grid, blk, 0, st, a);
-        hipLaunchKernelGGL(fin_resid_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, 1, a.ndone);
+        hipLaunchKernelGGL(fin_resid_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, 1, a.ndone, it.div_due);
+        if (it.div_due && (e = enqueue_div_test(f, y, st))) return e;
         VecArgs cb = a;
         cb.g = r;           // g = R
         cb.r = w.d;         // output direction
         hipLaunchKernelGGL((combine_kernel<MEMCAP>), grid, blk, 0, st, cb);
         // x-hat(r) and x-hat(d) in one two-right-hand-side sweep (p-NAMA)
-        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, r, w.d - r, hr, hd - hr, ctl), 2, st,
-                                  active)))
-            return e;
+        if ((e = dual_sweep(f, 0, nullptr, r, w.d - r, hr, hd - hr, done_flags(ctl), 2, st, active))) return e;
     } else {
         hipLaunchKernelGGL((resid_kernel<false, 0>), grid, blk, 0, st, a);
-        hipLaunchKernelGGL(fin_resid_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, 0, a.ndone);
+        hipLaunchKernelGGL(fin_resid_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, 0, a.ndone, it.div_due);
+        if (it.div_due && (e = enqueue_div_test(f, y, st))) return e;
         // grad phi = R + lambda s H xhat(s R)
-        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, r, 0, hr, 0, ctl), 1, st, active)))
-            return e;
+        if ((e = dual_sweep(f, 0, nullptr, r, 0, hr, 0, done_flags(ctl), 1, st, active))) return e;
         VecArgs ga = a;
         ga.hr = hr; ga.g = g; ga.gp = gp;
         hipLaunchKernelGGL((grad_kernel<MEMCAP>), grid, blk, 0, st, ga);
@@ -661,19 +1048,42 @@ hipError_t enqueue_iteration(const tree_factors *f, const double *x0, double *yb
         VecArgs cb = a;
         cb.g = g; cb.r = w.d;
         hipLaunchKernelGGL((combine_kernel<MEMCAP>), grid, blk, 0, st, cb);
-        if ((e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, w.d, 0, hd, 0, ctl), 1, st, active)))
-            return e;
+        if ((e = dual_sweep(f, 0, nullptr, w.d, 0, hd, 0, done_flags(ctl), 1, st, active))) return e;
     }
     VecArgs la = vec_args(f);
     la.method = method;
     la.y = y; la.rp = r; la.d = w.d; la.hx = w.hx; la.hr = hr; la.hd = hd; la.yn = yn;
     hipLaunchKernelGGL(ls_kernel<NUC>, grid, blk, 0, st, la);
-    hipLaunchKernelGGL(fin_ls_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks);
+    hipLaunchKernelGGL(fin_ls_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, a.ndone, it.trace, it.trace_iters);
+    if (it.backtrack == 1) { la.Rw = w.Rw; la.hw = w.hw; }
     hipLaunchKernelGGL(update_kernel, grid, blk, 0, st, la);
     return hipGetLastError();
 }
 
-using IterFn = hipError_t (*)(const tree_factors *, const double *, double *[2], int, int, int, hipStream_t);
+// One GPAD update at the point w (kept in ybuf[0], the caller's buffer), with
+// the main sequence y^k in ybuf[1].
+hipError_t enqueue_gpad(const tree_factors *f, const IterArgs &it, hipStream_t st)
+{
+    const SolverWS &w = f->sws;
+    VecArgs a = vec_args(f);
+    a.method = 2;
+    Ctl *ctl = a.ctl;
+    const dim3 grid(a.nblocks), blk(kVB), fgrid(f->ninst);
+    double *wv = it.ybuf[0], *ym = it.ybuf[1], *r = w.r[0];
+    hipError_t e;
+    if ((e = dual_sweep(f, 1, it.x0, wv, 0, w.hx, 0, done_flags(ctl), 1, st, it.active))) return e;
+    a.y = wv; a.hx = w.hx; a.r = r;
+    hipLaunchKernelGGL((resid_kernel<false, 0>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL(fin_resid_kernel, fgrid, blk, 0, st, ctl, a.part, a.nblocks, 0, a.ndone, it.div_due);
+    if (it.div_due && (e = enqueue_div_test(f, wv, st))) return e;
+    hipLaunchKernelGGL(fin_gpad_kernel, fgrid, dim3(64), 0, st, ctl);
+    VecArgs ua = a;
+    ua.g = wv; ua.r = r; ua.yn = ym;
+    hipLaunchKernelGGL(gpad_update_kernel, grid, blk, 0, st, ua);
+    return hipGetLastError();
+}
+
+using IterFn = hipError_t (*)(const tree_factors *, const IterArgs &, hipStream_t);
 
 // Variant for the L-BFGS memory (accumulators per pair slot) and the number
 // of line-search trials; the default options (mem 5, nu_max 10) have their own.
@@ -703,7 +1113,7 @@ int power_iterations(tree_factors *f, int iters, hipStream_t st)
     pa.yn = v;
     hipLaunchKernelGGL(power_init_kernel, grid, blk, 0, st, pa);
     for (int it = 0; it < iters; ++it) {
-        hipError_t e = launch_sweep_any(f, dual_layout_sweep(f, 0, nullptr, v, 0, hv, 0, nullptr), 1, st);
+        hipError_t e = dual_sweep(f, 0, nullptr, v, 0, hv, 0, nullptr, 1, st);
         if (e != hipSuccess) { set_error(std::string("dual_lipschitz: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
         pa.y = v; pa.hx = hv; pa.r = wv; pa.yn = v;
         hipLaunchKernelGGL(power_step_kernel, grid, blk, 0, st, pa);
@@ -725,6 +1135,8 @@ std::vector<Ctl> fresh_ctl(const tree_factors *f)
         const int next = b + 1 < f->ninst ? f->sws.blk_first[b + 1] : f->sws.nblocks;
         c.nblk = next - c.first_blk;
         c.gamma = 1.0;
+        c.theta = 1.0;
+        c.nodiv = 1;
         c.status = STOTREE_NOT_CONVERGED;
     }
     return h;
@@ -735,7 +1147,8 @@ std::vector<Ctl> fresh_ctl(const tree_factors *f)
 int lipschitz(const tree_factors *fc, int iters, double *L, hipStream_t st)
 {
     tree_factors *f = const_cast<tree_factors *>(fc);
-    int rc = ensure_solver_ws(f, f->sws.buf ? f->sws.mem : 1, false);
+    const SolverWS &w = f->sws;
+    int rc = ensure_solver_ws(f, WsNeed{w.buf ? w.mem : 1, w.has_g, w.has_div, w.has_bt});
     if (rc) return rc;
     if ((rc = ensure_sweep_ws(f, 2))) return rc;
     std::vector<Ctl> h = fresh_ctl(f);
@@ -752,14 +1165,23 @@ int solve(const tree_factors *fc, const double *x0, const solver_opts *opts_in, 
           double *u, solver_info *info, hipStream_t st, int method)
 {
     tree_factors *f = const_cast<tree_factors *>(fc);
-    solver_opts o{0.0, 1e-6, 1e-12, 5, 10, 1000, 1};
+    solver_opts o{};
+    o.eps = 1e-6; o.eps_curv = 1e-12; o.mem = 5; o.nu_max = 10; o.max_iter = 1000; o.check_every = 1;
     if (opts_in) o = *opts_in;
     if (o.mem < 1 || o.mem > kMemMax || o.nu_max < 0 || o.nu_max > kNuCap || o.max_iter < 0 ||
-        o.check_every < 1 || !(o.eps >= 0.0) || !(o.lambda >= 0.0) || !(o.eps_curv >= 0.0)) {
-        set_error("solve: options out of range (mem 1..16, nu_max 0..30, check_every >= 1)");
+        o.check_every < 1 || !(o.eps >= 0.0) || !(o.lambda >= 0.0) || !(o.eps_curv >= 0.0) ||
+        o.backtrack < 0 || o.backtrack > 2 || o.trace_iters < 0 || (o.trace_iters > 0 && !o.trace)) {
+        set_error("solve: options out of range (mem 1..16, nu_max 0..30, check_every >= 1, backtrack 0..2)");
         return STOTREE_ERR_ARG;
     }
-    int rc = ensure_solver_ws(f, o.mem, method == 0);
+    const int backtrack = method == 2 ? 0 : o.backtrack;
+    if ((backtrack == 1 && !(o.bt_param >= 0.0 && o.bt_param < 1.0)) ||
+        (backtrack == 2 && !(o.bt_param > 0.0 && o.bt_param < 0.5))) {
+        set_error("solve: bt_param must lie in [0, 1) for backtracking test 1 and in (0, 1/2) for test 2");
+        return STOTREE_ERR_ARG;
+    }
+    const int div_window = o.div_window == 0 ? 50 : (o.div_window < 0 ? 0 : o.div_window);
+    int rc = ensure_solver_ws(f, WsNeed{o.mem, method == 0, div_window > 0, backtrack == 1});
     if (rc) return rc;
     if ((rc = ensure_sweep_ws(f, 2))) return rc;
     const SolverWS &w = f->sws;
@@ -767,42 +1189,65 @@ int solve(const tree_factors *fc, const double *x0, const solver_opts *opts_in, 
     std::vector<Ctl> h = fresh_ctl(f);
     std::vector<double> lam(f->ninst, o.lambda);
     if (o.lambda == 0.0) {
+        // with backtracking a short power iteration suffices: its Rayleigh
+        // quotient is at most L, so the start 1/L-hat is at least 1/L and the
+        // tests bring it down
         std::vector<double> L(f->ninst);
-        if ((rc = lipschitz(f, 100, L.data(), st))) return rc;
+        if ((rc = lipschitz(f, backtrack ? 5 : 100, L.data(), st))) return rc;
         for (int b = 0; b < f->ninst; ++b) {
             if (!(L[b] > 0.0) || !std::isfinite(L[b])) {
                 set_error("solve: could not estimate L of instance " + std::to_string(b));
                 return STOTREE_ERR_NUMERIC;
             }
-            lam[b] = 1.0 / (1.1 * L[b]);
+            lam[b] = backtrack ? 1.0 / L[b] : 1.0 / (1.1 * L[b]);
         }
     }
     for (int b = 0; b < f->ninst; ++b) {
         Ctl &c = h[b];
         c.max_iter = o.max_iter; c.mem = o.mem; c.nu_max = o.nu_max; c.method = method;
         c.lam = lam[b]; c.eps = o.eps; c.eps_curv = o.eps_curv;
+        c.backtrack = backtrack; c.bt_param = o.bt_param;
     }
     STOTREE_HIP(hipMemcpyAsync(dctl, h.data(), sizeof(Ctl) * h.size(), hipMemcpyHostToDevice, st));
     STOTREE_HIP(hipMemsetAsync(w.ndone, 0, sizeof(int), st));
     double *ybuf[2] = {y_io, w.y[1]};
-    IterFn iter = pick_iter(o.mem, o.nu_max);
+    if (method == 2) {
+        // GPAD: y^0 = y^{-1} = the initial dual (w^0 = y^0 in the caller's buffer)
+        VecArgs ca = vec_args(f);
+        ca.y = y_io; ca.yn = w.y[1];
+        hipLaunchKernelGGL(copy_kernel, dim3(ca.nblocks), dim3(kVB), 0, st, ca);
+    }
+    IterFn iter = method == 2 ? enqueue_gpad : pick_iter(o.mem, o.nu_max);
+    // each halving of lambda costs one update that does not count
+    const int last = o.max_iter + (backtrack ? kBtMax + 1 : 0);
     int k = 0, ndone = 0;
-    while (ndone < f->ninst && k <= o.max_iter) {
+    while (ndone < f->ninst && k <= last) {
         // instances finished by the last check are skipped by the sweeps (the
         // count may lag behind by check_every iterations; it only grows)
-        for (int c = 0; c < o.check_every && k <= o.max_iter; ++c, ++k) {
-            hipError_t e = iter(f, x0, ybuf, k, method, f->ninst - ndone, st);
+        for (int c = 0; c < o.check_every && k <= last; ++c, ++k) {
+            IterArgs it{x0, {ybuf[0], ybuf[1]}, k, method, f->ninst - ndone,
+                        div_window > 0 && k % div_window == 0, backtrack, o.trace, o.trace_iters};
+            hipError_t e = iter(f, it, st);
             if (e != hipSuccess) { set_error(std::string("solve: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
         }
         STOTREE_HIP(hipMemcpyAsync(&ndone, w.ndone, sizeof(int), hipMemcpyDeviceToHost, st));
         STOTREE_HIP(hipStreamSynchronize(st));
     }
-    // last iterate of every instance into y_io, then x(y) in the caller's layout
-    VecArgs ga = vec_args(f);
-    ga.y = w.y[1]; ga.yn = y_io;
-    hipLaunchKernelGGL(gather_final_kernel, dim3(ga.nblocks), dim3(kVB), 0, st, ga);
+    if (method != 2) {
+        // last iterate of every instance into y_io (GPAD keeps it there)
+        VecArgs ga = vec_args(f);
+        ga.y = w.y[1]; ga.yn = y_io;
+        hipLaunchKernelGGL(gather_final_kernel, dim3(ga.nblocks), dim3(kVB), 0, st, ga);
+    }
+    // x(y) in the caller's layout
     SweepArgs a = sweep_args(f, 1);
-    a.x0 = x0; a.y = y_io;
+    a.x0 = x0;
+    a.y = y_io;
+    if (f->cmap) {
+        hipError_t e = map_to_xu(f, y_io, f->m_tot, w.xu, 1, st);
+        if (e != hipSuccess) { set_error(std::string("solve: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
+        a.y = w.xu;
+    }
     a.xo = x; a.uo = u; a.dual_out = 0;
     hipError_t e = launch_sweep_any(f, a, 1, st);
     if (e != hipSuccess) { set_error(std::string("solve: ") + hipGetErrorString(e)); return STOTREE_ERR_DEVICE; }
@@ -824,12 +1269,14 @@ int solve(const tree_factors *fc, const double *x0, const solver_opts *opts_in, 
         in.res_scaled_inf = c.res;
         in.res_unscaled_inf = c.resu;
         in.lambda = c.lam;
+        in.backtracks = c.backtracks;
         agg.iters = std::max(agg.iters, in.iters);
         agg.sweeps_affine = std::max(agg.sweeps_affine, in.sweeps_affine);
         agg.sweeps_hom = std::max(agg.sweeps_hom, in.sweeps_hom);
         agg.ls_trials += in.ls_trials;
         agg.lbfgs_push += in.lbfgs_push;
         agg.lbfgs_skip += in.lbfgs_skip;
+        agg.backtracks = std::max(agg.backtracks, in.backtracks);
         agg.res_scaled_inf = std::max(agg.res_scaled_inf, in.res_scaled_inf);
         agg.res_unscaled_inf = std::max(agg.res_unscaled_inf, in.res_unscaled_inf);
         if (in.status < 0) agg.status = std::min(agg.status, in.status);
@@ -837,7 +1284,8 @@ int solve(const tree_factors *fc, const double *x0, const solver_opts *opts_in, 
     }
     agg.lambda = h[0].lam;
     *info = agg;
-    if (agg.status == STOTREE_ERR_NUMERIC) set_error("solve: non-finite values in the iterates");
+    if (agg.status == STOTREE_ERR_NUMERIC) set_error("solve: non-finite values in the iterates (or lambda halved too often)");
+    if (agg.status == STOTREE_ERR_DIVERGED) set_error("solve: the infeasibility test fired (no point meets the constraints)");
     return agg.status;
 }
 

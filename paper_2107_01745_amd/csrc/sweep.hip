@@ -1012,7 +1012,7 @@ __global__ void __launch_bounds__(kWave *kWavesPerBlock, 2) narrow_chain_kernel(
 SweepArgs sweep_args(const tree_factors *f, int affine)
 {
     SweepArgs a{};
-    a.inst = f->d_inst;
+    a.inst = f->d_inst_xu;   // the sweeps work in the (x, u) layout
     a.sp = f->d_sp; a.cp = f->d_cp; a.anc = f->d_anc;
     a.Mb = f->Mb; a.Mf = f->Mf; a.Kb = f->Kb; a.Kf = f->Kf; a.Rn = f->Rn;
     a.chat = f->chat; a.sig = f->sig; a.cvec = f->cvec; a.sc = f->precondition ? f->sc : nullptr;
@@ -1274,6 +1274,7 @@ int dual_grad_ws_rhs(const tree_factors *f, int nrhs)
 
 // ws: null, the handle's own workspace (grown on demand); otherwise caller
 // memory of dual_grad_ws_rhs(f, nrhs) * (x_tot + u_tot) doubles, q-hat first.
+// y is in the (x, u) layout the sweeps read, mxu_tot per right-hand side.
 int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,
                       double *u, hipStream_t st, double *ws)
 {
@@ -1292,7 +1293,7 @@ int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int ho
     if (panel_route(f, f->ninst)) {
         for (int k = 0; k < nrhs; ++k) {
             a.x0 = x0 ? x0 + (long long)k * f->nx_tot : nullptr;
-            a.y = y + (long long)k * f->m_tot;
+            a.y = y + (long long)k * f->mxu_tot;
             a.xo = x + (long long)k * f->x_tot;
             a.uo = u + (long long)k * f->u_tot;
             const hipError_t e = launch_sweep_any(f, a, 1, st, f->ninst);
@@ -1307,14 +1308,14 @@ int enqueue_dual_grad(tree_factors *f, const double *x0, const double *y, int ho
     // pairs (a shared handle's panel work lists hold instance 0's nodes only)
     const bool panel = ws_rhs == kRhsPanel;
     const int npanel = panel ? nrhs / kRhsPanel * kRhsPanel : 0;
-    a.y_rs = f->m_tot;
+    a.y_rs = f->mxu_tot;
     a.x0_rs = f->nx_tot;
     a.xo_rs = f->x_tot;
     a.uo_rs = f->u_tot;
     for (int k0 = 0; k0 < nrhs;) {
         const int nk = k0 < npanel ? kRhsPanel : (nrhs - k0 >= 2 ? 2 : 1);
         a.x0 = x0 ? x0 + (long long)k0 * f->nx_tot : nullptr;
-        a.y = y + (long long)k0 * f->m_tot;
+        a.y = y + (long long)k0 * f->mxu_tot;
         a.xo = x + (long long)k0 * f->x_tot;
         a.uo = u + (long long)k0 * f->u_tot;
         hipError_t e = nk == kRhsPanel ? launch_panel_sweep(f, a, st) : launch_sweep_tree(f, a, nk, st);
@@ -1368,6 +1369,10 @@ int dual_grad_noalloc_impl(const tree_factors *fc, const double *x0, const doubl
                            double *x, double *u, hipStream_t st)
 {
     tree_factors *f = const_cast<tree_factors *>(fc);
+    if (f->cmap) {
+        set_error("dual_grad_noalloc: handles with a constraint map are not supported");
+        return STOTREE_ERR_ARG;
+    }
     const long long need = (long long)dual_grad_ws_rhs(f, nrhs) * (f->x_tot + f->u_tot);
     if (need > kScratchDoubles) {
         set_error("dual_grad_noalloc: the sweep workspace needs " + std::to_string(need * 8) +

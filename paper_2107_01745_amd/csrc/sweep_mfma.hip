@@ -635,7 +635,7 @@ hipError_t launch_sweep_any(const tree_factors *f, const SweepArgs &a, int nrhs,
     for (int d = 0; d < nrhs; ++d)
         for (int g = 0; g < f->ninst / kRhsPanel; ++g) {
             SweepArgs p = a;
-            p.inst = f->d_inst + (long long)g * kRhsPanel;
+            p.inst = f->d_inst_xu + (long long)g * kRhsPanel;
             // a panel is swept whole while any of its copies is unfinished
             p.done = a.done ? a.done + (long long)g * kRhsPanel * a.done_stride : nullptr;
             p.panel_done = a.done ? 1 : 0;

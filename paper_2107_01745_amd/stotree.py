@@ -35,24 +35,33 @@ class TreeDesc(C.Structure):
 
 
 class ProblemData(C.Structure):
-    _fields_ = [(n, _dp) for n in ("A", "B", "c", "Q", "R", "S", "q", "r", "P", "p",
-                                   "xmin", "xmax", "umin", "umax")]
+    _fields_ = ([(n, _dp) for n in ("A", "B", "c", "Q", "R", "S", "q", "r", "P", "p",
+                                    "xmin", "xmax", "umin", "umax")] +
+                [("nc", C.c_int32), ("ncN", C.c_int32)] +
+                [(n, _dp) for n in ("F", "G", "FN", "zmin", "zmax", "wgt", "hub")])
 
 
 class SolverOpts(C.Structure):
     _fields_ = [("lam", C.c_double), ("eps", C.c_double), ("eps_curv", C.c_double),
                 ("mem", C.c_int32), ("nu_max", C.c_int32), ("max_iter", C.c_int32),
-                ("check_every", C.c_int32)]
+                ("check_every", C.c_int32), ("backtrack", C.c_int32), ("div_window", C.c_int32),
+                ("bt_param", C.c_double), ("trace", C.c_void_p), ("trace_iters", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class SolverInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("sweeps_affine", C.c_int32), ("sweeps_hom", C.c_int32),
                 ("ls_trials", C.c_int32), ("lbfgs_push", C.c_int32), ("lbfgs_skip", C.c_int32),
                 ("status", C.c_int32), ("res_scaled_inf", C.c_double),
-                ("res_unscaled_inf", C.c_double), ("lam", C.c_double), ("seconds", C.c_double)]
+                ("res_unscaled_inf", C.c_double), ("lam", C.c_double), ("seconds", C.c_double),
+                ("backtracks", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+TRACE_COLS = 40   # solver trace row: lambda, ||R||_inf, accepted nu, nu_max, pairs, dphi[nu]...
+TRACE_PHI = 5
 
 
 EXPORTS = ("tree_factor", "tree_factor_batch", "tree_factors_free", "tree_dims",
@@ -61,7 +70,8 @@ EXPORTS = ("tree_factor", "tree_factor_batch", "tree_factors_free", "tree_dims",
            "warm_mlp_params", "warm_mlp_work_len", "warm_mlp_forward", "warm_mlp_backward",
            "warm_mse_grad", "warm_adam", "warm_features", "warm_scatter", "warm_targets",
            "dual_select", "tree_factor_shared", "sweep_schedule", "sweep_schedule_get", "sweep_autotune",
-           "sweep_graph_create", "sweep_graph_launch", "sweep_graph_free", "dual_grad_noalloc")
+           "sweep_graph_create", "sweep_graph_launch", "sweep_graph_free", "dual_grad_noalloc",
+           "gpad_solve")
 PHASES = ("bwd_chain", "bwd_stages", "fwd_stages", "fwd_chain")
 
 _lib = None
@@ -97,7 +107,7 @@ def lib():
             fn.restype = C.c_int
         L.dual_lipschitz.argtypes = [vp, C.c_int, _dp, vp]
         L.dual_lipschitz.restype = C.c_int
-        for fn in (L.minfbe_solve, L.nama_solve):
+        for fn in (L.minfbe_solve, L.nama_solve, L.gpad_solve):
             fn.argtypes = [vp, vp, C.POINTER(SolverOpts), vp, vp, vp, C.POINTER(SolverInfo), vp]
             fn.restype = C.c_int
         L.stotree_timing.argtypes = [C.c_int]
@@ -204,7 +214,11 @@ def _descs(prob, keep):
     td = TreeDesc(nx=prob.nx, nu=prob.nu, N=t.N, num_nodes=t.V,
                   stage_ptr=d(t.stage_ptr, np.int32), ancestor=d(t.anc, np.int32),
                   child_ptr=d(t.child_ptr, np.int32), prob=d(t.prob))
-    pd = ProblemData(**{n: d(getattr(prob, n)) for n, _ in ProblemData._fields_})
+    names = ("A", "B", "c", "Q", "R", "S", "q", "r", "P", "p", "xmin", "xmax", "umin", "umax",
+             "F", "G", "FN", "zmin", "zmax", "wgt", "hub")
+    pd = ProblemData(**{n: d(getattr(prob, n, None)) for n in names})
+    if getattr(prob, "F", None) is not None:
+        pd.nc, pd.ncN = int(prob.F.shape[0]), int(prob.FN.shape[0])
     return td, pd
 
 
@@ -363,9 +377,16 @@ def dual_lipschitz(tf: TreeFactors, iters: int = 100, stream=None):
     return L[0] if tf.ninst == 1 else list(L)
 
 
-def make_opts(lam=0.0, eps=1e-6, eps_curv=1e-12, mem=5, nu_max=10, max_iter=1000, check_every=1):
+def make_opts(lam=0.0, eps=1e-6, eps_curv=1e-12, mem=5, nu_max=10, max_iter=1000, check_every=1,
+              backtrack=0, bt_param=0.0, div_window=0, trace=None, trace_iters=0):
+    """solver_opts; trace: a float64 device tensor of [instances][trace_iters][TRACE_COLS]."""
+    tp = None
+    if trace is not None:
+        tp = _ptr(trace)
+        trace_iters = int(trace.shape[-2])
     return SolverOpts(lam=lam, eps=eps, eps_curv=eps_curv, mem=mem, nu_max=nu_max,
-                      max_iter=max_iter, check_every=check_every)
+                      max_iter=max_iter, check_every=check_every, backtrack=backtrack,
+                      div_window=div_window, bt_param=bt_param, trace=tp, trace_iters=trace_iters)
 
 
 def _solve(fn, tf, x0, y, x, u, opts, stream):
@@ -384,6 +405,12 @@ def minfbe_solve(tf, x0, y, x, u, opts=None, stream=None):
 def nama_solve(tf, x0, y, x, u, opts=None, stream=None):
     """Algorithm 2 (two-right-hand-side homogeneous sweep per iteration)."""
     return _solve(lib().nama_solve, tf, x0, y, x, u, opts or make_opts(), stream)
+
+
+def gpad_solve(tf, x0, y, x, u, opts=None, stream=None):
+    """Accelerated dual proximal gradient (one affine sweep per update); y
+    receives the last point evaluated."""
+    return _solve(lib().gpad_solve, tf, x0, y, x, u, opts or make_opts(), stream)
 
 
 def stotree_timing(enable: bool) -> None:
