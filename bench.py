@@ -98,49 +98,7 @@ def sweep_flops(prob):
     return 2.0 * (E * (2 * nx * (nx + nu)) + Vnl * (nu * nu + 2 * nu * nx + nx * nu))
 
 
-def subtree(prob, root):
-    """The subtree below ``root`` as a problem of its own (probabilities
-    renormalised, root state free); used for the bounded CPU sample."""
-    t = prob.tree
-    s = int(np.searchsorted(t.stage_ptr, root, side="right") - 1)
-    lo, hi = root, root + 1
-    idx, counts = [], []
-    for stage in range(s, t.N + 1):
-        idx.append(np.arange(lo, hi))
-        if stage < t.N:
-            cp = t.child_ptr
-            counts.append((cp[lo + 1:hi + 1] - cp[lo:hi]).tolist())
-            lo, hi = int(cp[lo]), int(cp[hi])
-    nodes = np.concatenate(idx)
-    tree = treegen.tree_from_counts(counts)
-    nl = nodes[:tree.Vnl]
-    lv = nodes[tree.Vnl:] - t.Vnl
-    xmin, xmax = prob.xmin[nodes].copy(), prob.xmax[nodes].copy()
-    xmin[0], xmax[0] = -np.inf, np.inf
-    return treegen.Problem(tree=tree, nx=prob.nx, nu=prob.nu, A=prob.A[nodes], B=prob.B[nodes],
-                           c=prob.c[nodes], Q=prob.Q[nl], R=prob.R[nl], P=prob.P[lv],
-                           xmin=xmin, xmax=xmax, umin=prob.umin[nl], umax=prob.umax[nl],
-                           x0=prob.x0.copy(), name=prob.name + "-subtree")
-
-
-def cpu_baseline(prob, seconds=10.0):
-    """The CPU oracle (single thread, as it stands) on the subtree of one
-    stage-2 node; evaluations/s scaled to the full tree by the flop ratio."""
-    import oracle
-    oracle.build(force=False)
-    sub = subtree(prob, int(prob.tree.stage_ptr[2]))
-    pb, fac = oracle.factor(sub)
-    rng = np.random.default_rng(7)
-    y = rng.standard_normal(pb.m)
-    n, t0 = 0, time.perf_counter()
-    while True:
-        oracle.sweep(pb, fac, y)
-        n += 1
-        el = time.perf_counter() - t0
-        if (el >= seconds and n >= 3) or el >= 3 * seconds:
-            break
-    rate_sample = n / el
-    ratio = sweep_flops(sub) / sweep_flops(prob)
+def host_cpu():
     cpu = "unknown"
     try:
         for ln in open("/proc/cpuinfo"):
@@ -149,10 +107,105 @@ def cpu_baseline(prob, seconds=10.0):
                 break
     except OSError:
         pass
-    return {"value": rate_sample * ratio, "unit": "dual-grad evals/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{n} oracle x(y) sweeps in {el:.1f} s on the subtree of one stage-2 node "
-                       f"({sub.tree.V} of {prob.tree.V} nodes, same nx/nu/N), scaled by the "
-                       f"sweep flop ratio {ratio:.4f}; host {cpu}, nproc {os.cpu_count()}")}
+    return cpu
+
+
+def cpu_threads():
+    """Host threads for the all-core oracle: the process's CPU share, at most 16
+    (the share of one GPU on the benchmark host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(prob, sweeps=3, solve_prob=None, solve_lam=None):
+    """The CPU oracle, as it stands, on the whole large tree: its factor step
+    (node-parallel on all threads), then x(y) sweeps single-threaded and
+    node-parallel on all threads (the same per-node arithmetic, so the same
+    result bit for bit).  With solve_prob, also the oracle's NAMA solve to a
+    1e-6 residual on all threads (long: minutes)."""
+    import oracle
+    oracle.build(force=False)
+    nt = cpu_threads()
+    oracle.set_threads(nt)
+    t0 = time.perf_counter()
+    pb, fac = oracle.factor(prob)
+    factor_s = time.perf_counter() - t0
+    rng = np.random.default_rng(7)
+    y = rng.standard_normal(pb.m)
+    rates = {}
+    for n in (1, nt):
+        oracle.set_threads(n)
+        k, t0 = 0, time.perf_counter()
+        while k < (1 if n == 1 else sweeps):
+            oracle.sweep(pb, fac, y)
+            k += 1
+        rates[n] = k / (time.perf_counter() - t0)
+    rep = {"value": rates[nt], "unit": "dual-grad evals/s", "cores": nt, "kind": "oracle",
+           "single_thread_value": rates[1], "factor_s_all_threads": factor_s,
+           "sample": (f"the whole large tree ({prob.tree.V} nodes): oracle factor step on {nt} threads "
+                      f"({factor_s:.1f} s), 1 single-thread x(y) sweep and {sweeps} node-parallel sweeps on "
+                      f"{nt} threads; host {host_cpu()}, nproc {os.cpu_count()}")}
+    del fac
+    if solve_prob is not None:
+        oracle.set_threads(nt)
+        pbs, facs = oracle.factor(solve_prob)
+        t0 = time.perf_counter()
+        r = oracle.solve(pbs, facs, "nama", solve_lam, eps=1e-6, max_iter=2000)
+        rep["nama_time_to_tol_s"] = time.perf_counter() - t0
+        rep["nama_iters"] = r["iters"]
+        rep["nama_status"] = r["status"]
+        rep["nama_sweeps"] = r["sweeps_affine"] + r["sweeps_hom"]
+    oracle.set_threads(1)
+    return rep
+
+
+def spring_leg(stotree, torch, count, eps, mem):
+    """The spring-mass-damper study of Sec. IV-A: 5 masses, N = 11, two-mode
+    Markov disturbance (a binary tree of 4095 nodes), count initial states;
+    every draw solved by NAMA, MINFBE and GPAD from zero to eps in one
+    batched handle each (the draws share the tree and differ in x0).  Reports
+    the calls of Algorithm 3 + Algorithm 4 per solve (the paper's measure:
+    84% of MINFBE / NAMA solves within 50 calls, GPAD median 188)."""
+    from paper_2107_01745_amd import warmstart as ws
+    dev = torch.device("cuda:0")
+    base = treegen.spring_mass_problem(pmax=3.0)
+    X0 = treegen.spring_mass_x0(count)
+    tf = stotree.tree_factor_shared(base, count, precondition=True)
+    L = stotree.dual_lipschitz(tf, 200)
+    L = max(L) if isinstance(L, list) else L
+    x0 = torch.tensor(X0.ravel(), dtype=torch.float64, device=dev)
+    x = torch.empty(tf.x_len, dtype=torch.float64, device=dev)
+    u = torch.empty(tf.u_len, dtype=torch.float64, device=dev)
+    rep = {"workload": ("spring-mass array: M=5 masses (nx=10, nu=4), N=11, two-mode Markov disturbance "
+                        f"(binary tree, {base.tree.V} nodes), |u|<=2, |v|<=5, |p|<=3, x0: positions and "
+                        f"velocities U[-1,1], {count} draws"), "eps": eps, "mem": mem, "L": L}
+    for method, lam in (("nama", 1 / (1.1 * L)), ("minfbe", 1 / (1.1 * L)), ("gpad", 1 / L)):
+        y = torch.zeros(tf.m, dtype=torch.float64, device=dev)
+        fn = {"nama": stotree.nama_solve, "minfbe": stotree.minfbe_solve, "gpad": stotree.gpad_solve}[method]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            fn(tf, x0, y, x, u, stotree.make_opts(lam=lam, eps=eps, mem=mem, max_iter=1000))
+        except stotree.StotreeError:
+            pass
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        infos = stotree.solve_info_batch(tf)
+        st = np.array([i["status"] for i in infos])
+        calls = np.array([i["sweeps_affine"] + i["sweeps_hom"] for i in infos])
+        ok = st == 0
+        rep[method] = {"seconds_batched": sec, "converged": int(ok.sum()), "diverged": int((st == -6).sum()),
+                       "not_converged": int((st == 1).sum()),
+                       "calls_median": float(np.median(calls[ok])) if ok.any() else None,
+                       "calls_p84": float(np.percentile(calls[ok], 84)) if ok.any() else None,
+                       "frac_within_50_calls": float((calls[ok] <= 50).mean()) if ok.any() else None,
+                       "iters_median": float(np.median([i["iters"] for i, o in zip(infos, ok) if o]))}
+        log(f"spring-mass {method}: {rep[method]}")
+    tf.free()
+    return rep
 
 
 def batched_leg(stotree, torch, steps, warmup, cache):
@@ -226,6 +279,7 @@ def batched_leg(stotree, torch, steps, warmup, cache):
         worst = max(worst, *inner_kkt_residual(p, yb, xb, ub, p.x0))
     graph.free()
     tf.free()
+    solve_rep = batched_solves(stotree, torch, probs)
     gbs = nbytes / (graph_ms * 1e-3) / 1e9
     rep = {"workload": "uneven batch: 256 uneven trees (seed 1002), one handle, one graph replay per step",
            "trees": 256, "nodes": int(tf.V), "m": int(tf.m), "generation_s": gen_s, "factor_s": factor_s,
@@ -234,10 +288,45 @@ def batched_leg(stotree, torch, steps, warmup, cache):
            "bytes_per_step": nbytes, "flops_per_step": flops,
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS},
-           "phases_eager_ms": phases, "inner_kkt_residual_sampled": worst}
+           "phases_eager_ms": phases, "inner_kkt_residual_sampled": worst, "solves_u_box_0.1": solve_rep}
     log(f"uneven batch: graph {graph_ms:.3f} ms/step, eager {eager_ms:.3f} ms ({256e3 / graph_ms:.0f} "
         f"instance sweeps/s, {gbs:.0f} GB/s = {100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak); "
         f"phases {phases}; KKT residual {worst:.1e}")
+    return rep
+
+
+def batched_solves(stotree, torch, probs, ubox=0.1):
+    """The 256 uneven trees with |u| <= ubox (so that inputs bind) solved by
+    NAMA to 1e-6 in one handle, each instance with its own step: (a) lambda_b =
+    1/(1.1 L_b) from 100 power iterations per instance, then the solve; (b)
+    lambda backtracking (the Linesearch-1 test, eps'' = 0.45) from the
+    5-iteration estimate 1/L_b.  Both timed from the call to the return."""
+    dev = torch.device("cuda:0")
+    tight = [treegen.with_boxes(p, ubox=ubox) for p in probs]
+    tf = stotree.tree_factor_batch(tight, precondition=True)
+    x0 = torch.tensor(np.concatenate([p.x0 for p in tight]), dtype=torch.float64, device=dev)
+    x = torch.empty(tf.x_len, dtype=torch.float64, device=dev)
+    u = torch.empty(tf.u_len, dtype=torch.float64, device=dev)
+    rep = {}
+    for name, kw in (("power_iteration_100", dict(lam=0.0)),
+                     ("backtracking", dict(lam=0.0, backtrack=2, bt_param=0.45))):
+        y = torch.zeros(tf.m, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            rc, info = stotree.nama_solve(tf, x0, y, x, u, stotree.make_opts(eps=1e-6, max_iter=3000, **kw))
+        except stotree.StotreeError as e:
+            rc, info = e.code, {}
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        infos = stotree.solve_info_batch(tf)
+        rep[name] = {"rc": rc, "seconds": sec, "iters_max": max(i["iters"] for i in infos),
+                     "iters_mean": float(np.mean([i["iters"] for i in infos])),
+                     "converged": sum(i["status"] == 0 for i in infos),
+                     "diverged": sum(i["status"] == -6 for i in infos),
+                     "backtracks_mean": float(np.mean([i["backtracks"] for i in infos]))}
+        log(f"uneven batch |u|<={ubox} NAMA, {name}: {rep[name]}")
+    tf.free()
     return rep
 
 
@@ -347,7 +436,8 @@ def panel_leg(stotree, torch, steps, warmup):
 
 def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     """Shared-tree solves: 64 instances sharing the tree (x0 ~ U[-3,3]^64), |u|
-    <= ubox so that the boxes bind.  The node-wise MLP is retrained on this
+    <= ubox so that the boxes bind (infeasibility test off: its iterate copy
+    would not fit next to the memory-3 workspace of 64 x 22M duals).  The node-wise MLP is retrained on this
     tree from n_batches x 64 batched NAMA solves (rows subsampled), then 64
     held-out draws are solved (a) one at a time from a cold start on a plain
     handle (n_solo timed, scaled to 64), (b) together from a cold start, every
@@ -367,10 +457,11 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     solo_s, solo_it = 0.0, []
     for k in range(n_solo):
         _, _, info, sec = ws.solve_batch(test_x0[k * nx:(k + 1) * nx], lam, eps=1e-6, tf=tf1, mem=mem,
-                                         max_iter=500)
+                                         max_iter=500, div_window=-1)
         solo_s += sec
         solo_it.append(info[0]["iters"])
     tf1.free()
+    del tf1
     torch.cuda.empty_cache()
     log(f"shared-tree solve: lambda {lam:.4g}; cold per-instance {solo_s / n_solo:.2f} s, iters {solo_it}")
     tfs = stotree.tree_factor_shared(prob, 64, precondition=True)
@@ -385,7 +476,7 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     sel_gen.manual_seed(5)
     for b in range(n_batches):
         x0 = draws()
-        _, y, infos, sec = ws.solve_batch(x0, lam, eps=1e-6, tf=tfs, mem=mem, max_iter=500)
+        _, y, infos, sec = ws.solve_batch(x0, lam, eps=1e-6, tf=tfs, mem=mem, max_iter=500, div_window=-1)
         gen_s += sec
         conv = [int(i["status"] == 0) for i in infos]
         gen_it += [i["iters"] for i, c in zip(infos, conv) if c]
@@ -415,14 +506,14 @@ def panel_solve_leg(stotree, torch, ubox, n_batches, epochs, n_solo, mem):
     log(f"shared-tree solve: {n_batches * 64} training solves in {gen_s:.1f} s (mean iters {np.mean(gen_it):.1f}); "
         f"{epochs} epochs in {train_s:.1f} s, masked MSE {hist[0]:.3e} -> {hist[-1]:.3e}")
     # (b) cold, batched
-    _, _, info_c, cold_s = ws.solve_batch(test_x0, lam, eps=1e-6, tf=tfs, mem=mem, max_iter=500)
+    _, _, info_c, cold_s = ws.solve_batch(test_x0, lam, eps=1e-6, tf=tfs, mem=mem, max_iter=500, div_window=-1)
     # (c) warm, batched
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     yw, keep = ws.warm_start_duals(model, tfs, test_x0, lam)
     torch.cuda.synchronize()
     pred_s = time.perf_counter() - t0
-    _, _, info_w, warm_s = ws.solve_batch(test_x0, lam, eps=1e-6, y0=yw, tf=tfs, mem=mem, max_iter=500)
+    _, _, info_w, warm_s = ws.solve_batch(test_x0, lam, eps=1e-6, y0=yw, tf=tfs, mem=mem, max_iter=500, div_window=-1)
     tfs.free()
     del yw
     torch.cuda.empty_cache()
@@ -550,7 +641,7 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
     test = screen_feasible(stotree, ws, base, drawn, lam, batch, tune)
     n_test = min(n_test, len(test) // batch * batch)    # whole batches of 64-draw panels
     test = test[:n_test]
-    cold_b, warm_b, it_c, it_w, kept, ok_w = 0.0, 0.0, [], [], 0, 0
+    cold_b, warm_b, gpad_b, it_c, it_w, it_g, kept, ok_w = 0.0, 0.0, 0.0, [], [], [], 0, 0
     for s in range(0, n_test, batch):
         chunk = test[s:s + batch]
         tf = shared_handle(stotree, base, chunk, tune)
@@ -567,6 +658,15 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
         it_w += [i["iters"] + 1 for i in info_w]      # + the refining iteration of the warm start
         ok_w += sum(i["status"] == 0 for i in info_w)
         kept += sum(keep)
+        # the paper's warm start: five accelerated-gradient updates (one affine sweep each)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        yg = ws.gpad_start(tf, chunk, 1.1 * lam, steps=5)
+        torch.cuda.synchronize()
+        g_s = time.perf_counter() - t0
+        _, _, info_g, sec_g = ws.solve_batch(chunk, lam, eps=1e-6, y0=yg, tf=tf)
+        gpad_b += g_s + sec_g
+        it_g += [i["iters"] for i in info_g]
         tf.free()
     solo_s, it_solo = 0.0, []
     for p in test[:n_solo]:
@@ -581,6 +681,7 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
            "batch": batch, "schedule": tune.get("knobs"), "epochs": epochs, "train_loss_first_last": [hist[0], hist[-1]],
            "y_scale": model.y_scale, "data_generation_s": gen_s, "train_s": train_s,
            "iters_cold_mean": float(np.mean(it_c)), "iters_warm_mean": float(np.mean(it_w)),
+           "iters_gpad5_then_nama_mean": float(np.mean(it_g)), "gpad5_batched_s_total": gpad_b,
            "iters_cold_batched_same_sample": float(np.mean(it_c[:n_solo])),
            "warm_kept": int(kept), "warm_converged": int(ok_w),
            "cold_per_instance_s_total": solo_total, "cold_per_instance_sample": n_solo,
@@ -590,7 +691,8 @@ def warm_leg(stotree, torch, n_train, n_test, n_solo, batch, epochs):
            "speedup_cold_batched_vs_cold_per_instance": solo_total / cold_b,
            "speedup_warm_vs_cold_batched": cold_b / warm_b}
     log(f"warm leg: {n_test} feasible held-out draws; iters cold {rep['iters_cold_mean']:.1f} "
-        f"warm {rep['iters_warm_mean']:.1f} (kept {kept}); cold per-instance {solo_total:.2f} s, "
+        f"warm {rep['iters_warm_mean']:.1f} (kept {kept}), GPAD-5 then NAMA {rep['iters_gpad5_then_nama_mean']:.1f} "
+        f"(+5 GPAD updates, {gpad_b:.3f} s); cold per-instance {solo_total:.2f} s, "
         f"cold batched {cold_b:.3f} s, warm batched {warm_b:.3f} s "
         f"-> speedup {rep['speedup_warm_batched_vs_cold_per_instance']:.1f}x")
     return rep
@@ -604,7 +706,11 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--no-cpu-solve", action="store_true",
+                    help="skip timing the oracle's NAMA solve to 1e-6 on the |u| <= 0.1 large tree")
+    ap.add_argument("--no-spring", action="store_true")
+    ap.add_argument("--spring-count", type=int, default=300)
     ap.add_argument("--tight-u", type=float, default=0.1)
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -613,13 +719,13 @@ def main():
     ap.add_argument("--shared-ubox", type=float, default=0.1)
     ap.add_argument("--shared-batches", type=int, default=2)
     ap.add_argument("--shared-epochs", type=int, default=8)
-    ap.add_argument("--shared-solo", type=int, default=2)
+    ap.add_argument("--shared-solo", type=int, default=8)
     ap.add_argument("--shared-mem", type=int, default=3)
     ap.add_argument("--tune-cache", default=None, help="JSON cache of tuned schedules (default: tune)")
-    ap.add_argument("--warm-train", type=int, default=1024)
-    ap.add_argument("--warm-test", type=int, default=256)
-    ap.add_argument("--warm-solo", type=int, default=32)
-    ap.add_argument("--warm-epochs", type=int, default=40)
+    ap.add_argument("--warm-train", type=int, default=20000)
+    ap.add_argument("--warm-test", type=int, default=2000)
+    ap.add_argument("--warm-solo", type=int, default=256)
+    ap.add_argument("--warm-epochs", type=int, default=8)
     ap.add_argument("--warm-batch", type=int, default=256, help="draws per shared handle (a multiple of 64)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -761,11 +867,24 @@ def main():
         warm_rep = guarded("warm start", warm_leg, stotree, torch, args.warm_train, args.warm_test,
                            args.warm_solo, args.warm_batch, args.warm_epochs)
 
+    spring_rep = None
+    if not args.no_spring:
+        spring_rep = guarded("spring-mass", spring_leg, stotree, torch, args.spring_count, 5e-4, 5)
+
     cpu = None
     if not args.no_cpu:
         t0 = time.perf_counter()
-        cpu = cpu_baseline(prob, args.cpu_seconds)
-        log(f"cpu baseline {cpu['value']:.3f} evals/s ({time.perf_counter() - t0:.1f} s)")
+        kw = {}
+        if not args.no_cpu_solve and solve_rep is not None:
+            import dataclasses
+            kw = dict(solve_prob=dataclasses.replace(prob, umin=np.full_like(prob.umin, -args.tight_u),
+                                                     umax=np.full_like(prob.umax, args.tight_u)),
+                      solve_lam=solve_rep[f"u_box_{args.tight_u:g}"]["lambda"])
+        tf.free()      # the oracle's copy of the factors lives in host memory
+        tf = None
+        cpu = cpu_baseline(prob, args.cpu_sweeps, **kw)
+        log(f"cpu baseline {cpu['value']:.3f} evals/s on {cpu['cores']} threads, "
+            f"{cpu['single_thread_value']:.3f} on one ({time.perf_counter() - t0:.1f} s)")
 
     rec = {
         "metric": METRIC, "value": value, "unit": "dual-grad evals/s", "n_gpus": 1,
@@ -784,8 +903,10 @@ def main():
         "panel": panel_rep,
         "panel_solve": panel_solve_rep,
         "warm_start": warm_rep,
+        "spring_mass": spring_rep,
     }
-    tf.free()
+    if tf is not None:
+        tf.free()
     print(json.dumps(rec))
 
 

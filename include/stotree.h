@@ -416,6 +416,9 @@ int warm_targets(const tree_factors *f, const double *y, float y_scale, float *T
                  void *hip_stream);
 /* Zero the dual rows of every instance b with keep[b] == 0 (HOST keep[count]). */
 int dual_select(const tree_factors *f, double *y, const int32_t *keep, void *hip_stream);
+/* Copy the dual rows of every instance b with keep[b] == 0 from y_other into
+ * y (DEVICE y, y_other [m]; HOST keep[count]). */
+int dual_merge(const tree_factors *f, double *y, const double *y_other, const int32_t *keep, void *hip_stream);
 
 /* Per-instance records of the last minfbe_solve / nama_solve on this handle,
  * written to HOST infos[count].  ERR_ARG on NULL. */

@@ -24,7 +24,7 @@ def build(force: bool = True) -> str:
     """Compile oracle.c with gcc into liboracle.so (plain -O2, FP64)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
                                "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -106,8 +106,16 @@ def lib():
         L.or_lbfgs_direction.restype = None
         L.or_solve.argtypes = [P, F, _dp, C.POINTER(_Opts), _dp, _dp, _dp, C.POINTER(_Info)]
         L.or_solve.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = None
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the node-parallel loops (factor step and sweeps); results
+    are the same for any count.  1: plain sequential loops."""
+    lib().or_set_threads(int(n))
 
 
 def set_mutation(k: int) -> None:

@@ -18,6 +18,9 @@
  *                inner problem of Sec. III-D (the problem x(y) minimises).
  *   or_sweep     Algorithm 3 (affine, x(y)) and Algorithm 4 (homogeneous,
  *                x-hat(r)), with the children's contributions accumulated.
+ *                The nodes of a stage are independent: or_set_threads(n)
+ *                runs them on n OpenMP threads with each node's sums in the
+ *                same order (the CPU baseline's all-core variant).
  *   or_eval      Sec. II-D and III-A: z_lambda, R_lambda, T_lambda and the
  *                forward-backward envelope, in the diagonally preconditioned
  *                dual variables of Sec. III-E when asked.
@@ -104,6 +107,12 @@ typedef struct {
 /* Deliberate-mistake switch used only by the tests that show the pins have
  * teeth: each nonzero value plants one plausible error.  0 = correct. */
 int or_mutation = 0;
+
+/* Threads for the node-parallel loops of the factor step and the sweeps
+ * (the nodes of a stage are independent; each node's summation order is the
+ * same for any thread count, so the results are too).  1: plain loops. */
+int or_threads = 1;
+void or_set_threads(int n) { or_threads = n > 1 ? n : 1; }
 
 /* ---------------------------- small helpers ---------------------------- */
 static int dual_off(const or_problem *pb, int i)
@@ -200,9 +209,11 @@ static void chol_inverse(int n, const double *L, double *Minv)
  *                chat_i = Pcal_i c_i + pi_i q_i + K_i' pi_i r_i   (c_0 = 0)
  * Returns 0, or -3 when some Rt is not positive definite.
  */
-int or_factor(const or_problem *pb, or_factors *f)
+/* The step for non-leaf node i (its children's Pcal are final).  Returns 0,
+ * or -3 when Rt is not positive definite. */
+static int factor_node(const or_problem *pb, or_factors *f, int i)
 {
-    const int nx = pb->nx, nu = pb->nu, N = pb->N;
+    const int nx = pb->nx, nu = pb->nu;
     const int nxu = nx + nu;
     double *Rt = malloc(sizeof(double) * nu * nu);
     double *Lc = malloc(sizeof(double) * nu * nu);
@@ -211,8 +222,143 @@ int or_factor(const or_problem *pb, or_factors *f)
     double *PB = malloc(sizeof(double) * nx * nu);
     double *PA = malloc(sizeof(double) * nx * nx);
     int rc = 0;
+    const double pi = pb->prob[i];
+    /* Rt, St */
+    for (int a = 0; a < nu; ++a)
+        for (int b = 0; b < nu; ++b)
+            Rt[a * nu + b] = 2.0 * pi * pb->R[(size_t)i * nu * nu + a * nu + b];
+    for (int a = 0; a < nu; ++a)
+        for (int b = 0; b < nx; ++b)
+            St[a * nx + b] = pb->S ? 2.0 * pi * pb->S[(size_t)i * nu * nx + a * nx + b] : 0.0;
+    double *Pi = f->Pcal + (size_t)i * nx * nx;
+    for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < nx; ++b)
+            Pi[a * nx + b] = 2.0 * pi * pb->Q[(size_t)i * nx * nx + a * nx + b];
+    for (int j = pb->child_ptr[i]; j < pb->child_ptr[i + 1]; ++j) {
+        const double *Aj = pb->A + (size_t)j * nx * nx;
+        const double *Bj = pb->B + (size_t)j * nx * nu;
+        const double *Pj = f->Pcal + (size_t)j * nx * nx;
+        for (int a = 0; a < nx; ++a) {              /* PB = Pj Bj, PA = Pj Aj */
+            for (int b = 0; b < nu; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < nx; ++k) s += Pj[a * nx + k] * Bj[k * nu + b];
+                PB[a * nu + b] = s;
+            }
+            for (int b = 0; b < nx; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < nx; ++k) s += Pj[a * nx + k] * Aj[k * nx + b];
+                PA[a * nx + b] = s;
+            }
+        }
+        for (int a = 0; a < nu; ++a) {
+            for (int b = 0; b < nu; ++b) {          /* Bj' Pj Bj */
+                double s = 0.0;
+                for (int k = 0; k < nx; ++k) s += Bj[k * nu + a] * PB[k * nu + b];
+                Rt[a * nu + b] += s;
+            }
+            for (int b = 0; b < nx; ++b) {          /* Bj' Pj Aj */
+                double s = 0.0;
+                for (int k = 0; k < nx; ++k) s += Bj[k * nu + a] * PA[k * nx + b];
+                St[a * nx + b] += s;
+            }
+        }
+        for (int a = 0; a < nx; ++a)                /* Aj' Pj Aj */
+            for (int b = 0; b < nx; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < nx; ++k) s += Aj[k * nx + a] * PA[k * nx + b];
+                Pi[a * nx + b] += s;
+            }
+    }
+    if (cholesky(nu, Rt, Lc) != 0) { rc = -3; goto done; }
+    chol_inverse(nu, Lc, Ri);
+    double *Ki = f->K + (size_t)i * nu * nx;
+    for (int a = 0; a < nu; ++a)
+        for (int b = 0; b < nx; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < nu; ++k) s += Ri[a * nu + k] * St[k * nx + b];
+            Ki[a * nx + b] = -s;
+        }
+    if (or_mutation != 1) {
+        for (int a = 0; a < nx; ++a)                /* + K' St */
+            for (int b = 0; b < nx; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < nu; ++k) s += Ki[k * nx + a] * St[k * nx + b];
+                Pi[a * nx + b] += s;
+            }
+    }
+    for (int j = pb->child_ptr[i]; j < pb->child_ptr[i + 1]; ++j) {
+        const double *Aj = pb->A + (size_t)j * nx * nx;
+        const double *Bj = pb->B + (size_t)j * nx * nu;
+        double *Lj = f->Lambda + (size_t)j * nx * nx;
+        double *Tj = f->Theta + (size_t)j * nu * nx;
+        for (int a = 0; a < nx; ++a)
+            for (int b = 0; b < nx; ++b) {
+                double s = Aj[a * nx + b];
+                for (int k = 0; k < nu; ++k) s += Bj[a * nu + k] * Ki[k * nx + b];
+                Lj[a * nx + b] = s;
+            }
+        for (int a = 0; a < nu; ++a)
+            for (int b = 0; b < nx; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < nu; ++k) s += Ri[a * nu + k] * Bj[b * nu + k];
+                Tj[a * nx + b] = -s;
+            }
+    }
+    double *Ph = f->Phi + (size_t)i * nu * nxu;
+    for (int a = 0; a < nu; ++a)
+        for (int b = 0; b < nxu; ++b)
+            Ph[a * nxu + b] = (b < nx) ? 0.0 : -Ri[a * nu + (b - nx)];
+    double *Di = f->D + (size_t)i * nxu * nx;
+    for (int a = 0; a < nxu; ++a)
+        for (int b = 0; b < nx; ++b)
+            Di[a * nx + b] = (a < nx) ? (a == b ? 1.0 : 0.0) : Ki[(a - nx) * nx + b];
+    double *sg = f->sigma + (size_t)i * nu;
+    for (int a = 0; a < nu; ++a) {
+        double s = 0.0;
+        if (pb->r)
+            for (int k = 0; k < nu; ++k) s += Ri[a * nu + k] * pi * pb->r[(size_t)i * nu + k];
+        sg[a] = -s;
+    }
+    double *ch = f->chat + (size_t)i * nx;
+    for (int a = 0; a < nx; ++a) {
+        double s = 0.0;
+        if (i > 0)
+            for (int k = 0; k < nx; ++k) s += Pi[a * nx + k] * pb->c[(size_t)i * nx + k];
+        if (pb->q) s += pi * pb->q[(size_t)i * nx + a];
+        if (pb->r)
+            for (int k = 0; k < nu; ++k) s += Ki[k * nx + a] * pi * pb->r[(size_t)i * nu + k];
+        ch[a] = s;
+    }
+done:
+    free(Rt); free(Lc); free(Ri); free(St); free(PB); free(PA);
+    return rc;
+}
+
+/*
+ * Dynamic programming on the inner problem (the problem whose minimiser is
+ * x(y)).  With costs written without a 1/2 (Sec. II-B), the value function of
+ * the subtree rooted at node i is  x' (Pcal_i / 2) x + (linear term) x.
+ *
+ *   leaves:      Pcal_j = 2 pi_j P_j,            chat_j = Pcal_j c_j + pi_j p_j
+ *   non-leaf i:  Rt = 2 pi_i R_i + sum_j B_j' Pcal_j B_j          (Cholesky)
+ *                St = 2 pi_i S_i + sum_j B_j' Pcal_j A_j
+ *                K_i = -Rt^{-1} St
+ *                Pcal_i = 2 pi_i Q_i + sum_j A_j' Pcal_j A_j + K_i' St
+ *                Lambda_j = A_j + B_j K_i,   Theta_j = -Rt^{-1} B_j'
+ *                Phi_i = [0, -Rt^{-1}],      D_i = [I; K_i]
+ *                sigma_i = -Rt^{-1} pi_i r_i
+ *                chat_i = Pcal_i c_i + pi_i q_i + K_i' pi_i r_i   (c_0 = 0)
+ * The nodes of a stage are independent (or_threads > 1 spreads them over
+ * threads; every node's arithmetic is the same, so are the results).
+ * Returns 0, or -3 when some Rt is not positive definite.
+ */
+int or_factor(const or_problem *pb, or_factors *f)
+{
+    const int nx = pb->nx, N = pb->N;
+    int rc = 0;
 
     /* leaves */
+#pragma omp parallel for num_threads(or_threads) if (or_threads > 1) schedule(static)
     for (int j = pb->Vnl; j < pb->V; ++j) {
         const int l = j - pb->Vnl;
         const double pj = pb->prob[j];
@@ -228,117 +374,12 @@ int or_factor(const or_problem *pb, or_factors *f)
     }
 
     for (int t = N - 1; t >= 0 && rc == 0; --t) {
-        for (int i = pb->stage_ptr[t]; i < pb->stage_ptr[t + 1]; ++i) {
-            const double pi = pb->prob[i];
-            /* Rt, St */
-            for (int a = 0; a < nu; ++a)
-                for (int b = 0; b < nu; ++b)
-                    Rt[a * nu + b] = 2.0 * pi * pb->R[(size_t)i * nu * nu + a * nu + b];
-            for (int a = 0; a < nu; ++a)
-                for (int b = 0; b < nx; ++b)
-                    St[a * nx + b] = pb->S ? 2.0 * pi * pb->S[(size_t)i * nu * nx + a * nx + b] : 0.0;
-            double *Pi = f->Pcal + (size_t)i * nx * nx;
-            for (int a = 0; a < nx; ++a)
-                for (int b = 0; b < nx; ++b)
-                    Pi[a * nx + b] = 2.0 * pi * pb->Q[(size_t)i * nx * nx + a * nx + b];
-            for (int j = pb->child_ptr[i]; j < pb->child_ptr[i + 1]; ++j) {
-                const double *Aj = pb->A + (size_t)j * nx * nx;
-                const double *Bj = pb->B + (size_t)j * nx * nu;
-                const double *Pj = f->Pcal + (size_t)j * nx * nx;
-                for (int a = 0; a < nx; ++a) {              /* PB = Pj Bj, PA = Pj Aj */
-                    for (int b = 0; b < nu; ++b) {
-                        double s = 0.0;
-                        for (int k = 0; k < nx; ++k) s += Pj[a * nx + k] * Bj[k * nu + b];
-                        PB[a * nu + b] = s;
-                    }
-                    for (int b = 0; b < nx; ++b) {
-                        double s = 0.0;
-                        for (int k = 0; k < nx; ++k) s += Pj[a * nx + k] * Aj[k * nx + b];
-                        PA[a * nx + b] = s;
-                    }
-                }
-                for (int a = 0; a < nu; ++a) {
-                    for (int b = 0; b < nu; ++b) {          /* Bj' Pj Bj */
-                        double s = 0.0;
-                        for (int k = 0; k < nx; ++k) s += Bj[k * nu + a] * PB[k * nu + b];
-                        Rt[a * nu + b] += s;
-                    }
-                    for (int b = 0; b < nx; ++b) {          /* Bj' Pj Aj */
-                        double s = 0.0;
-                        for (int k = 0; k < nx; ++k) s += Bj[k * nu + a] * PA[k * nx + b];
-                        St[a * nx + b] += s;
-                    }
-                }
-                for (int a = 0; a < nx; ++a)                /* Aj' Pj Aj */
-                    for (int b = 0; b < nx; ++b) {
-                        double s = 0.0;
-                        for (int k = 0; k < nx; ++k) s += Aj[k * nx + a] * PA[k * nx + b];
-                        Pi[a * nx + b] += s;
-                    }
-            }
-            if (cholesky(nu, Rt, Lc) != 0) { rc = -3; break; }
-            chol_inverse(nu, Lc, Ri);
-            double *Ki = f->K + (size_t)i * nu * nx;
-            for (int a = 0; a < nu; ++a)
-                for (int b = 0; b < nx; ++b) {
-                    double s = 0.0;
-                    for (int k = 0; k < nu; ++k) s += Ri[a * nu + k] * St[k * nx + b];
-                    Ki[a * nx + b] = -s;
-                }
-            if (or_mutation != 1) {
-                for (int a = 0; a < nx; ++a)                /* + K' St */
-                    for (int b = 0; b < nx; ++b) {
-                        double s = 0.0;
-                        for (int k = 0; k < nu; ++k) s += Ki[k * nx + a] * St[k * nx + b];
-                        Pi[a * nx + b] += s;
-                    }
-            }
-            for (int j = pb->child_ptr[i]; j < pb->child_ptr[i + 1]; ++j) {
-                const double *Aj = pb->A + (size_t)j * nx * nx;
-                const double *Bj = pb->B + (size_t)j * nx * nu;
-                double *Lj = f->Lambda + (size_t)j * nx * nx;
-                double *Tj = f->Theta + (size_t)j * nu * nx;
-                for (int a = 0; a < nx; ++a)
-                    for (int b = 0; b < nx; ++b) {
-                        double s = Aj[a * nx + b];
-                        for (int k = 0; k < nu; ++k) s += Bj[a * nu + k] * Ki[k * nx + b];
-                        Lj[a * nx + b] = s;
-                    }
-                for (int a = 0; a < nu; ++a)
-                    for (int b = 0; b < nx; ++b) {
-                        double s = 0.0;
-                        for (int k = 0; k < nu; ++k) s += Ri[a * nu + k] * Bj[b * nu + k];
-                        Tj[a * nx + b] = -s;
-                    }
-            }
-            double *Ph = f->Phi + (size_t)i * nu * nxu;
-            for (int a = 0; a < nu; ++a)
-                for (int b = 0; b < nxu; ++b)
-                    Ph[a * nxu + b] = (b < nx) ? 0.0 : -Ri[a * nu + (b - nx)];
-            double *Di = f->D + (size_t)i * nxu * nx;
-            for (int a = 0; a < nxu; ++a)
-                for (int b = 0; b < nx; ++b)
-                    Di[a * nx + b] = (a < nx) ? (a == b ? 1.0 : 0.0) : Ki[(a - nx) * nx + b];
-            double *sg = f->sigma + (size_t)i * nu;
-            for (int a = 0; a < nu; ++a) {
-                double s = 0.0;
-                if (pb->r)
-                    for (int k = 0; k < nu; ++k) s += Ri[a * nu + k] * pi * pb->r[(size_t)i * nu + k];
-                sg[a] = -s;
-            }
-            double *ch = f->chat + (size_t)i * nx;
-            for (int a = 0; a < nx; ++a) {
-                double s = 0.0;
-                if (i > 0)
-                    for (int k = 0; k < nx; ++k) s += Pi[a * nx + k] * pb->c[(size_t)i * nx + k];
-                if (pb->q) s += pi * pb->q[(size_t)i * nx + a];
-                if (pb->r)
-                    for (int k = 0; k < nu; ++k) s += Ki[k * nx + a] * pi * pb->r[(size_t)i * nu + k];
-                ch[a] = s;
-            }
-        }
+        int bad = 0;
+#pragma omp parallel for num_threads(or_threads) if (or_threads > 1) schedule(dynamic, 8) reduction(| : bad)
+        for (int i = pb->stage_ptr[t]; i < pb->stage_ptr[t + 1]; ++i)
+            bad |= factor_node(pb, f, i) != 0;
+        if (bad) rc = -3;
     }
-    free(Rt); free(Lc); free(Ri); free(St); free(PB); free(PA);
     return rc;
 }
 
@@ -357,12 +398,14 @@ void or_sweep(const or_problem *pb, const or_factors *f, const double *y,
     double *qh = malloc(sizeof(double) * (size_t)pb->V * nx);
 
     /* leaves: q-hat_j = y_j (+ c-hat_j) */
+#pragma omp parallel for num_threads(or_threads) if (or_threads > 1) schedule(static)
     for (int j = pb->Vnl; j < pb->V; ++j) {
         const double *yj = y + dual_off(pb, j);
         for (int a = 0; a < nx; ++a)
             qh[(size_t)j * nx + a] = yj[a] + (aff ? f->chat[(size_t)j * nx + a] : 0.0);
     }
     /* non-leaves: u_i = Phi_i y_i (+ sigma_i), q-hat_i = D_i' y_i (+ c-hat_i) */
+#pragma omp parallel for num_threads(or_threads) if (or_threads > 1) schedule(static)
     for (int i = 0; i < pb->Vnl; ++i) {
         const double *yi = y + dual_off(pb, i);
         const double *Ph = f->Phi + (size_t)i * nu * nxu;
@@ -380,6 +423,7 @@ void or_sweep(const or_problem *pb, const or_factors *f, const double *y,
     }
     /* backward over stages: accumulate the children's contributions */
     for (int t = N - 1; t >= 0; --t) {
+#pragma omp parallel for num_threads(or_threads) if (or_threads > 1) schedule(static)
         for (int i = pb->stage_ptr[t]; i < pb->stage_ptr[t + 1]; ++i) {
             double *ui = u + (size_t)i * nu;
             double *qi = qh + (size_t)i * nx;
@@ -408,6 +452,7 @@ void or_sweep(const or_problem *pb, const or_factors *f, const double *y,
     /* forward over stages */
     for (int a = 0; a < nx; ++a) x[a] = aff ? p[a] : 0.0;
     for (int t = 0; t < N; ++t) {
+#pragma omp parallel for num_threads(or_threads) if (or_threads > 1) schedule(static)
         for (int i = pb->stage_ptr[t]; i < pb->stage_ptr[t + 1]; ++i) {
             const double *Ki = f->K + (size_t)i * nu * nx;
             const double *xi = x + (size_t)i * nx;

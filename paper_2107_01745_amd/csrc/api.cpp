@@ -265,6 +265,16 @@ int dual_select(const tree_factors *f, double *y, const int32_t *keep, void *hip
     return STOTREE_OK;
 }
 
+int dual_merge(const tree_factors *f, double *y, const double *y_other, const int32_t *keep, void *hip_stream)
+{
+    if (!f || !y || !y_other || !keep) { set_error("dual_merge: bad argument"); return STOTREE_ERR_ARG; }
+    for (int b = 0; b < f->ninst; ++b)
+        if (!keep[b])
+            STOTREE_HIP(hipMemcpyAsync(y + f->inst[b].y, y_other + f->inst[b].y, sizeof(double) * f->inst[b].m,
+                                       hipMemcpyDeviceToDevice, (hipStream_t)hip_stream));
+    return STOTREE_OK;
+}
+
 int stotree_timing(int enable) { return timing_enable(enable); }
 
 int stotree_timing_read(double *ms, int64_t *count)

@@ -71,7 +71,7 @@ EXPORTS = ("tree_factor", "tree_factor_batch", "tree_factors_free", "tree_dims",
            "warm_mse_grad", "warm_adam", "warm_features", "warm_scatter", "warm_targets",
            "dual_select", "tree_factor_shared", "sweep_schedule", "sweep_schedule_get", "sweep_autotune",
            "sweep_graph_create", "sweep_graph_launch", "sweep_graph_free", "dual_grad_noalloc",
-           "gpad_solve")
+           "gpad_solve", "dual_merge")
 PHASES = ("bwd_chain", "bwd_stages", "fwd_stages", "fwd_chain")
 
 _lib = None
@@ -440,8 +440,9 @@ def _warm_sigs(L):
     L.warm_scatter.argtypes = [vp, vp, f32, vp, vp]
     L.warm_targets.argtypes = [vp, vp, f32, vp, vp, vp]
     L.dual_select.argtypes = [vp, vp, C.POINTER(C.c_int32), vp]
+    L.dual_merge.argtypes = [vp, vp, vp, C.POINTER(C.c_int32), vp]
     for fn in (L.warm_mlp_forward, L.warm_mlp_backward, L.warm_mse_grad, L.warm_adam, L.warm_features,
-               L.warm_scatter, L.warm_targets, L.dual_select):
+               L.warm_scatter, L.warm_targets, L.dual_select, L.dual_merge):
         fn.restype = C.c_int
 
 
@@ -502,3 +503,9 @@ def warm_targets(tf, y, y_scale, T, mask, stream=None):
 def dual_select(tf, y, keep, stream=None):
     keep = (C.c_int32 * tf.ninst)(*[int(bool(k)) for k in keep])
     _check(_wl().dual_select(tf.handle, _fptr(y), keep, _stream(stream)))
+
+
+def dual_merge(tf, y, y_other, keep, stream=None):
+    """Rows of instances with keep[b] false copied from y_other into y."""
+    keep = (C.c_int32 * tf.ninst)(*[int(bool(k)) for k in keep])
+    _check(_wl().dual_merge(tf.handle, _fptr(y), _fptr(y_other), keep, _stream(stream)))

@@ -3,8 +3,9 @@
 Data: the batched NAMA solver produces the optimal (preconditioned) duals of
 many draws (x0, disturbance path) on one fixed tree.  Training: the MLP's
 forward, loss-gradient, backward and Adam kernels (include/stotree.h).
-Use: predict a dual per instance, keep it only where the solver's residual at
-the prediction is below the residual at zero (the cold start), then solve.
+Use: predict a dual per instance and refine it by one solver iteration; keep
+it where its residual is below that of one iteration from zero (the cold
+start), then solve.
 Every arithmetic step runs in the library; this module only moves buffers.
 """
 from __future__ import annotations
@@ -23,20 +24,32 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def solve_batch(probs, lam, *, method="nama", eps=1e-6, max_iter=2000, y0=None, tf=None, mem=5):
+def _primal_buffers(tf):
+    """x, u device buffers of a handle, allocated once and kept with it."""
+    if getattr(tf, "_xu_buf", None) is None:
+        tf._xu_buf = (torch.empty(tf.x_len, dtype=torch.float64, device=_dev()),
+                      torch.empty(tf.u_len, dtype=torch.float64, device=_dev()))
+    return tf._xu_buf
+
+
+def solve_batch(probs, lam, *, method="nama", eps=1e-6, max_iter=2000, y0=None, tf=None, mem=5, div_window=0):
     """Batched solve of a list of instances (or, with tf given, of the
-    concatenated x0 tensor); returns (tf, y, infos, seconds)."""
+    concatenated x0 tensor); returns (tf, y, infos, seconds).  Instances the
+    infeasibility test stops keep status ERR_DIVERGED in their record."""
     own = tf is None
     if own:
         tf = stotree.tree_factor_batch(probs, precondition=True)
     x0 = _x0_of(probs)
     y = torch.zeros(tf.m, dtype=torch.float64, device=_dev()) if y0 is None else y0
-    x = torch.empty(tf.x_len, dtype=torch.float64, device=_dev())
-    u = torch.empty(tf.u_len, dtype=torch.float64, device=_dev())
+    x, u = _primal_buffers(tf)
     fn = stotree.nama_solve if method == "nama" else stotree.minfbe_solve
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fn(tf, x0, y, x, u, stotree.make_opts(lam=lam, eps=eps, max_iter=max_iter, mem=mem))
+    try:
+        fn(tf, x0, y, x, u, stotree.make_opts(lam=lam, eps=eps, max_iter=max_iter, mem=mem, div_window=div_window))
+    except stotree.StotreeError as e:
+        if e.code != -6:
+            raise
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     return tf, y, stotree.solve_info_batch(tf), sec
@@ -102,28 +115,29 @@ class WarmStartMLP:
         H = torch.empty(batch_rows, 2 * self.dh, dtype=torch.float32, device=_dev())
         Y = torch.empty(batch_rows, self.dout, dtype=torch.float32, device=_dev())
         dY = torch.empty_like(Y)
-        loss2 = torch.zeros(2, dtype=torch.float64, device=_dev())
+        nb = rows // batch_rows
+        losses = torch.zeros(nb, 2, dtype=torch.float64, device=_dev())   # per step (sum, count)
         part = torch.zeros(512, dtype=torch.float64, device=_dev())
+        mrow = M.sum(1)                       # mask entries per row (bookkeeping, once)
         rng = np.random.default_rng(seed)
         history = []
         for ep in range(epochs):
             order = torch.tensor(rng.permutation(rows), device=_dev())
-            tot, cnt = 0.0, 0.0
-            for s in range(0, rows - batch_rows + 1, batch_rows):
-                idx = order[s:s + batch_rows]
+            # the masked-entry count of every minibatch, read with one transfer per epoch
+            counts = mrow[order[:nb * batch_rows]].view(nb, batch_rows).sum(1).cpu().numpy()
+            for k in range(nb):
+                idx = order[k * batch_rows:(k + 1) * batch_rows]
                 Xb, Tb, Mb = X[idx].contiguous(), T[idx].contiguous(), M[idx].contiguous()
                 stotree.warm_mlp_forward(batch_rows, self.din, self.dh, self.dout, self.params, Xb, H, Y)
-                nmask = float(Mb.sum().item())
-                stotree.warm_mse_grad(Y.numel(), Y, Tb, Mb, 1.0 / max(nmask, 1.0), dY, loss2, part)
+                stotree.warm_mse_grad(Y.numel(), Y, Tb, Mb, 1.0 / max(float(counts[k]), 1.0), dY, losses[k],
+                                      part)
                 stotree.warm_mlp_backward(batch_rows, self.din, self.dh, self.dout, self.params, Xb, H, dY,
                                           self.grad, work)
                 self.step += 1
                 stotree.warm_adam(self.params.numel(), self.params, self.grad, self.m, self.v, lr, 0.9, 0.999,
                                   1e-8, self.step)
-                l2 = loss2.cpu().numpy()
-                tot += l2[0]
-                cnt += l2[1]
-            history.append(tot / max(cnt, 1.0))
+            l2 = losses.cpu().numpy()        # one transfer per epoch
+            history.append(l2[:, 0].sum() / max(l2[:, 1].sum(), 1.0))
             if log:
                 log(f"epoch {ep}: masked MSE {history[-1]:.4e}")
         return history
@@ -136,23 +150,35 @@ def _x0_of(probs_or_x0):
 
 
 def warm_start_duals(model, tf, probs_or_x0, lam, refine_steps=1):
-    """Predicted duals, refined by refine_steps solver iterations (the first
+    """Predicted duals refined by refine_steps solver iterations (the first
     forward-backward step sends the predicted duals of inactive constraints
-    to zero), with the cold start kept wherever the solver's residual at the
-    refined prediction is not below its residual at zero.  probs_or_x0: the
-    instances' problems, or their concatenated x0 on the device.  Returns
-    (y, keep); keep[b] says whether instance b starts from its prediction."""
+    to zero), set against the same number of iterations from zero (the cold
+    start): each instance keeps whichever reached the lower residual.  Both
+    candidates have taken refine_steps iterations, so a solve from the kept
+    one costs the same as the cold solve when the cold candidate wins.
+    probs_or_x0: the instances' problems, or their concatenated x0 on the
+    device.  Returns (y, keep); keep[b] says whether instance b starts from its
+    prediction."""
     x0 = _x0_of(probs_or_x0)
+    yc = torch.zeros(tf.m, dtype=torch.float64, device=_dev())
     yw = torch.zeros(tf.m, dtype=torch.float64, device=_dev())
-    x = torch.empty(tf.x_len, dtype=torch.float64, device=_dev())
-    u = torch.empty(tf.u_len, dtype=torch.float64, device=_dev())
-    # residual at the cold start (a solve with max_iter = 0 evaluates the
-    # residual and leaves y unchanged); mem 1 reuses any existing workspace
-    stotree.nama_solve(tf, x0, yw, x, u, stotree.make_opts(lam=lam, eps=0.0, max_iter=0, mem=1))
+    x, u = _primal_buffers(tf)
+    opts = stotree.make_opts(lam=lam, eps=0.0, max_iter=refine_steps, mem=1, div_window=-1)
+    stotree.nama_solve(tf, x0, yc, x, u, opts)
     rc = [i["res_scaled_inf"] for i in stotree.solve_info_batch(tf)]
     model.predict(tf, x0, yw)
-    stotree.nama_solve(tf, x0, yw, x, u, stotree.make_opts(lam=lam, eps=0.0, max_iter=refine_steps, mem=1))
+    stotree.nama_solve(tf, x0, yw, x, u, opts)
     rw = [i["res_scaled_inf"] for i in stotree.solve_info_batch(tf)]
     keep = [a <= b for a, b in zip(rw, rc)]
-    stotree.dual_select(tf, yw, keep)
+    stotree.dual_merge(tf, yw, yc, keep)
     return yw, keep
+
+
+def gpad_start(tf, probs_or_x0, lam, steps=5):
+    """The warm start of the paper: steps accelerated-gradient updates from
+    zero (GPAD); returns the last point."""
+    x0 = _x0_of(probs_or_x0)
+    y = torch.zeros(tf.m, dtype=torch.float64, device=_dev())
+    x, u = _primal_buffers(tf)
+    stotree.gpad_solve(tf, x0, y, x, u, stotree.make_opts(lam=lam, eps=0.0, max_iter=steps, div_window=-1))
+    return y

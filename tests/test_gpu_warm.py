@@ -127,11 +127,15 @@ def test_features_and_dual_maps_match_oracle(st):
     tf.free()
 
 
-def test_training_reduces_loss_and_warm_start_helps(st):
+def test_training_reduces_loss_and_warm_start_keeps_tolerance(st):
     """Train on solver-generated duals of a small tree; on held-out draws the
-    warm start keeps the tolerance, an instance whose prediction the residual
-    check rejects follows exactly the cold path, and the iterations with and
-    without the network are reported (the refining iteration counted)."""
+    warm start keeps the tolerance, a kept prediction has (after its one
+    refining iteration) a residual no larger than one iteration from zero, an
+    instance whose prediction is rejected starts from that cold iterate
+    itself, and the iterations with and without the network are reported
+    (the refining iteration counted).  No gain in iterations is asserted: on
+    these trees the node-wise network does not predict the dual well enough
+    for one (the full-size measurement is the benchmark's warm-start leg)."""
     from paper_2107_01745_amd import warmstart as ws
     base = small_base()
     pb, fac = oracle.factor(base)
@@ -153,12 +157,27 @@ def test_training_reduces_loss_and_warm_start_helps(st):
     tf_c, _, info_c, _ = ws.solve_batch(test, lam, eps=1e-8)
     tf_c.free()
     tf_w = st.tree_factor_batch(test, precondition=True)
+    x0t = torch.tensor(np.concatenate([p.x0 for p in test]), device="cuda:0")
+    yc = torch.zeros(tf_w.m, dtype=torch.float64, device="cuda:0")
+    xs = torch.empty(tf_w.x_len, dtype=torch.float64, device="cuda:0")
+    us = torch.empty(tf_w.u_len, dtype=torch.float64, device="cuda:0")
+    st.nama_solve(tf_w, x0t, yc, xs, us, st.make_opts(lam=lam, eps=0.0, max_iter=1, mem=1, div_window=-1))
+    rc = [i["res_scaled_inf"] for i in st.solve_info_batch(tf_w)]
     yw, keep = ws.warm_start_duals(model, tf_w, test, lam)
+    ywh, ych = yw.cpu().numpy(), yc.cpu().numpy()
+    for b, k in enumerate(keep):
+        d = tf_w.instances[b]
+        seg = slice(d["y_off"], d["y_off"] + d["m"])
+        if not k:
+            assert np.array_equal(ywh[seg], ych[seg]), b
+    # the kept start's residual (one iteration from it) is no larger than the cold one's
+    yk = yw.clone()
+    st.nama_solve(tf_w, x0t, yk, xs, us, st.make_opts(lam=lam, eps=0.0, max_iter=0, mem=1, div_window=-1))
+    rk = [i["res_scaled_inf"] for i in st.solve_info_batch(tf_w)]
+    for b, k in enumerate(keep):
+        assert rk[b] <= rc[b] * (1 + 1e-12), (b, rk[b], rc[b])
     _, _, info_w, _ = ws.solve_batch(test, lam, eps=1e-8, y0=yw, tf=tf_w)
     assert all(i["status"] == 0 and i["res_scaled_inf"] <= 1e-8 for i in info_w)
-    for b, k in enumerate(keep):
-        if not k:
-            assert info_w[b]["iters"] == info_c[b]["iters"], b
     it_cold = np.mean([i["iters"] for i in info_c])
     it_warm = np.mean([i["iters"] + 1 for i in info_w])   # + the refining iteration
     print(f"iterations cold {it_cold:.1f}, warm {it_warm:.1f}, kept {sum(keep)}/{len(keep)}", flush=True)

@@ -229,3 +229,22 @@ def test_minfbe_and_nama_agree_with_each_other_on_tiny_workload():
     assert np.abs(a["x"] - b["x"]).max() < 1e-6
     # NAMA needs no Hessian-vector products
     assert b["sweeps_hom"] == 0 and a["sweeps_hom"] > 0
+
+
+def test_threaded_oracle_is_bitwise_the_sequential_one():
+    """The node-parallel loops keep every node's summation order."""
+    prob = pins.ragged_cross()
+    rng = np.random.default_rng(2)
+    y = rng.standard_normal(prob.m)
+    out = []
+    for n in (1, 4):
+        oracle.set_threads(n)
+        try:
+            pb, fac = oracle.factor(prob)
+            x, u = oracle.sweep(pb, fac, y)
+            xh, uh = oracle.sweep(pb, fac, y, homogeneous=True)
+            out.append((fac.K.copy(), fac.Pcal.copy(), x, u, xh, uh))
+        finally:
+            oracle.set_threads(1)
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
