@@ -25,7 +25,10 @@
  *                forward-backward envelope, in the diagonally preconditioned
  *                dual variables of Sec. III-E when asked.
  *   or_solve     Algorithm 1 (dual MINFBE) and Algorithm 2 (NAMA), with the
- *                FBE evaluated directly (one affine sweep per trial step).
+ *                FBE evaluated directly (one affine sweep per trial step),
+ *                the two lambda-backtracking tests of Sec. III-B, and a
+ *                primal-infeasibility certificate; GPAD (the accelerated dual
+ *                proximal gradient method of Sec. III-F / IV-A) as method 2.
  *
  * Readings where the paper is silent or garbled are listed in the design
  * notes; the main ones appear next to the code they affect.
@@ -33,9 +36,12 @@
  * Parity pins (the tests) tie each function to the mathematics: dense KKT
  * solves of the inner problem, central differences of the dual function,
  * the dense Hessian's symmetry and spectrum, the FBE's conjugate form, the
- * secant identity of L-BFGS, and a dense interior-point solution of the whole
- * problem.  The iteration trajectory itself has no printed trace in the paper:
- * parity unpinned for the trajectory (only its end point is pinned).
+ * secant identity of L-BFGS, a dense interior-point solution of the whole
+ * problem, textbook FISTA on the dense dual (GPAD's whole trajectory), its
+ * O(1/k^2) bound, the descent lemma (backtracking), scalar minimisation of
+ * each soft row's prox, and an LP that proves infeasibility.  The MINFBE and
+ * NAMA trajectories have no printed trace in the paper: parity unpinned for
+ * those trajectories (their end point is pinned).
  */
 #include <math.h>
 #include <stdlib.h>
