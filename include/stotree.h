@@ -269,7 +269,14 @@ int dual_grad_noalloc(const tree_factors *f, const double *x0, const double *y, 
  *            (default); 1 the backward stages in one launch in which each
  *            node is taken up by the workgroup that finishes its last child;
  *            2 one launch per stage, the nodes of instances with nx + nu <= 64
- *            walked by lane groups as the chains are;
+ *            walked by lane groups as the chains are; 3 (4) each instance's
+ *            first stages of at most 64 (256) nodes in one launch per
+ *            direction, a workgroup per node that waits on device-wide
+ *            counters for its children (backward) or its parent (forward),
+ *            the other stages one launch each.  A wait in modes 3 and 4 that
+ *            has not ended after about a second gives up: that sweep and
+ *            every later one of the handle then write NaN to the nodes of
+ *            those stages, until the schedule is set again;
  *   knobs[4] shared handles whose copies form whole panels of 64: the fewest
  *            unfinished copies for which a sweep runs as panels on the
  *            matrix cores (a panel whose copies have all finished is

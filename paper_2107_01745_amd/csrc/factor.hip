@@ -400,6 +400,9 @@ void free_tree(tree_factors *f)
         if (cp.items) (void)hipFree(cp.items);
     for (auto &lv : f->levels) free_level(lv);
     for (auto &lv : f->panel_levels) free_level(lv);
+    for (auto &lv : f->rest_levels) free_level(lv);
+    free_level(f->fused_bwd);
+    free_level(f->fused_fwd);
     for (void *p : {(void *)f->panel_chain_items, (void *)f->trunk_entry.items, (void *)f->trunk_cnt,
                     (void *)f->Pcal})
         if (p) (void)hipFree(p);
@@ -537,6 +540,69 @@ int build_schedule(tree_factors *f)
             STOTREE_HIP(hipMemcpy(pl.items, items.data(), sizeof(Item) * pl.count, hipMemcpyHostToDevice));
         }
     }
+    // trunk modes 3 and 4: each instance's first stages with at most
+    // fuse_limit nodes run in one launch per direction (deepest stage first
+    // backward, root first forward); the other stages above s* one launch each
+    free_level(f->fused_bwd);
+    free_level(f->fused_fwd);
+    f->fused_bwd = LevelPlan{};
+    f->fused_fwd = LevelPlan{};
+    for (auto &lv : f->rest_levels) free_level(lv);
+    f->rest_levels.clear();
+    if (f->trunk_fused >= 3) {
+        const int lim = fuse_limit(f->trunk_fused);
+        std::vector<int> depth(f->ninst, 0);
+        int dmax = 0;
+        for (int b = 0; b < f->ninst; ++b) {
+            const InstDesc &I = f->inst[b];
+            const int *sp = f->sp_pool.data() + I.sp;
+            int d = 0;
+            while (d < I.sstar && sp[d + 1] - sp[d] <= lim) ++d;
+            depth[b] = d;
+            dmax = std::max(dmax, d);
+        }
+        std::vector<std::vector<Item>> by_stage(dmax);
+        int widest = 1;
+        for (int t = 0; t < dmax; ++t) {
+            for (int b = 0; b < f->ninst; ++b) {
+                if (t >= depth[b]) continue;
+                const int *sp = f->sp_pool.data() + f->inst[b].sp;
+                const int flag = t + 1 < depth[b] ? kFusedKids : 0;
+                for (int i = sp[t]; i < sp[t + 1]; ++i) by_stage[t].push_back({b, i | flag});
+            }
+            widest = std::max(widest, (int)by_stage[t].size());
+        }
+        std::vector<Item> bwd, fwd;
+        for (int t = dmax - 1; t >= 0; --t) bwd.insert(bwd.end(), by_stage[t].begin(), by_stage[t].end());
+        for (int t = 0; t < dmax; ++t) fwd.insert(fwd.end(), by_stage[t].begin(), by_stage[t].end());
+        for (int dir = 0; dir < 2; ++dir) {
+            LevelPlan &lv = dir == 0 ? f->fused_bwd : f->fused_fwd;
+            const std::vector<Item> &v = dir == 0 ? bwd : fwd;
+            lv.t = -1;
+            lv.count = (int)v.size();
+            lv.nw = trunk_waves(widest, 2, max_ldM, f->trunk_cap);
+            if (v.empty()) continue;
+            STOTREE_HIP(hipMalloc(&lv.items, sizeof(Item) * v.size()));
+            STOTREE_HIP(hipMemcpy(lv.items, v.data(), sizeof(Item) * v.size(), hipMemcpyHostToDevice));
+        }
+        for (int t = 0; t < max_sstar; ++t) {
+            std::vector<Item> items;
+            for (int b = 0; b < f->ninst; ++b) {
+                const InstDesc &I = f->inst[b];
+                if (t < depth[b] || t >= I.sstar) continue;
+                const int *sp = f->sp_pool.data() + I.sp;
+                for (int i = sp[t]; i < sp[t + 1]; ++i) items.push_back({b, i});
+            }
+            if (items.empty()) continue;
+            LevelPlan lv{};
+            lv.t = t;
+            lv.count = (int)items.size();
+            lv.nw = trunk_waves(lv.count, 2, max_ldM, f->trunk_cap);
+            STOTREE_HIP(hipMalloc(&lv.items, sizeof(Item) * items.size()));
+            f->rest_levels.push_back(lv);
+            STOTREE_HIP(hipMemcpy(lv.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+        }
+    }
     // one-launch backward trunk: its entry nodes and the per-node counters
     if (f->trunk_entry.items) { (void)hipFree(f->trunk_entry.items); f->trunk_entry.items = nullptr; }
     f->trunk_entry.count = 0;
@@ -555,10 +621,9 @@ int build_schedule(tree_factors *f)
             STOTREE_HIP(hipMalloc(&f->trunk_entry.items, sizeof(Item) * entry.size()));
             STOTREE_HIP(hipMemcpy(f->trunk_entry.items, entry.data(), sizeof(Item) * entry.size(),
                                   hipMemcpyHostToDevice));
-            if (!f->trunk_cnt) {
-                STOTREE_HIP(hipMalloc(&f->trunk_cnt, sizeof(int) * (size_t)f->V_tot));
-                STOTREE_HIP(hipMemset(f->trunk_cnt, 0, sizeof(int) * (size_t)f->V_tot));
-            }
+            if (!f->trunk_cnt) STOTREE_HIP(hipMalloc(&f->trunk_cnt, sizeof(int) * (size_t)(f->V_tot + 1)));
+            // counters, flags and the fused launches' error word start at zero
+            STOTREE_HIP(hipMemset(f->trunk_cnt, 0, sizeof(int) * (size_t)(f->V_tot + 1)));
         }
     }
     return STOTREE_OK;

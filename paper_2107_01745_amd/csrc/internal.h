@@ -150,10 +150,15 @@ struct tree_factors {
     int chain_order = 1;                    // 1: longest chains first, 0: instance order
     int group_min = 8;                      // smallest lane group used for chains
     int trunk_fused = 0;                    // stages above s*: 0 per-stage launches, 1 one backward
-                                            // launch, 2 per-stage launches with lane groups
+                                            // launch, 2 per-stage launches with lane groups, 3 / 4
+                                            // the first stages (at most kFuseNodes[mode] nodes each)
+                                            // in one launch per direction, the rest per stage
     int panel_min = 16;                     // shared handles: fewest unfinished copies swept as panels
     stotree::LevelPlan trunk_entry{};       // nodes of stage s*-1 of every instance
-    int *trunk_cnt = nullptr;               // per node (node0-indexed): children finished
+    int *trunk_cnt = nullptr;               // per node (node0-indexed): children finished / parent
+                                            // done; [V_tot]: error word of the fused launches
+    stotree::LevelPlan fused_bwd{}, fused_fwd{};  // trunk modes 3, 4: the first stages' nodes
+    std::vector<stotree::LevelPlan> rest_levels;  // trunk modes 3, 4: the other stages above s*
     long long schedule_epoch = 0;           // bumped whenever the work lists are rebuilt
     // sweep workspace (grows with nrhs)
     double *qhat = nullptr, *kbuf = nullptr;
@@ -208,6 +213,9 @@ int dual_grad_noalloc_impl(const tree_factors *f, const double *x0, const double
 
 // schedule.hip
 constexpr int kKnobs = 5;            // group_min, chain_order, trunk_cap, trunk_fused, panel_min
+constexpr int kFusedKids = 1 << 30;  // Item.idx flag of the fused trunk lists: the children are listed too
+// trunk modes 3 and 4: most nodes a stage may have to run in the fused launch
+inline int fuse_limit(int mode) { return mode == 3 ? 64 : mode == 4 ? 256 : 0; }
 int set_schedule(tree_factors *f, const int32_t *knobs);
 int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms_out, hipStream_t st);
 int graph_create(tree_factors *f, const double *x0, const double *y, int homogeneous, int nrhs, double *x,

@@ -6,7 +6,8 @@
 //   group_min   smallest lane group that walks one chain below s*;
 //   chain_order costliest wavefront items first, or instance order;
 //   trunk_cap   cap on the wavefronts that share one node above s*;
-//   trunk_fused the launch form of the stages above s*;
+//   trunk_fused the launch form of the stages above s* (per stage, one
+//               backward launch, lane groups, or the first stages fused);
 //   panel_min   on a shared handle, the fewest unfinished copies that are
 //               still swept as panels on the matrix cores (fewer: the
 //               lane-group sweeps, which skip finished copies one by one).
@@ -40,7 +41,7 @@ bool valid_knobs(const int32_t *k)
     const bool g = k[0] == 8 || k[0] == 16 || k[0] == 32 || k[0] == 64;
     const bool o = k[1] == 0 || k[1] == 1;
     const bool t = k[2] == 1 || k[2] == 2 || k[2] == 4 || k[2] == 8 || k[2] == 16;
-    const bool m = k[3] == 0 || k[3] == 1 || k[3] == 2;
+    const bool m = k[3] >= 0 && k[3] <= 4;
     const bool p = k[4] >= 0 && k[4] <= kPanelMinMax;
     return g && o && t && m && p;
 }
@@ -60,7 +61,7 @@ int set_schedule(tree_factors *f, const int32_t *knobs)
 {
     if (!valid_knobs(knobs)) {
         set_error("sweep_schedule: knobs must be group in {8,16,32,64}, order in {0,1}, cap in {1,2,4,8,16}, "
-                  "trunk mode in {0,1,2}, panel minimum in [0, 2^24]");
+                  "trunk mode in {0,...,4}, panel minimum in [0, 2^24]");
         return STOTREE_ERR_ARG;
     }
     // the old work lists may still be read by queued sweeps
@@ -118,7 +119,7 @@ int autotune(tree_factors *f, int nrhs, int reps, int32_t *knobs_out, double *ms
     if (shared) best[4] = kPanelMinMax;    // lane-group route while its knobs are tuned
     double best_ms = 0.0;
     rc = measure(best, &best_ms);
-    const std::vector<std::vector<int>> values = {{8, 16, 32, 64}, {1, 0}, {16, 8, 4, 2}, {0, 2, 1}};
+    const std::vector<std::vector<int>> values = {{8, 16, 32, 64}, {1, 0}, {16, 8, 4, 2}, {0, 2, 1, 3, 4}};
     for (int knob = 0; knob < kKnobs - 1 && !rc; ++knob) {
         const int32_t start = best[knob];
         for (int v : values[knob]) {

@@ -867,6 +867,447 @@ __global__ void __launch_bounds__(kWave *NW) fwd_trunk_kernel(SweepArgs a)
     }
 }
 
+// ---- the first stages above s* in one launch per direction ----
+//
+// The nodes of an instance's first stages (each with at most a set number of
+// nodes) form one work list per direction: deepest stage first backward, root
+// first forward, so a workgroup is dispatched only after every workgroup it
+// waits for (workgroups of a launch are dispatched in order; a waiting one
+// never holds back one it waits for).  A workgroup requests every row its
+// node needs first, then waits for its inputs: backward until each child has
+// counted itself in at the node's counter, forward until the parent has
+// raised the node's flag; it then clears that counter or flag, so all are
+// zero again when the launch ends.  The per-edge products are formed on the
+// child's side of each hand-off (backward, the child sends [A_j B_j]' qhat_j;
+// forward, the child forms its own x_j from its parent's x and u), so after a
+// wait a node reads one short vector per child and multiplies rows it already
+// holds.  Hand-offs are device-wide (the producing XCD's L2 is written back):
+// every thread completes its own stores before the barrier that precedes the
+// count, and thread 0 then releases them all device-wide with the count; on
+// the waiting side thread 0 acquires device-wide (the CU's caches are
+// invalidated) before the barrier that lets the workgroup read.  One
+// device-scope fence per node and side: a fence on every thread cost more
+// than the launches it replaced.  A wait gives up after kSpinLimit polls
+// (about a second; a correct launch waits microseconds) and records the
+// failure in the error word; from then on the fused launches of the handle
+// write NaN to their outputs and wait no more, until the schedule is rebuilt
+// (which clears the word and the counters).
+constexpr int kSpinLimit = 1 << 20;
+
+struct FusedWait {
+    int *c;        // counter or flag to wait for (null: inputs come from earlier launches)
+    int target;    // value it must reach
+    int *err;      // the handle's error word
+    int bad;       // the error word as read when the workgroup started
+    int *poison;   // LDS: this workgroup writes NaN (thread 0's decision; the node's
+                   // later barriers publish it)
+    __device__ void operator()() const
+    {
+        if (!c) {
+            if (threadIdx.x == 0) *poison = bad;
+            return;
+        }
+        if (threadIdx.x == 0) {
+            int b = bad;
+            if (!b) {
+                int spins = 0;
+                while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins >= kSpinLimit) {
+                        b = 1;
+                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                }
+                __hip_atomic_store(c, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            *poison = b;
+        }
+        __syncthreads();
+    }
+};
+
+// Every thread waits until its stores of this node have reached the L2 (the
+// workgroup-scope fence alone does not wait for them on this chip), then,
+// after the barrier, thread 0 releases them all device-wide with the count or
+// flag stores that publish them.
+__device__ __forceinline__ void release_node()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): every vector memory access of this wave done
+    __syncthreads();
+}
+
+// Backward step of a node of the fused list.  A node whose children are in
+// the list too (kids) does not form their products: each child j has sent
+// p_j = [A_j B_j]' qhat_j, written where the forward pass later writes x_j and
+// u_j (nothing reads those outputs before), so after its wait the node only
+// adds the p_j to its own terms.  A node whose parent is in the list (i != 0)
+// then sends its own p_i.  Nodes of the deepest listed stage form their
+// children's products as the per-stage kernel does.  Every row this needs
+// is requested before the wait.
+template <int NRHS, int CH, int NW>
+__device__ void bwd_fused_node(const SweepArgs &a, const InstDesc &I, int i, int w, int lane, bool kids,
+                               const FusedWait &wait)
+{
+    const int nx = I.nx, nu = I.nu, W = nx + nu, ldq = I.ldx, ldM = I.ldM;
+    const int *cp = a.cp + I.cp;
+    constexpr int kDepth = CH == 1 && NW <= 8 ? 2 : 1;
+    const int CB = child_batch(NRHS, ldq), ldv = CB * ldq;
+    extern __shared__ double lds[];
+    double *qs = lds;                          // [NRHS][ldv]: children's qhat, later this node's qhat
+    double *red = qs + NRHS * ldv;             // [NW][NRHS][ldM]
+    double *as = red + NW * NRHS * ldM;        // [NRHS][ldM]: [sum A'q ; g_i] plus the node's own terms
+    const int j0 = cp[i], nch = cp[i + 1] - j0;
+    const bool up = i != 0;
+    const int pr0 = nx * w / NW, pr1 = nx * (w + 1) / NW;
+    RowStream<CH> rk, rq, pm;
+    {
+        const int R = 2 * nu, r0 = R * w / NW, r1 = R * (w + 1) / NW;
+        stream_open<1, CH>(rk, a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, r0, r1 < nu ? r1 : nu, nu, lane);
+        stream_open<1, CH>(rq, a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, (r0 > nu ? r0 : nu) - nu, r1 - nu,
+                           nx, lane);
+    }
+    if (kids) {
+        if (up) stream_open<1, CH>(pm, a.Mb + I.Mb + (long long)i * nx * ldM, ldM, pr0, pr1, W, lane);
+        const double si = a.sc ? a.sc[I.sc + i] : 1.0;
+        // the node's own terms s_i y_i + [chat_i ; sigma_i], requested before the wait
+        const int e0 = threadIdx.x < NRHS * W ? threadIdx.x : 0, k0 = e0 / W, c0 = e0 - k0 * W;
+        const double y0 = y_ptr(a, I, k0, i)[c0];
+        const double h0 = c0 < nx ? a.chat[I.chat + (long long)i * nx + c0] : a.sig[I.sig + (long long)i * nu + c0 - nx];
+        wait();
+        for (int e = threadIdx.x; e < NRHS * W; e += blockDim.x) {
+            const int k = e / W, c = e - k * W;
+            double s;
+            if (e == e0) {
+                s = si * y0 + (a.affine ? h0 : 0.0);
+            } else {
+                const double h = c < nx ? a.chat[I.chat + (long long)i * nx + c] : a.sig[I.sig + (long long)i * nu + c - nx];
+                s = si * y_ptr(a, I, k, i)[c] + (a.affine ? h : 0.0);
+            }
+            // the children's p_j, eight loads in flight at a time (a chunk's
+            // unused slots re-read its first child and are not added)
+            for (int j = j0; j < j0 + nch; j += 8) {
+                double v[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int jj = j + t < j0 + nch ? j + t : j;
+                    v[t] = c < nx ? x_ptr(a, I, k, jj)[c] : u_ptr(a, I, k, jj)[c - nx];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (j + t < j0 + nch) s += v[t];
+            }
+            as[k * ldM + c] = s;
+        }
+    } else {
+        NodeTerms<NRHS, CH> nt;
+        node_terms<NRHS, CH, kWave>(a, I, i, lane, nt);
+        double acc[NRHS][CH][2];
+        zero(acc);
+        for (int cb = 0; cb < nch; cb += CB) {
+            const int nb = nch - cb < CB ? nch - cb : CB;
+            const int R = nb * nx, r0 = (int)((long long)R * w / NW), r1 = (int)((long long)R * (w + 1) / NW);
+            RowStream<CH> mb;
+            stream_open<kDepth, CH>(mb, a.Mb + I.Mb + (long long)(j0 + cb) * nx * ldM, ldM, r0, r1, W, lane);
+            if (cb == 0) wait();
+            for (int e = threadIdx.x; e < R; e += blockDim.x) {
+                const int c = e / nx, r = e - c * nx, j = j0 + cb + c;
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) {
+                    double q;
+                    if (j >= I.Vnl) {
+                        const double sj = a.sc ? a.sc[I.sc + j] : 1.0;
+                        q = sj * y_ptr(a, I, k, j)[r] + (a.affine ? a.chat[I.chat + (long long)j * nx + r] : 0.0);
+                    } else {
+                        q = qhat_ptr(a, I, k, j)[r];
+                    }
+                    qs[k * ldv + e] = q;
+                }
+            }
+            __syncthreads();
+            stream_run<kDepth, NRHS, CH>(mb, qs, ldv, acc);
+            __syncthreads();   // qs is refilled (or, last, holds this node's qhat)
+        }
+        if (up) stream_open<1, CH>(pm, a.Mb + I.Mb + (long long)i * nx * ldM, ldM, pr0, pr1, W, lane);
+        if (w == 0) add_node_terms(a, acc, nt);
+        store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, W, acc, lane);
+        __syncthreads();
+        for (int e = threadIdx.x; e < NRHS * W; e += blockDim.x) {
+            const int k = e / W, c = e - k * W;
+            double s = 0.0;
+            for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + c];
+            as[k * ldM + c] = s;
+        }
+    }
+    __syncthreads();
+    // g_i = as[nx:]: k_i = -R~_i^{-1} g_i and qhat_i = as[:nx] + K_i' g_i
+    double kacc[NRHS][CH][2], qacc[NRHS][CH][2];
+    zero(kacc);
+    zero(qacc);
+    stream_run<1, NRHS, CH>(rk, as + nx, ldM, kacc);
+    stream_run<1, NRHS, CH>(rq, as + nx, ldM, qacc);
+    store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nu, kacc, lane);
+    store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, nu, nx, qacc, lane);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NRHS * W; e += blockDim.x) {
+        const int k = e / W, c = e - k * W;
+        double s = 0.0;
+        for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + c];
+        if (c < nu) {
+            kbuf_ptr(a, I, k, i)[c] = s;
+        } else {
+            const double q = as[k * ldM + c - nu] + s;
+            qhat_ptr(a, I, k, i)[c - nu] = q;
+            qs[k * ldq + c - nu] = q;
+        }
+    }
+    if (!up) return;
+    // p_i = [A_i B_i]' qhat_i for the parent
+    __syncthreads();
+    double pacc[NRHS][CH][2];
+    zero(pacc);
+    stream_run<1, NRHS, CH>(pm, qs, ldq, pacc);
+    store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, W, pacc, lane);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NRHS * W; e += blockDim.x) {
+        const int k = e / W, c = e - k * W;
+        double s = 0.0;
+        for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + c];
+        if (c < nx)
+            x_ptr(a, I, k, i)[c] = s;
+        else
+            u_ptr(a, I, k, i)[c - nx] = s;
+    }
+}
+
+// Forward step of a node of the fused list: x_i = A_i x_p + B_i u_p + c_i
+// from its parent's x_p and u_p (x_0 at the root), then u_i = K_i x_i + k_i;
+// a node whose children are not in the list also forms their x_j, as the
+// per-stage kernel does.  Every row this needs is requested before the wait.
+template <int NRHS, int CH, int NW>
+__device__ void fwd_fused_node(const SweepArgs &a, const InstDesc &I, int i, int w, int lane, bool kids,
+                               const FusedWait &wait)
+{
+    const int nx = I.nx, nu = I.nu, W = nx + nu, ldM = I.ldM;
+    const int *cp = a.cp + I.cp;
+    extern __shared__ double lds[];
+    double *xs = lds;                     // [NRHS][ldM]: x_i then u_i
+    double *red = xs + NRHS * ldM;        // [NW][NRHS][ldM]
+    double *xp = red + NW * NRHS * ldM;   // [NRHS][ldM]: the parent's x and u
+    const bool root = i == 0;
+    RowStream<CH> me, kf, mf;
+    double cme[CH][2], kv[NRHS][CH][2], cv[CH][2];
+    if (!root) {
+        const int r0 = W * w / NW, r1 = W * (w + 1) / NW;
+        stream_open<1, CH>(me, a.Mf + I.Mf + (long long)i * W * I.ldx, I.ldx, r0, r1, nx, lane);
+        load_cvec<CH>(a, I, i, lane, cme);
+    }
+    {
+        const int r0 = nx * w / NW, r1 = nx * (w + 1) / NW;
+        stream_open<1, CH>(kf, a.Kf + I.Kf + (long long)i * nx * I.ldu, I.ldu, r0, r1, nu, lane);
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int c = 2 * lane + 2 * kWave * ch + e;
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) kv[k][ch][e] = kbuf_ptr(a, I, k, i)[c < nu ? c : nu - 1];
+            }
+    }
+    const int j0 = cp[i], nch = cp[i + 1] - j0;
+    const int RB = nch >= NW ? 1 : NW / nch;
+    int c = RB == 1 ? w : w / RB;
+    const int blk = RB == 1 ? 0 : w - c * RB;
+    if (!kids && c < nch) {
+        const int rr0 = W * blk / RB, rr1 = W * (blk + 1) / RB;
+        stream_open<1, CH>(mf, a.Mf + I.Mf + (long long)(j0 + c) * W * I.ldx, I.ldx, rr0, rr1, nx, lane);
+        load_cvec<CH>(a, I, j0 + c, lane, cv);
+    }
+    wait();
+    if (root) {
+        for (int e = threadIdx.x; e < NRHS * nx; e += blockDim.x) {
+            const int k = e / nx, cc = e - k * nx;
+            const double v = a.affine ? a.x0[k * a.x0_rs + I.x0 + cc] : 0.0;
+            x_ptr(a, I, k, 0)[cc] = v;
+            xs[k * ldM + cc] = v;
+        }
+    } else {
+        const int p = a.anc[I.sc + i];
+        for (int e = threadIdx.x; e < NRHS * W; e += blockDim.x) {
+            const int k = e / W, cc = e - k * W;
+            xp[k * ldM + cc] = cc < nx ? x_ptr(a, I, k, p)[cc] : u_ptr(a, I, k, p)[cc - nx];
+        }
+        __syncthreads();
+        double xacc[NRHS][CH][2];
+        zero(xacc);
+        stream_run<1, NRHS, CH>(me, xp, ldM, xacc);
+        if (w == 0)
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+                for (int ch = 0; ch < CH; ++ch) {
+                    xacc[k][ch][0] += a.affine ? cme[ch][0] : 0.0;
+                    xacc[k][ch][1] += a.affine ? cme[ch][1] : 0.0;
+                }
+        store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nx, xacc, lane);
+        __syncthreads();
+        for (int e = threadIdx.x; e < NRHS * nx; e += blockDim.x) {
+            const int k = e / nx, cc = e - k * nx;
+            double s = 0.0;
+            for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + cc];
+            x_ptr(a, I, k, i)[cc] = s;
+            xs[k * ldM + cc] = s;
+        }
+    }
+    __syncthreads();
+    double uacc[NRHS][CH][2];
+    zero(uacc);
+    stream_run<1, NRHS, CH>(kf, xs, ldM, uacc);
+    if (w == 0) add_to(uacc, kv);
+    store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nu, uacc, lane);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NRHS * nu; e += blockDim.x) {
+        const int k = e / nu, cc = e - k * nu;
+        double s = 0.0;
+        for (int ww = 0; ww < NW; ++ww) s += red[(ww * NRHS + k) * ldM + cc];
+        u_ptr(a, I, k, i)[cc] = s;
+        xs[k * ldM + nx + cc] = s;
+    }
+    if (kids) return;
+    __syncthreads();
+    // the children's x_j = [A_j B_j]' [x_i ; u_i] + c_j (as the per-stage kernel)
+    if (RB == 1) {
+        for (; c < nch; c += NW) {
+            double xacc[NRHS][CH][2];
+            zero(xacc);
+            stream_run<1, NRHS, CH>(mf, xs, ldM, xacc);
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+                for (int ch = 0; ch < CH; ++ch) {
+                    xacc[k][ch][0] += a.affine ? cv[ch][0] : 0.0;
+                    xacc[k][ch][1] += a.affine ? cv[ch][1] : 0.0;
+                }
+            const int j = j0 + c;
+            if (c + NW < nch) {
+                stream_open<1, CH>(mf, a.Mf + I.Mf + (long long)(j + NW) * W * I.ldx, I.ldx, 0, W, nx, lane);
+                load_cvec<CH>(a, I, j + NW, lane, cv);
+            }
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+                for (int e2 = 0; e2 < 2; ++e2) {
+                    const int col = 2 * lane + 2 * kWave * ch + e2;
+                    if (col < nx)
+#pragma unroll
+                        for (int k = 0; k < NRHS; ++k) x_ptr(a, I, k, j)[col] = xacc[k][ch][e2];
+                }
+        }
+    } else {
+        double xacc[NRHS][CH][2];
+        zero(xacc);
+        if (c < nch) {
+            stream_run<1, NRHS, CH>(mf, xs, ldM, xacc);
+            if (blk == 0)
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+                    for (int ch = 0; ch < CH; ++ch) {
+                        xacc[k][ch][0] += a.affine ? cv[ch][0] : 0.0;
+                        xacc[k][ch][1] += a.affine ? cv[ch][1] : 0.0;
+                    }
+        }
+        store_acc<NRHS, CH>(red + w * NRHS * ldM, ldM, 0, nx, xacc, lane);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nch * NRHS * nx; e += blockDim.x) {
+            const int cc = e / (NRHS * nx), rem = e - cc * NRHS * nx, k = rem / nx, col = rem - k * nx;
+            double s = 0.0;
+            for (int b = 0; b < RB; ++b) s += red[((cc * RB + b) * NRHS + k) * ldM + col];
+            x_ptr(a, I, k, j0 + cc)[col] = s;
+        }
+    }
+}
+
+template <int NRHS, int CH, int NW>
+__global__ void __launch_bounds__(kWave *NW) bwd_trunk_fused_kernel(SweepArgs a, int *cnt, int *err)
+{
+    const int bad = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const Item it = a.items[blockIdx.x];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int lane = threadIdx.x & (kWave - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int i = it.idx & ~kFusedKids;
+    const bool kids = (it.idx & kFusedKids) != 0;
+    __shared__ int poison;
+    FusedWait fw{nullptr, 0, err, bad, &poison};
+    if (kids) {
+        fw.c = cnt + I.node0 + i;
+        fw.target = a.cp[I.cp + i + 1] - a.cp[I.cp + i];
+    }
+    bwd_fused_node<NRHS, CH, NW>(a, I, i, w, lane, kids, fw);
+    if (poison) {
+        __syncthreads();
+        const double nan = __builtin_nan("");
+        const int W = I.nx + I.nu;
+        for (int e = threadIdx.x; e < NRHS * W; e += blockDim.x) {
+            const int k = e / W, c = e - k * W;
+            if (c < I.nu)
+                kbuf_ptr(a, I, k, i)[c] = nan;
+            else
+                qhat_ptr(a, I, k, i)[c - I.nu] = nan;
+            if (i != 0) {
+                if (c < I.nx)
+                    x_ptr(a, I, k, i)[c] = nan;
+                else
+                    u_ptr(a, I, k, i)[c - I.nx] = nan;
+            }
+        }
+    }
+    if (i == 0) return;
+    release_node();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(cnt + I.node0 + a.anc[I.sc + i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int NRHS, int CH, int NW>
+__global__ void __launch_bounds__(kWave *NW) fwd_trunk_fused_kernel(SweepArgs a, int *cnt, int *err)
+{
+    const int bad = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const Item it = a.items[blockIdx.x];
+    if (skipped(a, it.inst)) return;
+    const InstDesc I = a.inst[it.inst];
+    const int lane = threadIdx.x & (kWave - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int i = it.idx & ~kFusedKids;
+    const bool kids = (it.idx & kFusedKids) != 0;
+    __shared__ int poison;
+    FusedWait fw{i == 0 ? nullptr : cnt + I.node0 + i, 1, err, bad, &poison};
+    fwd_fused_node<NRHS, CH, NW>(a, I, i, w, lane, kids, fw);
+    const int j0 = a.cp[I.cp + i], nch = a.cp[I.cp + i + 1] - j0;
+    if (poison) {
+        __syncthreads();
+        const double nan = __builtin_nan("");
+        const int per = I.nx + I.nu + (kids ? 0 : nch * I.nx);
+        for (int e = threadIdx.x; e < NRHS * per; e += blockDim.x) {
+            const int k = e / per, r = e - k * per;
+            if (r < I.nx)
+                x_ptr(a, I, k, i)[r] = nan;
+            else if (r < I.nx + I.nu)
+                u_ptr(a, I, k, i)[r - I.nx] = nan;
+            else
+                x_ptr(a, I, k, j0 + (r - I.nx - I.nu) / I.nx)[(r - I.nx - I.nu) % I.nx] = nan;
+        }
+    }
+    if (!kids) return;
+    release_node();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        for (int j = j0; j < j0 + nch; ++j)
+            __hip_atomic_store(cnt + I.node0 + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // ---- stages s*..N-1: chain c of an instance covers the nodes
 // stage_ptr[t] + c for t = s*..N-1 (one child each) and its leaf ----
 //
@@ -1145,6 +1586,41 @@ static void launch_trunk_tree(const SweepArgs &a, const tree_factors *f, int max
     }
 }
 
+template <int NRHS, int CH, int NW>
+static void launch_trunk_fused_nw(bool backward, SweepArgs a, const tree_factors *f, int max_ldM, int max_qs,
+                                  hipStream_t st)
+{
+    const LevelPlan &lv = backward ? f->fused_bwd : f->fused_fwd;
+    a.items = lv.items;
+    a.nitems = lv.count;
+    a.t = -1;
+    int *err = f->trunk_cnt + f->V_tot;
+    if (backward) {
+        const size_t lds = sizeof(double) * ((size_t)max_qs * NRHS + (size_t)(NW + 1) * NRHS * max_ldM);
+        hipLaunchKernelGGL((bwd_trunk_fused_kernel<NRHS, CH, NW>), dim3(lv.count), dim3(kWave * NW), lds, st, a,
+                           f->trunk_cnt, err);
+    } else {
+        const size_t lds = sizeof(double) * (size_t)(NW + 2) * NRHS * max_ldM;
+        hipLaunchKernelGGL((fwd_trunk_fused_kernel<NRHS, CH, NW>), dim3(lv.count), dim3(kWave * NW), lds, st, a,
+                           f->trunk_cnt, err);
+    }
+}
+
+template <int NRHS, int CH>
+static void launch_trunk_fused(bool backward, const SweepArgs &a, const tree_factors *f, int max_ldM, int max_qs,
+                               hipStream_t st)
+{
+    // every row of a node is held in registers across its wait: at most 8
+    // wavefronts per node (4 for rows wider than 128 entries) keep them unspilled
+    switch ((backward ? f->fused_bwd : f->fused_fwd).nw) {
+    case 16:
+    case 8: launch_trunk_fused_nw<NRHS, CH, CH == 1 ? 8 : 4>(backward, a, f, max_ldM, max_qs, st); break;
+    case 4: launch_trunk_fused_nw<NRHS, CH, 4>(backward, a, f, max_ldM, max_qs, st); break;
+    case 2: launch_trunk_fused_nw<NRHS, CH, 2>(backward, a, f, max_ldM, max_qs, st); break;
+    default: launch_trunk_fused_nw<NRHS, CH, 1>(backward, a, f, max_ldM, max_qs, st); break;
+    }
+}
+
 // One stage above s*: per-node workgroups for every node, or (trunk mode 2)
 // lane groups for the narrow instances' nodes plus workgroups for the rest.
 template <int NRHS, int CH>
@@ -1244,16 +1720,28 @@ static hipError_t sweep_impl(const tree_factors *f, SweepArgs a, hipStream_t st)
     }
     if (!f->levels.empty()) {
         PhaseTimer tm(1, st);
-        if (f->trunk_fused == 1 && f->trunk_entry.count > 0)
+        if (f->trunk_fused == 1 && f->trunk_entry.count > 0) {
             launch_trunk_tree<NRHS, CH>(a, f, ldM, qs, ldu, st);
-        else
+        } else if (f->trunk_fused >= 3) {
+            // the deeper stages one launch each, then the first stages in one
+            for (int k = (int)f->rest_levels.size() - 1; k >= 0; --k)
+                launch_trunk<NRHS, CH>(true, a, f->rest_levels[k], ldM, qs, ldu, st);
+            if (f->fused_bwd.count > 0) launch_trunk_fused<NRHS, CH>(true, a, f, ldM, qs, st);
+        } else {
             for (int k = (int)f->levels.size() - 1; k >= 0; --k)
                 launch_level<NRHS, CH>(true, a, f, f->levels[k], ldM, qs, ldu, st);
+        }
     }
     if (!f->levels.empty()) {
         PhaseTimer tm(2, st);
-        for (size_t k = 0; k < f->levels.size(); ++k)
-            launch_level<NRHS, CH>(false, a, f, f->levels[k], ldM, qs, ldu, st);
+        if (f->trunk_fused >= 3) {
+            if (f->fused_fwd.count > 0) launch_trunk_fused<NRHS, CH>(false, a, f, ldM, qs, st);
+            for (size_t k = 0; k < f->rest_levels.size(); ++k)
+                launch_trunk<NRHS, CH>(false, a, f->rest_levels[k], ldM, qs, ldu, st);
+        } else {
+            for (size_t k = 0; k < f->levels.size(); ++k)
+                launch_level<NRHS, CH>(false, a, f, f->levels[k], ldM, qs, ldu, st);
+        }
     }
     if (!f->chains.empty()) {
         PhaseTimer tm(3, st);

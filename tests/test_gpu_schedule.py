@@ -80,23 +80,28 @@ def test_schedules_are_bit_identical(st):
                     s = np.abs(ref[nrhs][0]).max()
                     assert np.abs(xh - ref[nrhs][0]).max() <= 1e-12 * s, (g, order, nrhs)
                     assert np.abs(uh - ref[nrhs][1]).max() <= 1e-12 * s, (g, order, nrhs)
-    for cap in (1, 2, 4, 8):
-        for fused in (0, 1, 2):
+    for cap in (1, 2, 4, 8, 16):
+        for fused in (0, 1, 2, 3, 4):
             st.sweep_schedule(tf, (8, 1, cap, fused, 16))
             for nrhs in (1, 2):
                 xh, uh = _sweep(st, tf, x0, y, False, nrhs)
                 s = np.abs(ref[nrhs][0]).max()
                 assert np.abs(xh - ref[nrhs][0]).max() <= 1e-12 * s, (cap, fused, nrhs)
                 assert np.abs(uh - ref[nrhs][1]).max() <= 1e-12 * s, (cap, fused, nrhs)
-    # the one-launch trunk leaves its counters at zero: repeated sweeps agree bitwise
-    st.sweep_schedule(tf, (8, 1, 16, 1, 16))
-    a1 = _sweep(st, tf, x0, y, False, 1)
-    a2 = _sweep(st, tf, x0, y, False, 1)
-    assert np.array_equal(a1[0], a2[0]) and np.array_equal(a1[1], a2[1])
+    # the one-launch and fused trunks leave their counters at zero: repeated
+    # sweeps agree bitwise (a counter left behind would start the next sweep's
+    # waits early or never)
+    for fused in (1, 3, 4):
+        st.sweep_schedule(tf, (8, 1, 16, fused, 16))
+        a1 = _sweep(st, tf, x0, y, False, 1)
+        for _ in range(3):
+            a2 = _sweep(st, tf, x0, y, False, 1)
+            assert np.array_equal(a1[0], a2[0]) and np.array_equal(a1[1], a2[1]), fused
+        assert np.isfinite(a1[0]).all() and np.isfinite(a1[1]).all()
     with pytest.raises(st.StotreeError):
         st.sweep_schedule(tf, (12, 1, 16, 1, 16))
     with pytest.raises(st.StotreeError):
-        st.sweep_schedule(tf, (8, 1, 16, 3, 16))
+        st.sweep_schedule(tf, (8, 1, 16, 5, 16))
     with pytest.raises(st.StotreeError):
         st.sweep_schedule(tf, (8, 1, 16, 0, -1))
     with pytest.raises(ValueError):
@@ -114,7 +119,7 @@ def test_autotune_keeps_results_and_caches(st, tmp_path):
     rec = st.sweep_autotune(tf, nrhs=1, reps=3, cache=cache)
     assert not rec["cached"] and rec["ms"] > 0
     g, order, cap, fused, pmin = rec["knobs"]
-    assert g in (8, 16, 32, 64) and order in (0, 1) and cap in (1, 2, 4, 8, 16) and fused in (0, 1, 2)
+    assert g in (8, 16, 32, 64) and order in (0, 1) and cap in (1, 2, 4, 8, 16) and fused in (0, 1, 2, 3, 4)
     assert pmin == 16        # not a shared handle: the panel knob is left as it is
     assert st.sweep_schedule_get(tf) == tuple(rec["knobs"])
     for homogeneous in (False, True):
@@ -126,13 +131,15 @@ def test_autotune_keeps_results_and_caches(st, tmp_path):
     tf.free()
 
 
-@pytest.mark.parametrize("nrhs", [1, 2])
-def test_graph_replays_match_eager(st, nrhs):
+@pytest.mark.parametrize("nrhs,trunk", [(1, 0), (2, 0), (1, 3), (2, 4)])
+def test_graph_replays_match_eager(st, nrhs, trunk):
     """Replays of one recorded sweep, with eager work and synchronisation
-    between them, each against an eager sweep of the same inputs."""
+    between them, each against an eager sweep of the same inputs (trunk
+    modes 3 and 4: the fused launches' counters reset within each replay)."""
     import torch
     probs = mixed_forest()
     tf = st.tree_factor_batch(probs, precondition=True)
+    st.sweep_schedule(tf, (8, 1, 16, trunk, 16))
     rng = np.random.default_rng(7)
     y = _t(rng.standard_normal(nrhs * tf.m))
     x0 = _t(rng.standard_normal(nrhs * tf.x0_len))

@@ -124,4 +124,15 @@ def test_large_tree_full_size_kkt(st):
         dyn, stat = inner_kkt_residual(prob, sc * ybar, x[0], u[0], prob.x0, homogeneous)
         print(f"homogeneous={homogeneous}: dynamics {dyn:.2e}, stationarity {stat:.2e}", flush=True)
         assert dyn < TOL_GRAD and stat < TOL_GRAD
+        # the stages above s* in other launch forms (per stage with 8
+        # wavefronts a node, first stages fused): equal to rounding
+        for knobs in ((8, 1, 8, 0, 16), (8, 1, 8, 3, 16), (8, 1, 16, 3, 16), (8, 1, 8, 4, 16)):
+            st.sweep_schedule(tf, knobs)
+            for _ in range(2):
+                xk, uk = _run(st, tf, prob.x0, ybar, homogeneous)
+                s = np.abs(x[0]).max()
+                assert np.abs(xk[0] - x[0]).max() <= 1e-12 * s, knobs
+                assert np.abs(uk[0] - u[0]).max() <= 1e-12 * s, knobs
+            print(f"schedule {knobs}: equal to rounding", flush=True)
+        st.sweep_schedule(tf, (8, 1, 16, 0, 16))
     tf.free()
