@@ -786,6 +786,12 @@ def main():
     c1.record(stream)
     torch.cuda.synchronize()
     copy_gbs = 2 * 8 * n_copy / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
+    # two more calibration points for the HBM byte counters of a profiled run:
+    # a read-only reduction of the same 1 GiB and a 512 MiB fill
+    calib_sum = float(src.sum())
+    dst[: n_copy // 2].fill_(2.0)
+    torch.cuda.synchronize()
+    assert calib_sum == float(n_copy)
     del src, dst
     log(f"device copy (read+write) {copy_gbs:.0f} GB/s")
 

@@ -408,9 +408,16 @@ int warm_mlp_forward(int rows, int din, int dh, int dout, const float *params, c
 int warm_mlp_backward(int rows, int din, int dh, int dout, const float *params, const float *X,
                       const float *H, const float *dY, float *grad, float *work, void *hip_stream);
 /* Masked squared error: dY = 2 mask (Y - T) inv_count; loss2 [2] receives
- * (sum mask (Y - T)^2, sum mask); part is DEVICE scratch of 512 doubles. */
+ * (sum mask (Y - T)^2, sum mask); part is DEVICE scratch of 512 doubles.
+ * inv_count 0: 1 / max(1, sum mask) is formed on the device (no host read). */
 int warm_mse_grad(int64_t n, const float *Y, const float *T, const float *mask, float inv_count, float *dY,
                   double *loss2, double *part, void *hip_stream);
+/* Minibatch rows: dst [rows][cols] = src [idx[r]][cols] (src has src_rows
+ * rows; idx [rows] int64).  An index outside [0, src_rows) sets the DEVICE
+ * int *bad to 1 (it is never cleared here) and leaves that row of dst as it
+ * was; the caller clears and reads bad when it synchronises anyway. */
+int warm_gather(int64_t rows, int cols, const float *src, int64_t src_rows, const int64_t *idx, float *dst,
+                int *bad, void *hip_stream);
 /* One Adam step (Kingma and Ba) with bias correction at step >= 1. */
 int warm_adam(int64_t n, float *params, const float *grad, float *m, float *v, float lr, float beta1,
               float beta2, float eps, int step, void *hip_stream);

@@ -228,6 +228,17 @@ int warm_mse_grad(int64_t n, const float *Y, const float *T, const float *mask, 
     return mse_grad_impl(n, Y, T, mask, inv_count, dY, loss2, part, (hipStream_t)hip_stream);
 }
 
+int warm_gather(int64_t rows, int cols, const float *src, int64_t src_rows, const int64_t *idx, float *dst,
+                int *bad, void *hip_stream)
+{
+    if (rows < 1 || cols < 1 || src_rows < 1 || !src || !idx || !dst || !bad) {
+        set_error("warm_gather: bad argument");
+        return STOTREE_ERR_ARG;
+    }
+    return gather_rows_impl(rows, cols, src, src_rows, reinterpret_cast<const long long *>(idx), dst, bad,
+                            (hipStream_t)hip_stream);
+}
+
 int warm_adam(int64_t n, float *params, const float *grad, float *m, float *v, float lr, float beta1, float beta2,
               float eps, int step, void *hip_stream)
 {

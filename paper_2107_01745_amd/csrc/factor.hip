@@ -109,7 +109,65 @@ __global__ void factor_leaves_kernel(FactorArgs a, int b)
     }
 }
 
-__global__ void __launch_bounds__(256) factor_stage_kernel(FactorArgs a)
+// The children's products of a node, H = sum_j [A_j B_j]' P_j [A_j B_j]
+// (the blocks [Q-like ; S~] and R~ of it), tiled through LDS: the first
+// product T = P_j [A_j B_j] and then H += [A_j B_j]' T, both over chunks of
+// KC (16, or 8 where 16 does not fit) rows of the K dimension staged in LDS
+// (zero-padded to whole 4x4 blocks),
+// each thread accumulating kFB blocks of 4x4 outputs in registers; H stays in
+// registers across the children.  Used when the node's sizes fit kFactorLds
+// doubles of LDS and kFB blocks per thread; otherwise the entry-by-entry loop
+// below.
+constexpr int kFB = 2;
+constexpr int kFactorThreads = 256;
+constexpr int kFactorLds = 8192;
+
+struct FactorTiles {
+    int kc, nx4, nu4, ldB, nxK, cbT, nbT, cx, cu, nbH1, nbH;
+    __host__ __device__ FactorTiles(int nx, int nu, int kc_) : kc(kc_)
+    {
+        nx4 = (nx + 3) & ~3;
+        nu4 = (nu + 3) & ~3;
+        ldB = nx4 + nu4;
+        nxK = (nx + kc - 1) / kc * kc;
+        cbT = (nx + nu + 3) >> 2;
+        nbT = (nx4 >> 2) * cbT;
+        cx = nx4 >> 2;
+        cu = nu4 >> 2;
+        nbH1 = cbT * cx;
+        nbH = nbH1 + cu * cu;
+    }
+    // the node's tail after the products: R~ (then L), L^{-1}, R~^{-1}, S~ and K
+    __host__ __device__ int tail_doubles(int nx, int nu) const { return 3 * nu * nu + 2 * nu * nx; }
+    __host__ __device__ int lds_doubles(int nx, int nu) const
+    {
+        const int prod = nx4 * kc + kc * ldB + nxK * ldB, tail = tail_doubles(nx, nu);
+        return prod > tail ? prod : tail;
+    }
+    __host__ __device__ bool fits(int nx, int nu) const
+    {
+        return lds_doubles(nx, nu) <= kFactorLds && nbT <= kFB * kFactorThreads && nbH <= kFB * kFactorThreads;
+    }
+};
+
+// sum_{k0 <= k < k1} x[k sx] y[k sy] in four independent partial sums (the
+// loads of four terms in flight together)
+__device__ __forceinline__ double dot4(const double *x, int sx, const double *y, int sy, int k0, int k1)
+{
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int k = k0;
+    for (; k + 3 < k1; k += 4) {
+        v0 = fma(x[k * sx], y[k * sy], v0);
+        v1 = fma(x[(k + 1) * sx], y[(k + 1) * sy], v1);
+        v2 = fma(x[(k + 2) * sx], y[(k + 2) * sy], v2);
+        v3 = fma(x[(k + 3) * sx], y[(k + 3) * sy], v3);
+    }
+    for (; k < k1; ++k) v0 = fma(x[k * sx], y[k * sy], v0);
+    return (v0 + v1) + (v2 + v3);
+}
+
+template <bool kTiled, int KC = 8>
+__global__ void __launch_bounds__(kFactorThreads) factor_stage_kernel(FactorArgs a)
 {
     const Item it = a.items[blockIdx.x];
     const InstDesc I = a.inst[it.inst];
@@ -126,6 +184,220 @@ __global__ void __launch_bounds__(256) factor_stage_kernel(FactorArgs a)
     const double pi = a.prob[Rw.prob + i];
     double *Pi = a.Pcal + Rw.Pcal + (long long)i * nx * nx;
     if (tid == 0) fail = 0;
+    if (kTiled) {
+        extern __shared__ double fl[];
+        const FactorTiles ft(nx, nu, KC);
+        const int ldB = ft.ldB;
+        double *sA = fl, *sB = sA + ft.nx4 * KC, *sT = sB + KC * ldB;
+        // H blocks of this thread: rows [0, W) x columns [0, nx) (P and S~),
+        // then rows and columns [nx, W) (R~); origin -1: no block
+        double h[kFB][4][4];
+        int hr[kFB], hc[kFB];
+#pragma unroll
+        for (int s = 0; s < kFB; ++s) {
+            const int q = tid + kFactorThreads * s;
+            if (q < ft.nbH1) {
+                hr[s] = 4 * (q / ft.cx);
+                hc[s] = 4 * (q % ft.cx);
+            } else if (q < ft.nbH) {
+                const int q2 = q - ft.nbH1;
+                hr[s] = nx + 4 * (q2 / ft.cu);
+                hc[s] = nx + 4 * (q2 % ft.cu);
+            } else {
+                hr[s] = hc[s] = -1;
+            }
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = hr[s] + d, c = hc[s] + e;
+                    double v = 0.0;
+                    if (hr[s] >= 0 && r < W && c < W) {
+                        if (r < nx && c < nx)
+                            v = 2.0 * pi * a.Q[Rw.Q + (long long)i * nx * nx + r * nx + c];
+                        else if (r >= nx && c < nx)
+                            v = a.hasS ? 2.0 * pi * a.S[Rw.S + (long long)i * nu * nx + (r - nx) * nx + c] : 0.0;
+                        else if (r >= nx && c >= nx)
+                            v = 2.0 * pi * a.R[Rw.R + (long long)i * nu * nu + (r - nx) * nu + (c - nx)];
+                    }
+                    h[s][d][e] = v;
+                }
+        }
+        for (int e = tid; e < ft.nxK * ldB; e += nt) sT[e] = 0.0;   // rows and columns past T stay zero
+        __syncthreads();
+        for (int j = cp[i]; j < cp[i + 1]; ++j) {
+            const double *M = a.Mb + I.Mb + (long long)j * nx * I.ldM;
+            const double *Pj = a.Pcal + Rw.Pcal + (long long)j * nx * nx;
+            auto stage_M = [&](int k0) {          // sB[kk][c] = M[k0 + kk][c] (zero past the matrix)
+                for (int e = tid; e < KC * ldB; e += nt) {
+                    const int kk = e / ldB, c = e - kk * ldB, k = k0 + kk;
+                    sB[e] = k < nx && c < W ? M[(long long)k * I.ldM + c] : 0.0;
+                }
+            };
+            // T = P_j [A_j B_j] (rows [0, nx4), columns [0, 4 cbT))
+            double t[kFB][4][4];
+#pragma unroll
+            for (int s = 0; s < kFB; ++s)
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) t[s][d][e] = 0.0;
+            for (int k0 = 0; k0 < nx; k0 += KC) {
+                for (int e = tid; e < ft.nx4 * KC; e += nt) {
+                    const int r = e / KC, k = k0 + e - r * KC;
+                    sA[e] = r < nx && k < nx ? Pj[r * nx + k] : 0.0;
+                }
+                stage_M(k0);
+                __syncthreads();
+#pragma unroll
+                for (int s = 0; s < kFB; ++s) {
+                    const int q = tid + kFactorThreads * s;
+                    if (q >= ft.nbT) continue;
+                    const int r0 = 4 * (q / ft.cbT), c0 = 4 * (q % ft.cbT);
+#pragma unroll 8
+                    for (int kk = 0; kk < KC; ++kk) {
+                        double av[4], bv[4];
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) av[d] = sA[(r0 + d) * KC + kk];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) bv[e] = sB[kk * ldB + c0 + e];
+#pragma unroll
+                        for (int d = 0; d < 4; ++d)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) t[s][d][e] = fma(av[d], bv[e], t[s][d][e]);
+                    }
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int s = 0; s < kFB; ++s) {
+                const int q = tid + kFactorThreads * s;
+                if (q >= ft.nbT) continue;
+                const int r0 = 4 * (q / ft.cbT), c0 = 4 * (q % ft.cbT);
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) sT[(r0 + d) * ldB + c0 + e] = t[s][d][e];
+            }
+            // H += [A_j B_j]' T
+            for (int k0 = 0; k0 < nx; k0 += KC) {
+                stage_M(k0);
+                __syncthreads();
+#pragma unroll
+                for (int s = 0; s < kFB; ++s) {
+                    if (hr[s] < 0) continue;
+#pragma unroll 8
+                    for (int kk = 0; kk < KC; ++kk) {
+                        double av[4], bv[4];
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) av[d] = sB[kk * ldB + hr[s] + d];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) bv[e] = sT[(k0 + kk) * ldB + hc[s] + e];
+#pragma unroll
+                        for (int d = 0; d < 4; ++d)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) h[s][d][e] = fma(av[d], bv[e], h[s][d][e]);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // P_i to its slot; R~ and S~ into LDS for the tail (the products' LDS is free now)
+        double *sR = fl, *sLi = sR + nu * nu, *sRi = sLi + nu * nu, *sS = sRi + nu * nu, *sK = sS + nu * nx;
+#pragma unroll
+        for (int s = 0; s < kFB; ++s) {
+            if (hr[s] < 0) continue;
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = hr[s] + d, c = hc[s] + e;
+                    if (r >= W || c >= W) continue;
+                    if (hc[s] < nx) {           // a block of columns [0, nx): P_i and S~ (padding columns dropped)
+                        if (c >= nx) continue;
+                        if (r < nx)
+                            Pi[r * nx + c] = h[s][d][e];
+                        else
+                            sS[(r - nx) * nx + c] = h[s][d][e];
+                    } else {                    // a block of R~
+                        sR[(r - nx) * nu + (c - nx)] = h[s][d][e];
+                    }
+                }
+        }
+        __syncthreads();
+        // Cholesky R~ = L L' (lower triangle of sR), right-looking: pivot,
+        // column below it, then the trailing lower triangle in parallel
+        for (int jc = 0; jc < nu; ++jc) {
+            if (tid == 0) {
+                const double d = sR[jc * nu + jc];
+                if (!(d > 0.0)) fail = 1;
+                else sR[jc * nu + jc] = sqrt(d);
+            }
+            __syncthreads();
+            if (fail) break;
+            const double piv = sR[jc * nu + jc];
+            for (int r = jc + 1 + tid; r < nu; r += nt) sR[r * nu + jc] /= piv;
+            __syncthreads();
+            const int m = nu - jc - 1;
+            for (int e = tid; e < m * m; e += nt) {
+                const int r = jc + 1 + e / m, c = jc + 1 + e % m;
+                if (c <= r) sR[r * nu + c] -= sR[r * nu + jc] * sR[c * nu + jc];
+            }
+            __syncthreads();
+        }
+        if (fail) {
+            if (tid == 0) atomicExch(a.err, STOTREE_ERR_NOT_PD);
+            return;
+        }
+        // L^{-1} (lower), row by row: all columns of a row in parallel
+        for (int e = tid; e < nu * nu; e += nt) sLi[e] = 0.0;
+        __syncthreads();
+        for (int r = 0; r < nu; ++r) {
+            for (int c = tid; c <= r; c += nt) {
+                const double v = (r == c ? 1.0 : 0.0) - dot4(sR + r * nu, 1, sLi + c, nu, c, r);
+                sLi[r * nu + c] = v / sR[r * nu + r];
+            }
+            __syncthreads();
+        }
+        // R~^{-1} = L^{-T} L^{-1}
+        for (int e = tid; e < nu * nu; e += nt) {
+            const int r = e / nu, c = e - r * nu, k0 = r > c ? r : c;
+            sRi[e] = dot4(sLi + r, nu, sLi + c, nu, k0, nu);
+        }
+        __syncthreads();
+        // K = -R~^{-1} S~ (sK and both stored layouts), -R~^{-1} (Rn)
+        double *Kb = a.Kb + I.Kb + (long long)i * nu * I.ldx;
+        double *Kf = a.Kf + I.Kf + (long long)i * nx * I.ldu;
+        double *Rn = a.Rn + I.Rn + (long long)i * nu * I.ldu;
+        for (int e = tid; e < nu * nx; e += nt) {
+            const int r = e / nx, c = e - r * nx;
+            const double v = dot4(sRi + r * nu, 1, sS + c, nx, 0, nu);
+            sK[e] = -v;
+            Kb[r * I.ldx + c] = -v;
+            Kf[c * I.ldu + r] = -v;
+        }
+        for (int e = tid; e < nu * (I.ldx - nx); e += nt) Kb[(e / (I.ldx - nx)) * I.ldx + nx + e % (I.ldx - nx)] = 0.0;
+        for (int e = tid; e < nx * (I.ldu - nu); e += nt) Kf[(e / (I.ldu - nu)) * I.ldu + nu + e % (I.ldu - nu)] = 0.0;
+        for (int e = tid; e < nu * I.ldu; e += nt) {
+            const int r = e / I.ldu, c = e - r * I.ldu;
+            Rn[e] = c < nu ? -sRi[r * nu + c] : 0.0;
+        }
+        __syncthreads();
+        // P_i += K' S~
+        for (int e = tid; e < nx * nx; e += nt) {
+            const int r = e / nx, c = e - r * nx;
+            Pi[e] += dot4(sK + r, nx, sS + c, nx, 0, nu);
+        }
+        __syncthreads();
+        for (int rr = tid; rr < nx; rr += nt) {
+            double v = i > 0 ? dot4(Pi + rr * nx, 1, a.c + Rw.c + (long long)i * nx, 1, 0, nx) : 0.0;
+            if (a.hasq) v += pi * a.q[Rw.q + (long long)i * nx + rr];
+            a.chat[I.chat + (long long)i * nx + rr] = v;
+        }
+        for (int rr = tid; rr < nu; rr += nt)
+            a.sig[I.sig + (long long)i * nu + rr] = a.hasr ? pi * a.r[Rw.r + (long long)i * nu + rr] : 0.0;
+        return;
+    } else {
     for (int e = tid; e < nu * nu; e += nt) Rt[e] = 2.0 * pi * a.R[Rw.R + (long long)i * nu * nu + e];
     for (int e = tid; e < nu * nx; e += nt) St[e] = a.hasS ? 2.0 * pi * a.S[Rw.S + (long long)i * nu * nx + e] : 0.0;
     for (int e = tid; e < nx * nx; e += nt) Pi[e] = 2.0 * pi * a.Q[Rw.Q + (long long)i * nx * nx + e];
@@ -159,6 +431,7 @@ __global__ void __launch_bounds__(256) factor_stage_kernel(FactorArgs a)
             St[e] += s;
         }
         __syncthreads();
+    }
     }
     // Cholesky R~ = L L' in place (lower triangle), column by column.
     for (int jc = 0; jc < nu; ++jc) {
@@ -965,11 +1238,29 @@ int factor_forest(int count, const tree_desc *trees, const problem_data *datas, 
         hipLaunchKernelGGL(pack_dynamics_kernel, dim3(g), dim3(256), 0, st, a, b);
         hipLaunchKernelGGL(factor_leaves_kernel, dim3((unsigned)(I.V - I.Vnl)), dim3(64), 0, st, a, b);
     }
+    // the tiled children's products when every instance's sizes fit
+    bool tiled = true, wide_k = true;
+    int lds8 = 0, lds16 = 0;
+    for (int b = 0; b < count; ++b) {
+        const int nx = f->inst[b].nx, nu = f->inst[b].nu;
+        const FactorTiles f8(nx, nu, 8), f16(nx, nu, 16);
+        tiled = tiled && f8.fits(nx, nu);
+        wide_k = wide_k && f16.fits(nx, nu);
+        lds8 = std::max(lds8, f8.lds_doubles(nx, nu));
+        lds16 = std::max(lds16, f16.lds_doubles(nx, nu));
+    }
     for (int t = max_depth - 1; t >= 0; --t) {
         const size_t n = level_off[t + 1] - level_off[t];
         if (n == 0) continue;
         a.items = (const Item *)bitems.p + level_off[t];
-        hipLaunchKernelGGL(factor_stage_kernel, dim3((unsigned)n), dim3(256), 0, st, a);
+        if (tiled && wide_k)
+            hipLaunchKernelGGL((factor_stage_kernel<true, 16>), dim3((unsigned)n), dim3(kFactorThreads),
+                               sizeof(double) * (size_t)lds16, st, a);
+        else if (tiled)
+            hipLaunchKernelGGL((factor_stage_kernel<true, 8>), dim3((unsigned)n), dim3(kFactorThreads),
+                               sizeof(double) * (size_t)lds8, st, a);
+        else
+            hipLaunchKernelGGL(factor_stage_kernel<false>, dim3((unsigned)n), dim3(kFactorThreads), 0, st, a);
     }
     STOTREE_HIP(hipGetLastError());
     int err = 0;

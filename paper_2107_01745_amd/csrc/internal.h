@@ -232,6 +232,8 @@ int mlp_backward_impl(int rows, int din, int dh, int dout, const float *P, const
                       const float *dY, float *G, float *work, hipStream_t st);
 int mse_grad_impl(long long n, const float *Y, const float *T, const float *mask, float inv_count, float *dY,
                   double *loss2, double *part, hipStream_t st);
+int gather_rows_impl(long long rows, int cols, const float *src, long long src_rows, const long long *idx,
+                     float *dst, int *bad, hipStream_t st);
 int adam_impl(long long n, float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
               int step, hipStream_t st);
 int warm_features_impl(const tree_factors *f, const double *x0, float c_scale, float *X, hipStream_t st);

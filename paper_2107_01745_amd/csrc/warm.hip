@@ -104,16 +104,33 @@ __global__ void sum_rows_kernel(const float *part, int S, int n, float *out)
 
 // Loss 1/count sum mask (Y - T)^2 and its gradient dY = 2 mask (Y - T)/count.
 // Per-block partial sums of the loss and of the mask go to part[2*block].
+// Sum of the mask in one workgroup (fixed order), for the device-side count.
+__global__ void mask_count_kernel(long long n, const float *mask, float *inv_out)
+{
+    __shared__ double red[256];
+    double c = 0.0;
+    for (long long k = threadIdx.x; k < n; k += blockDim.x) c += mask[k];
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) inv_out[0] = (float)(1.0 / (red[0] > 1.0 ? red[0] : 1.0));
+}
+
+// inv_dev: the inverse count from mask_count_kernel, or null (inv_count given)
 __global__ void mse_grad_kernel(long long n, const float *Y, const float *T, const float *mask, float inv_count,
-                                float *dY, double *part)
+                                const float *inv_dev, float *dY, double *part)
 {
     __shared__ double red[2][256];
     double l = 0.0, c = 0.0;
+    const float inv = inv_dev ? inv_dev[0] : inv_count;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
          k += (long long)gridDim.x * blockDim.x) {
         const float d = Y[k] - T[k];
         const float w = mask[k];
-        dY[k] = 2.0f * w * d * inv_count;
+        dY[k] = 2.0f * w * d * inv;
         l += (double)w * d * d;
         c += w;
     }
@@ -321,6 +338,23 @@ long long mlp_work_len(int rows, int din, int dh, int dout)
 }
 
 namespace {
+// dst[r][:] = src[idx[r]][:] for r < rows (cols floats per row)
+__global__ void gather_rows_kernel(long long rows, int cols, const float *src, long long src_rows,
+                                   const long long *idx, float *dst, int *bad)
+{
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < rows * cols;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long r = e / cols;
+        const int c = (int)(e - r * cols);
+        const long long s = idx[r];
+        if (s < 0 || s >= src_rows) {   // an index outside the source: flagged, entry left as is
+            *bad = 1;
+            continue;
+        }
+        dst[e] = src[s * cols + c];
+    }
+}
+
 __global__ void fill_f32_kernel(float *v, long long n, float val)
 {
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
@@ -378,9 +412,26 @@ int mlp_backward_impl(int rows, int din, int dh, int dout, const float *P, const
 int mse_grad_impl(long long n, const float *Y, const float *T, const float *mask, float inv_count, float *dY,
                   double *loss2, double *part, hipStream_t st)
 {
-    const int nb = 256;
-    hipLaunchKernelGGL(mse_grad_kernel, dim3(nb), dim3(256), 0, st, n, Y, T, mask, inv_count, dY, part);
+    // 255 blocks: their (loss, count) pairs fill the first 510 of the 512
+    // scratch doubles; with inv_count 0 the inverse count, 1 / max(1, sum
+    // mask), formed on the device, goes in the 511th
+    const int nb = 255;
+    float *inv_dev = nullptr;
+    if (inv_count == 0.0f) {
+        inv_dev = reinterpret_cast<float *>(part + 2 * nb);
+        hipLaunchKernelGGL(mask_count_kernel, dim3(1), dim3(256), 0, st, n, mask, inv_dev);
+    }
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(nb), dim3(256), 0, st, n, Y, T, mask, inv_count, inv_dev, dY, part);
     hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(64), 0, st, part, nb, loss2);
+    STOTREE_HIP(hipGetLastError());
+    return STOTREE_OK;
+}
+
+int gather_rows_impl(long long rows, int cols, const float *src, long long src_rows, const long long *idx,
+                     float *dst, int *bad, hipStream_t st)
+{
+    const unsigned g = (unsigned)std::min<long long>(2048, (rows * cols + 255) / 256);
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(g), dim3(256), 0, st, rows, cols, src, src_rows, idx, dst, bad);
     STOTREE_HIP(hipGetLastError());
     return STOTREE_OK;
 }

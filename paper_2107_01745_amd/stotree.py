@@ -71,7 +71,7 @@ EXPORTS = ("tree_factor", "tree_factor_batch", "tree_factors_free", "tree_dims",
            "warm_mse_grad", "warm_adam", "warm_features", "warm_scatter", "warm_targets",
            "dual_select", "tree_factor_shared", "sweep_schedule", "sweep_schedule_get", "sweep_autotune",
            "sweep_graph_create", "sweep_graph_launch", "sweep_graph_free", "dual_grad_noalloc",
-           "gpad_solve", "dual_merge")
+           "gpad_solve", "dual_merge", "warm_gather")
 PHASES = ("bwd_chain", "bwd_stages", "fwd_stages", "fwd_chain")
 
 _lib = None
@@ -436,13 +436,14 @@ def _warm_sigs(L):
     L.warm_mlp_backward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]
     L.warm_mse_grad.argtypes = [C.c_int64, vp, vp, vp, f32, vp, vp, vp, vp]
     L.warm_adam.argtypes = [C.c_int64, vp, vp, vp, vp, f32, f32, f32, f32, C.c_int, vp]
+    L.warm_gather.argtypes = [C.c_int64, C.c_int, vp, C.c_int64, vp, vp, vp, vp]
     L.warm_features.argtypes = [vp, vp, f32, vp, vp]
     L.warm_scatter.argtypes = [vp, vp, f32, vp, vp]
     L.warm_targets.argtypes = [vp, vp, f32, vp, vp, vp]
     L.dual_select.argtypes = [vp, vp, C.POINTER(C.c_int32), vp]
     L.dual_merge.argtypes = [vp, vp, vp, C.POINTER(C.c_int32), vp]
     for fn in (L.warm_mlp_forward, L.warm_mlp_backward, L.warm_mse_grad, L.warm_adam, L.warm_features,
-               L.warm_scatter, L.warm_targets, L.dual_select, L.dual_merge):
+               L.warm_scatter, L.warm_targets, L.dual_select, L.dual_merge, L.warm_gather):
         fn.restype = C.c_int
 
 
@@ -481,6 +482,17 @@ def warm_mlp_backward(rows, din, dh, dout, params, X, H, dY, grad, work, stream=
 def warm_mse_grad(n, Y, T, mask, inv_count, dY, loss2, part, stream=None):
     _check(_wl().warm_mse_grad(n, _fptr(Y), _fptr(T), _fptr(mask), float(inv_count), _fptr(dY),
                                _fptr(loss2), _fptr(part), _stream(stream)))
+
+
+def warm_gather(src, idx, dst, bad, stream=None):
+    """dst[r] = src[idx[r]] for the rows of float32 matrices (idx int64, bad a
+    one-element int32 device flag set on an out-of-range index)."""
+    import torch
+    assert src.dtype == torch.float32 and dst.dtype == torch.float32 and idx.dtype == torch.int64
+    assert bad.dtype == torch.int32 and src.dim() == 2 and dst.dim() == 2 and src.shape[1] == dst.shape[1]
+    assert idx.numel() == dst.shape[0]
+    _check(_wl().warm_gather(dst.shape[0], dst.shape[1], _fptr(src), src.shape[0], _fptr(idx), _fptr(dst),
+                             _fptr(bad), _stream(stream)))
 
 
 def warm_adam(n, params, grad, m, v, lr, beta1, beta2, eps, step, stream=None):

@@ -108,6 +108,9 @@ class WarmStartMLP:
         stotree.warm_scatter(tf, Y, self.y_scale, y_out)
 
     def fit(self, X, T, M, *, epochs=30, batch_rows=65536, lr=1e-3, seed=0, log=None):
+        """Adam on the masked squared error over shuffled minibatches; the
+        minibatch rows are gathered and the masked count formed by the
+        library's kernels, and the host reads the losses once per epoch."""
         batch_rows = min(batch_rows, X.shape[0])
         rows = X.shape[0]
         work = torch.empty(stotree.warm_mlp_work_len(batch_rows, self.din, self.dh, self.dout),
@@ -115,28 +118,33 @@ class WarmStartMLP:
         H = torch.empty(batch_rows, 2 * self.dh, dtype=torch.float32, device=_dev())
         Y = torch.empty(batch_rows, self.dout, dtype=torch.float32, device=_dev())
         dY = torch.empty_like(Y)
+        Xb = torch.empty(batch_rows, self.din, dtype=torch.float32, device=_dev())
+        Tb = torch.empty(batch_rows, self.dout, dtype=torch.float32, device=_dev())
+        Mb = torch.empty_like(Tb)
         nb = rows // batch_rows
         losses = torch.zeros(nb, 2, dtype=torch.float64, device=_dev())   # per step (sum, count)
         part = torch.zeros(512, dtype=torch.float64, device=_dev())
-        mrow = M.sum(1)                       # mask entries per row (bookkeeping, once)
+        bad = torch.zeros(1, dtype=torch.int32, device=_dev())
         rng = np.random.default_rng(seed)
         history = []
         for ep in range(epochs):
-            order = torch.tensor(rng.permutation(rows), device=_dev())
-            # the masked-entry count of every minibatch, read with one transfer per epoch
-            counts = mrow[order[:nb * batch_rows]].view(nb, batch_rows).sum(1).cpu().numpy()
+            order = torch.tensor(rng.permutation(rows), dtype=torch.int64, device=_dev())
             for k in range(nb):
                 idx = order[k * batch_rows:(k + 1) * batch_rows]
-                Xb, Tb, Mb = X[idx].contiguous(), T[idx].contiguous(), M[idx].contiguous()
+                stotree.warm_gather(X, idx, Xb, bad)
+                stotree.warm_gather(T, idx, Tb, bad)
+                stotree.warm_gather(M, idx, Mb, bad)
                 stotree.warm_mlp_forward(batch_rows, self.din, self.dh, self.dout, self.params, Xb, H, Y)
-                stotree.warm_mse_grad(Y.numel(), Y, Tb, Mb, 1.0 / max(float(counts[k]), 1.0), dY, losses[k],
-                                      part)
+                # inverse count 0: the library forms 1 / (masked entries of the minibatch)
+                stotree.warm_mse_grad(Y.numel(), Y, Tb, Mb, 0.0, dY, losses[k], part)
                 stotree.warm_mlp_backward(batch_rows, self.din, self.dh, self.dout, self.params, Xb, H, dY,
                                           self.grad, work)
                 self.step += 1
                 stotree.warm_adam(self.params.numel(), self.params, self.grad, self.m, self.v, lr, 0.9, 0.999,
                                   1e-8, self.step)
             l2 = losses.cpu().numpy()        # one transfer per epoch
+            if int(bad.cpu()[0]):
+                raise RuntimeError("warm_gather: minibatch index out of range")
             history.append(l2[:, 0].sum() / max(l2[:, 1].sum(), 1.0))
             if log:
                 log(f"epoch {ep}: masked MSE {history[-1]:.4e}")

@@ -74,6 +74,46 @@ def test_forward_backward_loss_match_oracle(st):
     assert torch.equal(G, G2)
 
 
+def test_gather_and_device_count(st):
+    """Minibatch gather: rows picked by index (repeats allowed), an index
+    outside the source flagged without touching other rows; the loss
+    gradient with the count formed on the device equals the one with the
+    count given."""
+    import torch
+    rows = 1000
+    p, X, T, M = _net(3, rows)
+    Xd, Md = _f32(X), _f32(M)
+    idx_np = np.random.default_rng(4).integers(0, rows, 777)
+    idx_np[5] = idx_np[6]
+    idx = torch.tensor(idx_np, dtype=torch.int64, device="cuda:0")
+    dst = torch.full((777, DIN), -1.0, dtype=torch.float32, device="cuda:0")
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    st.warm_gather(Xd, idx, dst, bad)
+    torch.cuda.synchronize()
+    assert np.array_equal(dst.cpu().numpy(), X[idx_np]) and int(bad.cpu()[0]) == 0
+    idx_bad = idx.clone()
+    idx_bad[3] = rows            # one past the end
+    dst2 = torch.full((777, DIN), -1.0, dtype=torch.float32, device="cuda:0")
+    st.warm_gather(Xd, idx_bad, dst2, bad)
+    torch.cuda.synchronize()
+    d2 = dst2.cpu().numpy()
+    assert int(bad.cpu()[0]) == 1 and (d2[3] == -1.0).all()
+    keep = np.arange(777) != 3
+    assert np.array_equal(d2[keep], X[idx_np][keep])
+    # dY with the count formed on the device
+    Y = _f32(np.random.default_rng(5).standard_normal((rows, DOUT)))
+    Td = _f32(T)
+    dY1, dY2 = torch.empty_like(Y), torch.empty_like(Y)
+    l1 = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+    l2 = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+    part = torch.zeros(512, dtype=torch.float64, device="cuda:0")
+    st.warm_mse_grad(Y.numel(), Y, Td, Md, 1.0 / float(M.sum()), dY1, l1, part)
+    st.warm_mse_grad(Y.numel(), Y, Td, Md, 0.0, dY2, l2, part)
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l2)
+    assert np.abs(dY1.cpu().numpy() - dY2.cpu().numpy()).max() <= 1e-6 * np.abs(dY1.cpu().numpy()).max()
+
+
 def test_adam_matches_oracle(st):
     rng = np.random.default_rng(1)
     n = 1000
