@@ -104,19 +104,30 @@ __global__ void sum_rows_kernel(const float *part, int S, int n, float *out)
 
 // Loss 1/count sum mask (Y - T)^2 and its gradient dY = 2 mask (Y - T)/count.
 // Per-block partial sums of the loss and of the mask go to part[2*block].
-// Sum of the mask in one workgroup (fixed order), for the device-side count.
-__global__ void mask_count_kernel(long long n, const float *mask, float *inv_out)
+// Device-side count of the mask: per-block sums (fixed order) into part,
+// then one thread forms 1 / max(1, sum).
+__global__ void mask_count_kernel(long long n, const float *mask, double *part)
 {
     __shared__ double red[256];
     double c = 0.0;
-    for (long long k = threadIdx.x; k < n; k += blockDim.x) c += mask[k];
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        c += mask[k];
     red[threadIdx.x] = c;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) inv_out[0] = (float)(1.0 / (red[0] > 1.0 ? red[0] : 1.0));
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void mask_inverse_kernel(const double *part, int nb, float *inv_out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double c = 0.0;
+    for (int b = 0; b < nb; ++b) c += part[b];
+    inv_out[0] = (float)(1.0 / (c > 1.0 ? c : 1.0));
 }
 
 // inv_dev: the inverse count from mask_count_kernel, or null (inv_count given)
@@ -418,8 +429,10 @@ int mse_grad_impl(long long n, const float *Y, const float *T, const float *mask
     const int nb = 255;
     float *inv_dev = nullptr;
     if (inv_count == 0.0f) {
+        // the per-block counts use the scratch before the loss pairs overwrite it
         inv_dev = reinterpret_cast<float *>(part + 2 * nb);
-        hipLaunchKernelGGL(mask_count_kernel, dim3(1), dim3(256), 0, st, n, mask, inv_dev);
+        hipLaunchKernelGGL(mask_count_kernel, dim3(nb), dim3(256), 0, st, n, mask, part);
+        hipLaunchKernelGGL(mask_inverse_kernel, dim3(1), dim3(64), 0, st, part, nb, inv_dev);
     }
     hipLaunchKernelGGL(mse_grad_kernel, dim3(nb), dim3(256), 0, st, n, Y, T, mask, inv_count, inv_dev, dY, part);
     hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(64), 0, st, part, nb, loss2);
