@@ -180,6 +180,41 @@ def test_polling_interval_changes_no_iterate(st, method):
     tf.free()
 
 
+@pytest.mark.parametrize("trunk", [3, 4])
+def test_fused_trunk_solves_skip_finished_instances(st, trunk):
+    """Batched NAMA with each instance's first stages in one launch per
+    direction (trunk modes 3, 4): instances stop at different iterations and
+    are then skipped inside the fused launches, whose workgroups wait on one
+    another; polling every 1 or 5 iterations changes no bit, and every
+    instance's dual meets the tolerance in the oracle's residual."""
+    import torch
+    probs = solver_forest()
+    lams = []
+    for p in probs:
+        pb, fac = oracle.factor(p)
+        lams.append(1.0 / (1.1 * oracle.power_iteration(pb, fac, True, 300)))
+    lam = min(lams)
+    tf = st.tree_factor_batch(probs, precondition=True)
+    st.sweep_schedule(tf, (8, 1, 8, trunk, 16))
+    x0 = _t(np.concatenate([p.x0 for p in probs]))
+    out = []
+    for every in (1, 5):
+        y = _t(np.zeros(tf.m))
+        x = torch.zeros(tf.x_len, dtype=torch.float64, device="cuda:0")
+        u = torch.zeros(tf.u_len, dtype=torch.float64, device="cuda:0")
+        rc, _ = st.nama_solve(tf, x0, y, x, u, st.make_opts(lam=lam, eps=1e-8, check_every=every))
+        assert rc == 0
+        out.append((y.cpu().numpy(), x.cpu().numpy(), [i["iters"] for i in st.solve_info_batch(tf)]))
+    assert out[0][2] == out[1][2] and len(set(out[0][2])) > 1
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    for b, p in enumerate(probs):
+        (yb,) = _split(tf, b, y=out[0][0])
+        pb, fac = oracle.factor(p)
+        ev = oracle.evaluate(pb, fac, yb, lam, True)
+        assert np.abs(ev["R"]).max() <= 2e-8, b
+    tf.free()
+
+
 def test_uneven_batch_full_size_kkt(st):
     """The uneven batch at full size (256 trees, about 2.2M nodes), in the
     benchmark's launch configuration (autotuned schedule, one graph replay):
