@@ -40,13 +40,17 @@ def _both(st, tf, x0, y, homogeneous, nrhs):
     return out
 
 
-def test_noalloc_equals_dual_grad_on_two_calls(st):
+@pytest.mark.parametrize("trunk", [0, 4])
+def test_noalloc_equals_dual_grad_on_two_calls(st, trunk):
+    """trunk 4: the first stages above s* in one launch per direction, whose
+    child-side products pass through the caller's x and u outputs."""
     rng = np.random.default_rng(23)
     big = treegen.draw_problem(treegen.uniform_tree([4, 4, 4, 1, 1, 1]), 20, 10, rng)
     small = case("tiny")
-    print("noalloc: big tree nrhs 2, then tiny tree nrhs 1", flush=True)
+    print(f"noalloc (trunk mode {trunk}): big tree nrhs 2, then tiny tree nrhs 1", flush=True)
     for prob, nrhs in ((big, 2), (small, 1)):
         tf = st.tree_factor(prob, precondition=True)
+        st.sweep_schedule(tf, (8, 1, 16, trunk, 16))
         x0 = _dev(np.tile(prob.x0, nrhs))
         pb, fac = oracle.factor(prob)
         sc = row_scale(prob, True)
