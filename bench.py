@@ -729,8 +729,8 @@ def main():
     ap.add_argument("--warm-batch", type=int, default=256, help="draws per shared handle (a multiple of 64)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design "
-              "is described in DESIGN.md and is not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): sharding the sweep across GPUs "
+              "is designed but not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
