@@ -124,10 +124,15 @@ typedef struct {
      * iterations (an L from below, so a step at least 1/L). */
     int32_t backtrack;
     /* infeasibility test every div_window iterations (0: 50; < 0: off): the
-     * change of the dual over the window certifies that no point satisfies
-     * the dynamics and the constraints (it is annihilated by the dual
-     * Hessian and the dual objective falls linearly along it); the instance
-     * then stops with ERR_DIVERGED. */
+     * change d of the dual over the window certifies that no point satisfies
+     * the dynamics and the constraints (lambda ||H x-hat(d)|| <= 1e-3 ||d||:
+     * d is annihilated by the dual Hessian, and the dual objective falls
+     * along d at least 1e-3 ||d|| ||R||; for GPAD the first bound is
+     * 1e-5 ||d||); when two consecutive windows pass, the instance stops
+     * with ERR_DIVERGED.  The test is a numerical one: a
+     * feasible problem whose dual optimum is orders of magnitude beyond the
+     * dual's motion per window can be flagged (for example a constraint map
+     * that forces an unstable closed loop). */
     int32_t div_window;
     double bt_param;
     /* DEVICE [instances][trace_iters][40] or NULL: row k of an instance

@@ -965,13 +965,22 @@ static double inf_norm(int m, const double *a)
  *   sigma(d) - <d, Hb x(y^k)> <= -eps_div ||d||_inf ||R(y^k)||_inf,
  * with eps_div = 1e-3; rows with an infinite bound (and soft rows, whose g*
  * has a bounded domain) must carry no part of d (|d_k| <= 1e-9 ||d||_inf).
+ * Divergence is declared when two consecutive windows pass: along a true
+ * divergence direction every later window passes too (for MINFBE and NAMA
+ * the first ratio falls to rounding level, for GPAD it keeps falling), while
+ * the path of a feasible problem out of its start point can pass once.  For
+ * GPAD the first condition uses 1e-5 instead of eps_div: its momentum can
+ * carry a feasible, slowly converging problem along a nearly null direction
+ * for many windows (ratios near 3e-4 were measured).
  * Returns 1 on divergence.  One Algorithm-4 sweep per test.
  */
 #define OR_EPS_DIV 1e-3
-typedef struct { int last; double *yck; } or_divtest;
+#define OR_EPS_NULL_GPAD 1e-5
+#define OR_DIV_HITS 2
+typedef struct { int last; double *yck; int hits; } or_divtest;
 
 static int div_check(or_ctx *c, or_divtest *t, int window, int k, const double *y, const double *Hbx,
-                     const double *R)
+                     const double *R, double eps_null)
 {
     const int m = c->m;
     if (window <= 0 || k % window != 0 || k == t->last) return 0;
@@ -1001,7 +1010,9 @@ static int div_check(or_ctx *c, or_divtest *t, int window, int k, const double *
                 }
                 lin += (d[kk] > 0.0 ? hi * d[kk] : lo * d[kk]) - d[kk] * Hbx[kk];
             }
-            diverged = dom && c->lambda * hn <= OR_EPS_DIV * dn && lin <= -OR_EPS_DIV * dn * rn;
+            const int pass = dom && c->lambda * hn <= eps_null * dn && lin <= -OR_EPS_DIV * dn * rn;
+            t->hits = pass ? t->hits + 1 : 0;
+            diverged = t->hits >= OR_DIV_HITS;
         }
         free(d); free(hv);
     }
@@ -1035,7 +1046,7 @@ static int gpad(const or_problem *pb, const or_factors *f, const double *p,
     memcpy(yp, y_inout, sizeof(double) * m);
     double th = 1.0, thp = 1.0;
     double *hb = malloc(sizeof(double) * m);
-    or_divtest dt = {-1, malloc(sizeof(double) * m)};
+    or_divtest dt = {-1, malloc(sizeof(double) * m), 0};
     int status = 1, k = 0;
     double phi = 0.0;
     for (;;) {
@@ -1045,7 +1056,7 @@ static int gpad(const or_problem *pb, const or_factors *f, const double *p,
         const double rn = inf_norm(m, R);
         if (!isfinite(rn)) { status = -5; break; }
         if (rn <= o->eps) { status = 0; break; }
-        if (div_check(&c, &dt, o->div_window, k, w, hb, R)) { status = -6; break; }
+        if (div_check(&c, &dt, o->div_window, k, w, hb, R, OR_EPS_NULL_GPAD)) { status = -6; break; }
         if (k >= o->max_iter) { status = 1; break; }
         for (int kk = 0; kk < m; ++kk) {
             yp[kk] = y[kk];
@@ -1120,7 +1131,7 @@ int or_solve(const or_problem *pb, const or_factors *f, const double *p,
     int status = 1;
     double fh = 0.0;
     double *hb = malloc(sizeof(double) * m), *hbn = malloc(sizeof(double) * m);
-    or_divtest dt = {-1, malloc(sizeof(double) * m)};
+    or_divtest dt = {-1, malloc(sizeof(double) * m), 0};
 
     /* phi, R (and grad phi for MINFBE) at y with the current lambda */
 #define EVAL_AT_Y()                                                          \
@@ -1138,7 +1149,7 @@ int or_solve(const or_problem *pb, const or_factors *f, const double *p,
         const double rn = inf_norm(m, R);
         if (!isfinite(rn) || !isfinite(phi)) { status = -5; break; }
         if (rn <= o->eps) { status = 0; break; }
-        if (div_check(&c, &dt, o->div_window, k, y, hb, R)) { status = -6; break; }
+        if (div_check(&c, &dt, o->div_window, k, y, hb, R, OR_EPS_DIV)) { status = -6; break; }
         if (k >= o->max_iter) { status = 1; break; }
 
         int halve = 0;

@@ -53,7 +53,9 @@ constexpr int kVB = 256;      // threads per block of the vector kernels
 constexpr int kBtMax = 50;     // halvings of lambda before an instance gives up
 constexpr int kTraceCols = 40; // trace row: lambda, res, accepted nu, nu_max, pairs, dphi[nu]...
 constexpr int kTracePhi = 5;
-constexpr double kEpsDiv = 1e-3;  // tolerance of the infeasibility test
+constexpr double kEpsDiv = 1e-3;   // tolerance of the infeasibility test
+constexpr double kEpsNullGpad = 1e-5;  // its null-space part for GPAD (see fin_div_kernel)
+constexpr int kDivHits = 2;        // consecutive windows that must pass it
 
 // reduction slots
 constexpr int R_MAX = 0, R_MAXU = 1, R_MAX3 = 2, R_SS = 3, R_BAD = 4, PB = 5;
@@ -69,6 +71,7 @@ struct Ctl {
     int max_iter, mem, nu_max, method;
     int buf, bt_pending, backtracks, backtrack;
     int ck_set, div_now, div_store, nodiv;
+    int div_hits;                         // consecutive windows that passed the infeasibility test
     int order[kMemMax];
     double lam, eps, eps_curv, tau, cr;
     double res, resu, rr, gg_prev, gamma;
@@ -773,7 +776,13 @@ __global__ void __launch_bounds__(kVB) fin_div_kernel(Ctl *ctl, const double *pa
     c->nodiv = 1;
     c->sweeps_hom++;
     const double dn = red[0], hn = red[1], dbad = red[2], lin = red[kNMax];
-    if (dn > 0.0 && dbad <= 1e-9 * dn && c->lam * hn <= kEpsDiv * dn && lin <= -kEpsDiv * dn * c->res) {
+    // GPAD's momentum carries a feasible but slowly converging problem along
+    // a nearly null direction for many windows (ratios near 3e-4 were seen):
+    // its null-space part is held to a tighter tolerance
+    const double eps_null = c->method == 2 ? kEpsNullGpad : kEpsDiv;
+    const bool pass = dn > 0.0 && dbad <= 1e-9 * dn && c->lam * hn <= eps_null * dn && lin <= -kEpsDiv * dn * c->res;
+    c->div_hits = pass ? c->div_hits + 1 : 0;
+    if (c->div_hits >= kDivHits) {
         c->done = 1;
         c->status = STOTREE_ERR_DIVERGED;
     } else if (c->iter >= c->max_iter) {

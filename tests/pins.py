@@ -94,6 +94,20 @@ def general_map(seed=13, nc=3, ncN=2):
     raise RuntimeError("no feasible draw")
 
 
+def general_map_noleaf(seed=13):
+    """A constraint map with no leaf rows (ncN = 0): z_i = F x_i + G u_i,
+    |z| <= 0.3, with a weak state coupling (F ~ 0.15 N(0, 1)).  A strong
+    coupling with no leaf rows can force an unstable closed loop: feasible,
+    but with primal costs near 1e6 and dual optima near 1e7."""
+    rng = np.random.default_rng(seed)
+    pr = treegen.draw_problem(treegen.uniform_tree([2, 2, 2, 1, 1]), 4, 2, rng, x0_range=1.5)
+    F = rng.standard_normal((2, pr.nx)) * 0.15
+    G = rng.standard_normal((2, pr.nu))
+    pr = treegen.with_constraint_map(pr, F, G, np.zeros((0, pr.nx)), -0.3, 0.3, -1.5, 1.5)
+    assert feasible(pr)
+    return pr
+
+
 def soft_rows(prob, seed=17, frac=0.5):
     """``prob`` with about ``frac`` of its finite rows made soft: weights
     U[0.5, 3], half of them with a Huber threshold U[0.05, 0.5], and every
