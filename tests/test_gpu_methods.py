@@ -145,30 +145,55 @@ def test_line_search_trace_matches_oracle(st, method, name, nu_max):
 
 
 # ------------------------------- backtracking ------------------------------- #
+def _rounding_horizon(pb, fac, method, lam0, ref, seeds=(0, 1), **kw):
+    """First update at which the oracle's own step decisions change when the
+    starting dual point moves by 1e-14: past it, rounding differences alone
+    (amplified along directions where the dual is flat) can change a
+    line-search decision, so two correct implementations may legitimately
+    take different paths to the same solution."""
+    h = ref["iters"]
+    for seed in seeds:
+        y0 = np.random.default_rng(seed).standard_normal(pb.m) * 1e-14
+        q = oracle.solve(pb, fac, method, lam0, y0=y0, **kw)
+        m = min(ref["iters"], q["iters"], len(ref["trace"]))
+        d = np.nonzero(ref["trace"][:m, 2] != q["trace"][:m, 2])[0]
+        h = min(h, int(d[0]) if len(d) else m)
+    return h
+
+
+@pytest.mark.parametrize("name", ["tight_tiny", "general_soft", "general_noleaf"])
 @pytest.mark.parametrize("method", ["minfbe", "nama"])
 @pytest.mark.parametrize("rule,param", [(1, 0.1), (2, 0.4)])
-def test_backtracking_matches_oracle(st, method, rule, param):
-    prob = pins.tight_tiny()
-    print(f"backtrack {method} rule {rule}", flush=True)
+def test_backtracking_matches_oracle(st, name, method, rule, param):
+    prob = _cases()[name]()
+    print(f"backtrack {name} {method} rule {rule}", flush=True)
     pb, fac, L = _setup(prob)
     lam0 = 64.0 / (1.1 * L)
-    ref = oracle.solve(pb, fac, method, lam0, eps=1e-9, max_iter=3000, backtrack=rule, bt_param=param,
-                       trace_iters=400)
+    kw = dict(eps=1e-9, max_iter=3000, backtrack=rule, bt_param=param, trace_iters=400)
+    ref = oracle.solve(pb, fac, method, lam0, **kw)
     tf = st.tree_factor(prob, precondition=True)
-    g = _solve(st, tf, prob, method, lam0, eps=1e-9, max_iter=3000, backtrack=rule, bt_param=param,
-               trace_iters=400)
+    g = _solve(st, tf, prob, method, lam0, **kw)
     assert ref["status"] == 0 and g["rc"] == 0
-    assert g["info"]["backtracks"] == ref["backtracks"] >= 1
-    assert g["info"]["lam"] == pytest.approx(ref["lambda_final"], rel=1e-15)
     # the lambda sequence and the step decisions agree while the decisions
-    # are above rounding level
-    n = _robust_prefix(ref["trace"][:ref["iters"]], 10, 1e-9 * max(1.0, abs(ref["phi"])))
+    # are above rounding level and stable under rounding-size perturbations
+    n = min(_robust_prefix(ref["trace"][:ref["iters"]], 10, 1e-9 * max(1.0, abs(ref["phi"]))),
+            _rounding_horizon(pb, fac, method, lam0, ref, **kw))
     assert n >= 5, n
     assert np.array_equal(g["trace"][:n, 0], ref["trace"][:n, 0])
     assert np.array_equal(g["trace"][:n, 2], ref["trace"][:n, 2])
     assert np.array_equal(g["trace"][:n, 4], ref["trace"][:n, 4])
-    # every halving happened inside that prefix
-    assert ref["trace"][n - 1, 0] == ref["lambda_final"]
+    b = g["info"]["backtracks"]
+    assert b >= 1 and g["info"]["lam"] == lam0 * 0.5 ** b
+    if ref["trace"][n - 1, 0] == ref["lambda_final"]:
+        # every halving happened inside that prefix
+        assert b == ref["backtracks"]
+        assert g["info"]["lam"] == pytest.approx(ref["lambda_final"], rel=1e-15)
+    else:
+        # later halvings follow the GPU's own path: a halving needs
+        # lambda L above the rule's threshold, so lambda stays above half of it
+        thr = (1.0 - param) if rule == 1 else param
+        assert b >= int(round(np.log2(lam0 / ref["trace"][n - 1, 0])))
+        assert thr / (2 * L) * (1 - 1e-9) < g["info"]["lam"]
     scale = max(1.0, np.abs(ref["x"]).max(), np.abs(ref["u"]).max())
     assert np.abs(g["x"] - ref["x"]).max() / scale < TOL_PRIMAL
     tf.free()

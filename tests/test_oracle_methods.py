@@ -100,15 +100,17 @@ def test_gpad_reaches_interior_point_solution(name):
 
 
 # ------------------------------- backtracking ------------------------------ #
+@pytest.mark.parametrize("name", ["tight_tiny", "general_soft", "general_noleaf"])
 @pytest.mark.parametrize("method", ["minfbe", "nama"])
 @pytest.mark.parametrize("rule,param", [(1, 0.1), (2, 0.4)])
-def test_backtracking_from_a_large_step(method, rule, param):
+def test_backtracking_from_a_large_step(name, method, rule, param):
     """Started at lambda_0 = 64 / (1.1 L) >> 1/L, both tests of Sec. III-B
     bring lambda down and the solve still reaches the interior-point
     solution; a halving needs lambda L > 1 - beta (the descent lemma) or
     lambda L > eps'' (||Hess r|| <= L ||r||), so the final lambda stays above
-    half of that threshold."""
-    prob = pins.tight_tiny()
+    half of that threshold. The constraint-map cases take both tests through
+    H x with F, G rows and soft (Huber) rows, with and without leaf rows."""
+    prob = pins.tight_tiny() if name == "tight_tiny" else _soft_cases()[name]
     pb, fac, L = _lam(prob)
     lam0 = 64.0 / (1.1 * L)
     r = oracle.solve(pb, fac, method, lam0, eps=1e-9, max_iter=3000, backtrack=rule, bt_param=param)
