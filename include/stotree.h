@@ -127,7 +127,7 @@ typedef struct {
      * change d of the dual over the window certifies that no point satisfies
      * the dynamics and the constraints (lambda ||H x-hat(d)|| <= 1e-3 ||d||:
      * d is annihilated by the dual Hessian, and the dual objective falls
-     * along d at least 1e-3 ||d|| ||R||; for GPAD the first bound is
+     * along d at least 1e-4 ||d|| ||R||; for GPAD the first bound is
      * 1e-5 ||d||); when two consecutive windows pass, the instance stops
      * with ERR_DIVERGED.  The test is a numerical one: a
      * feasible problem whose dual optimum is orders of magnitude beyond the

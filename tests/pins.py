@@ -108,6 +108,26 @@ def general_map_noleaf(seed=13):
     return pr
 
 
+# Reduced uneven-batch draws (scale 0.02, nx 4..10, N 5..10) with |u| <= 0.1
+# that an LP proves infeasible and whose separating direction is weak in the
+# norms of the infeasibility test: along the null direction the iterates run
+# off on, the dual objective falls by only 3.9e-4 to 1.1e-3 of ||d|| ||R||.
+WEAK_INFEASIBLE = ((0, 0), (5, 5), (25, 1), (27, 5))
+# such a draw whose fall under NAMA (1.5e-4) is within a factor 1.5 of the
+# bound, and one whose fall (8.4e-5) is below it
+NEAR_BOUND_INFEASIBLE = (11, 0)
+WEAKER_INFEASIBLE = (7, 5)
+
+
+def reduced_uneven_boxed(seed, b):
+    """Instance b of a reduced uneven batch (``seed``) with |u| <= 0.1,
+    certified infeasible by an LP."""
+    p = treegen.draw_batch_instances(8, seed=seed, scale=0.02, nx_range=(4, 10), N_range=(5, 10))[b]
+    pr = treegen.with_boxes(p, ubox=0.1)
+    assert not feasible(pr)
+    return pr
+
+
 def soft_rows(prob, seed=17, frac=0.5):
     """``prob`` with about ``frac`` of its finite rows made soft: weights
     U[0.5, 3], half of them with a Huber threshold U[0.05, 0.5], and every

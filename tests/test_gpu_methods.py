@@ -236,6 +236,43 @@ def test_infeasible_problem_reports_diverged(st, method):
     tf.free()
 
 
+def test_weakly_separated_infeasible_batch_is_flagged(st):
+    """The LP-infeasible draws whose objective falls by only 3.9e-4 to 1.1e-3
+    of ||d|| ||R|| along the run-off direction, in one handle with a
+    feasible instance: both methods flag each of them within a window of
+    the oracle (the windows are 50 updates apart and the paths differ by
+    rounding) and solve the feasible one.  The draw whose fall is within a
+    factor 1.5 of the bound may be flagged or run to the limit, since a
+    rounding-level difference can move one window across the bound; it is
+    never reported solved."""
+    import torch
+    good = pins.tight_tiny()
+    cases = list(pins.WEAK_INFEASIBLE) + [pins.NEAR_BOUND_INFEASIBLE]
+    probs = [pins.reduced_uneven_boxed(*c) for c in cases] + [good]
+    tf = st.tree_factor_batch(probs, precondition=True)
+    x0 = _t(np.concatenate([p.x0 for p in probs]))
+    for method in ("minfbe", "nama"):
+        print(f"weak infeasible batch {method}", flush=True)
+        y = _t(np.zeros(tf.m))
+        x = torch.zeros(tf.x_len, dtype=torch.float64, device="cuda:0")
+        u = torch.zeros(tf.u_len, dtype=torch.float64, device="cuda:0")
+        fn = {"minfbe": st.minfbe_solve, "nama": st.nama_solve}[method]
+        with pytest.raises(st.StotreeError) as ei:
+            fn(tf, x0, y, x, u, st.make_opts(eps=1e-6, max_iter=3000, div_window=50))
+        assert ei.value.code == -6
+        infos = st.solve_info_batch(tf)
+        assert infos[-1]["status"] == 0
+        for c, p, info in zip(cases, probs[:-1], infos[:-1]):
+            if c == pins.NEAR_BOUND_INFEASIBLE:
+                assert info["status"] in (-6, 1), (c, info["status"])
+                continue
+            pb, fac = oracle.factor(p)
+            ref = oracle.solve(pb, fac, method, info["lam"], eps=1e-6, max_iter=3000, div_window=50)
+            assert ref["status"] == -6 and info["status"] == -6, (c, ref["status"], info["status"])
+            assert abs(info["iters"] - ref["iters"]) <= 50, (c, info["iters"], ref["iters"])
+    tf.free()
+
+
 def test_batch_stops_only_the_infeasible_instance(st):
     good = pins.tight_tiny()
     bad = treegen.with_boxes(pins.tight_tiny(), xbox=0.05, ubox=0.05)

@@ -166,6 +166,31 @@ def test_infeasible_problem_is_reported_diverged(method):
     assert off["status"] == 1 and np.abs(off["y"]).max() > 2 * np.abs(r["y"]).max()
 
 
+@pytest.mark.parametrize("case", pins.WEAK_INFEASIBLE + (pins.NEAR_BOUND_INFEASIBLE,))
+@pytest.mark.parametrize("method", ["minfbe", "nama"])
+def test_weakly_separated_infeasible_problems_are_flagged(case, method):
+    """LP-infeasible draws whose iterates run off along a null direction
+    (first ratio 1e-7 and below) while the objective falls by only 1.5e-4 to
+    1.1e-3 of ||d|| ||R||: the objective bound of the test must sit below
+    that for them to be flagged (with a bound of 1e-3 NAMA ran all of them
+    to 3,000 updates)."""
+    prob = pins.reduced_uneven_boxed(*case)
+    pb, fac, L = _lam(prob)
+    r = oracle.solve(pb, fac, method, 1 / (1.1 * L), eps=1e-6, max_iter=3000, div_window=50)
+    assert r["status"] == -6 and r["iters"] <= 300
+
+
+@pytest.mark.parametrize("method", ["minfbe", "nama"])
+def test_infeasible_problem_below_the_bound_is_never_solved(method):
+    """An LP-infeasible draw whose separating direction is weaker still
+    escapes the test: it must stop at the iteration limit, never with a
+    converged status."""
+    prob = pins.reduced_uneven_boxed(*pins.WEAKER_INFEASIBLE)
+    pb, fac, L = _lam(prob)
+    r = oracle.solve(pb, fac, method, 1 / (1.1 * L), eps=1e-6, max_iter=3000, div_window=50)
+    assert r["status"] == 1 and r["iters"] == 3000
+
+
 @pytest.mark.parametrize("method", ["minfbe", "nama", "gpad"])
 def test_feasible_problems_are_not_flagged(method):
     """Includes general_noleaf, whose first window passed the test under
