@@ -236,6 +236,30 @@ def test_infeasible_problem_reports_diverged(st, method):
     tf.free()
 
 
+@pytest.mark.parametrize("method", ["minfbe", "nama", "gpad"])
+def test_step_above_two_over_L_reports_numeric_error(st, method):
+    """lambda fixed by the host at 4/L and 16/L, no backtracking: the device
+    stops with ERR_NUMERIC, as the oracle does, and never reports a solve."""
+    import torch
+    prob = pins.tight_tiny()
+    pb, fac, L = _setup(prob)
+    tf = st.tree_factor(prob, precondition=True)
+    fn = {"minfbe": st.minfbe_solve, "nama": st.nama_solve, "gpad": st.gpad_solve}[method]
+    for scale in (4.0, 16.0):
+        print(f"lambda {scale}/L {method}", flush=True)
+        ref = oracle.solve(pb, fac, method, scale / L, eps=1e-9, max_iter=2000)
+        assert ref["status"] == -5
+        y = _t(np.zeros(tf.m))
+        x = torch.zeros(tf.V, tf.nx, dtype=torch.float64, device="cuda:0")
+        u = torch.zeros(tf.Vnl, tf.nu, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(st.StotreeError) as ei:
+            fn(tf, _t(prob.x0), y, x, u, st.make_opts(lam=scale / L, eps=1e-9, max_iter=2000))
+        assert ei.value.code == -5
+        info = st.solve_info_batch(tf)[0]
+        assert info["status"] == -5 and info["iters"] < 2000
+    tf.free()
+
+
 def test_weakly_separated_infeasible_batch_is_flagged(st):
     """The LP-infeasible draws whose objective falls by only 3.9e-4 to 1.1e-3
     of ||d|| ||R|| along the run-off direction, in one handle with a

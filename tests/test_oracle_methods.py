@@ -166,6 +166,25 @@ def test_infeasible_problem_is_reported_diverged(method):
     assert off["status"] == 1 and np.abs(off["y"]).max() > 2 * np.abs(r["y"]).max()
 
 
+@pytest.mark.parametrize("name", ["tight_tiny", "general_soft"])
+@pytest.mark.parametrize("method", ["minfbe", "nama", "gpad"])
+def test_step_above_two_over_L_is_never_reported_solved(name, method):
+    """A fixed lambda above 2/L (no backtracking) makes the forward-backward
+    step expansive: every method stops on non-finite values at 4/L and
+    16/L; a converged status needs a residual that an independent
+    evaluation confirms (NAMA's line search can still converge at 2.5/L)."""
+    prob = pins.tight_tiny() if name == "tight_tiny" else _soft_cases()[name]
+    pb, fac, L = _lam(prob)
+    for scale in (2.5, 4.0, 16.0):
+        r = oracle.solve(pb, fac, method, scale / L, eps=1e-9, max_iter=2000)
+        if scale > 2.5:
+            assert r["status"] == -5, (scale, r["status"], r["iters"])
+        assert r["status"] in (0, -5), (scale, r["status"])
+        if r["status"] == 0:
+            ev = oracle.evaluate(pb, fac, r["y"], scale / L, True)
+            assert np.isfinite(r["y"]).all() and np.abs(ev["R"]).max() <= 1e-9 * (1 + 1e-6)
+
+
 @pytest.mark.parametrize("case", pins.WEAK_INFEASIBLE + (pins.NEAR_BOUND_INFEASIBLE,))
 @pytest.mark.parametrize("method", ["minfbe", "nama"])
 def test_weakly_separated_infeasible_problems_are_flagged(case, method):
