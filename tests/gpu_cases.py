@@ -68,6 +68,14 @@ def case(name):
         return treegen.draw_problem(treegen.capped_tree(8, 13, 3), 24, 12, rng)
     if name == "shared_blocks":      # shared-tree blocks (nx=64, nu=32) on a small tree
         return treegen.draw_problem(treegen.uniform_tree([4, 4, 1, 1, 1]), 64, 32, rng)
+    if name == "scalar":          # nx = nu = 1
+        return treegen.draw_problem(treegen.uniform_tree([3, 2, 1, 1]), 1, 1, rng)
+    if name == "scalar_chain":    # nx = nu = 1 on a single chain (s* = 0)
+        return treegen.draw_problem(treegen.uniform_tree([1] * 6), 1, 1, rng)
+    if name == "one_stage":       # N = 1: the root and its leaves
+        return treegen.draw_problem(treegen.uniform_tree([5]), 4, 3, rng)
+    if name == "single_input":    # nu = 1 (the two-row pair layout has one input row)
+        return treegen.draw_problem(treegen.uniform_tree([2, 2, 1, 1, 1]), 6, 1, rng)
     if name == "warm_blocks":
         return treegen.draw_problem(treegen.uniform_tree([3, 3, 1, 1, 1, 1]), 20, 10, rng,
                                     x0_range=3.0)
@@ -75,7 +83,7 @@ def case(name):
 
 
 SWEEP_CASES = ["tiny", "odd_ragged", "large_blocks", "wide", "widest", "single_path", "no_chain", "capped",
-               "mid_width", "warm_blocks", "fanout"]
+               "mid_width", "warm_blocks", "fanout", "scalar", "scalar_chain", "one_stage", "single_input"]
 
 
 def with_tight_boxes(prob, xbox, ubox):
