@@ -29,6 +29,11 @@ def solver_cases():
         "tight_tiny": pins.tight_tiny,
         "ragged_cross": pins.ragged_cross,
         "warm_tight": lambda: with_tight_boxes(case("warm_blocks"), 3.0, 0.4),
+        # degenerate shapes with binding input bounds
+        "scalar_tight": lambda: with_tight_boxes(case("scalar"), 2.0, 0.3),
+        "scalar_chain_tight": lambda: with_tight_boxes(case("scalar_chain"), 2.0, 0.3),
+        "one_stage_tight": lambda: with_tight_boxes(case("one_stage"), 2.0, 0.05),
+        "single_input_tight": lambda: with_tight_boxes(case("single_input"), 5.0, 0.6),
     }
 
 
@@ -44,7 +49,8 @@ def _gpu_solve(st, tf, prob, method, lam, y0=None, **kw):
 
 
 @pytest.mark.parametrize("method", ["minfbe", "nama"])
-@pytest.mark.parametrize("name", ["tight_tiny", "ragged_cross", "warm_tight"])
+@pytest.mark.parametrize("name", ["tight_tiny", "ragged_cross", "warm_tight", "scalar_tight", "scalar_chain_tight",
+                                  "one_stage_tight", "single_input_tight"])
 def test_solution_matches_oracle(st, method, name):
     prob = solver_cases()[name]()
     print(f"{method} {name}", flush=True)

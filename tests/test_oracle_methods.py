@@ -99,6 +99,24 @@ def test_gpad_reaches_interior_point_solution(name):
     assert max(np.abs(r["x"] - x).max(), np.abs(r["u"] - u).max()) < 1e-6
 
 
+@pytest.mark.parametrize("name,xbox,ubox", [("scalar", 2.0, 0.3), ("scalar_chain", 2.0, 0.3),
+                                            ("one_stage", 2.0, 0.05), ("single_input", 5.0, 0.6)])
+@pytest.mark.parametrize("method", ["minfbe", "nama"])
+def test_degenerate_shapes_reach_the_interior_point_solution(name, xbox, ubox, method):
+    """nx = nu = 1, a scalar single chain, a one-stage tree and a single
+    input, each with binding input bounds: the solve ends at the dense
+    interior-point solution."""
+    from gpu_cases import case, with_tight_boxes
+    prob = with_tight_boxes(case(name), xbox, ubox)
+    assert pins.feasible(prob)
+    pb, fac, L = _lam(prob)
+    r = oracle.solve(pb, fac, method, 1 / (1.1 * L), eps=1e-10, max_iter=5000)
+    assert r["status"] == 0
+    x, u, opt = _ipm_soft(prob)
+    assert np.isclose(np.abs(u), ubox, atol=1e-7).any()          # a bound binds
+    assert max(np.abs(r["x"] - x).max(), np.abs(r["u"] - u).max()) < 1e-6
+
+
 # ------------------------------- backtracking ------------------------------ #
 @pytest.mark.parametrize("name", ["tight_tiny", "general_soft", "general_noleaf"])
 @pytest.mark.parametrize("method", ["minfbe", "nama"])
