@@ -128,7 +128,7 @@ typedef struct {
      * the dynamics and the constraints (lambda ||H x-hat(d)|| <= 1e-3 ||d||:
      * d is annihilated by the dual Hessian, and the dual objective falls
      * along d at least 1e-4 ||d|| ||R||; for GPAD the first bound is
-     * 1e-5 ||d||); when two consecutive windows pass, the instance stops
+     * 1e-4 ||d||); when two consecutive windows pass, the instance stops
      * with ERR_DIVERGED.  The test is a numerical one: a
      * feasible problem whose dual optimum is orders of magnitude beyond the
      * dual's motion per window can be flagged (for example a constraint map

@@ -974,9 +974,11 @@ static double inf_norm(int m, const double *a)
  * divergence direction every later window passes too (for MINFBE and NAMA
  * the first ratio falls to rounding level, for GPAD it keeps falling), while
  * the path of a feasible problem out of its start point can pass once.  For
- * GPAD the first condition uses 1e-5 instead of eps_div: its momentum can
+ * GPAD the first condition uses 1e-4 instead of eps_div: its momentum can
  * carry a feasible, slowly converging problem along a nearly null direction
- * for many windows (ratios near 3e-4 were measured).  The second bound is
+ * for many windows (ratios of 2e-4 to 6e-4 were measured), while on
+ * infeasible problems its ratio falls below 1e-4 within a few hundred
+ * updates.  The second bound is
  * the looser one because the null-space ratio is what separates the two
  * cases: on infeasible problems whose iterates run along a null direction
  * (first ratio 1e-9 and below) the objective ratio settles between 5e-4
@@ -986,7 +988,7 @@ static double inf_norm(int m, const double *a)
  */
 #define OR_EPS_DIV 1e-3
 #define OR_EPS_OBJ 1e-4
-#define OR_EPS_NULL_GPAD 1e-5
+#define OR_EPS_NULL_GPAD 1e-4
 #define OR_DIV_HITS 2
 typedef struct { int last; double *yck; int hits; } or_divtest;
 

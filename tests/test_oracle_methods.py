@@ -231,9 +231,9 @@ def test_infeasible_problem_below_the_bound_is_never_solved(method):
 @pytest.mark.parametrize("method", ["minfbe", "nama", "gpad"])
 def test_feasible_problems_are_not_flagged(method):
     """Includes general_noleaf, whose first window passed the test under
-    MINFBE and whose GPAD path passes it for seven windows in a row before it
-    turns: the test needs two consecutive windows (and for GPAD a 1e-5
-    null-space bound)."""
+    MINFBE and whose GPAD path stays within a 1e-3 null-space ratio (2e-4 to
+    6e-4) for seven windows in a row before it turns: the test needs two
+    consecutive windows (and for GPAD a 1e-4 null-space bound)."""
     for prob in (pins.tight_tiny(), pins.ragged_cross(), pins.general_map(), pins.general_map_noleaf()):
         pb, fac, L = _lam(prob)
         r = oracle.solve(pb, fac, method, 1 / (1.1 * L), eps=1e-8, max_iter=40000, div_window=50)
