@@ -950,7 +950,7 @@ static double inf_norm(int m, const double *a)
 {
     double s = 0.0;
     for (int k = 0; k < m; ++k) {
-        if (isnan(a[k])) return NAN;
+        if (isnan(a[k]) && or_mutation != 12) return NAN;
         s = fmax(s, fabs(a[k]));
     }
     return s;
@@ -1067,7 +1067,7 @@ static int gpad(const or_problem *pb, const or_factors *f, const double *p,
         for (int kk = 0; kk < m; ++kk) w[kk] = y[kk] + beta * (y[kk] - yp[kk]);
         phi = ctx_eval(&c, w, hb, R, NULL, NULL);
         const double rn = inf_norm(m, R);
-        if (!isfinite(rn) || !isfinite(phi)) { status = -5; break; }
+        if (!isfinite(rn) || (!isfinite(phi) && or_mutation != 12)) { status = -5; break; }
         if (rn <= o->eps) { status = 0; break; }
         if (div_check(&c, &dt, o->div_window, k, w, hb, R, OR_EPS_NULL_GPAD)) { status = -6; break; }
         if (k >= o->max_iter) { status = 1; break; }

@@ -75,8 +75,8 @@ def test_mutation_is_caught(k):
     assert fails, f"mutation {k} ({MUTATIONS[k]}) passed every pin"
 
 
-# Mistakes in the accelerated gradient, the soft-row prox and the
-# backtracking, each caught by the pin written for that part.
+# Mistakes in the accelerated gradient, the soft-row prox, the backtracking
+# and the non-finite test, each caught by the pin written for that part.
 def _targeted():
     import test_oracle_methods as tm
     return {
@@ -86,10 +86,12 @@ def _targeted():
              lambda: tm.test_soft_prox_by_scalar_minimisation("tiny_soft")),
         11: ("lambda halved without emptying the L-BFGS buffer",
              lambda: tm.test_halving_empties_the_lbfgs_buffer("nama")),
+        12: ("residual norm skips NaN entries and GPAD checks only that norm",
+             lambda: tm.test_step_above_two_over_L_is_never_reported_solved("tight_tiny", "gpad")),
     }
 
 
-@pytest.mark.parametrize("k", [9, 10, 11])
+@pytest.mark.parametrize("k", [9, 10, 11, 12])
 def test_targeted_mutation_is_caught(k):
     desc, pin = _targeted()[k]
     pin()                                   # passes on the correct oracle
