@@ -55,13 +55,15 @@ using namespace dev;
 // last, partial batch re-reads its final row in the unused slots (and skips
 // them in the sums), so no row is ever loaded on its own.
 constexpr int kRowBatch = 8;
+// the backward chain steps of 64-lane groups measured fastest with batches of 6 rows
+constexpr int kChainRowBatch = 6;
 
-template <int CH>
-__device__ __forceinline__ void load_rows(double2 (&m)[kRowBatch][CH], const double *__restrict__ M,
+template <int CH, int RB = kRowBatch>
+__device__ __forceinline__ void load_rows(double2 (&m)[RB][CH], const double *__restrict__ M,
                                           int ld, int r, int cnt, const int (&col)[CH])
 {
 #pragma unroll
-    for (int u = 0; u < kRowBatch; ++u) {
+    for (int u = 0; u < RB; ++u) {
         const int rr = r + (u < cnt ? u : cnt - 1);
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch)
@@ -69,12 +71,12 @@ __device__ __forceinline__ void load_rows(double2 (&m)[kRowBatch][CH], const dou
     }
 }
 
-template <int NRHS, int CH>
-__device__ __forceinline__ void fma_rows(const double2 (&m)[kRowBatch][CH], const double *v, int ldv,
+template <int NRHS, int CH, int RB = kRowBatch>
+__device__ __forceinline__ void fma_rows(const double2 (&m)[RB][CH], const double *v, int ldv,
                                          int r, int cnt, double (&acc)[NRHS][CH][2])
 {
 #pragma unroll
-    for (int u = 0; u < kRowBatch; ++u) {
+    for (int u = 0; u < RB; ++u) {
         if (u >= cnt) break;
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
@@ -88,7 +90,7 @@ __device__ __forceinline__ void fma_rows(const double2 (&m)[kRowBatch][CH], cons
     }
 }
 
-template <int NRHS, int CH, int G = kWave>
+template <int NRHS, int CH, int G = kWave, int RB = kRowBatch>
 __device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, int r0, int r1, int W,
                                           const double *v, int ldv, double (&acc)[NRHS][CH][2],
                                           int lane)
@@ -101,18 +103,18 @@ __device__ __forceinline__ void gemv_rows(const double *__restrict__ M, int ld, 
         const int c0 = 2 * lane + 2 * G * ch;
         col[ch] = c0 < W ? c0 : 0;
     }
-    const int nbt = (n + kRowBatch - 1) / kRowBatch;   // batches, the last one possibly partial
-    auto cnt = [&](int b) { return n - b * kRowBatch < kRowBatch ? n - b * kRowBatch : kRowBatch; };
-    double2 m0[kRowBatch][CH], m1[kRowBatch][CH];
-    load_rows<CH>(m0, M, ld, r0, cnt(0), col);
+    const int nbt = (n + RB - 1) / RB;   // batches, the last one possibly partial
+    auto cnt = [&](int b) { return n - b * RB < RB ? n - b * RB : RB; };
+    double2 m0[RB][CH], m1[RB][CH];
+    load_rows<CH, RB>(m0, M, ld, r0, cnt(0), col);
     int b = 0;
     for (; b + 2 <= nbt; b += 2) {
-        load_rows<CH>(m1, M, ld, r0 + (b + 1) * kRowBatch, cnt(b + 1), col);
-        fma_rows<NRHS, CH>(m0, v, ldv, r0 + b * kRowBatch, kRowBatch, acc);
-        if (b + 2 < nbt) load_rows<CH>(m0, M, ld, r0 + (b + 2) * kRowBatch, cnt(b + 2), col);
-        fma_rows<NRHS, CH>(m1, v, ldv, r0 + (b + 1) * kRowBatch, cnt(b + 1), acc);
+        load_rows<CH, RB>(m1, M, ld, r0 + (b + 1) * RB, cnt(b + 1), col);
+        fma_rows<NRHS, CH, RB>(m0, v, ldv, r0 + b * RB, RB, acc);
+        if (b + 2 < nbt) load_rows<CH, RB>(m0, M, ld, r0 + (b + 2) * RB, cnt(b + 2), col);
+        fma_rows<NRHS, CH, RB>(m1, v, ldv, r0 + (b + 1) * RB, cnt(b + 1), acc);
     }
-    if (b < nbt) fma_rows<NRHS, CH>(m0, v, ldv, r0 + b * kRowBatch, cnt(b), acc);
+    if (b < nbt) fma_rows<NRHS, CH, RB>(m0, v, ldv, r0 + b * RB, cnt(b), acc);
 }
 
 // The product of gemv_rows split in two so that its loads can be issued
@@ -174,22 +176,23 @@ __device__ __forceinline__ void stream_run(RowStream<CH> &s, const double *v, in
 // half owns columns 2l, 2l+1); the halves' partial sums are added at the end,
 // so the lower half holds the sums and the upper half (whose own columns are
 // >= G) a copy.
-__device__ __forceinline__ void load_pairs(double2 (&m)[kRowBatch], const double *__restrict__ M, int ld,
+template <int RB = kRowBatch>
+__device__ __forceinline__ void load_pairs(double2 (&m)[RB], const double *__restrict__ M, int ld,
                                            int rfirst, int rlast, int col)
 {
 #pragma unroll
-    for (int u = 0; u < kRowBatch; ++u) {
+    for (int u = 0; u < RB; ++u) {
         const int r = rfirst + 2 * u;
         m[u] = *reinterpret_cast<const double2 *>(M + (long long)(r < rlast ? r : rlast) * ld + col);
     }
 }
 
-template <int NRHS>
-__device__ __forceinline__ void fma_pairs(const double2 (&m)[kRowBatch], const double *v, int ldv, int rfirst,
+template <int NRHS, int RB = kRowBatch>
+__device__ __forceinline__ void fma_pairs(const double2 (&m)[RB], const double *v, int ldv, int rfirst,
                                           int r1, double (&acc)[NRHS][1][2])
 {
 #pragma unroll
-    for (int u = 0; u < kRowBatch; ++u) {
+    for (int u = 0; u < RB; ++u) {
         const int r = rfirst + 2 * u;
         const bool in = r < r1;
 #pragma unroll
@@ -201,28 +204,28 @@ __device__ __forceinline__ void fma_pairs(const double2 (&m)[kRowBatch], const d
     }
 }
 
-template <int NRHS, int G = kWave>
+template <int NRHS, int G = kWave, int RB = kRowBatch>
 __device__ __forceinline__ void gemv_pairs(const double *__restrict__ M, int ld, int r0, int r1, int W,
                                            const double *v, int ldv, double (&acc)[NRHS][1][2], int lane)
 {
     const int h = lane >= G / 2 ? 1 : 0, l = lane & (G / 2 - 1);
     const int col = 2 * l < W ? 2 * l : 0;
     const int np = (r1 - r0 + 1) / 2;
-    const int nbt = (np + kRowBatch - 1) / kRowBatch;
+    const int nbt = (np + RB - 1) / RB;
     const int rlast = r1 - 1;
     double part[NRHS][1][2];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) part[k][0][0] = part[k][0][1] = 0.0;
-    double2 m0[kRowBatch], m1[kRowBatch];
-    load_pairs(m0, M, ld, r0 + h, rlast, col);
+    double2 m0[RB], m1[RB];
+    load_pairs<RB>(m0, M, ld, r0 + h, rlast, col);
     int b = 0;
     for (; b + 2 <= nbt; b += 2) {
-        load_pairs(m1, M, ld, r0 + 2 * (b + 1) * kRowBatch + h, rlast, col);
-        fma_pairs<NRHS>(m0, v, ldv, r0 + 2 * b * kRowBatch + h, r1, part);
-        if (b + 2 < nbt) load_pairs(m0, M, ld, r0 + 2 * (b + 2) * kRowBatch + h, rlast, col);
-        fma_pairs<NRHS>(m1, v, ldv, r0 + 2 * (b + 1) * kRowBatch + h, r1, part);
+        load_pairs<RB>(m1, M, ld, r0 + 2 * (b + 1) * RB + h, rlast, col);
+        fma_pairs<NRHS, RB>(m0, v, ldv, r0 + 2 * b * RB + h, r1, part);
+        if (b + 2 < nbt) load_pairs<RB>(m0, M, ld, r0 + 2 * (b + 2) * RB + h, rlast, col);
+        fma_pairs<NRHS, RB>(m1, v, ldv, r0 + 2 * (b + 1) * RB + h, r1, part);
     }
-    if (b < nbt) fma_pairs<NRHS>(m0, v, ldv, r0 + 2 * b * kRowBatch + h, r1, part);
+    if (b < nbt) fma_pairs<NRHS, RB>(m0, v, ldv, r0 + 2 * b * RB + h, r1, part);
 #pragma unroll
     for (int k = 0; k < NRHS; ++k)
 #pragma unroll
@@ -341,7 +344,7 @@ __device__ __forceinline__ void add_to(double (&acc)[NRHS][CH][2], const double 
 // For a chain node (kChain) jc is the index of its only child; otherwise the
 // children are read from the child pointers.  The result qhat_i is left in
 // L.qx and, if store_q, written to the global buffer; k_i always goes to kbuf.
-template <int NRHS, int CH, int G, bool kChain = false>
+template <int NRHS, int CH, int G, bool kChain = false, int RB = kRowBatch>
 __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const WaveLds &L,
                          bool child_in_lds, bool store_q, int lane, int jc = -1)
 {
@@ -372,7 +375,7 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
             }
             wave_sync();
         }
-        gemv_rows<NRHS, CH, G>(a.Mb + I.Mb + (long long)j * nx * I.ldM, I.ldM, 0, nx, W, L.qx, L.ldq, acc, lane);
+        gemv_rows<NRHS, CH, G, RB>(a.Mb + I.Mb + (long long)j * nx * I.ldM, I.ldM, 0, nx, W, L.qx, L.ldq, acc, lane);
         wave_sync();
     }
     // early: L.as = [sum A'q + s_i y_i^x + chat_i ; g_i], g_i = sum B'q + s_i y_i^u + sigma_i;
@@ -396,15 +399,15 @@ __device__ void bwd_node(const SweepArgs &a, const InstDesc &I, int i, const Wav
     zero(qacc);
     if constexpr (CH == 1) {
         if (nx <= G && nu >= 2) {
-            gemv_pairs<NRHS, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, gs, L.ldq, kacc, lane);
-            gemv_pairs<NRHS, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, gs, L.ldq, qacc, lane);
+            gemv_pairs<NRHS, G, RB>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, gs, L.ldq, kacc, lane);
+            gemv_pairs<NRHS, G, RB>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, gs, L.ldq, qacc, lane);
         } else {
-            gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, gs, L.ldq, kacc, lane);
-            gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, gs, L.ldq, qacc, lane);
+            gemv_rows<NRHS, CH, G, RB>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, gs, L.ldq, kacc, lane);
+            gemv_rows<NRHS, CH, G, RB>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, gs, L.ldq, qacc, lane);
         }
     } else {
-        gemv_rows<NRHS, CH, G>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, gs, L.ldq, kacc, lane);
-        gemv_rows<NRHS, CH, G>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, gs, L.ldq, qacc, lane);
+        gemv_rows<NRHS, CH, G, RB>(a.Rn + I.Rn + (long long)i * nu * I.ldu, I.ldu, 0, nu, nu, gs, L.ldq, kacc, lane);
+        gemv_rows<NRHS, CH, G, RB>(a.Kb + I.Kb + (long long)i * nu * I.ldx, I.ldx, 0, nu, nx, gs, L.ldq, qacc, lane);
     }
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
@@ -1337,8 +1340,8 @@ __device__ __forceinline__ void bwd_chain_body(const SweepArgs &a, const Item *i
     const int head = sp[I.sstar] + chain;
     for (int t = I.N - 1; t >= I.sstar; --t) {
         const int i = head + (t - I.sstar) * I.nchains;
-        bwd_node<NRHS, CH, G, (G < kWave)>(a, I, i, L, t != I.N - 1, t == I.sstar && t > 0, lane,
-                                           i + I.nchains);
+        bwd_node<NRHS, CH, G, (G < kWave), G == kWave ? kChainRowBatch : kRowBatch>(
+            a, I, i, L, t != I.N - 1, t == I.sstar && t > 0, lane, i + I.nchains);
     }
 }
 
