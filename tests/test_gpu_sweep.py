@@ -57,6 +57,29 @@ def test_dual_grad_matches_oracle(st, name, precondition):
     tf.free()
 
 
+# 64-lane chains (64 < nx + nu <= 128) whose row products end on every
+# remainder of the backward batch depth: nx mod 6 (the [A B] rows) and
+# ceil(nu / 2) mod 6 (the paired rows of the nu x nu and nu x nx products)
+CHAIN_SHAPES = [(36, 30), (37, 33), (38, 37), (39, 29), (40, 32), (41, 35), (42, 27)]
+
+
+@pytest.mark.parametrize("nx,nu", CHAIN_SHAPES)
+def test_wide_chain_batch_remainders(st, nx, nu):
+    prob = treegen.draw_problem(treegen.uniform_tree([2, 1, 1, 1, 1, 1]), nx, nu, np.random.default_rng(nx))
+    print(f"chain shape nx={nx} nu={nu}", flush=True)
+    tf = st.tree_factor(prob, precondition=True)
+    pb, fac = oracle.factor(prob)
+    rng = np.random.default_rng(nu)
+    sc = row_scale(prob, True)
+    for homogeneous in (False, True):
+        ybar = rng.standard_normal(tf.m)
+        x, u = _run(st, tf, prob.x0, ybar, homogeneous)
+        xo, uo = oracle.sweep(pb, fac, sc * ybar, homogeneous=homogeneous)
+        assert _relerr(x[0], xo) < TOL_GRAD, (nx, nu, homogeneous, _relerr(x[0], xo))
+        assert _relerr(u[0], uo) < TOL_GRAD, (nx, nu, homogeneous, _relerr(u[0], uo))
+    tf.free()
+
+
 @pytest.mark.parametrize("nrhs", [2, 3, 5])
 @pytest.mark.parametrize("name", ["odd_ragged", "fanout"])
 def test_dual_grad_several_rhs(st, name, nrhs):
